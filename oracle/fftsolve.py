@@ -1,0 +1,182 @@
+"""FFT-embedded interaction matrix and plain BiCGSTAB, FP64, on the CPU.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``): never imported by the
+product path.
+
+The off-diagonal part of A depends only on r_j - r_l, so on a cubic lattice it
+is a three-level block-Toeplitz matrix; embedded in a circulant on a
+zero-padded grid it is applied with three-dimensional FFTs (Goodman, Draine &
+Flatau 1990, the method the guide names in "Choice of FFT Algorithm" and in
+its acknowledgments of the FFT convolution code).  The padded extent along each
+axis is 2n if that is a product of powers of 2, 3 and 5, otherwise the smallest
+such number >= 2n - 1 (any extent >= 2n - 1 holds every separation
+-(n-1)..(n-1) without wrap-around; the guide's "extension" of the
+computational volume to 2^i 3^j 5^k sizes is the same idea).
+
+BiCGSTAB is van der Vorst (1992), the PBCGST option of "Choice of Iterative
+Algorithm", with x0 = 0 (the guide's usual starting guess), shadow residual
+r^ = r0 and conjugated inner products <u, v> = sum conj(u) v.  It stops when
+|E - A P| / |E| < tol, checked after the half step (s) and after the full step.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+try:  # scipy's FFT is a library primitive with a thread-pool option
+    import scipy.fft as _fft
+
+    def _fftn(a, axes):
+        return _fft.fftn(a, axes=axes, workers=-1)
+
+    def _ifftn(a, axes):
+        return _fft.ifftn(a, axes=axes, workers=-1)
+except Exception:  # pragma: no cover
+    def _fftn(a, axes):
+        return np.fft.fftn(a, axes=axes)
+
+    def _ifftn(a, axes):
+        return np.fft.ifftn(a, axes=axes)
+
+from . import dense
+
+
+def is_smooth235(m: int) -> bool:
+    for p in (2, 3, 5):
+        while m % p == 0:
+            m //= p
+    return m == 1
+
+
+def padded_extent(n: int) -> int:
+    """2n when 2,3,5-smooth, else the smallest 2,3,5-smooth integer >= 2n-1."""
+    if is_smooth235(2 * n):
+        return 2 * n
+    m = max(2 * n - 1, 1)
+    while not is_smooth235(m):
+        m += 1
+    return m
+
+
+class FFTOperator:
+    """A (for one right-hand side's 1/alpha) applied by FFT convolution."""
+
+    def __init__(self, ijk, alpha_inv_sites, k: float):
+        ijk = np.asarray(ijk, dtype=np.int64)
+        self.lo = ijk.min(axis=0)
+        self.pos = ijk - self.lo
+        self.n = tuple(int(v) for v in self.pos.max(axis=0) + 1)
+        self.M = tuple(padded_extent(v) for v in self.n)
+        self.k = k
+        self.alpha_inv = np.asarray(alpha_inv_sites, dtype=np.complex128)
+        self.ghat = self._green_hat()
+
+    def _offsets(self, axis):
+        """Signed lattice separation stored at each padded index (None = empty slot)."""
+        n, M = self.n[axis], self.M[axis]
+        off = np.zeros(M)
+        valid = np.zeros(M, dtype=bool)
+        for m in range(M):
+            if m <= n - 1:
+                off[m], valid[m] = m, True
+            elif m >= M - (n - 1):
+                off[m], valid[m] = m - M, True
+        return off, valid
+
+    def _green_hat(self):
+        """FFT of the six distinct components of the off-diagonal tensor,
+        sampled at every separation on the padded grid (zero at R = 0 and in
+        the empty slots).  Order: xx, xy, xz, yy, yz, zz."""
+        ox, vx = self._offsets(0)
+        oy, vy = self._offsets(1)
+        oz, vz = self._offsets(2)
+        X, Y, Z = np.meshgrid(ox, oy, oz, indexing="ij")
+        V = vx[:, None, None] & vy[None, :, None] & vz[None, None, :]
+        r = np.sqrt(X * X + Y * Y + Z * Z)
+        V &= r > 0
+        rs = np.where(V, r, 1.0)
+        k = self.k
+        pref = np.exp(1j * k * rs) / rs
+        c_iso = pref * (-k * k - (1j * k * rs - 1.0) / rs ** 2)
+        c_nn = pref * (k * k + 3.0 * (1j * k * rs - 1.0) / rs ** 2) / rs ** 2
+        comps = []
+        R = (X, Y, Z)
+        for a, b in ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)):
+            g = c_nn * R[a] * R[b] + (c_iso if a == b else 0.0)
+            comps.append(np.where(V, g, 0.0))
+        return _fftn(np.stack(comps), axes=(1, 2, 3))
+
+    def apply(self, x):
+        """y = A x for x of shape [N, 3]."""
+        x = np.asarray(x, dtype=np.complex128)
+        grid = np.zeros((3,) + self.M, dtype=np.complex128)
+        p = self.pos
+        for a in range(3):
+            grid[a][p[:, 0], p[:, 1], p[:, 2]] = x[:, a]
+        xh = _fftn(grid, axes=(1, 2, 3))
+        g = self.ghat
+        full = ((g[0], g[1], g[2]), (g[1], g[3], g[4]), (g[2], g[4], g[5]))
+        yh = np.stack([full[a][0] * xh[0] + full[a][1] * xh[1] + full[a][2] * xh[2] for a in range(3)])
+        y = _ifftn(yh, axes=(1, 2, 3))
+        out = np.stack([y[a][p[:, 0], p[:, 1], p[:, 2]] for a in range(3)], axis=1)
+        return out + self.alpha_inv * x
+
+
+def bicgstab(apply, b, tol: float, max_iter: int, x0=None):
+    """Plain BiCGSTAB (van der Vorst 1992) on [N, 3] complex vectors.
+
+    Returns (x, info) with info = dict(iters, matvecs, rel_residual (recursive),
+    converged)."""
+    b = np.asarray(b, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    matvecs = 0
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - apply(x)
+        matvecs += 1
+    rhat = r.copy()
+    rho_old = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    if np.linalg.norm(r) / bnorm < tol:
+        return x, dict(iters=0, matvecs=matvecs, rel_residual=float(np.linalg.norm(r) / bnorm), converged=True)
+    for it in range(1, max_iter + 1):
+        rho = np.vdot(rhat, r)
+        beta = (rho / rho_old) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = apply(p)
+        matvecs += 1
+        alpha = rho / np.vdot(rhat, v)
+        s = r - alpha * v
+        sn = np.linalg.norm(s) / bnorm
+        if sn < tol:
+            x = x + alpha * p
+            return x, dict(iters=it, matvecs=matvecs, rel_residual=float(sn), converged=True)
+        t = apply(s)
+        matvecs += 1
+        omega = np.vdot(t, s) / np.vdot(t, t)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho_old = rho
+        rn = np.linalg.norm(r) / bnorm
+        if rn < tol:
+            return x, dict(iters=it, matvecs=matvecs, rel_residual=float(rn), converged=True)
+    return x, dict(iters=max_iter, matvecs=matvecs, rel_residual=float(rn), converged=False)
+
+
+def solve_case(ijk, m_sites, x: float, khat, e0, tol: float, scheme: str = dense.LATTDR,
+               m_medium: float = 1.0, max_iter: int = 1000) -> dict:
+    """FFT-BiCGSTAB solve of one right-hand side; returns P, E, the Q's and
+    solver counts (Q_sca = Q_ext - Q_abs here; the closed form is O(N^2))."""
+    n = len(ijk)
+    k = dense.kd_from_size_parameter(x, n)
+    m_rel = np.asarray(m_sites, dtype=np.complex128) / m_medium
+    ainv = dense.site_alpha_inverse(m_rel, k, khat, e0, scheme)
+    op = FFTOperator(ijk, ainv, k)
+    E = dense.incident_field(ijk, k, khat, e0)
+    P, info = bicgstab(op.apply, E, tol, max_iter)
+    qe, qa = dense.q_ext(E, P, k), dense.q_abs(P, ainv, k)
+    true_res = float(np.linalg.norm(E - op.apply(P)) / np.linalg.norm(E))
+    return dict(P=P, E=E, alpha_inv=ainv, k=k, op=op, qext=qe, qabs=qa, qsca=qe - qa,
+                qpha=dense.q_pha(E, P, k), true_residual=true_res, **info)

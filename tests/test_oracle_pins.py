@@ -1,0 +1,323 @@
+"""Pins of the CPU oracle to things other than itself (no GPU needed).
+
+Each test names what fixes the expected value: the guide's printed worked
+example, textbook limits, brute-force quadrature, finite differences, or
+exact algebraic identities of the physics (energy conservation).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import adjoint, dense, fftsolve, mie
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- worked example
+
+def _worked():
+    with open(os.path.join(GOLDEN, "worked_example_au_brick.json")) as f:
+        return json.load(f)
+
+
+def test_worked_example_lattice_constants():
+    """d/a_eff and kd printed in the .avg header of the guide's sample run."""
+    g = _worked()
+    ijk = w.brick(*g["shape"])
+    assert len(ijk) == g["n_sites"]
+    # one unit in the last printed place (the sample run is a single-precision build)
+    assert abs(1.0 / dense.aeff_over_d(len(ijk)) - g["d_over_aeff"]) < 1e-8
+    assert abs(dense.kd_from_size_parameter(g["x"], len(ijk)) - g["kd"]) < 5e-6
+
+
+def test_worked_example_efficiencies_gkdldr():
+    """The whole pipeline (interaction tensor, FFT embedding, GKDLDR
+    polarizability, E_inc, Q_ext/Q_abs/Q_pha) reproduces the printed
+    efficiencies of the 16x32x32 gold brick to the printed digits (1e-4
+    relative: the guide solved with PBCGS2 to TOL 1e-5)."""
+    g = _worked()
+    d = w.workload("au_brick")
+    m = np.full(len(d["ijk"]), complex(*g["m"]))
+    r = fftsolve.solve_case(d["ijk"], m, g["x"], d["khat"][0], d["e0"][0], tol=1e-7, scheme=dense.GKDLDR)
+    for key in ("qext", "qabs", "qsca", "qpha"):
+        assert abs(r[key] - g[key]) <= 1e-4 * abs(g[key]) + 5e-6, (key, r[key], g[key])
+
+
+def test_worked_example_discriminates_lattdr():
+    """The printed Q_ext is not reproduced by the LATTDR prescription (it
+    differs by ~0.26%), so the example pins the GKDLDR reading."""
+    g = _worked()
+    d = w.workload("au_brick")
+    m = np.full(len(d["ijk"]), complex(*g["m"]))
+    r = fftsolve.solve_case(d["ijk"], m, g["x"], d["khat"][0], d["e0"][0], tol=1e-6, scheme=dense.LATTDR)
+    assert abs(r["qext"] - g["qext"]) > 1e-3 * g["qext"]
+
+
+# ---------------------------------------------------------------- interaction tensor
+
+def _psi(r, k):
+    rr = np.linalg.norm(r)
+    return np.exp(1j * k * rr) / rr
+
+
+@pytest.mark.parametrize("k", [0.0, 0.3, 1.1])
+@pytest.mark.parametrize("R", [(1, 0, 0), (1, 2, -1), (-3, 1, 2), (0, -2, 5)])
+def test_interaction_tensor_is_dipole_field(k, R):
+    """-A_jl P is the field of an oscillating point dipole P at r_l:
+    E = k^2 psi P + grad(P . grad psi), psi = exp(ikr)/r.  The Hessian of psi
+    is taken by central finite differences, independently of the closed form
+    (k = 0 is the static dipole field)."""
+    R = np.array(R, dtype=np.float64)
+    h = 2e-4
+    H = np.zeros((3, 3), dtype=np.complex128)
+    eye = np.eye(3)
+    for a in range(3):
+        for b in range(3):
+            H[a, b] = (_psi(R + h * eye[a] + h * eye[b], k) - _psi(R + h * eye[a] - h * eye[b], k)
+                       - _psi(R - h * eye[a] + h * eye[b], k) + _psi(R - h * eye[a] - h * eye[b], k)) / (4 * h * h)
+    field = k * k * _psi(R, k) * eye + H
+    A = dense.interaction_block(R, k)
+    assert np.allclose(A, -field, rtol=0, atol=2e-6 * np.abs(field).max())
+
+
+def test_matrix_complex_symmetric_not_hermitian():
+    """A = A^T exactly (reciprocity); A != A^H for an absorbing target."""
+    ijk = w.sphere_integer(2.2)
+    k = 0.4
+    ainv = dense.site_alpha_inverse(np.full(len(ijk), 1.5 + 0.1j), k, [1, 0, 0], [0, 1, 0])
+    A = dense.assemble(ijk, ainv, k)
+    assert np.array_equal(A, A.T)
+    assert np.abs(A - A.conj().T).max() > 1e-3
+
+
+def test_assembly_blocks_match_pairwise_formula():
+    """Vectorised assembly agrees with the per-pair block and the 1/alpha diagonal."""
+    rng = np.random.default_rng(3)
+    ijk = rng.integers(-3, 4, size=(40, 3))
+    ijk = np.unique(ijk, axis=0)
+    k = 0.7
+    ainv = dense.site_alpha_inverse(np.full(len(ijk), 1.7 + 0.2j), k, [0, 0, 1], [1, 0, 0])
+    A = dense.assemble(ijk, ainv, k)
+    for j, l in [(0, 1), (5, 17), (len(ijk) - 1, 2)]:
+        assert np.allclose(A[3 * j:3 * j + 3, 3 * l:3 * l + 3], dense.interaction_block(ijk[j] - ijk[l], k), atol=1e-14)
+    assert np.allclose(np.diag(A)[:3], ainv[0])
+
+
+# ---------------------------------------------------------------- FFT embedding
+
+@pytest.mark.parametrize("shape", ["sphere", "ragged", "odd_pad", "line"])
+def test_fft_embedding_equals_dense(shape):
+    """The circulant embedding reproduces the dense product (any padded extent
+    >= 2n-1 is exact), including odd and 5-smooth extents (n=13 -> 25)."""
+    rng = np.random.default_rng(11)
+    if shape == "sphere":
+        ijk = w.sphere_integer(3.3)
+    elif shape == "ragged":
+        ijk = np.unique(rng.integers(0, 7, size=(150, 3)) * np.array([1, 1, 2]), axis=0)
+    elif shape == "odd_pad":
+        ijk = np.array([[i, j, 0] for i in range(13) for j in range(2)])
+    else:
+        ijk = np.array([[0, 0, i] for i in range(9)])
+    k = 0.55
+    ainv = dense.site_alpha_inverse(np.full(len(ijk), 1.4 + 0.05j), k, [0.6, 0.8, 0], [0, 0, 1])
+    A = dense.assemble(ijk, ainv, k)
+    op = fftsolve.FFTOperator(ijk, ainv, k)
+    x = w.random_vectors(5, (len(ijk), 3))
+    y = op.apply(x).reshape(-1)
+    assert np.abs(y - A @ x.reshape(-1)).max() <= 1e-12 * np.abs(y).max()
+
+
+def test_padded_extents():
+    """2n when 2,3,5-smooth, else the smallest smooth extent >= 2n-1."""
+    assert [fftsolve.padded_extent(n) for n in (1, 9, 13, 17, 41, 64, 48, 32, 40, 128)] == \
+        [2, 18, 25, 36, 81, 128, 96, 64, 80, 256]
+
+
+# ---------------------------------------------------------------- polarizability
+
+def test_polarizability_reduces_to_clausius_mossotti():
+    """kd -> 0: both LDR prescriptions tend to the Clausius-Mossotti value
+    alpha = (3/4pi)(eps-1)/(eps+2) d^3."""
+    for m in (1.33 + 0.01j, 2 + 1j):
+        eps = m * m
+        a_cm = 3.0 / (4 * math.pi) * (eps - 1) / (eps + 2)
+        for scheme in (dense.LATTDR, dense.GKDLDR):
+            ainv = dense.alpha_inverse(m, 1e-6, [1, 0, 0], [0, 1, 0], scheme)
+            assert np.allclose(1.0 / ainv, a_cm, rtol=1e-10)
+
+
+def test_radiative_reaction_makes_real_m_lossless():
+    """For real m the only imaginary part of 1/alpha is radiative reaction,
+    so Q_abs = 0 and Q_ext = Q_sca (energy conservation, Draine 1988)."""
+    ijk = w.sphere_integer(2.5)
+    s = dense.solve_case(ijk, np.full(len(ijk), 1.5 + 0j), 1.2, [1, 0, 0], [0, 1, 0])
+    assert abs(s["qabs"]) < 1e-13
+    assert abs(s["qext"] - s["qsca"]) < 1e-12 * s["qext"]
+
+
+# ---------------------------------------------------------------- efficiencies
+
+@pytest.mark.parametrize("scheme", [dense.LATTDR, dense.GKDLDR])
+def test_optical_theorem_at_lu_solution(scheme):
+    """Q_ext = Q_abs + Q_sca with Q_sca from the independent far-field
+    integral, at the exact (LU) solution, on the N=389 pseudosphere and on an
+    elliptically polarised oblique wave."""
+    d = w.workload("sphere389")
+    s = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], scheme)
+    assert abs(s["qext"] - s["qabs"] - s["qsca"]) < 1e-12 * s["qext"]
+    kh = np.array([0.36, 0.48, 0.8])
+    e0 = np.array([0.8, -0.6, 0]) + 1j * np.cross(kh, [0.8, -0.6, 0])
+    s = dense.solve_case(d["ijk"], np.full(389, 2.0 + 0.5j), 2.0, kh, e0, scheme)
+    assert abs(s["qext"] - s["qabs"] - s["qsca"]) < 1e-11 * s["qext"]
+
+
+def test_qsca_closed_form_matches_angular_quadrature():
+    """The analytic angular integral equals brute-force quadrature of
+    k^4 |sum_j (P_j - n (n.P_j)) exp(-i k n.r_j)|^2 over the sphere."""
+    rng = np.random.default_rng(2)
+    ijk = np.unique(rng.integers(-3, 4, size=(25, 3)), axis=0)
+    P = w.random_vectors(9, (len(ijk), 3))
+    k = 0.9
+    mu, wt = np.polynomial.legendre.leggauss(96)
+    phi = np.linspace(0, 2 * math.pi, 192, endpoint=False)
+    st = np.sqrt(1 - mu ** 2)
+    n = np.stack([np.outer(st, np.cos(phi)), np.outer(st, np.sin(phi)), np.outer(mu, np.ones_like(phi))], -1)
+    ph = np.exp(-1j * k * np.einsum("tpa,ja->tpj", n, ijk))
+    F = np.einsum("tpj,ja->tpa", ph, P)
+    Fperp = F - n * np.einsum("tpa,tpa->tp", n, F)[..., None]
+    integrand = k ** 4 * np.sum(np.abs(Fperp) ** 2, axis=-1)
+    csca = float(np.sum(wt[:, None] * integrand) * (2 * math.pi / len(phi)))
+    a = dense.aeff_over_d(len(ijk))
+    q_quad = csca / (math.pi * a * a)
+    assert abs(dense.q_sca_closed_form(ijk, P, k) - q_quad) < 1e-10 * q_quad
+
+
+def test_sphere_polarizations_equal():
+    """The pseudosphere is symmetric under y <-> z, so both polarizations
+    give the same efficiencies."""
+    d = w.workload("sphere389")
+    q = [dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][i], d["e0"][i], with_qsca=False) for i in range(2)]
+    assert abs(q[0]["qext"] - q[1]["qext"]) < 1e-13
+    assert abs(q[0]["qabs"] - q[1]["qabs"]) < 1e-13
+
+
+def test_single_dipole():
+    """One dipole: P = alpha E and energy balance Q_ext = Q_abs + Q_sca."""
+    ijk = np.zeros((1, 3), dtype=np.int32)
+    s = dense.solve_case(ijk, [1.7 + 0.3j], 0.3, [0, 0, 1], [1, 0, 0])
+    assert np.allclose(s["P"][0], s["E"][0] / s["alpha_inv"][0])
+    assert abs(s["qext"] - s["qabs"] - s["qsca"]) < 1e-14 * s["qext"]
+
+
+def test_rayleigh_limit():
+    """Small x at fixed N: the DDA sphere tends to the Rayleigh absorption
+    and scattering efficiencies of a small sphere (textbook) to within the
+    discretisation error of a 389-site pseudosphere (~1%)."""
+    d = w.workload("sphere389")
+    m = 1.33 + 0.01j
+    F = (m * m - 1) / (m * m + 2)
+    x = 0.01
+    s = dense.solve_case(d["ijk"], d["m"], x, d["khat"][0], d["e0"][0])
+    assert abs(s["qabs"] / (4 * x * F.imag) - 1) < 0.02
+    assert abs(s["qsca"] / (8 / 3 * x ** 4 * abs(F) ** 2) - 1) < 0.02
+
+
+# ---------------------------------------------------------------- Mie
+
+def test_mie_rayleigh_limit():
+    m = 1.5 + 0.1j
+    F = (m * m - 1) / (m * m + 2)
+    x = 1e-3
+    q = mie.efficiencies(m, x)
+    assert abs(q["qabs"] / (4 * x * F.imag) - 1) < 1e-5
+    assert abs(q["qsca"] / (8 / 3 * x ** 4 * abs(F) ** 2) - 1) < 1e-5
+
+
+def test_mie_lossless_and_extinction_paradox():
+    assert abs(mie.efficiencies(1.5, 3.0)["qabs"]) < 1e-13
+    assert abs(mie.efficiencies(1.5 + 0.5j, 300.0)["qext"] - 2.0) < 0.06
+
+
+def test_dda_vs_mie_sphere389():
+    """'Accurate to a few percent' ("Applicability of the DDA"): the N=389
+    pseudosphere at x=1, m=1.33+0.01i is within 3% of Mie in all three Q."""
+    d = w.workload("sphere389")
+    s = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0])
+    q = mie.efficiencies(1.33 + 0.01j, 1.0)
+    for key in ("qext", "qabs", "qsca"):
+        assert abs(s[key] / q[key] - 1) < 0.03, key
+
+
+# ---------------------------------------------------------------- solver
+
+def test_bicgstab_matches_lu():
+    d = w.workload("sphere389")
+    lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][1], d["e0"][1], with_qsca=False)
+    it = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][1], d["e0"][1], tol=1e-10)
+    assert it["converged"] and it["true_residual"] < 1e-9
+    assert np.abs(it["P"] - lu["P"]).max() < 1e-8 * np.abs(lu["P"]).max()
+    assert abs(it["qext"] - lu["qext"]) < 1e-9
+
+
+def test_normal_equation_residual_definition():
+    """eq. err_tol: |A^H A P - A^H E| / |A^H E| is zero at the exact solution
+    and equals the explicit expression for a perturbed P."""
+    d = w.workload("sphere389")
+    s = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], with_qsca=False)
+    true_r, ne_r = dense.residuals(s["A"], s["P"], s["E"])
+    assert true_r < 1e-13 and ne_r < 1e-12
+    Pp = s["P"] * (1 + 1e-3)
+    true_r, ne_r = dense.residuals(s["A"], Pp, s["E"])
+    assert 5e-4 < true_r < 2e-3 and ne_r > 0
+
+
+# ---------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("weights", [(1.0, 0.0), (0.0, 1.0)])
+def test_adjoint_gradient_matches_finite_differences(weights):
+    """Central differences of Q_abs (and of Q_ext) with respect to Re and Im
+    of eps_j on the 6^3 two-material target (dense solves)."""
+    d = w.workload("twomat6")
+    kh, e0 = d["khat"][0], d["e0"][0]
+    grad, sol = adjoint.gradient_dense(d["ijk"], d["m"], d["x"], kh, e0, *weights)
+    eps = np.asarray(d["m"]) ** 2
+    for j in (0, 37, 101, 215):
+        h = 1e-4 * abs(eps[j])
+        fd = []
+        for step in (h, 1j * h):
+            ep, em = eps.copy(), eps.copy()
+            ep[j] += step
+            em[j] -= step
+            fd.append((adjoint.objective_dense(d["ijk"], ep, d["x"], kh, e0, *weights)
+                       - adjoint.objective_dense(d["ijk"], em, d["x"], kh, e0, *weights)) / (2 * h))
+        fdc = fd[0] + 1j * fd[1]
+        assert abs(grad[j] - fdc) < 1e-6 * abs(grad).max(), (j, grad[j], fdc)
+
+
+# ---------------------------------------------------------------- inputs
+
+def test_orientation_frames():
+    """Lab axes in the target frame are orthonormal, right-handed, and hit
+    the guide's printed special cases: Theta=90, Phi=0, beta=0 puts a1 along
+    y_LF and a2 along -x_LF; beta=90 puts a2 along z_LF."""
+    for b, t, p in zip(*w.orientation_angles(0, 16)):
+        ax = w.lab_axes_in_target_frame(b, t, p)
+        assert np.allclose(ax @ ax.T, np.eye(3), atol=1e-14)
+        assert np.allclose(np.cross(ax[0], ax[1]), ax[2], atol=1e-14)
+    ax = w.lab_axes_in_target_frame(0.0, math.pi / 2, 0.0)
+    # a1 (TF x) along y_LF: y_LF = +x_TF;  a2 (TF y) along -x_LF: x_LF = -y_TF
+    assert np.allclose(ax[1], [1, 0, 0], atol=1e-15) and np.allclose(ax[0], [0, -1, 0], atol=1e-15)
+    ax = w.lab_axes_in_target_frame(math.pi / 2, math.pi / 2, 0.0)
+    assert np.allclose(ax[2], [0, 1, 0], atol=1e-15)
+    kh, e0 = w.incidences_for_orientations(0, 4)
+    assert np.allclose(np.cross(kh[0], np.conj(e0[0])), e0[1])
+
+
+def test_workload_sizes():
+    assert len(w.workload("sphere389")["ijk"]) == 389
+    assert len(w.workload("ellipsoid51k")["ijk"]) == 51488
+    assert len(w.box_sphere(128, 64.0)) == 1099136
