@@ -1,0 +1,181 @@
+/*
+ * dda.h -- C ABI of the MI355X (gfx950) discrete-dipole-approximation solver.
+ *
+ * The library solves A P = E for the 3N complex dipole polarizations P of a
+ * target made of N point dipoles on a cubic lattice, and returns P together
+ * with the efficiency factors Q_ext, Q_abs, Q_sca and Q_pha.  The problem
+ * statement follows the DDSCAT 7.2 User Guide (Draine & Flatau,
+ * arXiv:1202.3424):
+ *   - A P = E and the error measure: section "Choice of Iterative Algorithm"
+ *     (eq. AP=E and eq. err_tol);
+ *   - occupied lattice sites and per-site composition: "Target Generation:
+ *     Isolated Finite Targets" (the IXYZ/ICOMP site lists of FROM_FILE);
+ *   - refractive index per material and the ambient medium: "Dielectric
+ *     Functions" and "Application to Targets in Dielectric Media";
+ *   - wavelength and effective radius: "Vacuum Wavelengths", "Target Size
+ *     a_eff" and "Applicability of the DDA" (a_eff = (3N/4pi)^(1/3) d);
+ *   - incident direction and polarization in the target frame: "Target
+ *     Orientation" and "Incident Polarization State";
+ *   - TOL and MXITER: "Error Tolerance", "Maximum Number of Iterations";
+ *   - polarizability prescriptions LATTDR / GKDLDR: "Dipole Polarizabilities";
+ *   - Q_ext, Q_abs, Q_sca, Q_pha: "What Does It Calculate?";
+ *   - P and 1/alpha as stored for post-processing: appendix ".pol Files".
+ * The interaction matrix is applied as an FFT convolution on a zero-padded
+ * grid ("Choice of FFT Algorithm"), inside BiCGSTAB (the PBCGST option).
+ *
+ * Conventions
+ *   - Lengths are in units of the lattice spacing d internally; E0 has unit
+ *     amplitude; the phase of E_inc is referred to lattice index (0,0,0).
+ *   - Complex numbers are {re, im} pairs of doubles (dda_c64).
+ *   - Site-indexed device arrays are [n_rhs][n_sites][3] dda_c64, row-major,
+ *     in the caller's site order (the order of ijk passed to
+ *     dda_target_create).
+ *   - Every function returns a dda_status; nothing throws or exits across
+ *     the ABI.  After a non-OK status, dda_last_error() describes it.
+ *   - Host arrays passed in are borrowed for the duration of the call and
+ *     copied.  Device arrays are owned by the caller and never freed by the
+ *     library.  Handles are owned by the library until *_destroy.
+ *   - Work is enqueued on the context's HIP stream; functions that return
+ *     results on the host synchronise that stream before returning.
+ *   - A context and the targets created from it must be used from one host
+ *     thread at a time.
+ */
+#ifndef DDA_H
+#define DDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } dda_c64;
+
+typedef enum {
+    DDA_OK = 0,
+    DDA_E_INVALID = 1,        /* bad argument (see dda_last_error) */
+    DDA_E_NOMEM = 2,          /* device or host allocation failed */
+    DDA_E_DEVICE = 3,         /* a HIP call failed */
+    DDA_E_NOT_CONVERGED = 4,  /* max_iter reached; best iterate returned */
+    DDA_E_BREAKDOWN = 5,      /* Krylov breakdown persisted after one restart */
+    DDA_E_NONFINITE = 6       /* NaN or Inf met in the iteration */
+} dda_status;
+
+/* Polarizability prescription ("Dipole Polarizabilities"). */
+typedef enum { DDA_LATTDR = 0, DDA_GKDLDR = 1 } dda_polarizability;
+
+/* Iterative method ("Choice of Iterative Algorithm"): PBCGST = BiCGSTAB. */
+typedef enum { DDA_BICGSTAB = 0 } dda_solver;
+
+/* Arithmetic of the FFT matrix-vector product.  The Krylov recurrences,
+ * inner products, diagonal term and residual checks are FP64 in both modes
+ * ("Single vs. Double Precision" offers whole-program single or double). */
+typedef enum { DDA_FP64 = 0, DDA_FP32_MATVEC = 1 } dda_precision;
+
+typedef struct dda_ctx dda_ctx;
+typedef struct dda_target dda_target;
+
+/* One right-hand side: propagation direction khat (unit vector) and complex
+ * polarization e0 (normalised by the library; must be transverse to khat),
+ * both in the target frame. */
+typedef struct {
+    double khat[3];
+    dda_c64 e0[3];
+} dda_incidence;
+
+/* dda_opts.flags */
+#define DDA_FLAG_RECOMPUTE_GREEN 1u  /* rebuild the FFT of the Green tensor even if cached */
+#define DDA_FLAG_NO_FINAL_CHECKS 2u  /* skip the true-residual and eq. err_tol matvecs */
+
+typedef struct {
+    double wavelength;   /* vacuum wavelength (any physical unit) > 0 */
+    double aeff;         /* effective radius, same unit > 0 */
+    double m_medium;     /* real refractive index of the ambient medium > 0 (1 = vacuum) */
+    double tol;          /* stop when |E - A P| / |E| < tol; > 0 */
+    int32_t max_iter;    /* BiCGSTAB iteration cap >= 1 (two matvecs per iteration) */
+    int32_t polarizability;  /* dda_polarizability */
+    int32_t solver;          /* dda_solver */
+    int32_t precision;       /* dda_precision */
+    uint32_t flags;          /* DDA_FLAG_* */
+    int32_t reserved;
+} dda_opts;
+
+typedef struct {
+    double qext, qabs, qsca, qpha;   /* efficiency factors; qsca = qext - qabs */
+    double rel_residual;             /* true |E - A P| / |E| at the returned P */
+    double normal_eq_residual;       /* |A^H A P - A^H E| / |A^H E| (eq. err_tol) */
+    double kd;                       /* k d in the ambient medium */
+    double aeff_d;                   /* a_eff / d */
+    int32_t iters;                   /* BiCGSTAB iterations taken */
+    int32_t matvecs;                 /* FFT matrix-vector products in the iteration */
+    int32_t status;                  /* dda_status of this right-hand side */
+    int32_t restarts;                /* breakdown restarts taken (0 or 1) */
+} dda_result;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+dda_status dda_ctx_create(int device, void* hip_stream, dda_ctx** out);
+dda_status dda_ctx_destroy(dda_ctx* ctx);
+
+/* Upload a target.
+ *   ijk    host int32 [n_sites][3]: lattice indices of the occupied sites
+ *          (any integers; duplicates are an error).
+ *   m_site host dda_c64 [n_sites]: complex refractive index of each site
+ *          (equal values share one material).
+ * The library keeps sorted device copies, the occupancy map of the bounding
+ * box and, lazily, the FFT of the interaction tensor per (kd, precision).
+ * Errors: DDA_E_INVALID for n_sites < 1, duplicate sites, a box extent above
+ * 4096, more than 65535 distinct materials, or non-finite m; DDA_E_NOMEM. */
+dda_status dda_target_create(dda_ctx* ctx, int64_t n_sites, const int32_t* ijk,
+                             const dda_c64* m_site, dda_target** out);
+dda_status dda_target_destroy(dda_target* t);
+
+/* Geometry of a target: box[3] = bounding-box extents n, grid[3] = padded
+ * FFT extents M (2n when 2,3,5-smooth, else the smallest such >= 2n-1). */
+dda_status dda_target_geometry(const dda_target* t, int32_t box[3], int32_t grid[3]);
+
+/* y = A x for n_rhs right-hand sides (A depends on the incidence through
+ * 1/alpha).  x, y: device [n_rhs][n_sites][3], caller order; x and y may not
+ * alias.  Enqueued on the context stream; returns without synchronising. */
+dda_status dda_apply(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
+                     const dda_incidence* inc, const dda_c64* x, dda_c64* y);
+
+/* Solve A P = E for n_rhs incidences on one target (batched in every kernel;
+ * the right-hand sides share the interaction-tensor FFT).
+ *   P   device [n_rhs][n_sites][3] output (may be NULL: Q only);
+ *   P0  device warm start of the same shape, or NULL for P = 0;
+ *   res host [n_rhs] results.
+ * Returns the worst per-right-hand-side status (DDA_OK if all converged);
+ * the best iterate and its residuals are returned in every case. */
+dda_status dda_solve(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
+                     const dda_incidence* inc, dda_c64* P, const dda_c64* P0, dda_result* res);
+
+/* Solve several targets, each with its own right-hand sides, in one call.
+ *   targets[n_targets], opts[n_targets];
+ *   rhs_target[n_rhs] gives the target index of each right-hand side,
+ *   inc[n_rhs], P[n_rhs] (per right-hand side device pointer of
+ *   [n_sites(target)][3], or NULL), res[n_rhs]. */
+dda_status dda_solve_batched(dda_ctx* ctx, int32_t n_targets, dda_target* const* targets,
+                             const dda_opts* opts, int32_t n_rhs, const int32_t* rhs_target,
+                             const dda_incidence* inc, dda_c64* const* P, dda_result* res);
+
+/* Gradient of w_qabs*Q_abs + w_qext*Q_ext with respect to the permittivity
+ * eps_j = m_j^2 of every site, for one incidence, by the adjoint method (A is
+ * complex symmetric, so the adjoint system reuses the forward matvec).
+ *   P     device [n_sites][3] converged solution from dda_solve (caller order);
+ *   grad  device [n_sites] output, dQ/dRe(eps_j) + i dQ/dIm(eps_j);
+ *   adj   host result of the adjoint solve (iterations, residual, status). */
+dda_status dda_grad_eps(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const dda_incidence* inc,
+                        const dda_c64* P, double w_qabs, double w_qext, dda_c64* grad,
+                        dda_result* adj);
+
+/* Description of the last error or warning on this thread ("" if none).
+ * Valid until the next library call on the thread.  |m|kd >= 1 (the validity
+ * bound of "Applicability of the DDA") is reported here as a warning. */
+const char* dda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDA_H */

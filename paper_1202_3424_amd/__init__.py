@@ -1,0 +1,24 @@
+"""MI355X-native discrete-dipole-approximation solver.
+
+The DDA scattering problem of the DDSCAT 7.2 User Guide (Draine & Flatau,
+arXiv:1202.3424): N polarizable points on a cubic lattice, A P = E solved by
+BiCGSTAB whose matrix-vector product is an FFT convolution with the lattice
+Green tensor plus the lattice-dispersion-relation diagonal; returns P and
+Q_ext, Q_abs, Q_sca, Q_pha.  The compute path is libdda.so (HIP kernels for
+gfx950 behind the C ABI of include/dda.h); this package only marshals
+arguments.  ``paper_1202_3424_amd.build.build()`` compiles the library.
+
+The public names below load libdda.so on first use and raise ImportError if
+it has not been built: there is no fallback implementation.
+"""
+_PUBLIC = ("DDAError", "Options", "QEff", "Target", "apply", "context", "grad_eps", "last_error", "solve",
+           "solve_batched")
+
+__all__ = list(_PUBLIC)
+
+
+def __getattr__(name):
+    if name in _PUBLIC:
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

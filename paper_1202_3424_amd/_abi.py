@@ -1,0 +1,106 @@
+"""ctypes mirror of include/dda.h.  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdda.so")
+
+DDA_OK = 0
+DDA_E_INVALID = 1
+DDA_E_NOMEM = 2
+DDA_E_DEVICE = 3
+DDA_E_NOT_CONVERGED = 4
+DDA_E_BREAKDOWN = 5
+DDA_E_NONFINITE = 6
+
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_CONVERGED",
+                5: "E_BREAKDOWN", 6: "E_NONFINITE"}
+
+DDA_LATTDR = 0
+DDA_GKDLDR = 1
+DDA_BICGSTAB = 0
+DDA_FP64 = 0
+DDA_FP32_MATVEC = 1
+DDA_FLAG_RECOMPUTE_GREEN = 1
+DDA_FLAG_NO_FINAL_CHECKS = 2
+
+
+class C64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Incidence(ctypes.Structure):
+    _fields_ = [("khat", ctypes.c_double * 3), ("e0", C64 * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("wavelength", ctypes.c_double),
+        ("aeff", ctypes.c_double),
+        ("m_medium", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("polarizability", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("qext", ctypes.c_double),
+        ("qabs", ctypes.c_double),
+        ("qsca", ctypes.c_double),
+        ("qpha", ctypes.c_double),
+        ("rel_residual", ctypes.c_double),
+        ("normal_eq_residual", ctypes.c_double),
+        ("kd", ctypes.c_double),
+        ("aeff_d", ctypes.c_double),
+        ("iters", ctypes.c_int32),
+        ("matvecs", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+    ]
+
+
+# name -> (restype, argtypes): every symbol include/dda.h declares
+VP = ctypes.c_void_p
+SIGNATURES = {
+    "dda_ctx_create": (ctypes.c_int, [ctypes.c_int, VP, ctypes.POINTER(VP)]),
+    "dda_ctx_destroy": (ctypes.c_int, [VP]),
+    "dda_target_create": (ctypes.c_int, [VP, ctypes.c_int64, VP, VP, ctypes.POINTER(VP)]),
+    "dda_target_destroy": (ctypes.c_int, [VP]),
+    "dda_target_geometry": (ctypes.c_int, [VP, VP, VP]),
+    "dda_apply": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP]),
+    "dda_solve": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP,
+                                 ctypes.POINTER(Result)]),
+    "dda_solve_batched": (ctypes.c_int, [VP, ctypes.c_int32, VP, ctypes.POINTER(Opts), ctypes.c_int32, VP,
+                                         ctypes.POINTER(Incidence), VP, ctypes.POINTER(Result)]),
+    "dda_grad_eps": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Incidence), VP, ctypes.c_double,
+                                    ctypes.c_double, VP, ctypes.POINTER(Result)]),
+    "dda_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdda.so (built in-tree by ``paper_1202_3424_amd.build``).  Raises
+    if it is missing: there is no fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1202_3424_amd.build.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,249 @@
+"""Python binding of the C ABI (include/dda.h).
+
+Argument marshalling only: device memory and streams come from PyTorch, every
+step of the solve runs in the HIP kernels of libdda.so.  Importing this module
+loads the library and fails loudly if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _abi
+
+_lib = _abi.load()
+
+
+class DDAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.dda_last_error().decode()
+        super().__init__(f"{where}: {_abi.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str, allow=()):
+    if status != _abi.DDA_OK and status not in allow:
+        raise DDAError(status, where)
+    return status
+
+
+def last_error() -> str:
+    return _lib.dda_last_error().decode()
+
+
+# ------------------------------------------------------------------ contexts
+
+_contexts: dict = {}
+
+
+def context(device: int | None = None) -> ctypes.c_void_p:
+    """The library context bound to ``device`` and torch's current stream there."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    h = _contexts.get(key)
+    if h is None:
+        h = ctypes.c_void_p()
+        _check(_lib.dda_ctx_create(dev, ctypes.c_void_p(stream), ctypes.byref(h)), "dda_ctx_create")
+        _contexts[key] = h
+    return h
+
+
+# ------------------------------------------------------------------ options
+
+_POLZ = {"LATTDR": _abi.DDA_LATTDR, "GKDLDR": _abi.DDA_GKDLDR}
+_PREC = {"fp64": _abi.DDA_FP64, "fp32_matvec": _abi.DDA_FP32_MATVEC}
+
+
+@dataclass
+class Options:
+    """Solve options (see dda_opts).  ``for_size_parameter`` builds the
+    wavelength/a_eff pair of a given x = 2 pi a_eff m_medium / lambda."""
+    wavelength: float = 2 * math.pi
+    aeff: float = 1.0
+    m_medium: float = 1.0
+    tol: float = 1e-5
+    max_iter: int = 1000
+    polarizability: str = "LATTDR"
+    precision: str = "fp64"
+    recompute_green: bool = False
+    final_checks: bool = True
+
+    @classmethod
+    def for_size_parameter(cls, x: float, **kw) -> "Options":
+        m_med = kw.get("m_medium", 1.0)
+        return cls(wavelength=2 * math.pi * m_med / x, aeff=1.0, **kw)
+
+    def c(self) -> _abi.Opts:
+        flags = 0
+        if self.recompute_green:
+            flags |= _abi.DDA_FLAG_RECOMPUTE_GREEN
+        if not self.final_checks:
+            flags |= _abi.DDA_FLAG_NO_FINAL_CHECKS
+        return _abi.Opts(self.wavelength, self.aeff, self.m_medium, self.tol, int(self.max_iter),
+                         _POLZ[self.polarizability], _abi.DDA_BICGSTAB, _PREC[self.precision], flags, 0)
+
+
+def _incidences(khat, e0) -> ctypes.Array:
+    kh = np.atleast_2d(np.asarray(khat, dtype=np.float64))
+    ee = np.atleast_2d(np.asarray(e0, dtype=np.complex128))
+    if kh.shape != ee.shape or kh.shape[1] != 3:
+        raise ValueError("khat and e0 must both be [n_rhs, 3]")
+    arr = (_abi.Incidence * len(kh))()
+    for q in range(len(kh)):
+        for m in range(3):
+            arr[q].khat[m] = float(kh[q, m])
+            arr[q].e0[m] = _abi.C64(float(ee[q, m].real), float(ee[q, m].imag))
+    return arr
+
+
+def _dev_c128(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.complex128 and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a complex128 CUDA tensor of shape {tuple(shape)}")
+    return t.contiguous()
+
+
+# ------------------------------------------------------------------ targets
+
+class Target:
+    """A target uploaded to the device: occupied lattice sites ``ijk``
+    (int [N, 3]) and per-site complex refractive index ``m`` ([N])."""
+
+    def __init__(self, ijk, m, device: int | None = None):
+        ijk = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32))
+        if ijk.ndim != 2 or ijk.shape[1] != 3:
+            raise ValueError("ijk must be [N, 3]")
+        m = np.ascontiguousarray(np.broadcast_to(np.asarray(m, dtype=np.complex128), (len(ijk),)))
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.ctx = context(self.device)
+        self.n_sites = len(ijk)
+        h = ctypes.c_void_p()
+        _check(_lib.dda_target_create(self.ctx, self.n_sites, ijk.ctypes.data, m.ctypes.data, ctypes.byref(h)),
+               "dda_target_create")
+        self._h = h
+        box = (ctypes.c_int32 * 3)()
+        grid = (ctypes.c_int32 * 3)()
+        _check(_lib.dda_target_geometry(h, box, grid), "dda_target_geometry")
+        self.box = tuple(box)
+        self.grid = tuple(grid)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dda_target_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _result_dict(r: _abi.Result) -> dict:
+    return dict(qext=r.qext, qabs=r.qabs, qsca=r.qsca, qpha=r.qpha, rel_residual=r.rel_residual,
+                normal_eq_residual=r.normal_eq_residual, kd=r.kd, aeff_d=r.aeff_d, iters=r.iters,
+                matvecs=r.matvecs, status=r.status, restarts=r.restarts)
+
+
+# ------------------------------------------------------------------ calls
+
+def apply(target: Target, opts: Options, khat, e0, x: torch.Tensor) -> torch.Tensor:
+    """y = A x for each right-hand side (x: complex128 CUDA [n_rhs, N, 3])."""
+    inc = _incidences(khat, e0)
+    x = _dev_c128(x, (len(inc), target.n_sites, 3), "x")
+    y = torch.empty_like(x)
+    o = opts.c()
+    _check(_lib.dda_apply(target.ctx, target.handle, ctypes.byref(o), len(inc), inc, x.data_ptr(), y.data_ptr()),
+           "dda_apply")
+    return y
+
+
+def solve(target: Target, opts: Options, khat, e0, P0: torch.Tensor | None = None, want_P: bool = True,
+          raise_on_failure: bool = False):
+    """Solve A P = E for every incidence; returns (P or None, [result dict])."""
+    inc = _incidences(khat, e0)
+    n = len(inc)
+    P = torch.empty((n, target.n_sites, 3), dtype=torch.complex128, device=f"cuda:{target.device}") if want_P else None
+    p0 = _dev_c128(P0, (n, target.n_sites, 3), "P0") if P0 is not None else None
+    res = (_abi.Result * n)()
+    o = opts.c()
+    st = _lib.dda_solve(target.ctx, target.handle, ctypes.byref(o), n, inc, P.data_ptr() if P is not None else None,
+                        p0.data_ptr() if p0 is not None else None, res)
+    allow = () if raise_on_failure else (_abi.DDA_E_NOT_CONVERGED, _abi.DDA_E_BREAKDOWN, _abi.DDA_E_NONFINITE)
+    _check(st, "dda_solve", allow)
+    return P, [_result_dict(r) for r in res]
+
+
+def solve_batched(targets, opts, rhs_target, khat, e0, want_P: bool = True):
+    """Several targets, each with its own right-hand sides, in one call.
+    ``opts`` is one Options per target.  Returns ([P per rhs], [result dict])."""
+    inc = _incidences(khat, e0)
+    n = len(inc)
+    rt = np.asarray(rhs_target, dtype=np.int32)
+    if rt.shape != (n,):
+        raise ValueError("rhs_target must have one entry per right-hand side")
+    hs = (ctypes.c_void_p * len(targets))(*[t.handle.value for t in targets])
+    oa = (_abi.Opts * len(targets))(*[o.c() for o in opts])
+    Ps = []
+    ptrs = (ctypes.c_void_p * n)()
+    for q in range(n):
+        t = targets[int(rt[q])]
+        if want_P:
+            P = torch.empty((t.n_sites, 3), dtype=torch.complex128, device=f"cuda:{t.device}")
+            ptrs[q] = P.data_ptr()
+            Ps.append(P)
+        else:
+            Ps.append(None)
+    res = (_abi.Result * n)()
+    st = _lib.dda_solve_batched(targets[0].ctx, len(targets), hs, oa, n, rt.ctypes.data, inc, ptrs, res)
+    _check(st, "dda_solve_batched", (_abi.DDA_E_NOT_CONVERGED, _abi.DDA_E_BREAKDOWN, _abi.DDA_E_NONFINITE))
+    return Ps, [_result_dict(r) for r in res]
+
+
+def grad_eps(target: Target, opts: Options, khat, e0, P: torch.Tensor, w_qabs: float = 1.0, w_qext: float = 0.0):
+    """Gradient of w_qabs Q_abs + w_qext Q_ext with respect to eps_j = m_j^2
+    (dQ/dRe eps + i dQ/dIm eps), by one adjoint solve.  P: [N, 3] solution."""
+    inc = _incidences(khat, e0)
+    if len(inc) != 1:
+        raise ValueError("grad_eps takes one incidence")
+    P = _dev_c128(P, (target.n_sites, 3), "P")
+    g = torch.empty(target.n_sites, dtype=torch.complex128, device=P.device)
+    r = _abi.Result()
+    o = opts.c()
+    st = _lib.dda_grad_eps(target.ctx, target.handle, ctypes.byref(o), inc, P.data_ptr(), float(w_qabs),
+                           float(w_qext), g.data_ptr(), ctypes.byref(r))
+    _check(st, "dda_grad_eps", (_abi.DDA_E_NOT_CONVERGED,))
+    return g, _result_dict(r)
+
+
+class QEff(torch.autograd.Function):
+    """(Q_abs, Q_ext) of a target as a differentiable function of the per-site
+    permittivity eps ([N] complex128).  Backward runs one adjoint solve.
+
+        q = QEff.apply(eps, ijk, opts, khat, e0)   # q = tensor([Q_abs, Q_ext])
+    """
+
+    @staticmethod
+    def forward(ctx, eps, ijk, opts, khat, e0):
+        m = torch.sqrt(eps.detach().to("cpu", torch.complex128)).numpy()
+        tgt = Target(ijk, m)
+        P, res = solve(tgt, opts, [khat], [e0], raise_on_failure=True)
+        ctx.tgt, ctx.opts, ctx.khat, ctx.e0 = tgt, opts, khat, e0
+        ctx.save_for_backward(P[0])
+        ctx.eps_device = eps.device
+        return torch.tensor([res[0]["qabs"], res[0]["qext"]], dtype=torch.float64, device=eps.device)
+
+    @staticmethod
+    def backward(ctx, gq):
+        (P,) = ctx.saved_tensors
+        g = gq.detach().to("cpu", torch.float64)
+        grad, _ = grad_eps(ctx.tgt, ctx.opts, ctx.khat, ctx.e0, P, float(g[0]), float(g[1]))
+        return grad.to(ctx.eps_device), None, None, None, None

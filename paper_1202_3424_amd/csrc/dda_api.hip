@@ -1,0 +1,732 @@
+// C ABI of the DDA solver (include/dda.h): contexts, targets, the
+// FFT-matvec plan, the cached FFT of the interaction tensor, and the batched
+// BiCGSTAB driver.  Every arithmetic step runs in the kernels of
+// dda_kernels.hip; this file validates, plans, allocates and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/dda.h"
+#include "dda_kernels.h"
+
+using namespace dda;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const std::string& m) { g_err = m; }
+
+struct Fail {
+    dda_status st;
+};
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_err(std::string(#expr) + " failed: " + hipGetErrorString(e_));            \
+            throw Fail{e_ == hipErrorOutOfMemory ? DDA_E_NOMEM : DDA_E_DEVICE};           \
+        }                                                                                 \
+    } while (0)
+
+[[noreturn]] void invalid(const std::string& m) {
+    set_err(m);
+    throw Fail{DDA_E_INVALID};
+}
+
+// Device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void* ensure(size_t need) {
+        if (need <= bytes) return p;
+        if (p) HIPCHK(hipFree(p));
+        p = nullptr;
+        bytes = 0;
+        HIPCHK(hipMalloc(&p, need));
+        bytes = need;
+        return p;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+bool smooth235(int m) {
+    for (int f : {2, 3, 5})
+        while (m % f == 0) m /= f;
+    return m == 1;
+}
+
+// 2n when 2,3,5-smooth, else the smallest smooth extent >= 2n - 1: every
+// separation -(n-1)..(n-1) then has its own slot, so the circulant product
+// equals the Toeplitz one exactly.
+int padded_extent(int n) {
+    if (smooth235(2 * n)) return 2 * n;
+    int m = std::max(2 * n - 1, 1);
+    while (!smooth235(m)) ++m;
+    return m;
+}
+
+// Radix sequence: powers of two as 8s and 4s (a single 2 only for L = 2^1 or
+// 2^(3j+1) with j = 0), then 3s, then 5s.
+AxisPlan make_plan(int L) {
+    AxisPlan pl{};
+    pl.L = L;
+    int m = L, e2 = 0;
+    while (m % 2 == 0) { m /= 2; ++e2; }
+    std::vector<int> r;
+    if (e2 % 3 == 1 && e2 >= 4) { r.push_back(4); r.push_back(4); e2 -= 4; }
+    if (e2 % 3 == 2) { r.push_back(4); e2 -= 2; }
+    if (e2 % 3 == 1) { r.push_back(2); e2 -= 1; }
+    while (e2 >= 3) { r.push_back(8); e2 -= 3; }
+    while (m % 3 == 0) { r.push_back(3); m /= 3; }
+    while (m % 5 == 0) { r.push_back(5); m /= 5; }
+    if (m != 1 || (int)r.size() > MAXST) invalid("unsupported FFT length " + std::to_string(L));
+    pl.nst = (int)r.size();
+    for (int i = 0; i < pl.nst; ++i) pl.R[i] = r[i];
+    return pl;
+}
+
+}  // namespace
+
+struct dda_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf grid, vecs, state, partials, counters, inc, ainv, dainv, mrel, aux, gtmp;
+    RhsState* host_state = nullptr;
+    int host_state_cap = 0;
+};
+
+struct dda_target {
+    dda_ctx* ctx = nullptr;
+    int nsites = 0;
+    int nmat = 0;
+    Geo geo{};
+    std::vector<double2> mats;       // distinct refractive indices
+    DevBuf map, mat, coords, perm, tw;
+    // cached FFT of the interaction tensor
+    double green_kd = -1.0;
+    bool have64 = false, have32 = false;
+    DevBuf gh64, gh32;
+};
+
+namespace {
+
+struct Scope {  // make the context's device current for the duration of a call
+    int prev = 0;
+    explicit Scope(const dda_ctx* c) {
+        (void)hipGetDevice(&prev);
+        if (c && c->device != prev) HIPCHK(hipSetDevice(c->device));
+    }
+    ~Scope() { (void)hipSetDevice(prev); }
+};
+
+double aeff_over_d(int n) { return std::cbrt(3.0 * n / (4.0 * M_PI)); }
+
+double kd_of(const dda_opts* o, int nsites) {
+    const double d = o->aeff / aeff_over_d(nsites);
+    return 2.0 * M_PI * o->m_medium / o->wavelength * d;
+}
+
+void check_opts(const dda_opts* o) {
+    if (!o) invalid("opts is NULL");
+    if (!(o->wavelength > 0) || !std::isfinite(o->wavelength)) invalid("wavelength must be > 0");
+    if (!(o->aeff > 0) || !std::isfinite(o->aeff)) invalid("aeff must be > 0");
+    if (!(o->m_medium > 0) || !std::isfinite(o->m_medium)) invalid("m_medium must be > 0");
+    if (!(o->tol > 0) || !std::isfinite(o->tol)) invalid("tol must be > 0");
+    if (o->max_iter < 1) invalid("max_iter must be >= 1");
+    if (o->polarizability != DDA_LATTDR && o->polarizability != DDA_GKDLDR) invalid("unknown polarizability");
+    if (o->solver != DDA_BICGSTAB) invalid("unknown solver");
+    if (o->precision != DDA_FP64 && o->precision != DDA_FP32_MATVEC) invalid("unknown precision");
+}
+
+// Normalised incidences packed for the device: khat [n][3], e0 [n][3].
+void pack_incidence(int n, const dda_incidence* inc, std::vector<double>& kh, std::vector<double2>& e0) {
+    if (!inc) invalid("incidence array is NULL");
+    kh.resize((size_t)n * 3);
+    e0.resize((size_t)n * 3);
+    for (int q = 0; q < n; ++q) {
+        const dda_incidence& I = inc[q];
+        double kn = 0, en = 0;
+        for (int m = 0; m < 3; ++m) {
+            if (!std::isfinite(I.khat[m]) || !std::isfinite(I.e0[m].re) || !std::isfinite(I.e0[m].im))
+                invalid("non-finite incidence " + std::to_string(q));
+            kn += I.khat[m] * I.khat[m];
+            en += I.e0[m].re * I.e0[m].re + I.e0[m].im * I.e0[m].im;
+        }
+        kn = std::sqrt(kn);
+        en = std::sqrt(en);
+        if (std::fabs(kn - 1.0) > 1e-6) invalid("khat of incidence " + std::to_string(q) + " is not a unit vector");
+        if (en == 0.0) invalid("e0 of incidence " + std::to_string(q) + " is zero");
+        double dre = 0, dim = 0;
+        for (int m = 0; m < 3; ++m) {
+            dre += I.e0[m].re * I.khat[m] / kn;
+            dim += I.e0[m].im * I.khat[m] / kn;
+        }
+        if (std::sqrt(dre * dre + dim * dim) > 1e-6 * en)
+            invalid("e0 of incidence " + std::to_string(q) + " is not transverse to khat");
+        for (int m = 0; m < 3; ++m) {
+            kh[(size_t)q * 3 + m] = I.khat[m] / kn;
+            e0[(size_t)q * 3 + m] = double2{I.e0[m].re / en, I.e0[m].im / en};
+        }
+    }
+}
+
+// Everything one batched solve on one target needs on the device.
+struct Work {
+    dda_ctx* c;
+    dda_target* t;
+    int nrhs;
+    double kd;
+    bool fp32;
+    SiteArgs a{};
+    int site_blocks = 1;
+    void* grid = nullptr;
+    double* kh = nullptr;
+    double2* e0 = nullptr;
+
+    Work(dda_ctx* c_, dda_target* t_, int nrhs_, double kd_, bool fp32_) : c(c_), t(t_), nrhs(nrhs_), kd(kd_), fp32(fp32_) {
+        const Geo& g = t->geo;
+        const long long n3 = 3LL * t->nsites;
+        const size_t vbytes = (size_t)nrhs * n3 * sizeof(double2);
+        char* v = (char*)c->vecs.ensure(7 * vbytes);
+        a.nsites = t->nsites;
+        a.n3 = n3;
+        a.nrhs = nrhs;
+        a.nmat = t->nmat;
+        a.map = (const int*)t->map.p;
+        a.mat = (const int*)t->mat.p;
+        a.x = (double2*)(v + 0 * vbytes);
+        a.r = (double2*)(v + 1 * vbytes);
+        a.rhat = (double2*)(v + 2 * vbytes);
+        a.p = (double2*)(v + 3 * vbytes);
+        a.v = (double2*)(v + 4 * vbytes);
+        a.t = (double2*)(v + 5 * vbytes);
+        a.b = (double2*)(v + 6 * vbytes);
+        a.kd = kd;
+        const size_t cbytes = fp32 ? sizeof(float2) : sizeof(double2);
+        grid = c->grid.ensure((size_t)nrhs * g.npts * 3 * cbytes);
+        a.st = (RhsState*)c->state.ensure((size_t)nrhs * sizeof(RhsState));
+        // blocks of every reduction kernel, per right-hand side
+        const int xl = x_lines_per_tile(g.M[0], 3, fp32);
+        const int pass_blocks = ((g.n[1] + xl - 1) / xl) * g.n[2];
+        site_blocks = (int)std::min<long long>(1024, std::max<long long>(1, (n3 + 4LL * NT - 1) / (4LL * NT)));
+        a.maxblk = std::max(pass_blocks, site_blocks);
+        a.partials = (double*)c->partials.ensure((size_t)nrhs * a.maxblk * 4 * sizeof(double));
+        a.counters = (unsigned*)c->counters.ensure((size_t)nrhs * sizeof(unsigned) * 4);
+        // counters start at zero; every grid_sum leaves them at zero
+        launch_fill((double2*)a.counters, ((long long)nrhs * 4 * sizeof(unsigned) + 15) / 16, c->stream);
+        a.ainv = (const double2*)c->ainv.ensure((size_t)nrhs * t->nmat * 3 * sizeof(double2));
+        char* ib = (char*)c->inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
+        kh = (double*)ib;
+        e0 = (double2*)(ib + (((size_t)nrhs * 3 * sizeof(double) + 15) & ~(size_t)15));
+    }
+
+    void upload_incidence(const std::vector<double>& khv, const std::vector<double2>& e0v) {
+        HIPCHK(hipMemcpyAsync(kh, khv.data(), khv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(e0, e0v.data(), e0v.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    }
+
+    // 1/alpha for every (right-hand side, material); scheme + 2 = derivative
+    void alpha_table(int scheme, double m_medium, double2* out) {
+        std::vector<double2> mrel(t->nmat);
+        for (int i = 0; i < t->nmat; ++i) mrel[i] = double2{t->mats[i].x / m_medium, t->mats[i].y / m_medium};
+        double2* dm = (double2*)c->mrel.ensure(mrel.size() * sizeof(double2));
+        HIPCHK(hipMemcpyAsync(dm, mrel.data(), mrel.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+        launch_alpha(nrhs, t->nmat, dm, kh, e0, kd, scheme, out, c->stream);
+    }
+
+    template <typename T>
+    void matvec_t(int sc, int ga, int chk_sc, int chk_rest) {
+        using C = typename V2<T>::t;
+        const Geo& g = t->geo;
+        C* gr = (C*)grid;
+        const C* gh = (const C*)(fp32 ? t->gh32.p : t->gh64.p);
+        const double2* tw = (const double2*)t->tw.p;
+        hipStream_t s = c->stream;
+        launch_scatter_x<T>(sc, chk_sc, g, a, gr, tw, s);
+        launch_strided<T>(1, -1, chk_rest, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, s);
+        launch_strided<T>(2, 0, chk_rest, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, s);
+        launch_strided<T>(1, 1, chk_rest, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, s);
+        launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
+    }
+    void matvec(int sc, int ga, int chk_sc, int chk_rest) {
+        if (fp32) matvec_t<float>(sc, ga, chk_sc, chk_rest);
+        else matvec_t<double>(sc, ga, chk_sc, chk_rest);
+        HIPCHK(hipGetLastError());
+    }
+};
+
+// Build (or reuse) the octant FFT of the interaction tensor for this kd.
+void ensure_green(dda_ctx* c, dda_target* t, double kd, bool fp32, bool force) {
+    const bool fresh = force || t->green_kd != kd;
+    if (!fresh && (fp32 ? t->have32 : t->have64)) return;
+    const Geo& g = t->geo;
+    double2* G = (double2*)c->gtmp.ensure((size_t)g.npts * 6 * sizeof(double2));
+    const double2* tw = (const double2*)t->tw.p;
+    launch_green_sample(g, kd, G, c->stream);
+    launch_xgrid6(g, G, tw, c->stream);
+    launch_strided<double>(1, -1, CHK_NONE, g, 1, 6, g.M[2], g.M[1], g.M[1], G, tw, nullptr, nullptr, c->stream);
+    launch_strided<double>(2, -1, CHK_NONE, g, 1, 6, g.M[1], g.M[2], g.M[2], G, tw, nullptr, nullptr, c->stream);
+    const size_t nh = (size_t)g.H[0] * g.H[1] * g.H[2] * 6;
+    if (fresh) t->have64 = t->have32 = false;
+    double2* g64 = (double2*)t->gh64.ensure(nh * sizeof(double2));
+    float2* g32 = fp32 ? (float2*)t->gh32.ensure(nh * sizeof(float2)) : nullptr;
+    launch_green_octant(g, G, g64, g32, c->stream);
+    HIPCHK(hipGetLastError());
+    t->green_kd = kd;
+    t->have64 = true;
+    if (fp32) t->have32 = true;
+}
+
+void fetch_state(dda_ctx* c, const Work& w) {
+    if (c->host_state_cap < w.nrhs) {
+        if (c->host_state) (void)hipHostFree(c->host_state);
+        c->host_state = nullptr;
+        HIPCHK(hipHostMalloc((void**)&c->host_state, (size_t)w.nrhs * sizeof(RhsState), hipHostMallocDefault));
+        c->host_state_cap = w.nrhs;
+    }
+    HIPCHK(hipMemcpyAsync(c->host_state, w.a.st, (size_t)w.nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// BiCGSTAB on every right-hand side of w (b, ainv, state prepared); warm
+// start when x0_sorted != null (already in x).  Leaves P in w.a.x.
+void iterate(Work& w, const dda_opts* o, bool warm) {
+    dda_ctx* c = w.c;
+    launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, c->stream);
+    if (warm) {
+        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE);  // r = b - A x0 (in = x)
+        launch_init_warm(w.a, w.site_blocks, c->stream);
+    } else {
+        launch_init_cold(w.a, w.site_blocks, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    int launched = 0;
+    const int chunk = std::min(8, o->max_iter);
+    while (true) {
+        fetch_state(c, w);
+        bool active = false, restart = false;
+        for (int q = 0; q < w.nrhs; ++q) {
+            const RhsState& s = c->host_state[q];
+            if (s.status == ST_ACTIVE) active = true;
+            if (s.status == ST_BREAKDOWN && s.restarts == 0) restart = true;
+        }
+        if (restart) {
+            launch_restart(w.a, w.site_blocks, c->stream);
+            active = true;
+        }
+        if (!active || launched > o->max_iter + 2 * chunk) break;
+        for (int k = 0; k < chunk; ++k) {
+            w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
+            w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
+            launch_update(w.a, w.site_blocks, c->stream);
+        }
+        HIPCHK(hipGetLastError());
+        launched += chunk;
+    }
+}
+
+// true residual, eq. err_tol and the efficiency sums at x
+void final_checks(Work& w, bool normal_eq) {
+    dda_ctx* c = w.c;
+    SiteArgs& a = w.a;
+    a.in = a.x;
+    w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE);  // r = b - A x, red[0] = |r|^2
+    if (normal_eq) {
+        // A^H y = conj(A conj(y)) because A = A^T
+        a.in = a.r;
+        a.out = a.t;
+        a.slot = 1;
+        w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE);
+        a.in = a.b;
+        a.out = a.v;
+        a.slot = 2;
+        w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE);
+    }
+    launch_qsum(a, w.site_blocks, c->stream);
+    HIPCHK(hipGetLastError());
+}
+
+dda_status to_status(int s) {
+    switch (s) {
+        case ST_CONVERGED: return DDA_OK;
+        case ST_MAXITER: return DDA_E_NOT_CONVERGED;
+        case ST_BREAKDOWN: return DDA_E_BREAKDOWN;
+        case ST_NONFINITE: return DDA_E_NONFINITE;
+        default: return DDA_E_NOT_CONVERGED;
+    }
+}
+
+dda_status fill_results(const Work& w, bool normal_eq, dda_result* res) {
+    const double a = aeff_over_d(w.t->nsites);
+    const double cq = 4.0 * M_PI * w.kd / (M_PI * a * a);
+    dda_status worst = DDA_OK;
+    for (int q = 0; q < w.nrhs; ++q) {
+        const RhsState& s = w.c->host_state[q];
+        dda_result r{};
+        r.qext = cq * s.red[3];
+        r.qabs = cq * s.red[4];
+        r.qpha = 0.5 * cq * s.red[5];
+        r.qsca = r.qext - r.qabs;
+        r.rel_residual = std::sqrt(s.red[0] / s.bnorm2);
+        r.normal_eq_residual = normal_eq ? std::sqrt(s.red[1] / s.red[2]) : -1.0;
+        r.kd = w.kd;
+        r.aeff_d = a;
+        r.iters = s.iters;
+        r.matvecs = s.matvecs;
+        r.restarts = s.restarts;
+        r.status = to_status(s.status);
+        if (r.status != DDA_OK && (worst == DDA_OK || r.status > worst)) worst = (dda_status)r.status;
+        if (res) res[q] = r;
+    }
+    return worst;
+}
+
+void warn_validity(const dda_target* t, double kd, double m_medium) {
+    double mx = 0;
+    for (const double2& m : t->mats) mx = std::max(mx, std::hypot(m.x, m.y) / m_medium);
+    if (mx * kd >= 1.0) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "warning: |m|kd = %.3f >= 1, outside the DDA validity bound", mx * kd);
+        set_err(buf);
+    }
+}
+
+template <typename F> dda_status guarded(F&& f) {
+    g_err.clear();
+    try {
+        return f();
+    } catch (const Fail& e) {
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        set_err("host allocation failed");
+        return DDA_E_NOMEM;
+    } catch (...) {
+        set_err("unexpected C++ exception");
+        return DDA_E_DEVICE;
+    }
+}
+
+// One batched solve on one target: Q's in res, P (caller order) to P_out
+// (contiguous [nrhs][n][3]) or per-right-hand-side pointers.
+dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, const dda_incidence* inc,
+                     dda_c64* P, dda_c64* const* Pper, const dda_c64* P0, dda_result* res) {
+    check_opts(o);
+    if (nrhs < 1) invalid("n_rhs must be >= 1");
+    std::vector<double> kh;
+    std::vector<double2> e0;
+    pack_incidence(nrhs, inc, kh, e0);
+    const double kd = kd_of(o, t->nsites);
+    const bool fp32 = o->precision == DDA_FP32_MATVEC;
+    ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+    Work w(c, t, nrhs, kd, fp32);
+    w.upload_incidence(kh, e0);
+    w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
+    launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
+    const bool warm = P0 != nullptr;
+    if (warm) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P0, w.a.x, true, c->stream);
+    w.a.in = w.a.x;
+    iterate(w, o, warm);
+    const bool ne = (o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0;
+    final_checks(w, ne);
+    if (P) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, w.a.x, (double2*)P, false, c->stream);
+    if (Pper) {
+        for (int q = 0; q < nrhs; ++q)
+            if (Pper[q])
+                launch_permute(1, t->nsites, 3, (const int*)t->perm.p, w.a.x + (size_t)q * w.a.n3, (double2*)Pper[q],
+                               false, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    fetch_state(c, w);
+    dda_status st = fill_results(w, ne, res);
+    if (st == DDA_OK) warn_validity(t, kd, o->m_medium);
+    return st;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+dda_status dda_ctx_create(int device, void* hip_stream, dda_ctx** out) {
+    return guarded([&]() -> dda_status {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        int n = 0;
+        HIPCHK(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) invalid("no HIP device " + std::to_string(device));
+        auto* c = new dda_ctx();
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        *out = c;
+        return DDA_OK;
+    });
+}
+
+dda_status dda_ctx_destroy(dda_ctx* c) {
+    return guarded([&]() -> dda_status {
+        if (!c) return DDA_OK;
+        {
+            Scope sc(c);
+            (void)hipStreamSynchronize(c->stream);
+            for (DevBuf* b : {&c->grid, &c->vecs, &c->state, &c->partials, &c->counters, &c->inc, &c->ainv, &c->dainv,
+                              &c->mrel, &c->aux, &c->gtmp})
+                b->release();
+            if (c->host_state) (void)hipHostFree(c->host_state);
+        }
+        delete c;
+        return DDA_OK;
+    });
+}
+
+dda_status dda_target_create(dda_ctx* c, int64_t n_sites, const int32_t* ijk, const dda_c64* m_site,
+                             dda_target** out) {
+    return guarded([&]() -> dda_status {
+        if (!c || !out) invalid("ctx or out is NULL");
+        *out = nullptr;
+        if (n_sites < 1 || n_sites > (int64_t)1 << 30) invalid("n_sites out of range");
+        if (!ijk || !m_site) invalid("ijk or m_site is NULL");
+        Scope sc(c);
+        const int n = (int)n_sites;
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) { lo[a] = ijk[a]; hi[a] = ijk[a]; }
+        for (int j = 0; j < n; ++j)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], ijk[3 * j + a]);
+                hi[a] = std::max(hi[a], ijk[3 * j + a]);
+            }
+        Geo g{};
+        for (int a = 0; a < 3; ++a) {
+            const long long ext = (long long)hi[a] - lo[a] + 1;
+            if (ext > 4096) invalid("target extent above 4096 sites on an axis");
+            g.n[a] = (int)ext;
+            g.M[a] = padded_extent(g.n[a]);
+            g.H[a] = g.M[a] / 2 + 1;
+        }
+        for (int a = 0; a < 3; ++a)
+            if (6 * g.M[a] > Tile<double>::EMAX)
+                invalid("padded FFT extent " + std::to_string(g.M[a]) + " above the supported 341");
+        g.npts = (long long)g.M[0] * g.M[1] * g.M[2];
+        const long long boxv = (long long)g.n[0] * g.n[1] * g.n[2];
+        if (boxv > ((long long)1 << 31) - 1) invalid("bounding box too large");
+        // sort sites in box-scan order (x fastest), reject duplicates
+        std::vector<std::pair<long long, int>> key(n);
+        for (int j = 0; j < n; ++j) {
+            const long long x = ijk[3 * j] - lo[0], y = ijk[3 * j + 1] - lo[1], z = ijk[3 * j + 2] - lo[2];
+            key[j] = {(z * g.n[1] + y) * g.n[0] + x, j};
+        }
+        std::sort(key.begin(), key.end());
+        for (int j = 1; j < n; ++j)
+            if (key[j].first == key[j - 1].first)
+                invalid("duplicate lattice site (" + std::to_string(ijk[3 * key[j].second]) + "," +
+                        std::to_string(ijk[3 * key[j].second + 1]) + "," + std::to_string(ijk[3 * key[j].second + 2]) +
+                        ")");
+        auto* t = new dda_target();
+        t->ctx = c;
+        t->nsites = n;
+        std::vector<int> map((size_t)boxv, -1), perm(n), mat(n), coords((size_t)n * 3);
+        std::map<std::pair<double, double>, int> mid;
+        try {
+            for (int s = 0; s < n; ++s) {
+                const int j = key[s].second;
+                map[(size_t)key[s].first] = s;
+                perm[s] = j;
+                for (int a = 0; a < 3; ++a) coords[(size_t)s * 3 + a] = ijk[3 * j + a];
+                const dda_c64 m = m_site[j];
+                if (!std::isfinite(m.re) || !std::isfinite(m.im)) invalid("non-finite refractive index");
+                if (m.re == 1.0 && m.im == 0.0) invalid("refractive index 1 (vacuum) on an occupied site");
+                auto it = mid.find({m.re, m.im});
+                if (it == mid.end()) {
+                    if (mid.size() >= 65535) invalid("more than 65535 distinct materials");
+                    it = mid.emplace(std::make_pair(m.re, m.im), (int)mid.size()).first;
+                    t->mats.push_back(double2{m.re, m.im});
+                }
+                mat[s] = it->second;
+            }
+            t->nmat = (int)t->mats.size();
+            // FFT plans and their twiddle tables W_L^t = exp(-2 pi i t / L)
+            std::vector<double2> tw;
+            std::map<int, int> twoff;
+            for (int a = 0; a < 3; ++a) {
+                g.ax[a] = make_plan(g.M[a]);
+                auto it = twoff.find(g.M[a]);
+                if (it == twoff.end()) {
+                    const int off = (int)tw.size();
+                    for (int i = 0; i < g.M[a]; ++i) {
+                        const double ang = -2.0 * M_PI * (double)i / (double)g.M[a];
+                        tw.push_back(double2{std::cos(ang), std::sin(ang)});
+                    }
+                    it = twoff.emplace(g.M[a], off).first;
+                }
+                g.ax[a].tw = it->second;
+            }
+            t->geo = g;
+            auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+                b.ensure(bytes);
+                HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+            };
+            up(t->map, map.data(), map.size() * sizeof(int));
+            up(t->perm, perm.data(), perm.size() * sizeof(int));
+            up(t->mat, mat.data(), mat.size() * sizeof(int));
+            up(t->coords, coords.data(), coords.size() * sizeof(int));
+            up(t->tw, tw.data(), tw.size() * sizeof(double2));
+        } catch (...) {
+            for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw}) b->release();
+            delete t;
+            throw;
+        }
+        *out = t;
+        return DDA_OK;
+    });
+}
+
+dda_status dda_target_destroy(dda_target* t) {
+    return guarded([&]() -> dda_status {
+        if (!t) return DDA_OK;
+        {
+            Scope sc(t->ctx);
+            (void)hipStreamSynchronize(t->ctx->stream);
+            for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->gh64, &t->gh32}) b->release();
+        }
+        delete t;
+        return DDA_OK;
+    });
+}
+
+dda_status dda_target_geometry(const dda_target* t, int32_t box[3], int32_t grid[3]) {
+    return guarded([&]() -> dda_status {
+        if (!t || !box || !grid) invalid("NULL argument");
+        for (int a = 0; a < 3; ++a) {
+            box[a] = t->geo.n[a];
+            grid[a] = t->geo.M[a];
+        }
+        return DDA_OK;
+    });
+}
+
+dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs, const dda_incidence* inc,
+                     const dda_c64* x, dda_c64* y) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !x || !y) invalid("NULL argument");
+        if (x == y) invalid("x and y alias");
+        if (n_rhs < 1) invalid("n_rhs must be >= 1");
+        check_opts(o);
+        Scope sc(c);
+        std::vector<double> kh;
+        std::vector<double2> e0;
+        pack_incidence(n_rhs, inc, kh, e0);
+        const double kd = kd_of(o, t->nsites);
+        const bool fp32 = o->precision == DDA_FP32_MATVEC;
+        ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+        Work w(c, t, n_rhs, kd, fp32);
+        w.upload_incidence(kh, e0);
+        w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
+        launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)x, w.a.p, true, c->stream);
+        w.a.in = w.a.p;
+        w.a.out = w.a.v;
+        w.matvec(SC_PLAIN, GA_PLAIN, CHK_NONE, CHK_NONE);
+        launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, w.a.v, (double2*)y, false, c->stream);
+        HIPCHK(hipGetLastError());
+        return DDA_OK;
+    });
+}
+
+dda_status dda_solve(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs, const dda_incidence* inc,
+                     dda_c64* P, const dda_c64* P0, dda_result* res) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t) invalid("NULL ctx or target");
+        Scope sc(c);
+        return solve_one(c, t, o, n_rhs, inc, P, nullptr, P0, res);
+    });
+}
+
+dda_status dda_solve_batched(dda_ctx* c, int32_t n_targets, dda_target* const* targets, const dda_opts* opts,
+                             int32_t n_rhs, const int32_t* rhs_target, const dda_incidence* inc, dda_c64* const* P,
+                             dda_result* res) {
+    return guarded([&]() -> dda_status {
+        if (!c || !targets || !opts || !rhs_target || !inc) invalid("NULL argument");
+        if (n_targets < 1 || n_rhs < 1) invalid("n_targets and n_rhs must be >= 1");
+        Scope sc(c);
+        for (int q = 0; q < n_rhs; ++q)
+            if (rhs_target[q] < 0 || rhs_target[q] >= n_targets) invalid("rhs_target out of range");
+        dda_status worst = DDA_OK;
+        for (int ti = 0; ti < n_targets; ++ti) {
+            std::vector<int> idx;
+            for (int q = 0; q < n_rhs; ++q)
+                if (rhs_target[q] == ti) idx.push_back(q);
+            if (idx.empty()) continue;
+            if (!targets[ti]) invalid("NULL target");
+            std::vector<dda_incidence> sub(idx.size());
+            std::vector<dda_c64*> sp(idx.size());
+            std::vector<dda_result> sr(idx.size());
+            for (size_t i = 0; i < idx.size(); ++i) {
+                sub[i] = inc[idx[i]];
+                sp[i] = P ? P[idx[i]] : nullptr;
+            }
+            const dda_status st = solve_one(c, targets[ti], &opts[ti], (int)idx.size(), sub.data(), nullptr,
+                                            sp.data(), nullptr, sr.data());
+            for (size_t i = 0; i < idx.size(); ++i)
+                if (res) res[idx[i]] = sr[i];
+            if (st != DDA_OK && (worst == DDA_OK || st > worst)) worst = st;
+        }
+        return worst;
+    });
+}
+
+dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_incidence* inc, const dda_c64* P,
+                        double w_qabs, double w_qext, dda_c64* grad, dda_result* adj) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !P || !grad) invalid("NULL argument");
+        if (!std::isfinite(w_qabs) || !std::isfinite(w_qext)) invalid("non-finite weights");
+        check_opts(o);
+        Scope sc(c);
+        std::vector<double> kh;
+        std::vector<double2> e0;
+        pack_incidence(1, inc, kh, e0);
+        const double kd = kd_of(o, t->nsites);
+        const bool fp32 = o->precision == DDA_FP32_MATVEC;
+        ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+        Work w(c, t, 1, kd, fp32);
+        w.upload_incidence(kh, e0);
+        w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
+        double2* dainv = (double2*)c->dainv.ensure((size_t)t->nmat * 3 * sizeof(double2));
+        w.alpha_table(o->polarizability + 2, o->m_medium, dainv);
+        // P in sorted order, kept for the gradient
+        double2* Ps = (double2*)c->aux.ensure((size_t)w.a.n3 * sizeof(double2) + (size_t)t->nsites * sizeof(double2));
+        double2* gs = Ps + w.a.n3;
+        launch_permute(1, t->nsites, 3, (const int*)t->perm.p, (const double2*)P, Ps, true, c->stream);
+        launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
+        launch_adjoint_rhs(w.a, Ps, w_qabs, w_qext, c->stream);
+        w.a.in = w.a.x;
+        iterate(w, o, false);
+        final_checks(w, false);
+        w.a.in = Ps;
+        launch_grad(w.a, dainv, w_qabs, gs, c->stream);
+        launch_permute(1, t->nsites, 1, (const int*)t->perm.p, gs, (double2*)grad, false, c->stream);
+        HIPCHK(hipGetLastError());
+        fetch_state(c, w);
+        dda_result r{};
+        const dda_status st = fill_results(w, false, &r);
+        // the efficiency fields of an adjoint solve carry no physical meaning
+        r.qext = r.qabs = r.qsca = r.qpha = 0.0;
+        if (adj) *adj = r;
+        return st;
+    });
+}
+
+const char* dda_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

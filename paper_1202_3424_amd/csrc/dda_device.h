@@ -1,0 +1,331 @@
+// Device-side building blocks of the DDA solver for gfx950 (CDNA4):
+// complex helpers, the mixed-radix Stockham FFT over lines held in LDS, and
+// deterministic workgroup / grid reductions.
+//
+// The FFT follows the autosort (Stockham) formulation: a line of length
+// L = R_1 R_2 ... R_s is transformed in s passes; in the pass with radix R,
+// after the radices already applied multiply to Ns, butterfly j (0 <= j < L/R)
+// reads x[j + r L/R], multiplies input r by W_{Ns R}^{r (j mod Ns)}, takes a
+// length-R DFT and writes output q to ((j - j mod Ns) R + j mod Ns + q Ns).
+// The result is in natural order.  Twiddles W_L^t are FP64 tables computed
+// on the host and staged in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dda {
+
+constexpr int NT = 256;      // threads per workgroup, every kernel
+constexpr int MAXST = 12;    // radix stages per line
+
+// One FFT axis: length, radix sequence, offset of its W_L^t table.
+struct AxisPlan {
+    int L;
+    int nst;
+    int R[MAXST];
+    int tw;
+};
+
+enum RhsStatus : int {
+    ST_ACTIVE = 0,
+    ST_CONVERGED = 1,
+    ST_MAXITER = 2,
+    ST_BREAKDOWN = 3,
+    ST_NONFINITE = 4
+};
+
+// Per right-hand-side solver state, device resident.  Scalars of BiCGSTAB
+// (van der Vorst 1992) and the reductions that produce them.
+struct RhsState {
+    double2 rho;     // <rhat, r>
+    double2 alpha;
+    double2 omega;
+    double2 beta;
+    double bnorm2;   // |E|^2
+    double rnorm2;   // |r|^2 of the latest residual
+    double snorm2;   // |s|^2 of the latest half step
+    double tol2;     // tol^2
+    double red[8];   // end-of-solve reductions (see kernels)
+    int status;
+    int iters;
+    int matvecs;
+    int sconv;       // converged at the half step of the current iteration
+    int max_iter;
+    int restarts;
+    int pad0, pad1;
+};
+
+template <typename T> struct V2;
+template <> struct V2<double> { using t = double2; };
+template <> struct V2<float> { using t = float2; };
+
+template <typename C> __device__ __forceinline__ C mk(double re, double im) {
+    C c;
+    c.x = re;
+    c.y = im;
+    return c;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { C c; c.x = a.x + b.x; c.y = a.y + b.y; return c; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { C c; c.x = a.x - b.x; c.y = a.y - b.y; return c; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    C c;
+    c.x = a.x * b.x - a.y * b.y;
+    c.y = a.x * b.y + a.y * b.x;
+    return c;
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { C c; c.x = a.x; c.y = -a.y; return c; }
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { C c; c.x = a.x * s; c.y = a.y * s; return c; }
+// conj(a) * b
+template <typename C> __device__ __forceinline__ C cdotc(C a, C b) {
+    C c;
+    c.x = a.x * b.x + a.y * b.y;
+    c.y = a.x * b.y - a.y * b.x;
+    return c;
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    double d = b.x * b.x + b.y * b.y;
+    double2 c;
+    c.x = (a.x * b.x + a.y * b.y) / d;
+    c.y = (a.y * b.x - a.x * b.y) / d;
+    return c;
+}
+// multiply by exp(DIR i pi/2): -i for the forward transform, +i for the inverse
+template <int DIR, typename C> __device__ __forceinline__ C rot(C a) {
+    C c;
+    if (DIR < 0) { c.x = a.y; c.y = -a.x; } else { c.x = -a.y; c.y = a.x; }
+    return c;
+}
+
+// ---------------------------------------------------------------- small DFTs
+// y_q = sum_r v_r exp(DIR 2 pi i q r / R), in place.
+
+template <int R, int DIR, typename C> struct Dft;
+
+template <int DIR, typename C> struct Dft<2, DIR, C> {
+    static __device__ __forceinline__ void run(C* v) {
+        C a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <int DIR, typename C> struct Dft<4, DIR, C> {
+    static __device__ __forceinline__ void run(C* v) {
+        C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        C s13 = cadd(v[1], v[3]), d13 = rot<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    }
+};
+
+template <int DIR, typename C> struct Dft<8, DIR, C> {
+    static __device__ __forceinline__ void run(C* v) {
+        using S = decltype(v[0].x);
+        const S h = (S)0.70710678118654752440;
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, DIR, C>::run(e);
+        Dft<4, DIR, C>::run(o);
+        // o[q] *= exp(DIR 2 pi i q / 8)
+        C t1, t3;
+        t1.x = (o[1].x - DIR * o[1].y) * h;
+        t1.y = (o[1].y + DIR * o[1].x) * h;
+        t3.x = (-o[3].x - DIR * o[3].y) * h;
+        t3.y = (-o[3].y + DIR * o[3].x) * h;
+        C t2 = rot<DIR>(o[2]);
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], t1);
+        v[5] = csub(e[1], t1);
+        v[2] = cadd(e[2], t2);
+        v[6] = csub(e[2], t2);
+        v[3] = cadd(e[3], t3);
+        v[7] = csub(e[3], t3);
+    }
+};
+
+template <int DIR, typename C> struct Dft<3, DIR, C> {
+    static __device__ __forceinline__ void run(C* v) {
+        using S = decltype(v[0].x);
+        const S s = (S)0.86602540378443864676;
+        C t1 = cadd(v[1], v[2]);
+        C t2 = cscale(rot<DIR>(csub(v[1], v[2])), s);
+        C m = csub(v[0], cscale(t1, (S)0.5));
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(m, t2);
+        v[2] = csub(m, t2);
+    }
+};
+
+template <int DIR, typename C> struct Dft<5, DIR, C> {
+    static __device__ __forceinline__ void run(C* v) {
+        using S = decltype(v[0].x);
+        const S c1 = (S)0.30901699437494742410, c2 = (S)-0.80901699437494742410;
+        const S s1 = (S)0.95105651629515357212, s2 = (S)0.58778525229247312917;
+        C a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        C a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        C p1 = cadd(v[0], cadd(cscale(a1, c1), cscale(a2, c2)));
+        C p2 = cadd(v[0], cadd(cscale(a1, c2), cscale(a2, c1)));
+        C q1 = rot<DIR>(cadd(cscale(b1, s1), cscale(b2, s2)));
+        C q2 = rot<DIR>(csub(cscale(b1, s2), cscale(b2, s1)));
+        v[0] = cadd(v[0], cadd(a1, a2));
+        v[1] = cadd(p1, q1);
+        v[4] = csub(p1, q1);
+        v[2] = cadd(p2, q2);
+        v[3] = csub(p2, q2);
+    }
+};
+
+// ---------------------------------------------------------------- LDS FFT
+
+// Elements of one FFT tile (lines x line length) held in LDS: 32 KB.
+template <typename T> struct Tile { static constexpr int EMAX = 32768 / (int)sizeof(typename V2<T>::t); };
+
+// One Stockham pass of radix R over `nlines` lines of length L stored at
+// lds[line * Lp + e].  Every thread holds up to MAXB butterflies in registers
+// between the two barriers, so the pass is in place.
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void fft_pass(typename V2<T>::t* lds, const typename V2<T>::t* tw, int nlines, int Lp,
+                                         int L, int Ns) {
+    using C = typename V2<T>::t;
+    constexpr int MAXB = (Tile<T>::EMAX + R * NT - 1) / (R * NT);
+    const int LR = L / R;
+    const int B = nlines * LR;
+    const int tstep = L / (Ns * R);
+    C v[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * NT;
+        if (b < B) {
+            const int line = b % nlines;
+            const int j = b / nlines;
+            const C* src = lds + line * Lp + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = src[r * LR];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * NT;
+        if (b < B) {
+            const int line = b % nlines;
+            const int j = b / nlines;
+            const int k = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tw[r * k * tstep];
+                    if (DIR > 0) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+            Dft<R, DIR, C>::run(v[i]);
+            C* dst = lds + line * Lp + (j - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) dst[q * Ns] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of every line in the tile (direction DIR: -1 forward, +1
+// inverse, unnormalised).  Caller has synchronised after filling the tile.
+template <typename T, int DIR>
+__device__ void fft_lines(typename V2<T>::t* lds, const typename V2<T>::t* tw, int nlines, int Lp, const AxisPlan& pl) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int R = pl.R[s];
+        switch (R) {
+            case 8: fft_pass<T, 8, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 4: fft_pass<T, 4, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 2: fft_pass<T, 2, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 3: fft_pass<T, 3, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            default: fft_pass<T, 5, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+        }
+        Ns *= R;
+    }
+}
+
+// Stage the W_L^t table of an axis into LDS (FP64 table converted to T).
+template <typename T>
+__device__ __forceinline__ void load_twiddles(typename V2<T>::t* dst, const double2* tw64, const AxisPlan& pl) {
+    using C = typename V2<T>::t;
+    for (int i = threadIdx.x; i < pl.L; i += NT) {
+        double2 w = tw64[pl.tw + i];
+        C c;
+        c.x = (T)w.x;
+        c.y = (T)w.y;
+        dst[i] = c;
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Sum NV doubles over the workgroup; the result is valid in thread 0.
+// Fixed order: xor-butterfly inside each 64-lane wavefront, then the four
+// wavefront sums in index order.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[wid * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = sh[i];
+            for (int w = 1; w < NT / 64; ++w) s += sh[w * NV + i];
+            v[i] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide deterministic sum: every workgroup publishes its block sum to
+// partials[blk]; the last workgroup to arrive (counted with a device-scope
+// atomic) adds the partials in block order and resets the counter.  Returns
+// true in the last workgroup, whose thread 0 then holds the totals in v.
+template <int NV>
+__device__ bool grid_sum(double (&v)[NV], double* partials, unsigned* counter, int nblk, int blk, double* sh,
+                         int* flag) {
+    block_sum<NV>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) partials[(long)blk * NV + i] = v[i];
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        *flag = (prev == (unsigned)(nblk - 1));
+    }
+    __syncthreads();
+    const bool last = *flag != 0;
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += NT) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += __builtin_nontemporal_load(&partials[(long)b * NV + i]);
+    }
+    block_sum<NV>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = acc[i];
+        *counter = 0u;
+    }
+    return true;
+}
+
+}  // namespace dda

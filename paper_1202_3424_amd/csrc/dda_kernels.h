@@ -1,0 +1,94 @@
+// Host-visible declarations of the DDA kernels' launchers and the argument
+// blocks they take.  Included by the kernels file and by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dda_device.h"
+
+namespace dda {
+
+// Geometry of one target's FFT grid.
+//   n[a]  occupied bounding-box extent on axis a (x = first ijk index)
+//   M[a]  padded FFT extent (>= 2n-1, 2,3,5-smooth)
+//   H[a]  M[a]/2 + 1: extent of the stored octant of the tensor FFT
+// Grids hold NC complex components interleaved per point, point index
+// (z * My + y) * Mx + x, right-hand side outermost.
+struct Geo {
+    int n[3];
+    int M[3];
+    int H[3];
+    long long npts;
+    AxisPlan ax[3];
+};
+
+// Site-indexed FP64 vectors of one batched solve, each [nrhs][n3] with
+// n3 = 3 * nsites, sites in box-scan order (x fastest, then y, then z).
+struct SiteArgs {
+    int nsites;
+    long long n3;
+    int nrhs;
+    int nmat;
+    const int* map;        // [nz][ny][nx] -> sorted site index or -1
+    const int* mat;        // [nsites] material index
+    const double2* ainv;   // [nrhs][nmat][3] diagonal of 1/alpha
+    double2* x;
+    double2* r;
+    double2* rhat;
+    double2* p;
+    double2* v;
+    double2* t;
+    double2* b;
+    const double2* in;     // input of the plain / conjugated product
+    double2* out;          // output of the plain / conjugated product
+    RhsState* st;          // [nrhs]
+    double* partials;      // [nrhs][maxblk][4]
+    unsigned* counters;    // [nrhs]
+    int maxblk;
+    int slot;              // RhsState::red slot written by the conjugated product
+    double kd;
+};
+
+enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3 };
+enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4 };
+// which right-hand sides a pass skips
+enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
+
+// tile sizes chosen by the host
+int x_lines_per_tile(int Mx, int nc, bool fp32);
+int strided_cols_per_tile(int L, int nc, bool fp32);
+
+template <typename T>
+void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typename V2<T>::t* grid, const double2* tw,
+                      hipStream_t s);
+template <typename T>
+void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const typename V2<T>::t* grid,
+                     const double2* tw, hipStream_t s);
+// strided FFT along axis 1 (y) or 2 (z) over lines whose other coordinates
+// are x in [0, Mx) and outer in [0, n_outer); loads e < lin (zero beyond),
+// stores e < lout; ghat != null fuses forward FFT, tensor product, inverse.
+template <typename T>
+void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
+                    typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
+                    hipStream_t s);
+void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
+
+void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);
+void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* gh32, hipStream_t s);
+void launch_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, const double2* e0, double kd,
+                  int scheme, double2* ainv, hipStream_t s);
+void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s);
+void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s);
+void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s);
+void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s);
+void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s);
+void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
+// width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]
+void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,
+                    bool to_sorted, hipStream_t s);
+void launch_fill(double2* p, long long n, hipStream_t s);
+void launch_set_state(RhsState* st, int nrhs, double tol, int max_iter, hipStream_t s);
+void launch_grad(const SiteArgs& a, const double2* dainv, double w_qabs, double2* grad, hipStream_t s);
+void launch_adjoint_rhs(const SiteArgs& a, const double2* P_sorted, double w_qabs, double w_qext, hipStream_t s);
+
+}  // namespace dda

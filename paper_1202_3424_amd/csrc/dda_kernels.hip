@@ -1,0 +1,895 @@
+// HIP kernels of the DDA solve for gfx950.
+//
+// The product y = A x (A: the interaction matrix of Draine 1988 plus the
+// diagonal 1/alpha of "Dipole Polarizabilities") is evaluated as a
+// convolution on a zero-padded grid (Goodman, Draine & Flatau 1990; "Choice
+// of FFT Algorithm") in five passes over three interleaved component grids:
+//   1. scatter + forward FFT along x of the occupied (y < ny, z < nz) lines
+//   2. forward FFT along y of the z < nz planes (inputs y < ny only)
+//   3. along z for every (x, y): forward FFT of the z < nz inputs, product
+//      with the symmetric 3x3 tensor FFT, inverse FFT, keep z < nz
+//   4. inverse FFT along y of the z < nz planes, keep y < ny
+//   5. inverse FFT along x, gather the occupied sites, add 1/alpha x.
+// Passes 1 and 5 also carry the BiCGSTAB vector updates and reductions that
+// touch the same sites, so the iteration needs no separate pass for them.
+#include "dda_kernels.h"
+
+namespace dda {
+
+namespace {
+
+template <typename C> __device__ __forceinline__ C to_c(double2 u) {
+    C c;
+    c.x = u.x;
+    c.y = u.y;
+    return c;
+}
+template <typename C> __device__ __forceinline__ double2 to_d(C u) {
+    double2 c;
+    c.x = (double)u.x;
+    c.y = (double)u.y;
+    return c;
+}
+__device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+__device__ __forceinline__ bool skip_rhs(const RhsState* st, int chk) {
+    if (chk == CHK_NONE) return false;
+    if (st->status != ST_ACTIVE) return true;
+    return chk == CHK_ACTIVE_NOT_SCONV && st->sconv;
+}
+
+// LDS carve-up shared by every FFT kernel:
+//   [twiddles: L complex][tile: nlines * Lp complex][reduction scratch]
+struct Smem {
+    unsigned char* base;
+    template <typename C> __device__ C* tw() const { return (C*)base; }
+    template <typename C> __device__ C* tile(int L) const { return (C*)base + ((L + 1) & ~1); }
+};
+__host__ __device__ inline int pad_len(int L) { return L | 1; }
+template <typename C> __host__ inline size_t fft_smem(int L, int nlines) {
+    return ((size_t)((L + 1) & ~1) + (size_t)nlines * pad_len(L)) * sizeof(C) + 8 * (NT / 64) * sizeof(double) + 64;
+}
+template <typename C> __device__ inline double* red_scratch(unsigned char* base, int L, int nlines) {
+    return (double*)(base + ((size_t)((L + 1) & ~1) + (size_t)nlines * pad_len(L)) * sizeof(C));
+}
+
+// ------------------------------------------------------------------ pass 1
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_scatter_x(Geo g, SiteArgs a, typename V2<T>::t* grid, const double2* tw64,
+                                                 int XL, int chk) {
+    using C = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int q = blockIdx.z;
+    RhsState* st = a.st + q;
+    if (skip_rhs(st, chk)) return;
+    const int nx = g.n[0], ny = g.n[1];
+    const int Mx = g.M[0], My = g.M[1];
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * XL;
+    const int nl = min(XL, ny - y0);
+    const int nlines = 3 * nl;
+    const int Lp = pad_len(Mx);
+    C* tws = (C*)smem;
+    C* lds = tws + ((Mx + 1) & ~1);
+    load_twiddles<T>(tws, tw64, g.ax[0]);
+
+    double2 beta = {0, 0}, omega = {0, 0}, alpha = {0, 0};
+    if (MODE == SC_P) { beta = st->beta; omega = st->omega; }
+    if (MODE == SC_S) alpha = st->alpha;
+    const long long vb = (long long)q * a.n3;
+    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    double ss = 0.0;
+    const int tot = nl * Mx * 3;
+    for (int idx = threadIdx.x; idx < tot; idx += NT) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        C val;
+        val.x = 0;
+        val.y = 0;
+        if (e < nx) {
+            const int s = mrow[yo * nx + e];
+            if (s >= 0) {
+                const long long i = vb + (long long)s * 3 + c;
+                double2 u;
+                if (MODE == SC_PLAIN) {
+                    u = a.in[i];
+                } else if (MODE == SC_CONJ) {
+                    u = cconj(a.in[i]);
+                } else if (MODE == SC_P) {
+                    // p = r + beta (p - omega v)
+                    u = cadd(a.r[i], cmul(beta, csub(a.p[i], cmul(omega, a.v[i]))));
+                    a.p[i] = u;
+                } else {
+                    // s = r - alpha v, stored over r
+                    u = csub(a.r[i], cmul(alpha, a.v[i]));
+                    a.r[i] = u;
+                    ss += u.x * u.x + u.y * u.y;
+                }
+                val = to_c<C>(u);
+            }
+        }
+        lds[(yo * 3 + c) * Lp + e] = val;
+    }
+    __syncthreads();
+    fft_lines<T, -1>(lds, tws, nlines, Lp, g.ax[0]);
+    C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
+    for (int idx = threadIdx.x; idx < tot; idx += NT) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        gq[((long long)yo * Mx + e) * 3 + c] = lds[(yo * 3 + c) * Lp + e];
+    }
+    if (MODE == SC_S) {
+        double v[1] = {ss};
+        __shared__ int flag;
+        double* sh = red_scratch<C>(smem, Mx, nlines);
+        const int nblk = gridDim.x * gridDim.y;
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        if (grid_sum<1>(v, a.partials + (long long)q * a.maxblk * 4, a.counters + q, nblk, blk, sh, &flag)) {
+            if (threadIdx.x == 0) {
+                st->snorm2 = v[0];
+                if (!isfinite(v[0])) st->status = ST_NONFINITE;
+                else st->sconv = (v[0] <= st->tol2 * st->bnorm2) ? 1 : 0;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ pass 5
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_gather_x(Geo g, SiteArgs a, const typename V2<T>::t* grid,
+                                                const double2* tw64, int XL, int chk) {
+    using C = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int q = blockIdx.z;
+    RhsState* st = a.st + q;
+    if (skip_rhs(st, chk)) return;
+    const int nx = g.n[0], ny = g.n[1];
+    const int Mx = g.M[0], My = g.M[1];
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * XL;
+    const int nl = min(XL, ny - y0);
+    const int nlines = 3 * nl;
+    const int Lp = pad_len(Mx);
+    C* tws = (C*)smem;
+    C* lds = tws + ((Mx + 1) & ~1);
+    load_twiddles<T>(tws, tw64, g.ax[0]);
+    const C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
+    const int tot = nl * Mx * 3;
+    for (int idx = threadIdx.x; idx < tot; idx += NT) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        lds[(yo * 3 + c) * Lp + e] = gq[((long long)yo * Mx + e) * 3 + c];
+    }
+    __syncthreads();
+    fft_lines<T, 1>(lds, tws, nlines, Lp, g.ax[0]);
+
+    const long long vb = (long long)q * a.n3;
+    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    const double2* ai = a.ainv + (long long)q * a.nmat * 3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int tout = nl * nx * 3;
+    for (int idx = threadIdx.x; idx < tout; idx += NT) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % nx;
+        const int yo = rest / nx;
+        const int s = mrow[yo * nx + e];
+        if (s < 0) continue;
+        const long long i = vb + (long long)s * 3 + c;
+        const double2 gv = to_d(lds[(yo * 3 + c) * Lp + e]);
+        const double2 d = ai[a.mat[s] * 3 + c];
+        double2 xin;
+        if (MODE == SC_PLAIN || MODE == GA_PLAIN) xin = a.in[i];
+        if (MODE == GA_CONJ) xin = cconj(a.in[i]);
+        if (MODE == GA_V) xin = a.p[i];
+        if (MODE == GA_T) xin = a.r[i];
+        if (MODE == GA_RES) xin = a.x[i];
+        const double2 y = cadd(gv, cmul(d, xin));
+        if (MODE == GA_PLAIN) {
+            a.out[i] = y;
+        } else if (MODE == GA_CONJ) {
+            const double2 yc = cconj(y);
+            a.out[i] = yc;
+            acc[0] += yc.x * yc.x + yc.y * yc.y;
+        } else if (MODE == GA_V) {
+            a.v[i] = y;
+            const double2 w = cdotc(a.rhat[i], y);
+            acc[0] += w.x;
+            acc[1] += w.y;
+        } else if (MODE == GA_T) {
+            a.t[i] = y;
+            const double2 w = cdotc(y, xin);   // <t, s>
+            acc[0] += w.x;
+            acc[1] += w.y;
+            acc[2] += y.x * y.x + y.y * y.y;
+        } else {
+            const double2 rr = csub(a.b[i], y);
+            a.r[i] = rr;
+            acc[0] += rr.x * rr.x + rr.y * rr.y;
+        }
+    }
+    if (MODE != GA_PLAIN) {
+        __shared__ int flag;
+        double* sh = red_scratch<C>(smem, Mx, nlines);
+        const int nblk = gridDim.x * gridDim.y;
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        if (grid_sum<3>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, nblk, blk, sh, &flag)) {
+            if (threadIdx.x == 0) {
+                if (MODE == GA_V) {
+                    const double2 rv = {acc[0], acc[1]};
+                    st->matvecs += 1;
+                    if (!finite2(rv)) {
+                        st->status = ST_NONFINITE;
+                    } else if (rv.x == 0.0 && rv.y == 0.0) {
+                        st->status = ST_BREAKDOWN;
+                    } else {
+                        st->alpha = cdiv(st->rho, rv);
+                    }
+                } else if (MODE == GA_T) {
+                    const double2 ts = {acc[0], acc[1]};
+                    st->matvecs += 1;
+                    if (!finite2(ts) || !isfinite(acc[2])) {
+                        st->status = ST_NONFINITE;
+                    } else if (acc[2] == 0.0) {
+                        st->omega = double2{0.0, 0.0};
+                    } else {
+                        st->omega = double2{ts.x / acc[2], ts.y / acc[2]};
+                    }
+                } else if (MODE == GA_RES) {
+                    st->red[0] = acc[0];
+                } else {
+                    st->red[a.slot] = acc[0];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ passes 2-4
+
+template <typename T, int NC, int GH, int DIR>
+__global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, const double2* tw64,
+                                               const typename V2<T>::t* ghat, const RhsState* st, int axis, int TX,
+                                               int lin, int lout, int chk) {
+    using C = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int q = blockIdx.z;
+    if (skip_rhs(st + q, chk)) return;
+    const int Mx = g.M[0], My = g.M[1];
+    const AxisPlan& pl = g.ax[axis];
+    const int L = pl.L;
+    const int Lp = pad_len(L);
+    const int x0 = blockIdx.x * TX;
+    const int nxl = min(TX, Mx - x0);
+    const int nlines = NC * nxl;
+    const int o = blockIdx.y;
+    const long long estride = (axis == 1) ? (long long)Mx * NC : (long long)My * Mx * NC;
+    const long long obase = (axis == 1) ? (long long)o * My * Mx * NC : (long long)o * Mx * NC;
+    C* tws = (C*)smem;
+    C* lds = tws + ((L + 1) & ~1);
+    load_twiddles<T>(tws, tw64, pl);
+    C* gq = grid + (long long)q * g.npts * NC + obase + (long long)x0 * NC;
+    const int tin = nlines * L;
+    for (int idx = threadIdx.x; idx < tin; idx += NT) {
+        const int inner = idx % nlines;
+        const int e = idx / nlines;
+        C v;
+        if (e < lin) {
+            v = gq[e * estride + inner];
+        } else {
+            v.x = 0;
+            v.y = 0;
+        }
+        lds[inner * Lp + e] = v;
+    }
+    __syncthreads();
+    if (GH) {
+        fft_lines<T, -1>(lds, tws, nlines, Lp, pl);
+        // y_a = sum_b Ghat_ab x_b at every (kx, ky = o, kz = e); the tensor
+        // FFT is stored on the octant 0..M/2 per axis, each component even
+        // or odd in each index (diagonal: even; ab: odd in a and b).
+        const int Hx = g.H[0], Hy = g.H[1];
+        const int ky = o;
+        const int fy = (ky <= My / 2) ? ky : My - ky;
+        const int sy = (ky <= My / 2) ? 1 : -1;
+        const int Mz = g.M[2];
+        const int npt = nxl * L;
+        for (int pidx = threadIdx.x; pidx < npt; pidx += NT) {
+            const int xo = pidx % nxl;
+            const int kz = pidx / nxl;
+            const int kx = x0 + xo;
+            const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
+            const int sx = (kx <= Mx / 2) ? 1 : -1;
+            const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
+            const int sz = (kz <= Mz / 2) ? 1 : -1;
+            const C* G = ghat + (((long long)fz * Hy + fy) * Hx + fx) * 6;
+            const C gxx = G[0], gyy = G[3], gzz = G[5];
+            C gxy = G[1], gxz = G[2], gyz = G[4];
+            if (sx * sy < 0) { gxy.x = -gxy.x; gxy.y = -gxy.y; }
+            if (sx * sz < 0) { gxz.x = -gxz.x; gxz.y = -gxz.y; }
+            if (sy * sz < 0) { gyz.x = -gyz.x; gyz.y = -gyz.y; }
+            C* px = lds + (xo * 3 + 0) * Lp + kz;
+            C* py = lds + (xo * 3 + 1) * Lp + kz;
+            C* pz = lds + (xo * 3 + 2) * Lp + kz;
+            const C X = *px, Y = *py, Z = *pz;
+            *px = cadd(cadd(cmul(gxx, X), cmul(gxy, Y)), cmul(gxz, Z));
+            *py = cadd(cadd(cmul(gxy, X), cmul(gyy, Y)), cmul(gyz, Z));
+            *pz = cadd(cadd(cmul(gxz, X), cmul(gyz, Y)), cmul(gzz, Z));
+        }
+        __syncthreads();
+        fft_lines<T, 1>(lds, tws, nlines, Lp, pl);
+    } else {
+        fft_lines<T, DIR>(lds, tws, nlines, Lp, pl);
+    }
+    const int tout = nlines * lout;
+    for (int idx = threadIdx.x; idx < tout; idx += NT) {
+        const int inner = idx % nlines;
+        const int e = idx / nlines;
+        gq[e * estride + inner] = lds[inner * Lp + e];
+    }
+}
+
+// Forward FFT along x of every line of a six-component FP64 grid (the
+// interaction tensor).
+__global__ __launch_bounds__(NT) void k_xgrid6(Geo g, double2* grid, const double2* tw64, int XL) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Mx = g.M[0], My = g.M[1];
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * XL;
+    const int nl = min(XL, My - y0);
+    const int nlines = 6 * nl;
+    const int Lp = pad_len(Mx);
+    double2* tws = (double2*)smem;
+    double2* lds = tws + ((Mx + 1) & ~1);
+    load_twiddles<double>(tws, tw64, g.ax[0]);
+    double2* gq = grid + ((long long)z * My + y0) * Mx * 6;
+    const int tot = nl * Mx * 6;
+    for (int idx = threadIdx.x; idx < tot; idx += NT) {
+        const int c = idx % 6;
+        const int rest = idx / 6;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        lds[(yo * 6 + c) * Lp + e] = gq[idx];
+    }
+    __syncthreads();
+    fft_lines<double, -1>(lds, tws, nlines, Lp, g.ax[0]);
+    for (int idx = threadIdx.x; idx < tot; idx += NT) {
+        const int c = idx % 6;
+        const int rest = idx / 6;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        gq[idx] = lds[(yo * 6 + c) * Lp + e];
+    }
+}
+
+// ------------------------------------------------------------------ setup
+
+// Signed lattice separation held by padded index m on an axis of box extent
+// n and padded extent M; false for the empty slots between +(n-1) and -(n-1).
+__device__ __forceinline__ bool sep(int m, int n, int M, int& d) {
+    if (m <= n - 1) { d = m; return true; }
+    if (m >= M - (n - 1)) { d = m - M; return true; }
+    return false;
+}
+
+// Off-diagonal interaction tensor (Draine 1988) sampled at every separation:
+// A_jl = exp(ikr)/r [k^2 (nn - I) + (ikr - 1)/r^2 (3nn - I)], stored as its six
+// distinct components xx, xy, xz, yy, yz, zz; zero at R = 0 and empty slots.
+__global__ __launch_bounds__(NT) void k_green_sample(Geo g, double kd, double2* G) {
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= g.npts) return;
+    const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
+    const int mx = (int)(i % Mx);
+    const int my = (int)((i / Mx) % My);
+    const int mz = (int)(i / ((long long)Mx * My));
+    int dx, dy, dz;
+    double2* out = G + i * 6;
+    const bool ok = sep(mx, g.n[0], Mx, dx) && sep(my, g.n[1], My, dy) && sep(mz, g.n[2], Mz, dz);
+    if (!ok || (dx == 0 && dy == 0 && dz == 0)) {
+        for (int c = 0; c < 6; ++c) out[c] = double2{0.0, 0.0};
+        return;
+    }
+    const double X = dx, Y = dy, Z = dz;
+    const double r2 = X * X + Y * Y + Z * Z;
+    const double r = sqrt(r2);
+    double sn, cs;
+    sincos(kd * r, &sn, &cs);
+    const double2 pref = {cs / r, sn / r};                       // exp(ikr)/r
+    const double2 ikr1 = {-1.0 / r2, kd * r / r2};               // (ikr - 1)/r^2
+    // A = pref [ (-k^2 - (ikr-1)/r^2) I + (k^2 + 3(ikr-1)/r^2) R R / r^2 ]
+    const double2 ciso = cmul(pref, double2{-kd * kd - ikr1.x, -ikr1.y});
+    const double2 cnn = cscale(cmul(pref, double2{kd * kd + 3.0 * ikr1.x, 3.0 * ikr1.y}), 1.0 / r2);
+    const double R[3] = {X, Y, Z};
+    const int ab[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int c = 0; c < 6; ++c) {
+        double2 v = cscale(cnn, R[ab[c][0]] * R[ab[c][1]]);
+        if (ab[c][0] == ab[c][1]) v = cadd(v, ciso);
+        out[c] = v;
+    }
+}
+
+// Keep the octant 0..M/2 of the tensor FFT, scaled by 1/M so that the
+// inverse transforms of the product need no further normalisation.
+__global__ __launch_bounds__(NT) void k_green_octant(Geo g, const double2* G, double2* gh64, float2* gh32) {
+    const long long nh = (long long)g.H[0] * g.H[1] * g.H[2];
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= nh) return;
+    const int hx = (int)(i % g.H[0]);
+    const int hy = (int)((i / g.H[0]) % g.H[1]);
+    const int hz = (int)(i / ((long long)g.H[0] * g.H[1]));
+    const long long src = (((long long)hz * g.M[1] + hy) * g.M[0] + hx) * 6;
+    const double sc = 1.0 / (double)g.npts;
+    for (int c = 0; c < 6; ++c) {
+        const double2 v = cscale(G[src + c], sc);
+        if (gh64) gh64[i * 6 + c] = v;
+        if (gh32) gh32[i * 6 + c] = float2{(float)v.x, (float)v.y};
+    }
+}
+
+// 1/alpha (or its derivative with respect to eps, scheme + 2) per
+// (right-hand side, material): "Dipole Polarizabilities".
+//   LATTDR (Draine & Goodman 1993): 1/alpha = 1/alpha_CM
+//       + (b1 + eps b2 + eps b3 S) (kd)^2 - (2/3) i (kd)^3,
+//       S = sum_mu khat_mu^2 |e_mu|^2, 1/alpha_CM = (4 pi/3)(eps+2)/(eps-1).
+//   GKDLDR (Gutkowicz-Krusin & Draine 2004): S -> khat_mu^2 on axis mu.
+__global__ void k_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, const double2* e0, double kd,
+                        int scheme, double2* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrhs * nmat) return;
+    const int q = i / nmat, mt = i % nmat;
+    const double b1 = -1.891531, b2 = 0.1648469, b3 = -1.7700004;
+    const double pi = 3.14159265358979323846;
+    const double2 m = m_rel[mt];
+    const double2 eps = cmul(m, m);
+    const double* kh = khat + q * 3;
+    const double2* e = e0 + q * 3;
+    double S = 0.0;
+    for (int mu = 0; mu < 3; ++mu) S += kh[mu] * kh[mu] * (e[mu].x * e[mu].x + e[mu].y * e[mu].y);
+    const double k2 = kd * kd;
+    const double2 em1 = {eps.x - 1.0, eps.y};
+    const bool deriv = scheme >= 2;
+    const int sch = scheme & 1;
+    for (int mu = 0; mu < 3; ++mu) {
+        const double Smu = sch ? kh[mu] * kh[mu] : S;
+        double2 v;
+        if (!deriv) {
+            const double2 cm = cscale(cdiv(double2{eps.x + 2.0, eps.y}, em1), 4.0 * pi / 3.0);
+            const double2 ldr = cscale(cadd(double2{b1, 0.0}, cscale(eps, b2 + b3 * Smu)), k2);
+            v = cadd(cm, ldr);
+            v.y -= (2.0 / 3.0) * k2 * kd;
+        } else {
+            // d/deps: -4 pi/(eps-1)^2 + (b2 + b3 S) k^2
+            const double2 d = cdiv(double2{-4.0 * pi, 0.0}, cmul(em1, em1));
+            v = cadd(d, double2{(b2 + b3 * Smu) * k2, 0.0});
+        }
+        out[(long long)i * 3 + mu] = v;
+    }
+}
+
+// E_inc at every site: e exp(i kd khat . r), "Incident Polarization State".
+__global__ __launch_bounds__(NT) void k_einc(SiteArgs a, const int* coords, const double* khat, const double2* e0) {
+    const int q = blockIdx.y;
+    const double* kh = khat + q * 3;
+    const double2* e = e0 + q * 3;
+    for (int s = blockIdx.x * NT + threadIdx.x; s < a.nsites; s += gridDim.x * NT) {
+        const double ph = a.kd * (kh[0] * coords[s * 3 + 0] + kh[1] * coords[s * 3 + 1] + kh[2] * coords[s * 3 + 2]);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double2 w = {cs, sn};
+        double2* b = a.b + (long long)q * a.n3 + (long long)s * 3;
+        for (int c = 0; c < 3; ++c) b[c] = cmul(e[c], w);
+    }
+}
+
+// ------------------------------------------------------------------ Krylov
+
+// Cold start x = 0: r = rhat = b, p = v = 0; rho = |b|^2.
+__global__ __launch_bounds__(NT) void k_init_cold(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    __shared__ int flag;
+    const int q = blockIdx.y;
+    RhsState* st = a.st + q;
+    const long long vb = (long long)q * a.n3;
+    double acc[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 bb = a.b[vb + i];
+        a.r[vb + i] = bb;
+        a.rhat[vb + i] = bb;
+        a.x[vb + i] = double2{0.0, 0.0};
+        a.p[vb + i] = double2{0.0, 0.0};
+        a.v[vb + i] = double2{0.0, 0.0};
+        acc[0] += bb.x * bb.x + bb.y * bb.y;
+    }
+    if (grid_sum<1>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
+        if (threadIdx.x == 0) {
+            st->bnorm2 = acc[0];
+            st->rnorm2 = acc[0];
+            st->rho = double2{acc[0], 0.0};
+            st->alpha = double2{1.0, 0.0};
+            st->omega = double2{1.0, 0.0};
+            st->beta = double2{0.0, 0.0};
+            st->iters = 0;
+            st->matvecs = 0;
+            st->sconv = 0;
+            st->restarts = 0;
+            st->status = isfinite(acc[0]) ? (acc[0] > 0.0 ? ST_ACTIVE : ST_CONVERGED) : ST_NONFINITE;
+        }
+    }
+}
+
+// Warm start: x already holds P0 and r = b - A P0.  rhat = r, p = v = 0.
+__global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    __shared__ int flag;
+    const int q = blockIdx.y;
+    RhsState* st = a.st + q;
+    const long long vb = (long long)q * a.n3;
+    double acc[2] = {0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 rr = a.r[vb + i];
+        const double2 bb = a.b[vb + i];
+        a.rhat[vb + i] = rr;
+        a.p[vb + i] = double2{0.0, 0.0};
+        a.v[vb + i] = double2{0.0, 0.0};
+        acc[0] += rr.x * rr.x + rr.y * rr.y;
+        acc[1] += bb.x * bb.x + bb.y * bb.y;
+    }
+    if (grid_sum<2>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
+        if (threadIdx.x == 0) {
+            st->bnorm2 = acc[1];
+            st->rnorm2 = acc[0];
+            st->rho = double2{acc[0], 0.0};
+            st->alpha = double2{1.0, 0.0};
+            st->omega = double2{1.0, 0.0};
+            st->beta = double2{0.0, 0.0};
+            st->iters = 0;
+            st->matvecs = 1;
+            st->sconv = 0;
+            st->restarts = 0;
+            if (!isfinite(acc[0]) || !isfinite(acc[1])) st->status = ST_NONFINITE;
+            else st->status = (acc[0] <= st->tol2 * acc[1]) ? ST_CONVERGED : ST_ACTIVE;
+        }
+    }
+}
+
+// End of a BiCGSTAB iteration: x += alpha p + omega s, r = s - omega t (or,
+// after a half-step convergence, x += alpha p, r = s); rho = <rhat, r>,
+// beta for the next direction, convergence |r|^2 <= tol^2 |b|^2.
+__global__ __launch_bounds__(NT) void k_update(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    __shared__ int flag;
+    const int q = blockIdx.y;
+    RhsState* st = a.st + q;
+    if (st->status != ST_ACTIVE) return;
+    const int sconv = st->sconv;
+    const double2 alpha = st->alpha, omega = st->omega;
+    const long long vb = (long long)q * a.n3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 s = a.r[vb + i];
+        double2 xx = cadd(a.x[vb + i], cmul(alpha, a.p[vb + i]));
+        double2 rr = s;
+        if (!sconv) {
+            xx = cadd(xx, cmul(omega, s));
+            rr = csub(s, cmul(omega, a.t[vb + i]));
+            a.r[vb + i] = rr;
+        }
+        a.x[vb + i] = xx;
+        const double2 w = cdotc(a.rhat[vb + i], rr);
+        acc[0] += w.x;
+        acc[1] += w.y;
+        acc[2] += rr.x * rr.x + rr.y * rr.y;
+    }
+    if (grid_sum<3>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
+        if (threadIdx.x == 0) {
+            st->iters += 1;
+            st->rnorm2 = acc[2];
+            const double2 rho_new = {acc[0], acc[1]};
+            if (!isfinite(acc[2]) || !finite2(rho_new)) {
+                st->status = ST_NONFINITE;
+            } else if (sconv || acc[2] <= st->tol2 * st->bnorm2) {
+                st->status = ST_CONVERGED;
+            } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) || (omega.x == 0.0 && omega.y == 0.0)) {
+                st->status = ST_BREAKDOWN;
+            } else {
+                st->beta = cmul(cdiv(rho_new, st->rho), cdiv(alpha, omega));
+                st->rho = rho_new;
+            }
+            if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
+        }
+    }
+}
+
+// One restart after a breakdown: rhat = r, p = v = 0, rho = |r|^2.
+__global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    __shared__ int flag;
+    const int q = blockIdx.y;
+    RhsState* st = a.st + q;
+    if (st->status != ST_BREAKDOWN || st->restarts > 0) return;
+    const long long vb = (long long)q * a.n3;
+    double acc[1] = {0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 rr = a.r[vb + i];
+        a.rhat[vb + i] = rr;
+        a.p[vb + i] = double2{0.0, 0.0};
+        a.v[vb + i] = double2{0.0, 0.0};
+        acc[0] += rr.x * rr.x + rr.y * rr.y;
+    }
+    if (grid_sum<1>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
+        if (threadIdx.x == 0) {
+            st->rho = double2{acc[0], 0.0};
+            st->alpha = double2{1.0, 0.0};
+            st->omega = double2{1.0, 0.0};
+            st->beta = double2{0.0, 0.0};
+            st->sconv = 0;
+            st->restarts += 1;
+            st->status = (acc[0] > 0.0 && isfinite(acc[0])) ? ST_ACTIVE : ST_BREAKDOWN;
+        }
+    }
+}
+
+// Efficiency sums at the solution x (Draine 1988):
+//   red[3] = sum Im(E* . P), red[4] = sum (-Im(1/alpha) - (2/3) k^3) |P|^2,
+//   red[5] = sum Re(E* . P).
+__global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    __shared__ int flag;
+    const int q = blockIdx.y;
+    RhsState* st = a.st + q;
+    const long long vb = (long long)q * a.n3;
+    const double2* ai = a.ainv + (long long)q * a.nmat * 3;
+    const double rr = (2.0 / 3.0) * a.kd * a.kd * a.kd;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 P = a.x[vb + i];
+        const double2 E = a.b[vb + i];
+        const double2 w = cdotc(E, P);
+        const int s = (int)(i / 3), c = (int)(i % 3);
+        const double2 d = ai[a.mat[s] * 3 + c];
+        acc[0] += w.y;
+        acc[1] += (-d.y - rr) * (P.x * P.x + P.y * P.y);
+        acc[2] += w.x;
+    }
+    if (grid_sum<3>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
+        if (threadIdx.x == 0) {
+            st->red[3] = acc[0];
+            st->red[4] = acc[1];
+            st->red[5] = acc[2];
+        }
+    }
+}
+
+// Adjoint right-hand side for the gradient of w_abs Q_abs + w_ext Q_ext
+// (with b holding E on entry, g on exit):
+//   g = c_Q [ w_abs (-Im(1/alpha) - (2/3) k^3) conj(P) + w_ext conj(E) / (2i) ]
+__global__ __launch_bounds__(NT) void k_adjoint_rhs(SiteArgs a, const double2* P, double cq_abs, double cq_ext) {
+    const double2* ai = a.ainv;
+    const double rr = (2.0 / 3.0) * a.kd * a.kd * a.kd;
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const int s = (int)(i / 3), c = (int)(i % 3);
+        const double2 d = ai[a.mat[s] * 3 + c];
+        const double wabs = -d.y - rr;
+        const double2 pc = cconj(P[i]);
+        const double2 ec = cconj(a.b[i]);
+        // conj(E)/(2i) = -i conj(E)/2
+        const double2 ext = {0.5 * ec.y, -0.5 * ec.x};
+        a.b[i] = cadd(cscale(pc, cq_abs * wabs), cscale(ext, cq_ext));
+    }
+}
+
+// grad_j = 2 conj(-sum_mu h_mu lam_mu P_mu) - i w_abs c_Q sum_mu conj(h_mu) |P_mu|^2
+__global__ __launch_bounds__(NT) void k_grad(SiteArgs a, const double2* P, const double2* dainv, double cq_abs,
+                                            double2* grad) {
+    for (int s = blockIdx.x * NT + threadIdx.x; s < a.nsites; s += gridDim.x * NT) {
+        double2 imp = {0.0, 0.0};
+        double2 expl = {0.0, 0.0};
+        for (int c = 0; c < 3; ++c) {
+            const double2 h = dainv[a.mat[s] * 3 + c];
+            const double2 lam = a.x[(long long)s * 3 + c];
+            const double2 p = P[(long long)s * 3 + c];
+            imp = cadd(imp, cmul(h, cmul(lam, p)));
+            expl = cadd(expl, cscale(cconj(h), p.x * p.x + p.y * p.y));
+        }
+        // 2 conj(-imp) = (-2 imp.x, 2 imp.y);  -i cq expl = (cq expl.y, -cq expl.x)
+        grad[s] = double2{-2.0 * imp.x + cq_abs * expl.y, 2.0 * imp.y - cq_abs * expl.x};
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_permute(int nrhs, int nsites, int width, const int* perm, const double2* src,
+                                               double2* dst, int to_sorted) {
+    const long long per = (long long)nsites * width;
+    const long long tot = per * nrhs;
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < tot; i += (long long)gridDim.x * NT) {
+        const long long q = i / per;
+        const long long rem = i % per;
+        const int s = (int)(rem / width), c = (int)(rem % width);
+        const long long caller = q * per + (long long)perm[s] * width + c;
+        if (to_sorted) dst[i] = src[caller];
+        else dst[caller] = src[i];
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_fill(double2* p, long long n) {
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+        p[i] = double2{0.0, 0.0};
+}
+
+__global__ void k_set_state(RhsState* st, int nrhs, double tol2, int max_iter) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nrhs) return;
+    RhsState s = {};
+    s.tol2 = tol2;
+    s.max_iter = max_iter;
+    s.status = ST_ACTIVE;
+    st[q] = s;
+}
+
+inline int blocks_for(long long n, int cap) {
+    long long b = (n + NT - 1) / NT;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+int x_lines_per_tile(int Mx, int nc, bool fp32) {
+    const int emax = fp32 ? Tile<float>::EMAX : Tile<double>::EMAX;
+    int xl = emax / (nc * Mx);
+    return xl < 1 ? 1 : xl;
+}
+
+int strided_cols_per_tile(int L, int nc, bool fp32) {
+    const int emax = fp32 ? Tile<float>::EMAX : Tile<double>::EMAX;
+    int tx = emax / (nc * L);
+    if (tx < 1) tx = 1;
+    int p = 1;
+    while (p * 2 <= tx && p * 2 <= 16) p *= 2;
+    return p;
+}
+
+template <typename T>
+void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typename V2<T>::t* grid, const double2* tw,
+                      hipStream_t s) {
+    using C = typename V2<T>::t;
+    const int XL = x_lines_per_tile(g.M[0], 3, sizeof(T) == 4);
+    dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
+    const size_t sm = fft_smem<C>(g.M[0], 3 * XL);
+    switch (mode) {
+        case SC_PLAIN: hipLaunchKernelGGL((k_scatter_x<T, SC_PLAIN>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        case SC_CONJ: hipLaunchKernelGGL((k_scatter_x<T, SC_CONJ>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        case SC_P: hipLaunchKernelGGL((k_scatter_x<T, SC_P>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        default: hipLaunchKernelGGL((k_scatter_x<T, SC_S>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+    }
+}
+
+template <typename T>
+void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const typename V2<T>::t* grid,
+                     const double2* tw, hipStream_t s) {
+    using C = typename V2<T>::t;
+    const int XL = x_lines_per_tile(g.M[0], 3, sizeof(T) == 4);
+    dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
+    const size_t sm = fft_smem<C>(g.M[0], 3 * XL);
+    switch (mode) {
+        case GA_PLAIN: hipLaunchKernelGGL((k_gather_x<T, GA_PLAIN>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        case GA_CONJ: hipLaunchKernelGGL((k_gather_x<T, GA_CONJ>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        case GA_V: hipLaunchKernelGGL((k_gather_x<T, GA_V>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        case GA_T: hipLaunchKernelGGL((k_gather_x<T, GA_T>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+        default: hipLaunchKernelGGL((k_gather_x<T, GA_RES>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
+    }
+}
+
+template <typename T>
+void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
+                    typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
+                    hipStream_t s) {
+    using C = typename V2<T>::t;
+    const int L = g.M[axis];
+    const int TX = strided_cols_per_tile(L, nc, sizeof(T) == 4);
+    dim3 grd((g.M[0] + TX - 1) / TX, n_outer, nrhs);
+    const size_t sm = fft_smem<C>(L, nc * TX);
+    if (nc == 3) {
+        if (ghat)
+            hipLaunchKernelGGL((k_strided<T, 3, 1, -1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
+        else if (dir < 0)
+            hipLaunchKernelGGL((k_strided<T, 3, 0, -1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
+        else
+            hipLaunchKernelGGL((k_strided<T, 3, 0, 1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
+    } else {
+        hipLaunchKernelGGL((k_strided<T, 6, 0, -1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
+    }
+}
+
+template void launch_scatter_x<double>(int, int, const Geo&, const SiteArgs&, double2*, const double2*, hipStream_t);
+template void launch_scatter_x<float>(int, int, const Geo&, const SiteArgs&, float2*, const double2*, hipStream_t);
+template void launch_gather_x<double>(int, int, const Geo&, const SiteArgs&, const double2*, const double2*, hipStream_t);
+template void launch_gather_x<float>(int, int, const Geo&, const SiteArgs&, const float2*, const double2*, hipStream_t);
+template void launch_strided<double>(int, int, int, const Geo&, int, int, int, int, int, double2*, const double2*,
+                                     const double2*, const RhsState*, hipStream_t);
+template void launch_strided<float>(int, int, int, const Geo&, int, int, int, int, int, float2*, const double2*,
+                                    const float2*, const RhsState*, hipStream_t);
+
+void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s) {
+    const int XL = x_lines_per_tile(g.M[0], 6, false);
+    dim3 grd((g.M[1] + XL - 1) / XL, g.M[2], 1);
+    hipLaunchKernelGGL(k_xgrid6, grd, dim3(NT), fft_smem<double2>(g.M[0], 6 * XL), s, g, grid, tw, XL);
+}
+
+void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s) {
+    hipLaunchKernelGGL(k_green_sample, dim3((unsigned)((g.npts + NT - 1) / NT)), dim3(NT), 0, s, g, kd, G);
+}
+
+void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* gh32, hipStream_t s) {
+    const long long nh = (long long)g.H[0] * g.H[1] * g.H[2];
+    hipLaunchKernelGGL(k_green_octant, dim3((unsigned)((nh + NT - 1) / NT)), dim3(NT), 0, s, g, G, gh64, gh32);
+}
+
+void launch_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, const double2* e0, double kd,
+                  int scheme, double2* ainv, hipStream_t s) {
+    const int n = nrhs * nmat;
+    hipLaunchKernelGGL(k_alpha, dim3((n + 63) / 64), dim3(64), 0, s, nrhs, nmat, m_rel, khat, e0, kd, scheme, ainv);
+}
+
+void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s) {
+    hipLaunchKernelGGL(k_einc, dim3(blocks_for(a.nsites, 1024), a.nrhs), dim3(NT), 0, s, a, coords, khat, e0);
+}
+
+void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_cold, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_warm, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_restart, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_qsum, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+
+void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,
+                    bool to_sorted, hipStream_t s) {
+    const long long tot = (long long)nrhs * nsites * width;
+    hipLaunchKernelGGL(k_permute, dim3(blocks_for(tot, 4096)), dim3(NT), 0, s, nrhs, nsites, width, perm, src, dst,
+                       to_sorted ? 1 : 0);
+}
+
+void launch_fill(double2* p, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 4096)), dim3(NT), 0, s, p, n);
+}
+
+void launch_set_state(RhsState* st, int nrhs, double tol, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_state, dim3((nrhs + 63) / 64), dim3(64), 0, s, st, nrhs, tol * tol, max_iter);
+}
+
+void launch_adjoint_rhs(const SiteArgs& a, const double2* P_sorted, double w_qabs, double w_qext, hipStream_t s) {
+    const double pi = 3.14159265358979323846;
+    const double aeff = cbrt(3.0 * a.nsites / (4.0 * pi));
+    const double cq = 4.0 * pi * a.kd / (pi * aeff * aeff);
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3(blocks_for(a.n3, 4096)), dim3(NT), 0, s, a, P_sorted, cq * w_qabs,
+                       cq * w_qext);
+}
+
+void launch_grad(const SiteArgs& a, const double2* dainv, double w_qabs, double2* grad, hipStream_t s) {
+    const double pi = 3.14159265358979323846;
+    const double aeff = cbrt(3.0 * a.nsites / (4.0 * pi));
+    const double cq = 4.0 * pi * a.kd / (pi * aeff * aeff);
+    // P (sorted) is passed in a.in
+    hipLaunchKernelGGL(k_grad, dim3(blocks_for(a.nsites, 4096)), dim3(NT), 0, s, a, a.in, dainv, cq * w_qabs, grad);
+}
+
+}  // namespace dda

@@ -1,0 +1,264 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances:
+* matrix-vector product, FP64: every element within 1e-12 of max|y| (the
+  FFT route and the dense sum differ only by rounding, ~1e-15 log2 M);
+* FP32 matvec mode: within 2e-5 of max|y| (single-precision FFT, ~1e-7
+  log2 M per pass, three passes each way);
+* solutions at tolerance h: P within ~10 h of the LU solution (the true
+  residual bound times a modest condition number), Q within 1e-4 relative of
+  the oracle (the target this build works to).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle import adjoint, dense, fftsolve, mie
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dda():
+    import paper_1202_3424_amd as pkg
+    assert torch.cuda.is_available()
+    return pkg
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _dense_A(ijk, m, x, kh, e0, scheme):
+    k = dense.kd_from_size_parameter(x, len(ijk))
+    ainv = dense.site_alpha_inverse(np.asarray(m), k, kh, e0, scheme)
+    return dense.assemble(ijk, ainv, k)
+
+
+def _ragged():
+    rng = np.random.default_rng(17)
+    pts = rng.integers(0, [9, 7, 13], size=(300, 3))
+    return np.unique(pts, axis=0).astype(np.int32)
+
+
+MATVEC_CASES = {
+    "sphere389": lambda: (w.sphere_integer(4.5), 1.33 + 0.01j),
+    "ragged_9x7x13": lambda: (_ragged(), 1.5 + 0.2j),
+    "line_z9": lambda: (np.array([[0, 0, i] for i in range(9)], dtype=np.int32), 2.0 + 0.5j),
+    "single_site": lambda: (np.array([[3, -2, 5]], dtype=np.int32), 1.7 + 0.3j),
+    "box_8x3x40": lambda: (w.brick(8, 3, 40), 1.6 + 0.1j),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MATVEC_CASES))
+@pytest.mark.parametrize("scheme", ["LATTDR", "GKDLDR"])
+def test_matvec_matches_dense(dda, name, scheme):
+    ijk, mval = MATVEC_CASES[name]()
+    n = len(ijk)
+    m = np.full(n, mval)
+    if name == "box_8x3x40":
+        m = np.where(np.arange(n) % 3 == 0, mval, 1.2 + 0.0j)
+    x = 1.3
+    kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
+    e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
+    tgt = dda.Target(ijk, m)
+    opts = dda.Options.for_size_parameter(x, polarizability=scheme)
+    xv = w.random_vectors(3, (2, n, 3))
+    y = dda.apply(tgt, opts, kh, e0, _cuda(xv)).cpu().numpy()
+    for q in range(2):
+        A = _dense_A(ijk, m, x, kh[q], e0[q], scheme)
+        ref = (A @ xv[q].reshape(-1)).reshape(n, 3)
+        err = np.abs(y[q] - ref).max()
+        assert err <= 1e-12 * np.abs(ref).max(), (name, q, err)
+
+
+def test_matvec_fp32_mode(dda):
+    ijk = _ragged()
+    n = len(ijk)
+    m = np.full(n, 1.5 + 0.2j)
+    tgt = dda.Target(ijk, m)
+    opts = dda.Options.for_size_parameter(1.3, precision="fp32_matvec")
+    kh, e0 = w.along_x_yz()
+    xv = w.random_vectors(4, (2, n, 3))
+    y = dda.apply(tgt, opts, kh, e0, _cuda(xv)).cpu().numpy()
+    for q in range(2):
+        ref = (_dense_A(ijk, m, 1.3, kh[q], e0[q], "LATTDR") @ xv[q].reshape(-1)).reshape(n, 3)
+        assert np.abs(y[q] - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_matvec_full_size_ellipsoid(dda):
+    """The 51,488-site ellipsoid on its 128x96x64 grid: every element of
+    A x against the oracle's FFT operator (the bench's launch configuration)."""
+    d = w.workload("ellipsoid51k")
+    n = len(d["ijk"])
+    tgt = dda.Target(d["ijk"], d["m"])
+    assert tgt.grid == (128, 96, 64)
+    opts = dda.Options.for_size_parameter(d["x"])
+    xv = w.random_vectors(5, (1, n, 3))
+    y = dda.apply(tgt, opts, d["khat"][:1], d["e0"][:1], _cuda(xv)).cpu().numpy()[0]
+    k = dense.kd_from_size_parameter(d["x"], n)
+    ainv = dense.site_alpha_inverse(d["m"], k, d["khat"][0], d["e0"][0])
+    ref = fftsolve.FFTOperator(d["ijk"], ainv, k).apply(xv[0])
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ solves
+
+def test_solve_sphere389_vs_lu_and_mie(dda):
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8)
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P = P.cpu().numpy()
+    q_mie = mie.efficiencies(1.33 + 0.01j, 1.0)
+    for q in range(2):
+        lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q])
+        r = res[q]
+        assert r["status"] == 0 and r["rel_residual"] < 1e-8
+        assert np.abs(P[q] - lu["P"]).max() <= 1e-7 * np.abs(lu["P"]).max()
+        for key in ("qext", "qabs", "qsca", "qpha"):
+            assert abs(r[key] - lu[key]) <= 1e-7 * abs(lu[key]), key
+            if key != "qpha":
+                assert abs(r[key] / q_mie[key] - 1) < 0.03
+        tr, ne = dense.residuals(lu["A"], P[q], lu["E"])
+        assert abs(r["rel_residual"] - tr) <= 0.05 * tr + 1e-15
+        assert abs(r["normal_eq_residual"] - ne) <= 0.05 * ne + 1e-15
+        assert abs(r["kd"] - lu["k"]) < 1e-14
+
+
+@pytest.mark.parametrize("scheme", ["LATTDR", "GKDLDR"])
+def test_solve_two_material_vs_lu(dda, scheme):
+    d = w.workload("twomat6")
+    tgt = dda.Target(d["ijk"], d["m"])
+    kh = np.array([[0.36, 0.48, 0.8]])
+    e0 = np.array([np.array([0.8, -0.6, 0]) + 0.5j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-10, polarizability=scheme)
+    P, res = dda.solve(tgt, opts, kh, e0)
+    lu = dense.solve_case(d["ijk"], d["m"], d["x"], kh[0], e0[0], scheme)
+    assert res[0]["status"] == 0
+    assert np.abs(P.cpu().numpy()[0] - lu["P"]).max() <= 1e-8 * np.abs(lu["P"]).max()
+    assert abs(res[0]["qabs"] - lu["qabs"]) <= 1e-8 * lu["qabs"]
+    assert abs(res[0]["qsca"] - lu["qsca"]) <= 1e-8 * lu["qsca"]
+
+
+def test_worked_example_on_gpu(dda):
+    """The guide's printed 16x32x32 gold brick (GKDLDR, TOL 1e-5)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_au_brick.json")))
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(g["x"], tol=1e-5, polarizability="GKDLDR")
+    _, res = dda.solve(tgt, opts, d["khat"], d["e0"], want_P=False)
+    for r in res:
+        assert r["status"] == 0
+        for key in ("qext", "qabs", "qsca", "qpha"):
+            assert abs(r[key] - g[key]) <= 1e-4 * abs(g[key]) + 5e-6, (key, r[key])
+    assert abs(res[0]["qext"] - res[1]["qext"]) < 1e-4
+
+
+def test_solve_full_size_ellipsoid_vs_oracle(dda):
+    """The 51,488-site ellipsoid at tol 1e-5 (the benchmark workload):
+    Q within 1e-4 of the oracle's FFT-BiCGSTAB, P close at sampled sites."""
+    d = w.workload("ellipsoid51k")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5)
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P = P.cpu().numpy()
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(d["ijk"]), 500, replace=False)
+    for q in range(2):
+        o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-9)
+        r = res[q]
+        assert r["status"] == 0 and r["rel_residual"] < 1e-5
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(r[key] - o[key]) <= 1e-4 * abs(o[key]), (key, r[key], o[key])
+        assert np.abs(P[q][sample] - o["P"][sample]).max() <= 1e-3 * np.abs(o["P"]).max()
+
+
+def test_batched_equals_single_bitwise(dda):
+    """Each right-hand side of a batch is computed with exactly the
+    arithmetic of its single solve (no cross-RHS mixing)."""
+    d = w.workload("brick48")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5)
+    kh, e0 = d["khat"][:6], d["e0"][:6]
+    Pb, rb = dda.solve(tgt, opts, kh, e0)
+    for q in (0, 3, 5):
+        Ps, rs = dda.solve(tgt, opts, kh[q:q + 1], e0[q:q + 1])
+        assert torch.equal(Pb[q], Ps[0])
+        assert rb[q]["qext"] == rs[0]["qext"] and rb[q]["iters"] == rs[0]["iters"]
+
+
+def test_deterministic(dda):
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8)
+    P1, r1 = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P2, r2 = dda.solve(tgt, opts, d["khat"], d["e0"])
+    assert torch.equal(P1, P2) and r1 == r2
+
+
+def test_warm_start_at_solution(dda):
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8)
+    P, _ = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P2, res = dda.solve(tgt, opts, d["khat"], d["e0"], P0=P)
+    assert all(r["iters"] == 0 and r["status"] == 0 for r in res)
+    assert torch.equal(P, P2)
+
+
+def test_error_paths(dda):
+    from paper_1202_3424_amd import DDAError
+    ijk = w.sphere_integer(2.0)
+    with pytest.raises(DDAError) as e:
+        dda.Target(np.vstack([ijk, ijk[:1]]), 1.5)
+    assert e.value.status == 1 and "duplicate" in str(e.value)
+    with pytest.raises(DDAError):
+        dda.Target(ijk, np.full(len(ijk), complex(np.nan, 0)))
+    tgt = dda.Target(ijk, 1.5 + 0.1j)
+    opts = dda.Options.for_size_parameter(1.0)
+    with pytest.raises(DDAError):      # e0 not transverse to khat
+        dda.solve(tgt, opts, [[1, 0, 0]], [[1, 0, 0]])
+    with pytest.raises(DDAError):      # khat not unit
+        dda.solve(tgt, opts, [[2, 0, 0]], [[0, 1, 0]])
+    with pytest.raises(DDAError):
+        dda.solve(tgt, dda.Options.for_size_parameter(1.0, tol=-1.0), [[1, 0, 0]], [[0, 1, 0]])
+    _, res = dda.solve(tgt, dda.Options.for_size_parameter(1.0, tol=1e-14, max_iter=1), [[1, 0, 0]], [[0, 1, 0]])
+    assert res[0]["status"] == 4 and res[0]["iters"] == 1 and res[0]["qext"] > 0
+
+
+def test_validity_warning(dda):
+    ijk = w.brick(6, 6, 6)
+    tgt = dda.Target(ijk, 2.0 + 0.5j)
+    _, res = dda.solve(tgt, dda.Options.for_size_parameter(6.0, tol=1e-4), [[1, 0, 0]], [[0, 1, 0]], want_P=False)
+    assert "|m|kd" in dda.last_error()
+
+
+def test_fp32_matvec_solve(dda):
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5, precision="fp32_matvec")
+    _, res = dda.solve(tgt, opts, d["khat"], d["e0"], want_P=False)
+    for q in range(2):
+        lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], with_qsca=False)
+        assert res[q]["status"] == 0 and res[q]["rel_residual"] < 2e-5
+        assert abs(res[q]["qext"] - lu["qext"]) <= 1e-4 * lu["qext"]
+        assert abs(res[q]["qabs"] - lu["qabs"]) <= 1e-4 * lu["qabs"]
+
+
+@pytest.mark.parametrize("weights", [(1.0, 0.0), (0.0, 1.0), (0.7, -0.3)])
+def test_adjoint_gradient_vs_dense(dda, weights):
+    d = w.workload("twomat6")
+    kh, e0 = d["khat"][0], d["e0"][0]
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-11)
+    P, _ = dda.solve(tgt, opts, [kh], [e0])
+    g, adj = dda.grad_eps(tgt, opts, kh, e0, P[0], *weights)
+    ref, _ = adjoint.gradient_dense(d["ijk"], d["m"], d["x"], kh, e0, *weights)
+    assert adj["status"] == 0
+    assert np.abs(g.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
