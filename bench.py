@@ -1,0 +1,217 @@
+"""Benchmark: DDA time-to-solution on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ellipsoid51k]
+
+A step is one whole solve of one target orientation (both polarizations,
+batched as two right-hand sides): interaction-tensor sampling and FFT,
+polarizabilities, incident field, BiCGSTAB to the tolerance, the true and
+normal-equation residual checks and the efficiencies.  Inputs are synthetic
+(seeded lattice targets); nothing is cached between steps.
+
+Prints one JSON line: the metric value is seconds per orientation; the
+``roofline`` object reports the dominant kernel's algorithmic HBM bytes per
+launch over its average launch time (HIP events on the library's stream over
+the timed steps) against MI355X's 8 TB/s; ``cpu_baseline`` times the CPU
+oracle (FFT-BiCGSTAB in FP64) on one polarization of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DDA time-to-solution (s/orientation at 1e-5 residual); FFT-matvec HBM GB/s"
+
+WORKLOADS = {
+    # name: (description, precision)
+    "ellipsoid51k": ("ellipsoid, semi-axes 32/24/16 on a 64x48x32 box (N=51488), m=1.5+0.02i, x=5, LATTDR, "
+                     "BiCGSTAB to 1e-5, FFT grid 128x96x64, incidence +x, polarizations y and z", "fp64"),
+    "sphere389": ("integer-site sphere r=4.5 (N=389), m=1.33+0.01i, x=1, LATTDR, BiCGSTAB to 1e-8, FFT grid 18^3",
+                  "fp64"),
+    "au_brick": ("16x32x32 gold brick (N=16384), m=0.9656+1.8628i, x=3.093665, BiCGSTAB to 1e-5, FFT grid 32x64x64",
+                 "fp64"),
+    "sphere1m": ("sphere of radius 64 in a 128^3 box (N=1099136), m=1.33+0.01i, x=20, LATTDR, BiCGSTAB to 1e-5, "
+                 "FFT grid 256^3", "fp64"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("dda_kernels.hip", "dda_device.h"):
+        with open(os.path.join(ROOT, "paper_1202_3424_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
+    """Algorithmic HBM bytes of each matvec pass for one right-hand side
+    (one read and one write of exactly the data the pruned pass needs)."""
+    nx, ny, nz = tgt.box
+    Mx, My, Mz = tgt.grid
+    Hx, Hy, Hz = Mx // 2 + 1, My // 2 + 1, Mz // 2 + 1
+    g = 3 * csize                       # three components per grid point
+    site = 3 * n_sites * 16             # one FP64 site vector
+    nbox = nx * ny * nz
+    return {
+        # write the x-transformed occupied lines; read the box map and on
+        # average 2.5 site vectors, write 1 (p = r + beta(p - omega v) / s = r - alpha v)
+        "scatter_fft_x": Mx * ny * nz * g + 4 * nbox + 3.5 * site,
+        "fft_y_fwd": Mx * ny * nz * g + Mx * My * nz * g,
+        "fft_z_green": 2 * Mx * My * nz * g + Hx * Hy * Hz * 6 * csize,
+        "fft_y_inv": Mx * My * nz * g + Mx * ny * nz * g,
+        # read the x lines, box map, materials, the input and one more site vector, write the output
+        "fft_x_gather": Mx * ny * nz * g + 4 * nbox + 4 * n_sites + 3 * site,
+    }
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(d: dict, workload: str) -> dict:
+    """The oracle (FFT-BiCGSTAB, FP64) on one of the two polarizations."""
+    workers = min(os.cpu_count() or 1, len(os.sched_getaffinity(0)), 16)
+    os.environ["DDA_ORACLE_FFT_WORKERS"] = str(workers)
+    import importlib
+
+    from oracle import fftsolve
+    importlib.reload(fftsolve)
+    t0 = time.perf_counter()
+    r = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], tol=d["tol"])
+    dt = time.perf_counter() - t0
+    n_pol = len(d["khat"])
+    return {"value": dt * n_pol, "unit": "s/orientation", "cores": workers, "kind": "oracle",
+            "sample": f"{workload}: polarization 1 of {n_pol} solved by the CPU oracle (scipy.fft FFT-BiCGSTAB, "
+                      f"FP64, tol {d['tol']:g}, {r['iters']} iterations, {r['matvecs']} matvecs) in {dt:.2f} s; "
+                      f"value = {n_pol} x that time",
+            "qext": r["qext"], "qabs": r["qabs"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ellipsoid51k", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32_matvec"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
+              "right-hand sides is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1202_3424_amd as dda
+    import workloads as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    d = w.workload(args.workload, args.seed)
+    desc, prec = WORKLOADS[args.workload]
+    prec = args.precision or prec
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=d["tol"], precision=prec, recompute_green=True)
+    kh, e0 = d["khat"], d["e0"]
+    n_rhs = len(kh)
+    log(f"workload {args.workload}: N={tgt.n_sites} box={tgt.box} grid={tgt.grid} rhs={n_rhs} prec={prec}")
+
+    for i in range(args.warmup):
+        _, res = dda.solve(tgt, opts, kh, e0, want_P=False)
+        log(f"warmup {i}: iters={[r['iters'] for r in res]} status={[r['status'] for r in res]}")
+
+    dda.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    units = 0
+    results = None
+    for i in range(args.steps):
+        _, results = dda.solve(tgt, opts, kh, e0, want_P=False)
+        units += sum(r["matvecs"] for r in results) + 3 * n_rhs
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = dda.get_timing()
+    dda.set_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    s_per_orientation = ms_per_step / 1e3 / (n_rhs / 2.0)
+    for r in results:
+        if r["status"] != 0:
+            raise SystemExit(f"solve did not converge: {r}")
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; results {results[0]}")
+
+    csize = 8 if prec == "fp32_matvec" else 16
+    bpu = pass_bytes(tgt, tgt.n_sites, csize)
+    passes = {}
+    for name, b in bpu.items():
+        ms, launches = timing[name]
+        if launches == 0 or ms == 0:
+            continue
+        gbs = b * units / (ms * 1e-3) / 1e9
+        passes[name] = {"ms_per_launch": ms / launches, "launches": launches, "bytes_per_rhs_matvec": b,
+                        "GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+    dominant = max(passes, key=lambda k: timing[k][0])
+    dom = passes[dominant]
+    ms_tot, launches = timing[dominant]
+    bytes_per_launch = bpu[dominant] * units / launches
+    traffic = load_traffic(dominant)
+    roofline = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
+                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": ms_tot / launches * 1e3}
+    matvec_ms = sum(timing[k][0] for k in bpu)
+    matvec_bytes = sum(bpu.values()) * units
+    out = {
+        "metric": METRIC,
+        "value": s_per_orientation,
+        "unit": "s/orientation",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32 matvec / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n_sites": tgt.n_sites, "fft_grid": list(tgt.grid),
+                   "rhs_per_step": n_rhs, "orientations_per_step": n_rhs / 2.0, "precision": prec,
+                   "seed": args.seed},
+        "roofline": roofline,
+        "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9, "units_per_step": units / args.steps,
+                   "passes": passes},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
+        "solver": {"iters": [r["iters"] for r in results], "matvecs": [r["matvecs"] for r in results],
+                   "qext": [r["qext"] for r in results], "qabs": [r["qabs"] for r in results],
+                   "qsca": [r["qsca"] for r in results], "rel_residual": [r["rel_residual"] for r in results],
+                   "normal_eq_residual": [r["normal_eq_residual"] for r in results]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on one polarization ...")
+        out["cpu_baseline"] = cpu_baseline(d, args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

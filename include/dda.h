@@ -169,6 +169,23 @@ dda_status dda_grad_eps(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const
                         const dda_c64* P, double w_qabs, double w_qext, dda_c64* grad,
                         dda_result* adj);
 
+/* Kernel timing on the context stream (HIP events around every launch of
+ * the solver's kernels, read back at the stream synchronisations the calls
+ * already make).  Categories (index into dda_timing arrays):
+ *   0 scatter + forward FFT along x      1 forward FFT along y
+ *   2 FFT along z with the tensor product 3 inverse FFT along y
+ *   4 inverse FFT along x + gather        5 Krylov updates and reductions
+ *   6 interaction-tensor sampling + FFT   7 other setup (E_inc, 1/alpha, permutes)
+ * dda_ctx_set_timing(ctx, 1) clears the totals and starts recording;
+ * (ctx, 0) stops.  dda_ctx_get_timing copies the totals accumulated so far. */
+#define DDA_TIMING_CATEGORIES 8
+typedef struct {
+    double ms[DDA_TIMING_CATEGORIES];        /* summed kernel time */
+    int64_t launches[DDA_TIMING_CATEGORIES];  /* kernel launches timed */
+} dda_timing;
+dda_status dda_ctx_set_timing(dda_ctx* ctx, int enable);
+dda_status dda_ctx_get_timing(dda_ctx* ctx, dda_timing* out);
+
 /* Description of the last error or warning on this thread ("" if none).
  * Valid until the next library call on the thread.  |m|kd >= 1 (the validity
  * bound of "Applicability of the DDA") is reported here as a warning. */

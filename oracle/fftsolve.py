@@ -20,16 +20,22 @@ r^ = r0 and conjugated inner products <u, v> = sum conj(u) v.  It stops when
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+
+# threads for scipy's FFT (-1: all CPUs); the CPU-baseline timing sets it to
+# the host's CPU share and reports it
+WORKERS = int(os.environ.get("DDA_ORACLE_FFT_WORKERS", "-1"))
 
 try:  # scipy's FFT is a library primitive with a thread-pool option
     import scipy.fft as _fft
 
     def _fftn(a, axes):
-        return _fft.fftn(a, axes=axes, workers=-1)
+        return _fft.fftn(a, axes=axes, workers=WORKERS)
 
     def _ifftn(a, axes):
-        return _fft.ifftn(a, axes=axes, workers=-1)
+        return _fft.ifftn(a, axes=axes, workers=WORKERS)
 except Exception:  # pragma: no cover
     def _fftn(a, axes):
         return np.fft.fftn(a, axes=axes)

@@ -104,3 +104,16 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+DDA_TIMING_CATEGORIES = 8
+TIMING_NAMES = ["scatter_fft_x", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x_gather", "krylov", "green_setup",
+                "setup"]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * DDA_TIMING_CATEGORIES), ("launches", ctypes.c_int64 * DDA_TIMING_CATEGORIES)]
+
+
+SIGNATURES["dda_ctx_set_timing"] = (ctypes.c_int, [VP, ctypes.c_int])
+SIGNATURES["dda_ctx_get_timing"] = (ctypes.c_int, [VP, ctypes.POINTER(Timing)])

@@ -247,3 +247,15 @@ class QEff(torch.autograd.Function):
         g = gq.detach().to("cpu", torch.float64)
         grad, _ = grad_eps(ctx.tgt, ctx.opts, ctx.khat, ctx.e0, P, float(g[0]), float(g[1]))
         return grad.to(ctx.eps_device), None, None, None, None
+
+
+def set_timing(enable: bool, device: int | None = None) -> None:
+    """Start (clearing totals) or stop per-kernel-category GPU timing."""
+    _check(_lib.dda_ctx_set_timing(context(device), 1 if enable else 0), "dda_ctx_set_timing")
+
+
+def get_timing(device: int | None = None) -> dict:
+    """{category: (total ms, launches)} accumulated since set_timing(True)."""
+    t = _abi.Timing()
+    _check(_lib.dda_ctx_get_timing(context(device), ctypes.byref(t)), "dda_ctx_get_timing")
+    return {name: (t.ms[i], int(t.launches[i])) for i, name in enumerate(_abi.TIMING_NAMES)}

@@ -106,6 +106,16 @@ struct dda_ctx {
     DevBuf grid, vecs, state, partials, counters, inc, ainv, dainv, mrel, aux, gtmp;
     RhsState* host_state = nullptr;
     int host_state_cap = 0;
+    // kernel timing (dda_ctx_set_timing)
+    bool timing = false;
+    struct Pending {
+        int cat;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> evpool;
+    std::vector<Pending> pending;
+    double tms[DDA_TIMING_CATEGORIES] = {};
+    long long tlaunch[DDA_TIMING_CATEGORIES] = {};
 };
 
 struct dda_target {
@@ -133,6 +143,59 @@ struct Scope {  // make the context's device current for the duration of a call
 };
 
 double aeff_over_d(int n) { return std::cbrt(3.0 * n / (4.0 * M_PI)); }
+
+enum TimingCat { T_SCATTER = 0, T_FFTY_FWD = 1, T_FFTZ_G = 2, T_FFTY_INV = 3, T_GATHER = 4, T_KRYLOV = 5,
+                 T_GREEN = 6, T_SETUP = 7 };
+
+hipEvent_t take_event(dda_ctx* c) {
+    if (!c->evpool.empty()) {
+        hipEvent_t e = c->evpool.back();
+        c->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+// Events around the launches issued in this scope, when timing is enabled.
+struct Timed {
+    dda_ctx* c;
+    int cat;
+    hipEvent_t a = nullptr;
+    Timed(dda_ctx* c_, int cat_) : c(c_), cat(cat_) {
+        if (!c->timing) return;
+        a = take_event(c);
+        HIPCHK(hipEventRecord(a, c->stream));
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (!c->evpool.empty()) {
+            b = c->evpool.back();
+            c->evpool.pop_back();
+        } else if (hipEventCreate(&b) != hipSuccess) {
+            c->evpool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({cat, a, b});
+    }
+};
+
+// Accumulate the timed launches; the stream has been synchronised.
+void flush_timing(dda_ctx* c) {
+    for (const auto& p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->tms[p.cat] += ms;
+            c->tlaunch[p.cat] += 1;
+        }
+        c->evpool.push_back(p.a);
+        c->evpool.push_back(p.b);
+    }
+    c->pending.clear();
+}
 
 double kd_of(const dda_opts* o, int nsites) {
     const double d = o->aeff / aeff_over_d(nsites);
@@ -255,11 +318,26 @@ struct Work {
         const C* gh = (const C*)(fp32 ? t->gh32.p : t->gh64.p);
         const double2* tw = (const double2*)t->tw.p;
         hipStream_t s = c->stream;
-        launch_scatter_x<T>(sc, chk_sc, g, a, gr, tw, s);
-        launch_strided<T>(1, -1, chk_rest, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, s);
-        launch_strided<T>(2, 0, chk_rest, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, s);
-        launch_strided<T>(1, 1, chk_rest, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, s);
-        launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
+        {
+            Timed tm(c, T_SCATTER);
+            launch_scatter_x<T>(sc, chk_sc, g, a, gr, tw, s);
+        }
+        {
+            Timed tm(c, T_FFTY_FWD);
+            launch_strided<T>(1, -1, chk_rest, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, s);
+        }
+        {
+            Timed tm(c, T_FFTZ_G);
+            launch_strided<T>(2, 0, chk_rest, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, s);
+        }
+        {
+            Timed tm(c, T_FFTY_INV);
+            launch_strided<T>(1, 1, chk_rest, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, s);
+        }
+        {
+            Timed tm(c, T_GATHER);
+            launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
+        }
     }
     void matvec(int sc, int ga, int chk_sc, int chk_rest) {
         if (fp32) matvec_t<float>(sc, ga, chk_sc, chk_rest);
@@ -275,6 +353,7 @@ void ensure_green(dda_ctx* c, dda_target* t, double kd, bool fp32, bool force) {
     const Geo& g = t->geo;
     double2* G = (double2*)c->gtmp.ensure((size_t)g.npts * 6 * sizeof(double2));
     const double2* tw = (const double2*)t->tw.p;
+    Timed tm(c, T_GREEN);
     launch_green_sample(g, kd, G, c->stream);
     launch_xgrid6(g, G, tw, c->stream);
     launch_strided<double>(1, -1, CHK_NONE, g, 1, 6, g.M[2], g.M[1], g.M[1], G, tw, nullptr, nullptr, c->stream);
@@ -299,6 +378,7 @@ void fetch_state(dda_ctx* c, const Work& w) {
     }
     HIPCHK(hipMemcpyAsync(c->host_state, w.a.st, (size_t)w.nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    flush_timing(c);
 }
 
 // BiCGSTAB on every right-hand side of w (b, ainv, state prepared); warm
@@ -308,8 +388,10 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
     launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, c->stream);
     if (warm) {
         w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE);  // r = b - A x0 (in = x)
+        Timed tm(c, T_KRYLOV);
         launch_init_warm(w.a, w.site_blocks, c->stream);
     } else {
+        Timed tm(c, T_KRYLOV);
         launch_init_cold(w.a, w.site_blocks, c->stream);
     }
     HIPCHK(hipGetLastError());
@@ -324,6 +406,7 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
             if (s.status == ST_BREAKDOWN && s.restarts == 0) restart = true;
         }
         if (restart) {
+            Timed tm(c, T_KRYLOV);
             launch_restart(w.a, w.site_blocks, c->stream);
             active = true;
         }
@@ -331,6 +414,7 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
         for (int k = 0; k < chunk; ++k) {
             w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
             w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
+            Timed tm(c, T_KRYLOV);
             launch_update(w.a, w.site_blocks, c->stream);
         }
         HIPCHK(hipGetLastError());
@@ -355,7 +439,10 @@ void final_checks(Work& w, bool normal_eq) {
         a.slot = 2;
         w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE);
     }
-    launch_qsum(a, w.site_blocks, c->stream);
+    {
+        Timed tm(c, T_KRYLOV);
+        launch_qsum(a, w.site_blocks, c->stream);
+    }
     HIPCHK(hipGetLastError());
 }
 
@@ -433,20 +520,27 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
     Work w(c, t, nrhs, kd, fp32);
     w.upload_incidence(kh, e0);
-    w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
-    launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
     const bool warm = P0 != nullptr;
-    if (warm) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P0, w.a.x, true, c->stream);
+    {
+        Timed tm(c, T_SETUP);
+        w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
+        launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
+        if (warm)
+            launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P0, w.a.x, true, c->stream);
+    }
     w.a.in = w.a.x;
     iterate(w, o, warm);
     const bool ne = (o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0;
     final_checks(w, ne);
-    if (P) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, w.a.x, (double2*)P, false, c->stream);
-    if (Pper) {
-        for (int q = 0; q < nrhs; ++q)
-            if (Pper[q])
-                launch_permute(1, t->nsites, 3, (const int*)t->perm.p, w.a.x + (size_t)q * w.a.n3, (double2*)Pper[q],
-                               false, c->stream);
+    {
+        Timed tm(c, T_SETUP);
+        if (P) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, w.a.x, (double2*)P, false, c->stream);
+        if (Pper) {
+            for (int q = 0; q < nrhs; ++q)
+                if (Pper[q])
+                    launch_permute(1, t->nsites, 3, (const int*)t->perm.p, w.a.x + (size_t)q * w.a.n3,
+                                   (double2*)Pper[q], false, c->stream);
+        }
     }
     HIPCHK(hipGetLastError());
     fetch_state(c, w);
@@ -486,6 +580,11 @@ dda_status dda_ctx_destroy(dda_ctx* c) {
                               &c->mrel, &c->aux, &c->gtmp})
                 b->release();
             if (c->host_state) (void)hipHostFree(c->host_state);
+            for (const auto& p : c->pending) {
+                (void)hipEventDestroy(p.a);
+                (void)hipEventDestroy(p.b);
+            }
+            for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
         }
         delete c;
         return DDA_OK;
@@ -724,6 +823,37 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         r.qext = r.qabs = r.qsca = r.qpha = 0.0;
         if (adj) *adj = r;
         return st;
+    });
+}
+
+dda_status dda_ctx_set_timing(dda_ctx* c, int enable) {
+    return guarded([&]() -> dda_status {
+        if (!c) invalid("ctx is NULL");
+        Scope sc(c);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        flush_timing(c);
+        if (enable) {
+            for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) {
+                c->tms[i] = 0.0;
+                c->tlaunch[i] = 0;
+            }
+        }
+        c->timing = enable != 0;
+        return DDA_OK;
+    });
+}
+
+dda_status dda_ctx_get_timing(dda_ctx* c, dda_timing* out) {
+    return guarded([&]() -> dda_status {
+        if (!c || !out) invalid("NULL argument");
+        Scope sc(c);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        flush_timing(c);
+        for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) {
+            out->ms[i] = c->tms[i];
+            out->launches[i] = c->tlaunch[i];
+        }
+        return DDA_OK;
     });
 }
 
