@@ -86,6 +86,8 @@ typedef struct {
 /* dda_opts.flags */
 #define DDA_FLAG_RECOMPUTE_GREEN 1u  /* rebuild the FFT of the Green tensor even if cached */
 #define DDA_FLAG_NO_FINAL_CHECKS 2u  /* skip the true-residual and eq. err_tol matvecs */
+#define DDA_FLAG_NO_AUTOTUNE 4u      /* use the default kernel tiling instead of timing the
+                                        variants once per grid shape (results are identical) */
 
 typedef struct {
     double wavelength;   /* vacuum wavelength (any physical unit) > 0 */
@@ -176,14 +178,15 @@ dda_status dda_grad_eps(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const
  *   2 FFT along z with the tensor product 3 inverse FFT along y
  *   4 inverse FFT along x + gather        5 Krylov updates and reductions
  *   6 interaction-tensor sampling + FFT   7 other setup (E_inc, 1/alpha, permutes)
- * dda_ctx_set_timing(ctx, 1) clears the totals and starts recording;
- * (ctx, 0) stops.  dda_ctx_get_timing copies the totals accumulated so far. */
+ * dda_ctx_set_timing(ctx, mask) clears the totals and records the
+ * categories whose bit (1 << category) is set in mask (0xff: all; 0: stop).
+ * dda_ctx_get_timing copies the totals accumulated so far. */
 #define DDA_TIMING_CATEGORIES 8
 typedef struct {
     double ms[DDA_TIMING_CATEGORIES];        /* summed kernel time */
     int64_t launches[DDA_TIMING_CATEGORIES];  /* kernel launches timed */
 } dda_timing;
-dda_status dda_ctx_set_timing(dda_ctx* ctx, int enable);
+dda_status dda_ctx_set_timing(dda_ctx* ctx, int mask);
 dda_status dda_ctx_get_timing(dda_ctx* ctx, dda_timing* out);
 
 /* Description of the last error or warning on this thread ("" if none).

@@ -25,6 +25,7 @@ DDA_FP64 = 0
 DDA_FP32_MATVEC = 1
 DDA_FLAG_RECOMPUTE_GREEN = 1
 DDA_FLAG_NO_FINAL_CHECKS = 2
+DDA_FLAG_NO_AUTOTUNE = 4
 
 
 class C64(ctypes.Structure):

@@ -72,6 +72,7 @@ class Options:
     precision: str = "fp64"
     recompute_green: bool = False
     final_checks: bool = True
+    autotune: bool = True
 
     @classmethod
     def for_size_parameter(cls, x: float, **kw) -> "Options":
@@ -84,6 +85,8 @@ class Options:
             flags |= _abi.DDA_FLAG_RECOMPUTE_GREEN
         if not self.final_checks:
             flags |= _abi.DDA_FLAG_NO_FINAL_CHECKS
+        if not self.autotune:
+            flags |= _abi.DDA_FLAG_NO_AUTOTUNE
         return _abi.Opts(self.wavelength, self.aeff, self.m_medium, self.tol, int(self.max_iter),
                          _POLZ[self.polarizability], _abi.DDA_BICGSTAB, _PREC[self.precision], flags, 0)
 
@@ -249,9 +252,18 @@ class QEff(torch.autograd.Function):
         return grad.to(ctx.eps_device), None, None, None, None
 
 
-def set_timing(enable: bool, device: int | None = None) -> None:
-    """Start (clearing totals) or stop per-kernel-category GPU timing."""
-    _check(_lib.dda_ctx_set_timing(context(device), 1 if enable else 0), "dda_ctx_set_timing")
+def set_timing(categories=True, device: int | None = None) -> None:
+    """Start (clearing totals) or stop per-kernel-category GPU timing.
+    ``categories``: True (all), False (stop) or an iterable of category names."""
+    if categories is True:
+        mask = (1 << _abi.DDA_TIMING_CATEGORIES) - 1
+    elif categories is False or categories is None:
+        mask = 0
+    else:
+        mask = 0
+        for name in categories:
+            mask |= 1 << _abi.TIMING_NAMES.index(name)
+    _check(_lib.dda_ctx_set_timing(context(device), mask), "dda_ctx_set_timing")
 
 
 def get_timing(device: int | None = None) -> dict:

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdda.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["dda_kernels.hip", "dda_api.hip"]
+SOURCES = ["dda_kernels.hip", "dda_passes_f64.hip", "dda_passes_f32.hip", "dda_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

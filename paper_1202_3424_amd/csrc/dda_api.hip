@@ -8,8 +8,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -103,11 +105,11 @@ AxisPlan make_plan(int L) {
 struct dda_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    DevBuf grid, vecs, state, partials, counters, inc, ainv, dainv, mrel, aux, gtmp;
+    DevBuf grid, vecs, state, partials, inc, ainv, dainv, mrel, aux, gtmp;
     RhsState* host_state = nullptr;
     int host_state_cap = 0;
     // kernel timing (dda_ctx_set_timing)
-    bool timing = false;
+    int timing = 0;   // bit mask of recorded categories
     struct Pending {
         int cat;
         hipEvent_t a, b;
@@ -116,6 +118,8 @@ struct dda_ctx {
     std::vector<Pending> pending;
     double tms[DDA_TIMING_CATEGORIES] = {};
     long long tlaunch[DDA_TIMING_CATEGORIES] = {};
+    // autotuned strided-pass variants per (grid, box, right-hand sides, precision)
+    std::map<std::tuple<int, int, int, int, int, int, int, int>, std::array<int, 3>> tuned;
 };
 
 struct dda_target {
@@ -164,7 +168,7 @@ struct Timed {
     int cat;
     hipEvent_t a = nullptr;
     Timed(dda_ctx* c_, int cat_) : c(c_), cat(cat_) {
-        if (!c->timing) return;
+        if (!(c->timing & (1 << cat))) return;
         a = take_event(c);
         HIPCHK(hipEventRecord(a, c->stream));
     }
@@ -255,6 +259,8 @@ struct Work {
     bool fp32;
     SiteArgs a{};
     int site_blocks = 1;
+    int pass_blocks = 1;
+    int var[3] = {0, 0, 0};   // strided-pass variants: y forward, z with tensor, y inverse
     void* grid = nullptr;
     double* kh = nullptr;
     double2* e0 = nullptr;
@@ -281,15 +287,11 @@ struct Work {
         const size_t cbytes = fp32 ? sizeof(float2) : sizeof(double2);
         grid = c->grid.ensure((size_t)nrhs * g.npts * 3 * cbytes);
         a.st = (RhsState*)c->state.ensure((size_t)nrhs * sizeof(RhsState));
-        // blocks of every reduction kernel, per right-hand side
-        const int xl = x_lines_per_tile(g.M[0], 3, fp32);
-        const int pass_blocks = ((g.n[1] + xl - 1) / xl) * g.n[2];
-        site_blocks = (int)std::min<long long>(1024, std::max<long long>(1, (n3 + 4LL * NT - 1) / (4LL * NT)));
+        // workgroups of every reducing kernel, per right-hand side
+        pass_blocks = x_pass_blocks(g, nrhs, fp32);
+        site_blocks = site_blocks_for(n3, nrhs);
         a.maxblk = std::max(pass_blocks, site_blocks);
         a.partials = (double*)c->partials.ensure((size_t)nrhs * a.maxblk * 4 * sizeof(double));
-        a.counters = (unsigned*)c->counters.ensure((size_t)nrhs * sizeof(unsigned) * 4);
-        // counters start at zero; every grid_sum leaves them at zero
-        launch_fill((double2*)a.counters, ((long long)nrhs * 4 * sizeof(unsigned) + 15) / 16, c->stream);
         a.ainv = (const double2*)c->ainv.ensure((size_t)nrhs * t->nmat * 3 * sizeof(double2));
         char* ib = (char*)c->inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
         kh = (double*)ib;
@@ -310,6 +312,67 @@ struct Work {
         launch_alpha(nrhs, t->nmat, dm, kh, e0, kd, scheme, out, c->stream);
     }
 
+    // the three strided passes: 0 = y forward, 1 = z with the tensor product, 2 = y inverse
+    template <typename T>
+    void strided_slot(int slot, int chk, int variant) {
+        using C = typename V2<T>::t;
+        const Geo& g = t->geo;
+        C* gr = (C*)grid;
+        const C* gh = (const C*)(fp32 ? t->gh32.p : t->gh64.p);
+        const double2* tw = (const double2*)t->tw.p;
+        if (slot == 0)
+            launch_strided<T>(1, -1, chk, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, c->stream, variant);
+        else if (slot == 1)
+            launch_strided<T>(2, 0, chk, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, c->stream, variant);
+        else
+            launch_strided<T>(1, 1, chk, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, c->stream, variant);
+    }
+
+    // Pick, once per (grid, box, right-hand sides, precision), the fastest
+    // compile-time variant of each strided pass by timing every candidate on
+    // the workspace grid (its contents are scratch at this point; all
+    // variants compute bitwise-identical results).
+    void autotune(bool enabled) {
+        const Geo& g = t->geo;
+        auto key = std::make_tuple(g.M[0], g.M[1], g.M[2], g.n[0], g.n[1], g.n[2], nrhs, fp32 ? 1 : 0);
+        auto it = c->tuned.find(key);
+        if (it != c->tuned.end()) {
+            for (int i = 0; i < 3; ++i) var[i] = it->second[i];
+            return;
+        }
+        std::array<int, 3> best{0, 0, 0};
+        if (enabled) {
+            hipEvent_t e0 = take_event(c), e1 = take_event(c);
+            for (int slot = 0; slot < 3; ++slot) {
+                const int L = g.M[slot == 1 ? 2 : 1];
+                const int nv = strided_variants(L, slot == 1);
+                float best_ms = 1e30f;
+                for (int v = 0; v < nv; ++v) {
+                    auto run = [&]() {
+                        if (fp32) strided_slot<float>(slot, CHK_NONE, v);
+                        else strided_slot<double>(slot, CHK_NONE, v);
+                    };
+                    run();
+                    HIPCHK(hipEventRecord(e0, c->stream));
+                    for (int k = 0; k < 3; ++k) run();
+                    HIPCHK(hipEventRecord(e1, c->stream));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best[slot] = v;
+                    }
+                }
+            }
+            HIPCHK(hipGetLastError());
+            c->evpool.push_back(e0);
+            c->evpool.push_back(e1);
+            c->tuned[key] = best;
+        }
+        for (int i = 0; i < 3; ++i) var[i] = best[i];
+    }
+
     template <typename T>
     void matvec_t(int sc, int ga, int chk_sc, int chk_rest) {
         using C = typename V2<T>::t;
@@ -322,21 +385,30 @@ struct Work {
             Timed tm(c, T_SCATTER);
             launch_scatter_x<T>(sc, chk_sc, g, a, gr, tw, s);
         }
+        if (sc == SC_S) {
+            Timed tm(c, T_KRYLOV);
+            launch_finalize(a, FIN_S, pass_blocks, s);
+        }
         {
             Timed tm(c, T_FFTY_FWD);
-            launch_strided<T>(1, -1, chk_rest, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, s);
+            strided_slot<T>(0, chk_rest, var[0]);
         }
         {
             Timed tm(c, T_FFTZ_G);
-            launch_strided<T>(2, 0, chk_rest, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, s);
+            strided_slot<T>(1, chk_rest, var[1]);
         }
         {
             Timed tm(c, T_FFTY_INV);
-            launch_strided<T>(1, 1, chk_rest, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, s);
+            strided_slot<T>(2, chk_rest, var[2]);
         }
         {
             Timed tm(c, T_GATHER);
             launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
+        }
+        if (ga != GA_PLAIN) {
+            static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES};
+            Timed tm(c, T_KRYLOV);
+            launch_finalize(a, kind_of[ga], pass_blocks, s);
         }
     }
     void matvec(int sc, int ga, int chk_sc, int chk_rest) {
@@ -390,9 +462,11 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
         w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE);  // r = b - A x0 (in = x)
         Timed tm(c, T_KRYLOV);
         launch_init_warm(w.a, w.site_blocks, c->stream);
+        launch_finalize(w.a, FIN_WARM, w.site_blocks, c->stream);
     } else {
         Timed tm(c, T_KRYLOV);
         launch_init_cold(w.a, w.site_blocks, c->stream);
+        launch_finalize(w.a, FIN_COLD, w.site_blocks, c->stream);
     }
     HIPCHK(hipGetLastError());
     int launched = 0;
@@ -408,6 +482,7 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
         if (restart) {
             Timed tm(c, T_KRYLOV);
             launch_restart(w.a, w.site_blocks, c->stream);
+            launch_finalize(w.a, FIN_RESTART, w.site_blocks, c->stream);
             active = true;
         }
         if (!active || launched > o->max_iter + 2 * chunk) break;
@@ -416,6 +491,7 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
             w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
             Timed tm(c, T_KRYLOV);
             launch_update(w.a, w.site_blocks, c->stream);
+            launch_finalize(w.a, FIN_UPD, w.site_blocks, c->stream);
         }
         HIPCHK(hipGetLastError());
         launched += chunk;
@@ -442,6 +518,7 @@ void final_checks(Work& w, bool normal_eq) {
     {
         Timed tm(c, T_KRYLOV);
         launch_qsum(a, w.site_blocks, c->stream);
+        launch_finalize(a, FIN_QSUM, w.site_blocks, c->stream);
     }
     HIPCHK(hipGetLastError());
 }
@@ -519,6 +596,7 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     const bool fp32 = o->precision == DDA_FP32_MATVEC;
     ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
     Work w(c, t, nrhs, kd, fp32);
+    w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0);
     w.upload_incidence(kh, e0);
     const bool warm = P0 != nullptr;
     {
@@ -576,7 +654,7 @@ dda_status dda_ctx_destroy(dda_ctx* c) {
         {
             Scope sc(c);
             (void)hipStreamSynchronize(c->stream);
-            for (DevBuf* b : {&c->grid, &c->vecs, &c->state, &c->partials, &c->counters, &c->inc, &c->ainv, &c->dainv,
+            for (DevBuf* b : {&c->grid, &c->vecs, &c->state, &c->partials, &c->inc, &c->ainv, &c->dainv,
                               &c->mrel, &c->aux, &c->gtmp})
                 b->release();
             if (c->host_state) (void)hipHostFree(c->host_state);
@@ -731,6 +809,7 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, t, n_rhs, kd, fp32);
+        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
         launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)x, w.a.p, true, c->stream);
@@ -799,6 +878,7 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, t, 1, kd, fp32);
+        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
         double2* dainv = (double2*)c->dainv.ensure((size_t)t->nmat * 3 * sizeof(double2));
@@ -826,19 +906,19 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
     });
 }
 
-dda_status dda_ctx_set_timing(dda_ctx* c, int enable) {
+dda_status dda_ctx_set_timing(dda_ctx* c, int mask) {
     return guarded([&]() -> dda_status {
         if (!c) invalid("ctx is NULL");
         Scope sc(c);
         HIPCHK(hipStreamSynchronize(c->stream));
         flush_timing(c);
-        if (enable) {
+        if (mask) {
             for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) {
                 c->tms[i] = 0.0;
                 c->tlaunch[i] = 0;
             }
         }
-        c->timing = enable != 0;
+        c->timing = mask & ((1 << DDA_TIMING_CATEGORIES) - 1);
         return DDA_OK;
     });
 }

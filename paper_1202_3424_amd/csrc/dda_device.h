@@ -187,18 +187,18 @@ template <typename T> struct Tile { static constexpr int EMAX = 32768 / (int)siz
 // One Stockham pass of radix R over `nlines` lines of length L stored at
 // lds[line * Lp + e].  Every thread holds up to MAXB butterflies in registers
 // between the two barriers, so the pass is in place.
-template <typename T, int R, int DIR>
+template <typename T, int R, int DIR, int NTHR = NT>
 __device__ __forceinline__ void fft_pass(typename V2<T>::t* lds, const typename V2<T>::t* tw, int nlines, int Lp,
                                          int L, int Ns) {
     using C = typename V2<T>::t;
-    constexpr int MAXB = (Tile<T>::EMAX + R * NT - 1) / (R * NT);
+    constexpr int MAXB = (Tile<T>::EMAX + R * NTHR - 1) / (R * NTHR);
     const int LR = L / R;
     const int B = nlines * LR;
     const int tstep = L / (Ns * R);
     C v[MAXB][R];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-        const int b = threadIdx.x + i * NT;
+        const int b = threadIdx.x + i * NTHR;
         if (b < B) {
             const int line = b % nlines;
             const int j = b / nlines;
@@ -210,7 +210,7 @@ __device__ __forceinline__ void fft_pass(typename V2<T>::t* lds, const typename 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
-        const int b = threadIdx.x + i * NT;
+        const int b = threadIdx.x + i * NTHR;
         if (b < B) {
             const int line = b % nlines;
             const int j = b / nlines;
@@ -234,27 +234,133 @@ __device__ __forceinline__ void fft_pass(typename V2<T>::t* lds, const typename 
 
 // Full transform of every line in the tile (direction DIR: -1 forward, +1
 // inverse, unnormalised).  Caller has synchronised after filling the tile.
-template <typename T, int DIR>
+template <typename T, int DIR, int NTHR = NT>
 __device__ void fft_lines(typename V2<T>::t* lds, const typename V2<T>::t* tw, int nlines, int Lp, const AxisPlan& pl) {
     int Ns = 1;
     for (int s = 0; s < pl.nst; ++s) {
         const int R = pl.R[s];
         switch (R) {
-            case 8: fft_pass<T, 8, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
-            case 4: fft_pass<T, 4, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
-            case 2: fft_pass<T, 2, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
-            case 3: fft_pass<T, 3, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
-            default: fft_pass<T, 5, DIR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 8: fft_pass<T, 8, DIR, NTHR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 4: fft_pass<T, 4, DIR, NTHR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 2: fft_pass<T, 2, DIR, NTHR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            case 3: fft_pass<T, 3, DIR, NTHR>(lds, tw, nlines, Lp, pl.L, Ns); break;
+            default: fft_pass<T, 5, DIR, NTHR>(lds, tw, nlines, Lp, pl.L, Ns); break;
         }
         Ns *= R;
     }
 }
 
+// ------------------------------------------------ compile-time FFT lengths
+// The radix sequence the host's planner uses (powers of two as 8s and 4s,
+// one 2 only when unavoidable, then 3s, then 5s): ct_plan(L, -1) is the
+// number of passes, ct_plan(L, s) the radix of pass s.
+constexpr int ct_plan(int L, int s) {
+    int r[16] = {};
+    int n = 0, m = L, e2 = 0;
+    while (m % 2 == 0) { m /= 2; ++e2; }
+    if (e2 % 3 == 1 && e2 >= 4) { r[n++] = 4; r[n++] = 4; e2 -= 4; }
+    if (e2 % 3 == 2) { r[n++] = 4; e2 -= 2; }
+    if (e2 % 3 == 1) { r[n++] = 2; e2 -= 1; }
+    while (e2 >= 3) { r[n++] = 8; e2 -= 3; }
+    while (m % 3 == 0) { r[n++] = 3; m /= 3; }
+    while (m % 5 == 0) { r[n++] = 5; m /= 5; }
+    return s < 0 ? n : r[s];
+}
+
+// One radix-R pass over NL lines of compile-time length L (same in-place
+// scheme as fft_pass; the twiddles W_L^t are read from the FP64 table in
+// global memory, which stays cache resident, before the first barrier).
+// HALF_IN: the upper half of every line is zero (the first pass of a forward
+// transform of zero-padded data; R even), so inputs r >= R/2 are not read.
+// HALF_OUT: only the lower half of every line is wanted (the last pass of an
+// inverse transform; R even), so outputs q >= R/2 are not written.
+template <typename T, int R, int DIR, int L, int NL, int NS, int NTHR, bool HALF_IN = false, bool HALF_OUT = false>
+__device__ __forceinline__ void fft_pass_ct(typename V2<T>::t* lds, const double2* tw) {
+    static_assert(!(HALF_IN || HALF_OUT) || R % 2 == 0, "half-line pruning needs an even radix");
+    constexpr int RIN = HALF_IN ? R / 2 : R;
+    constexpr int ROUT = HALF_OUT ? R / 2 : R;
+    using C = typename V2<T>::t;
+    constexpr int LR = L / R;
+    constexpr int B = NL * LR;
+    constexpr int MAXB = (B + NTHR - 1) / NTHR;
+    constexpr int LP = L | 1;
+    constexpr int TSTEP = L / (NS * R);
+    C v[MAXB][R];
+    C w[MAXB][R];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * NTHR;
+        if ((B % NTHR) == 0 || b < B) {
+            const int line = b % NL;
+            const int j = b / NL;
+            const C* src = lds + line * LP + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r < RIN) {
+                    v[i][r] = src[r * LR];
+                } else {
+                    v[i][r].x = 0;
+                    v[i][r].y = 0;
+                }
+            }
+            if (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const double2 t = tw[r * k * TSTEP];
+                    w[i][r].x = (decltype(w[i][r].x))t.x;
+                    w[i][r].y = (decltype(w[i][r].y))(DIR > 0 ? -t.y : t.y);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = threadIdx.x + i * NTHR;
+        if ((B % NTHR) == 0 || b < B) {
+            const int line = b % NL;
+            const int j = b / NL;
+            const int k = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], w[i][r]);
+            }
+            Dft<R, DIR, C>::run(v[i]);
+            C* dst = lds + line * LP + (j - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < ROUT; ++q) dst[q * NS] = v[i][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Every pass of a compile-time length.  HALF_IN / HALF_OUT (see fft_pass_ct)
+// apply to the first / last pass; the caller sets them only when the data
+// allow it (inputs e >= L/2 zero, outputs e >= L/2 unused).
+template <typename T, int DIR, int L, int NL, int NTHR, bool HALF_IN = false, bool HALF_OUT = false, int S = 0,
+          int NS = 1>
+__device__ __forceinline__ void fft_lines_ct(typename V2<T>::t* lds, const double2* tw) {
+    constexpr int NST = ct_plan(L, -1);
+    if constexpr (S < NST) {
+        constexpr int R = ct_plan(L, S);
+        constexpr bool HI = HALF_IN && S == 0 && R % 2 == 0;
+        constexpr bool HO = HALF_OUT && S == NST - 1 && R % 2 == 0;
+        fft_pass_ct<T, R, DIR, L, NL, NS, NTHR, HI, HO>(lds, tw);
+        fft_lines_ct<T, DIR, L, NL, NTHR, HALF_IN, HALF_OUT, S + 1, NS * R>(lds, tw);
+    }
+}
+
+// L/2 pruning is exact for this length when the first pass (forward) or the
+// last pass (inverse) has an even radix.
+constexpr bool ct_half_in_ok(int L) { return ct_plan(L, 0) % 2 == 0; }
+constexpr bool ct_half_out_ok(int L) { return ct_plan(L, ct_plan(L, -1) - 1) % 2 == 0; }
+
 // Stage the W_L^t table of an axis into LDS (FP64 table converted to T).
-template <typename T>
+template <typename T, int NTHR = NT>
 __device__ __forceinline__ void load_twiddles(typename V2<T>::t* dst, const double2* tw64, const AxisPlan& pl) {
     using C = typename V2<T>::t;
-    for (int i = threadIdx.x; i < pl.L; i += NT) {
+    for (int i = threadIdx.x; i < pl.L; i += NTHR) {
         double2 w = tw64[pl.tw + i];
         C c;
         c.x = (T)w.x;
@@ -268,13 +374,14 @@ __device__ __forceinline__ void load_twiddles(typename V2<T>::t* dst, const doub
 // Sum NV doubles over the workgroup; the result is valid in thread 0.
 // Fixed order: xor-butterfly inside each 64-lane wavefront, then the four
 // wavefront sums in index order.
-template <int NV>
+template <int NV, int NTHR = NT>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
     }
+    if constexpr (NTHR == 64) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
@@ -285,47 +392,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             double s = sh[i];
-            for (int w = 1; w < NT / 64; ++w) s += sh[w * NV + i];
+            for (int w = 1; w < NTHR / 64; ++w) s += sh[w * NV + i];
             v[i] = s;
         }
     }
     __syncthreads();
 }
 
-// Grid-wide deterministic sum: every workgroup publishes its block sum to
-// partials[blk]; the last workgroup to arrive (counted with a device-scope
-// atomic) adds the partials in block order and resets the counter.  Returns
-// true in the last workgroup, whose thread 0 then holds the totals in v.
-template <int NV>
-__device__ bool grid_sum(double (&v)[NV], double* partials, unsigned* counter, int nblk, int blk, double* sh,
-                         int* flag) {
-    block_sum<NV>(v, sh);
+// This workgroup's sums go to partials[blk * 4 + i] (no atomics, no fences:
+// the consumer is a later kernel on the same stream).
+template <int NV, int NTHR = NT>
+__device__ __forceinline__ void publish_partial(double (&v)[NV], double* partials, int blk, double* sh) {
+    block_sum<NV, NTHR>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) partials[(long)blk * NV + i] = v[i];
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        *flag = (prev == (unsigned)(nblk - 1));
+        for (int i = 0; i < NV; ++i) partials[(long)blk * 4 + i] = v[i];
     }
-    __syncthreads();
-    const bool last = *flag != 0;
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc[NV];
+}
+
+// Sum the partials of nblk workgroups in block order; result in thread 0.
+template <int NV>
+__device__ __forceinline__ void sum_partials(double (&acc)[NV], const double* partials, int nblk, double* sh) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += NT) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += __builtin_nontemporal_load(&partials[(long)b * NV + i]);
+        for (int i = 0; i < NV; ++i) acc[i] += partials[(long)b * 4 + i];
     }
     block_sum<NV>(acc, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = acc[i];
-        *counter = 0u;
-    }
-    return true;
 }
 
 }  // namespace dda

@@ -42,8 +42,7 @@ struct SiteArgs {
     const double2* in;     // input of the plain / conjugated product
     double2* out;          // output of the plain / conjugated product
     RhsState* st;          // [nrhs]
-    double* partials;      // [nrhs][maxblk][4]
-    unsigned* counters;    // [nrhs]
+    double* partials;      // [nrhs][maxblk][4] per-workgroup sums of the last reducing kernel
     int maxblk;
     int slot;              // RhsState::red slot written by the conjugated product
     double kd;
@@ -53,10 +52,21 @@ enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3 };
 enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4 };
 // which right-hand sides a pass skips
 enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
+// what k_finalize makes of the partial sums of the kernel before it
+enum FinKind { FIN_S = 0, FIN_V, FIN_T, FIN_UPD, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ };
 
-// tile sizes chosen by the host
-int x_lines_per_tile(int Mx, int nc, bool fp32);
+// FFT lengths with compile-time kernels (dda_passes.h)
+inline bool ct_length(int L) {
+    return L == 32 || L == 48 || L == 64 || L == 80 || L == 96 || L == 128 || L == 256;
+}
+
+// tile sizes chosen by the host: x-lines (along y) per workgroup of the x
+// passes, x columns per workgroup of the strided passes
+int x_lines_per_tile(const Geo& g, int nrhs, bool fp32);
 int strided_cols_per_tile(int L, int nc, bool fp32);
+// workgroups of the x passes and of the site-level kernels, per right-hand side
+int x_pass_blocks(const Geo& g, int nrhs, bool fp32);
+int site_blocks_for(long long n3, int nrhs);
 
 template <typename T>
 void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typename V2<T>::t* grid, const double2* tw,
@@ -67,10 +77,13 @@ void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const t
 // strided FFT along axis 1 (y) or 2 (z) over lines whose other coordinates
 // are x in [0, Mx) and outer in [0, n_outer); loads e < lin (zero beyond),
 // stores e < lout; ghat != null fuses forward FFT, tensor product, inverse.
+// variant: one of strided_variants(L, ghat != null) compile-time tilings
+// (all give bitwise-identical results; the autotuner picks the fastest)
 template <typename T>
 void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
-                    hipStream_t s);
+                    hipStream_t s, int variant = 0);
+inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 5 : 3) : 1; }
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);
@@ -83,6 +96,7 @@ void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
+void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,
                     bool to_sorted, hipStream_t s);

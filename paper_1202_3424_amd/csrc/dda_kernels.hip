@@ -1,17 +1,7 @@
-// HIP kernels of the DDA solve for gfx950.
-//
-// The product y = A x (A: the interaction matrix of Draine 1988 plus the
-// diagonal 1/alpha of "Dipole Polarizabilities") is evaluated as a
-// convolution on a zero-padded grid (Goodman, Draine & Flatau 1990; "Choice
-// of FFT Algorithm") in five passes over three interleaved component grids:
-//   1. scatter + forward FFT along x of the occupied (y < ny, z < nz) lines
-//   2. forward FFT along y of the z < nz planes (inputs y < ny only)
-//   3. along z for every (x, y): forward FFT of the z < nz inputs, product
-//      with the symmetric 3x3 tensor FFT, inverse FFT, keep z < nz
-//   4. inverse FFT along y of the z < nz planes, keep y < ny
-//   5. inverse FFT along x, gather the occupied sites, add 1/alpha x.
-// Passes 1 and 5 also carry the BiCGSTAB vector updates and reductions that
-// touch the same sites, so the iteration needs no separate pass for them.
+// HIP kernels of the DDA solve for gfx950, other than the matvec passes
+// (dda_passes.h): the interaction-tensor sampling and its FFT, 1/alpha,
+// E_inc, the BiCGSTAB updates and their reductions, the efficiency sums, the
+// adjoint right-hand side and gradient, and small utilities.
 #include "dda_kernels.h"
 
 namespace dda {
@@ -32,309 +22,10 @@ template <typename C> __device__ __forceinline__ double2 to_d(C u) {
 }
 __device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
-__device__ __forceinline__ bool skip_rhs(const RhsState* st, int chk) {
-    if (chk == CHK_NONE) return false;
-    if (st->status != ST_ACTIVE) return true;
-    return chk == CHK_ACTIVE_NOT_SCONV && st->sconv;
-}
 
-// LDS carve-up shared by every FFT kernel:
-//   [twiddles: L complex][tile: nlines * Lp complex][reduction scratch]
-struct Smem {
-    unsigned char* base;
-    template <typename C> __device__ C* tw() const { return (C*)base; }
-    template <typename C> __device__ C* tile(int L) const { return (C*)base + ((L + 1) & ~1); }
-};
 __host__ __device__ inline int pad_len(int L) { return L | 1; }
 template <typename C> __host__ inline size_t fft_smem(int L, int nlines) {
     return ((size_t)((L + 1) & ~1) + (size_t)nlines * pad_len(L)) * sizeof(C) + 8 * (NT / 64) * sizeof(double) + 64;
-}
-template <typename C> __device__ inline double* red_scratch(unsigned char* base, int L, int nlines) {
-    return (double*)(base + ((size_t)((L + 1) & ~1) + (size_t)nlines * pad_len(L)) * sizeof(C));
-}
-
-// ------------------------------------------------------------------ pass 1
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_scatter_x(Geo g, SiteArgs a, typename V2<T>::t* grid, const double2* tw64,
-                                                 int XL, int chk) {
-    using C = typename V2<T>::t;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int q = blockIdx.z;
-    RhsState* st = a.st + q;
-    if (skip_rhs(st, chk)) return;
-    const int nx = g.n[0], ny = g.n[1];
-    const int Mx = g.M[0], My = g.M[1];
-    const int z = blockIdx.y;
-    const int y0 = blockIdx.x * XL;
-    const int nl = min(XL, ny - y0);
-    const int nlines = 3 * nl;
-    const int Lp = pad_len(Mx);
-    C* tws = (C*)smem;
-    C* lds = tws + ((Mx + 1) & ~1);
-    load_twiddles<T>(tws, tw64, g.ax[0]);
-
-    double2 beta = {0, 0}, omega = {0, 0}, alpha = {0, 0};
-    if (MODE == SC_P) { beta = st->beta; omega = st->omega; }
-    if (MODE == SC_S) alpha = st->alpha;
-    const long long vb = (long long)q * a.n3;
-    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
-    double ss = 0.0;
-    const int tot = nl * Mx * 3;
-    for (int idx = threadIdx.x; idx < tot; idx += NT) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % Mx;
-        const int yo = rest / Mx;
-        C val;
-        val.x = 0;
-        val.y = 0;
-        if (e < nx) {
-            const int s = mrow[yo * nx + e];
-            if (s >= 0) {
-                const long long i = vb + (long long)s * 3 + c;
-                double2 u;
-                if (MODE == SC_PLAIN) {
-                    u = a.in[i];
-                } else if (MODE == SC_CONJ) {
-                    u = cconj(a.in[i]);
-                } else if (MODE == SC_P) {
-                    // p = r + beta (p - omega v)
-                    u = cadd(a.r[i], cmul(beta, csub(a.p[i], cmul(omega, a.v[i]))));
-                    a.p[i] = u;
-                } else {
-                    // s = r - alpha v, stored over r
-                    u = csub(a.r[i], cmul(alpha, a.v[i]));
-                    a.r[i] = u;
-                    ss += u.x * u.x + u.y * u.y;
-                }
-                val = to_c<C>(u);
-            }
-        }
-        lds[(yo * 3 + c) * Lp + e] = val;
-    }
-    __syncthreads();
-    fft_lines<T, -1>(lds, tws, nlines, Lp, g.ax[0]);
-    C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
-    for (int idx = threadIdx.x; idx < tot; idx += NT) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % Mx;
-        const int yo = rest / Mx;
-        gq[((long long)yo * Mx + e) * 3 + c] = lds[(yo * 3 + c) * Lp + e];
-    }
-    if (MODE == SC_S) {
-        double v[1] = {ss};
-        __shared__ int flag;
-        double* sh = red_scratch<C>(smem, Mx, nlines);
-        const int nblk = gridDim.x * gridDim.y;
-        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        if (grid_sum<1>(v, a.partials + (long long)q * a.maxblk * 4, a.counters + q, nblk, blk, sh, &flag)) {
-            if (threadIdx.x == 0) {
-                st->snorm2 = v[0];
-                if (!isfinite(v[0])) st->status = ST_NONFINITE;
-                else st->sconv = (v[0] <= st->tol2 * st->bnorm2) ? 1 : 0;
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------------ pass 5
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_gather_x(Geo g, SiteArgs a, const typename V2<T>::t* grid,
-                                                const double2* tw64, int XL, int chk) {
-    using C = typename V2<T>::t;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int q = blockIdx.z;
-    RhsState* st = a.st + q;
-    if (skip_rhs(st, chk)) return;
-    const int nx = g.n[0], ny = g.n[1];
-    const int Mx = g.M[0], My = g.M[1];
-    const int z = blockIdx.y;
-    const int y0 = blockIdx.x * XL;
-    const int nl = min(XL, ny - y0);
-    const int nlines = 3 * nl;
-    const int Lp = pad_len(Mx);
-    C* tws = (C*)smem;
-    C* lds = tws + ((Mx + 1) & ~1);
-    load_twiddles<T>(tws, tw64, g.ax[0]);
-    const C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
-    const int tot = nl * Mx * 3;
-    for (int idx = threadIdx.x; idx < tot; idx += NT) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % Mx;
-        const int yo = rest / Mx;
-        lds[(yo * 3 + c) * Lp + e] = gq[((long long)yo * Mx + e) * 3 + c];
-    }
-    __syncthreads();
-    fft_lines<T, 1>(lds, tws, nlines, Lp, g.ax[0]);
-
-    const long long vb = (long long)q * a.n3;
-    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
-    const double2* ai = a.ainv + (long long)q * a.nmat * 3;
-    double acc[3] = {0.0, 0.0, 0.0};
-    const int tout = nl * nx * 3;
-    for (int idx = threadIdx.x; idx < tout; idx += NT) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % nx;
-        const int yo = rest / nx;
-        const int s = mrow[yo * nx + e];
-        if (s < 0) continue;
-        const long long i = vb + (long long)s * 3 + c;
-        const double2 gv = to_d(lds[(yo * 3 + c) * Lp + e]);
-        const double2 d = ai[a.mat[s] * 3 + c];
-        double2 xin;
-        if (MODE == SC_PLAIN || MODE == GA_PLAIN) xin = a.in[i];
-        if (MODE == GA_CONJ) xin = cconj(a.in[i]);
-        if (MODE == GA_V) xin = a.p[i];
-        if (MODE == GA_T) xin = a.r[i];
-        if (MODE == GA_RES) xin = a.x[i];
-        const double2 y = cadd(gv, cmul(d, xin));
-        if (MODE == GA_PLAIN) {
-            a.out[i] = y;
-        } else if (MODE == GA_CONJ) {
-            const double2 yc = cconj(y);
-            a.out[i] = yc;
-            acc[0] += yc.x * yc.x + yc.y * yc.y;
-        } else if (MODE == GA_V) {
-            a.v[i] = y;
-            const double2 w = cdotc(a.rhat[i], y);
-            acc[0] += w.x;
-            acc[1] += w.y;
-        } else if (MODE == GA_T) {
-            a.t[i] = y;
-            const double2 w = cdotc(y, xin);   // <t, s>
-            acc[0] += w.x;
-            acc[1] += w.y;
-            acc[2] += y.x * y.x + y.y * y.y;
-        } else {
-            const double2 rr = csub(a.b[i], y);
-            a.r[i] = rr;
-            acc[0] += rr.x * rr.x + rr.y * rr.y;
-        }
-    }
-    if (MODE != GA_PLAIN) {
-        __shared__ int flag;
-        double* sh = red_scratch<C>(smem, Mx, nlines);
-        const int nblk = gridDim.x * gridDim.y;
-        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        if (grid_sum<3>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, nblk, blk, sh, &flag)) {
-            if (threadIdx.x == 0) {
-                if (MODE == GA_V) {
-                    const double2 rv = {acc[0], acc[1]};
-                    st->matvecs += 1;
-                    if (!finite2(rv)) {
-                        st->status = ST_NONFINITE;
-                    } else if (rv.x == 0.0 && rv.y == 0.0) {
-                        st->status = ST_BREAKDOWN;
-                    } else {
-                        st->alpha = cdiv(st->rho, rv);
-                    }
-                } else if (MODE == GA_T) {
-                    const double2 ts = {acc[0], acc[1]};
-                    st->matvecs += 1;
-                    if (!finite2(ts) || !isfinite(acc[2])) {
-                        st->status = ST_NONFINITE;
-                    } else if (acc[2] == 0.0) {
-                        st->omega = double2{0.0, 0.0};
-                    } else {
-                        st->omega = double2{ts.x / acc[2], ts.y / acc[2]};
-                    }
-                } else if (MODE == GA_RES) {
-                    st->red[0] = acc[0];
-                } else {
-                    st->red[a.slot] = acc[0];
-                }
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------------ passes 2-4
-
-template <typename T, int NC, int GH, int DIR>
-__global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, const double2* tw64,
-                                               const typename V2<T>::t* ghat, const RhsState* st, int axis, int TX,
-                                               int lin, int lout, int chk) {
-    using C = typename V2<T>::t;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int q = blockIdx.z;
-    if (skip_rhs(st + q, chk)) return;
-    const int Mx = g.M[0], My = g.M[1];
-    const AxisPlan& pl = g.ax[axis];
-    const int L = pl.L;
-    const int Lp = pad_len(L);
-    const int x0 = blockIdx.x * TX;
-    const int nxl = min(TX, Mx - x0);
-    const int nlines = NC * nxl;
-    const int o = blockIdx.y;
-    const long long estride = (axis == 1) ? (long long)Mx * NC : (long long)My * Mx * NC;
-    const long long obase = (axis == 1) ? (long long)o * My * Mx * NC : (long long)o * Mx * NC;
-    C* tws = (C*)smem;
-    C* lds = tws + ((L + 1) & ~1);
-    load_twiddles<T>(tws, tw64, pl);
-    C* gq = grid + (long long)q * g.npts * NC + obase + (long long)x0 * NC;
-    const int tin = nlines * L;
-    for (int idx = threadIdx.x; idx < tin; idx += NT) {
-        const int inner = idx % nlines;
-        const int e = idx / nlines;
-        C v;
-        if (e < lin) {
-            v = gq[e * estride + inner];
-        } else {
-            v.x = 0;
-            v.y = 0;
-        }
-        lds[inner * Lp + e] = v;
-    }
-    __syncthreads();
-    if (GH) {
-        fft_lines<T, -1>(lds, tws, nlines, Lp, pl);
-        // y_a = sum_b Ghat_ab x_b at every (kx, ky = o, kz = e); the tensor
-        // FFT is stored on the octant 0..M/2 per axis, each component even
-        // or odd in each index (diagonal: even; ab: odd in a and b).
-        const int Hx = g.H[0], Hy = g.H[1];
-        const int ky = o;
-        const int fy = (ky <= My / 2) ? ky : My - ky;
-        const int sy = (ky <= My / 2) ? 1 : -1;
-        const int Mz = g.M[2];
-        const int npt = nxl * L;
-        for (int pidx = threadIdx.x; pidx < npt; pidx += NT) {
-            const int xo = pidx % nxl;
-            const int kz = pidx / nxl;
-            const int kx = x0 + xo;
-            const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
-            const int sx = (kx <= Mx / 2) ? 1 : -1;
-            const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
-            const int sz = (kz <= Mz / 2) ? 1 : -1;
-            const C* G = ghat + (((long long)fz * Hy + fy) * Hx + fx) * 6;
-            const C gxx = G[0], gyy = G[3], gzz = G[5];
-            C gxy = G[1], gxz = G[2], gyz = G[4];
-            if (sx * sy < 0) { gxy.x = -gxy.x; gxy.y = -gxy.y; }
-            if (sx * sz < 0) { gxz.x = -gxz.x; gxz.y = -gxz.y; }
-            if (sy * sz < 0) { gyz.x = -gyz.x; gyz.y = -gyz.y; }
-            C* px = lds + (xo * 3 + 0) * Lp + kz;
-            C* py = lds + (xo * 3 + 1) * Lp + kz;
-            C* pz = lds + (xo * 3 + 2) * Lp + kz;
-            const C X = *px, Y = *py, Z = *pz;
-            *px = cadd(cadd(cmul(gxx, X), cmul(gxy, Y)), cmul(gxz, Z));
-            *py = cadd(cadd(cmul(gxy, X), cmul(gyy, Y)), cmul(gyz, Z));
-            *pz = cadd(cadd(cmul(gxz, X), cmul(gyz, Y)), cmul(gzz, Z));
-        }
-        __syncthreads();
-        fft_lines<T, 1>(lds, tws, nlines, Lp, pl);
-    } else {
-        fft_lines<T, DIR>(lds, tws, nlines, Lp, pl);
-    }
-    const int tout = nlines * lout;
-    for (int idx = threadIdx.x; idx < tout; idx += NT) {
-        const int inner = idx % nlines;
-        const int e = idx / nlines;
-        gq[e * estride + inner] = lds[inner * Lp + e];
-    }
 }
 
 // Forward FFT along x of every line of a six-component FP64 grid (the
@@ -494,9 +185,7 @@ __global__ __launch_bounds__(NT) void k_einc(SiteArgs a, const int* coords, cons
 // Cold start x = 0: r = rhat = b, p = v = 0; rho = |b|^2.
 __global__ __launch_bounds__(NT) void k_init_cold(SiteArgs a) {
     __shared__ double sh[8 * NT / 64];
-    __shared__ int flag;
     const int q = blockIdx.y;
-    RhsState* st = a.st + q;
     const long long vb = (long long)q * a.n3;
     double acc[1] = {0.0};
     for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
@@ -508,29 +197,13 @@ __global__ __launch_bounds__(NT) void k_init_cold(SiteArgs a) {
         a.v[vb + i] = double2{0.0, 0.0};
         acc[0] += bb.x * bb.x + bb.y * bb.y;
     }
-    if (grid_sum<1>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
-        if (threadIdx.x == 0) {
-            st->bnorm2 = acc[0];
-            st->rnorm2 = acc[0];
-            st->rho = double2{acc[0], 0.0};
-            st->alpha = double2{1.0, 0.0};
-            st->omega = double2{1.0, 0.0};
-            st->beta = double2{0.0, 0.0};
-            st->iters = 0;
-            st->matvecs = 0;
-            st->sconv = 0;
-            st->restarts = 0;
-            st->status = isfinite(acc[0]) ? (acc[0] > 0.0 ? ST_ACTIVE : ST_CONVERGED) : ST_NONFINITE;
-        }
-    }
+    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
 }
 
 // Warm start: x already holds P0 and r = b - A P0.  rhat = r, p = v = 0.
 __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
     __shared__ double sh[8 * NT / 64];
-    __shared__ int flag;
     const int q = blockIdx.y;
-    RhsState* st = a.st + q;
     const long long vb = (long long)q * a.n3;
     double acc[2] = {0.0, 0.0};
     for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
@@ -542,22 +215,7 @@ __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
         acc[0] += rr.x * rr.x + rr.y * rr.y;
         acc[1] += bb.x * bb.x + bb.y * bb.y;
     }
-    if (grid_sum<2>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
-        if (threadIdx.x == 0) {
-            st->bnorm2 = acc[1];
-            st->rnorm2 = acc[0];
-            st->rho = double2{acc[0], 0.0};
-            st->alpha = double2{1.0, 0.0};
-            st->omega = double2{1.0, 0.0};
-            st->beta = double2{0.0, 0.0};
-            st->iters = 0;
-            st->matvecs = 1;
-            st->sconv = 0;
-            st->restarts = 0;
-            if (!isfinite(acc[0]) || !isfinite(acc[1])) st->status = ST_NONFINITE;
-            else st->status = (acc[0] <= st->tol2 * acc[1]) ? ST_CONVERGED : ST_ACTIVE;
-        }
-    }
+    publish_partial<2>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
 }
 
 // End of a BiCGSTAB iteration: x += alpha p + omega s, r = s - omega t (or,
@@ -565,9 +223,8 @@ __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
 // beta for the next direction, convergence |r|^2 <= tol^2 |b|^2.
 __global__ __launch_bounds__(NT) void k_update(SiteArgs a) {
     __shared__ double sh[8 * NT / 64];
-    __shared__ int flag;
     const int q = blockIdx.y;
-    RhsState* st = a.st + q;
+    const RhsState* st = a.st + q;
     if (st->status != ST_ACTIVE) return;
     const int sconv = st->sconv;
     const double2 alpha = st->alpha, omega = st->omega;
@@ -588,32 +245,14 @@ __global__ __launch_bounds__(NT) void k_update(SiteArgs a) {
         acc[1] += w.y;
         acc[2] += rr.x * rr.x + rr.y * rr.y;
     }
-    if (grid_sum<3>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
-        if (threadIdx.x == 0) {
-            st->iters += 1;
-            st->rnorm2 = acc[2];
-            const double2 rho_new = {acc[0], acc[1]};
-            if (!isfinite(acc[2]) || !finite2(rho_new)) {
-                st->status = ST_NONFINITE;
-            } else if (sconv || acc[2] <= st->tol2 * st->bnorm2) {
-                st->status = ST_CONVERGED;
-            } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) || (omega.x == 0.0 && omega.y == 0.0)) {
-                st->status = ST_BREAKDOWN;
-            } else {
-                st->beta = cmul(cdiv(rho_new, st->rho), cdiv(alpha, omega));
-                st->rho = rho_new;
-            }
-            if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
-        }
-    }
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
 }
 
 // One restart after a breakdown: rhat = r, p = v = 0, rho = |r|^2.
 __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
     __shared__ double sh[8 * NT / 64];
-    __shared__ int flag;
     const int q = blockIdx.y;
-    RhsState* st = a.st + q;
+    const RhsState* st = a.st + q;
     if (st->status != ST_BREAKDOWN || st->restarts > 0) return;
     const long long vb = (long long)q * a.n3;
     double acc[1] = {0.0};
@@ -624,17 +263,7 @@ __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
         a.v[vb + i] = double2{0.0, 0.0};
         acc[0] += rr.x * rr.x + rr.y * rr.y;
     }
-    if (grid_sum<1>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
-        if (threadIdx.x == 0) {
-            st->rho = double2{acc[0], 0.0};
-            st->alpha = double2{1.0, 0.0};
-            st->omega = double2{1.0, 0.0};
-            st->beta = double2{0.0, 0.0};
-            st->sconv = 0;
-            st->restarts += 1;
-            st->status = (acc[0] > 0.0 && isfinite(acc[0])) ? ST_ACTIVE : ST_BREAKDOWN;
-        }
-    }
+    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
 }
 
 // Efficiency sums at the solution x (Draine 1988):
@@ -642,9 +271,7 @@ __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
 //   red[5] = sum Re(E* . P).
 __global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
     __shared__ double sh[8 * NT / 64];
-    __shared__ int flag;
     const int q = blockIdx.y;
-    RhsState* st = a.st + q;
     const long long vb = (long long)q * a.n3;
     const double2* ai = a.ainv + (long long)q * a.nmat * 3;
     const double rr = (2.0 / 3.0) * a.kd * a.kd * a.kd;
@@ -659,12 +286,115 @@ __global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
         acc[1] += (-d.y - rr) * (P.x * P.x + P.y * P.y);
         acc[2] += w.x;
     }
-    if (grid_sum<3>(acc, a.partials + (long long)q * a.maxblk * 4, a.counters + q, gridDim.x, blockIdx.x, sh, &flag)) {
-        if (threadIdx.x == 0) {
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+}
+
+// Turn the partial sums of a producer kernel into the right-hand side's
+// scalars and status.  One workgroup per right-hand side; it applies the
+// same skip rule as the producer so a skipped right-hand side is untouched.
+__global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk) {
+    __shared__ double sh[8 * NT / 64];
+    const int q = blockIdx.x;
+    RhsState* st = a.st + q;
+    const double* part = a.partials + (long long)q * a.maxblk * 4;
+    bool run;
+    switch (kind) {
+        case FIN_S: case FIN_V: case FIN_UPD: run = st->status == ST_ACTIVE; break;
+        case FIN_T: run = st->status == ST_ACTIVE && !st->sconv; break;
+        case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
+        default: run = true; break;
+    }
+    if (!run) return;
+    double acc[3];
+    sum_partials<3>(acc, part, nblk, sh);
+    if (threadIdx.x != 0) return;
+    switch (kind) {
+        case FIN_S:
+            st->snorm2 = acc[0];
+            if (!isfinite(acc[0])) st->status = ST_NONFINITE;
+            else st->sconv = (acc[0] <= st->tol2 * st->bnorm2) ? 1 : 0;
+            break;
+        case FIN_V: {
+            const double2 rv = {acc[0], acc[1]};
+            st->matvecs += 1;
+            if (!finite2(rv)) st->status = ST_NONFINITE;
+            else if (rv.x == 0.0 && rv.y == 0.0) st->status = ST_BREAKDOWN;
+            else st->alpha = cdiv(st->rho, rv);
+            break;
+        }
+        case FIN_T: {
+            const double2 ts = {acc[0], acc[1]};
+            st->matvecs += 1;
+            if (!finite2(ts) || !isfinite(acc[2])) st->status = ST_NONFINITE;
+            else if (acc[2] == 0.0) st->omega = double2{0.0, 0.0};
+            else st->omega = double2{ts.x / acc[2], ts.y / acc[2]};
+            break;
+        }
+        case FIN_UPD: {
+            const double2 alpha = st->alpha, omega = st->omega;
+            st->iters += 1;
+            st->rnorm2 = acc[2];
+            const double2 rho_new = {acc[0], acc[1]};
+            if (!isfinite(acc[2]) || !finite2(rho_new)) {
+                st->status = ST_NONFINITE;
+            } else if (st->sconv || acc[2] <= st->tol2 * st->bnorm2) {
+                st->status = ST_CONVERGED;
+            } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) || (omega.x == 0.0 && omega.y == 0.0)) {
+                st->status = ST_BREAKDOWN;
+            } else {
+                st->beta = cmul(cdiv(rho_new, st->rho), cdiv(alpha, omega));
+                st->rho = rho_new;
+            }
+            if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
+            break;
+        }
+        case FIN_COLD:
+            st->bnorm2 = acc[0];
+            st->rnorm2 = acc[0];
+            st->rho = double2{acc[0], 0.0};
+            st->alpha = double2{1.0, 0.0};
+            st->omega = double2{1.0, 0.0};
+            st->beta = double2{0.0, 0.0};
+            st->iters = 0;
+            st->matvecs = 0;
+            st->sconv = 0;
+            st->restarts = 0;
+            st->status = isfinite(acc[0]) ? (acc[0] > 0.0 ? ST_ACTIVE : ST_CONVERGED) : ST_NONFINITE;
+            break;
+        case FIN_WARM:
+            st->bnorm2 = acc[1];
+            st->rnorm2 = acc[0];
+            st->rho = double2{acc[0], 0.0};
+            st->alpha = double2{1.0, 0.0};
+            st->omega = double2{1.0, 0.0};
+            st->beta = double2{0.0, 0.0};
+            st->iters = 0;
+            st->matvecs = 1;
+            st->sconv = 0;
+            st->restarts = 0;
+            if (!isfinite(acc[0]) || !isfinite(acc[1])) st->status = ST_NONFINITE;
+            else st->status = (acc[0] <= st->tol2 * acc[1]) ? ST_CONVERGED : ST_ACTIVE;
+            break;
+        case FIN_RESTART:
+            st->rho = double2{acc[0], 0.0};
+            st->alpha = double2{1.0, 0.0};
+            st->omega = double2{1.0, 0.0};
+            st->beta = double2{0.0, 0.0};
+            st->sconv = 0;
+            st->restarts += 1;
+            st->status = (acc[0] > 0.0 && isfinite(acc[0])) ? ST_ACTIVE : ST_BREAKDOWN;
+            break;
+        case FIN_QSUM:
             st->red[3] = acc[0];
             st->red[4] = acc[1];
             st->red[5] = acc[2];
-        }
+            break;
+        case FIN_RES:
+            st->red[0] = acc[0];
+            break;
+        default:  // FIN_CONJ
+            st->red[a.slot] = acc[0];
+            break;
     }
 }
 
@@ -744,10 +474,34 @@ inline int blocks_for(long long n, int cap) {
 
 // ------------------------------------------------------------------ launchers
 
-int x_lines_per_tile(int Mx, int nc, bool fp32) {
+int x_lines_per_tile(const Geo& g, int nrhs, bool fp32) {
+    // compile-time lengths: one x-line (three components) per workgroup
+    if (ct_length(g.M[0])) return 1;
+    // otherwise as many lines as fit one tile, but no fewer than ~2048
+    // workgroups when the problem allows it
     const int emax = fp32 ? Tile<float>::EMAX : Tile<double>::EMAX;
-    int xl = emax / (nc * Mx);
-    return xl < 1 ? 1 : xl;
+    int cap = emax / (3 * g.M[0]);
+    if (cap < 1) cap = 1;
+    const long long lines = (long long)g.n[1] * g.n[2] * nrhs;
+    long long xl = lines / 2048;
+    if (xl < 1) xl = 1;
+    if (xl > cap) xl = cap;
+    return (int)xl;
+}
+
+int x_pass_blocks(const Geo& g, int nrhs, bool fp32) {
+    const int xl = x_lines_per_tile(g, nrhs, fp32);
+    return ((g.n[1] + xl - 1) / xl) * g.n[2];
+}
+
+int site_blocks_for(long long n3, int nrhs) {
+    // ~2048 workgroups over all right-hand sides, at least one element per thread
+    long long b = (2048 + nrhs - 1) / nrhs;
+    const long long most = (n3 + NT - 1) / NT;
+    if (b > most) b = most;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
 }
 
 int strided_cols_per_tile(int L, int nc, bool fp32) {
@@ -759,69 +513,9 @@ int strided_cols_per_tile(int L, int nc, bool fp32) {
     return p;
 }
 
-template <typename T>
-void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typename V2<T>::t* grid, const double2* tw,
-                      hipStream_t s) {
-    using C = typename V2<T>::t;
-    const int XL = x_lines_per_tile(g.M[0], 3, sizeof(T) == 4);
-    dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
-    const size_t sm = fft_smem<C>(g.M[0], 3 * XL);
-    switch (mode) {
-        case SC_PLAIN: hipLaunchKernelGGL((k_scatter_x<T, SC_PLAIN>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        case SC_CONJ: hipLaunchKernelGGL((k_scatter_x<T, SC_CONJ>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        case SC_P: hipLaunchKernelGGL((k_scatter_x<T, SC_P>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        default: hipLaunchKernelGGL((k_scatter_x<T, SC_S>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-    }
-}
-
-template <typename T>
-void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const typename V2<T>::t* grid,
-                     const double2* tw, hipStream_t s) {
-    using C = typename V2<T>::t;
-    const int XL = x_lines_per_tile(g.M[0], 3, sizeof(T) == 4);
-    dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
-    const size_t sm = fft_smem<C>(g.M[0], 3 * XL);
-    switch (mode) {
-        case GA_PLAIN: hipLaunchKernelGGL((k_gather_x<T, GA_PLAIN>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        case GA_CONJ: hipLaunchKernelGGL((k_gather_x<T, GA_CONJ>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        case GA_V: hipLaunchKernelGGL((k_gather_x<T, GA_V>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        case GA_T: hipLaunchKernelGGL((k_gather_x<T, GA_T>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-        default: hipLaunchKernelGGL((k_gather_x<T, GA_RES>), grd, dim3(NT), sm, s, g, a, grid, tw, XL, chk); break;
-    }
-}
-
-template <typename T>
-void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
-                    typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
-                    hipStream_t s) {
-    using C = typename V2<T>::t;
-    const int L = g.M[axis];
-    const int TX = strided_cols_per_tile(L, nc, sizeof(T) == 4);
-    dim3 grd((g.M[0] + TX - 1) / TX, n_outer, nrhs);
-    const size_t sm = fft_smem<C>(L, nc * TX);
-    if (nc == 3) {
-        if (ghat)
-            hipLaunchKernelGGL((k_strided<T, 3, 1, -1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
-        else if (dir < 0)
-            hipLaunchKernelGGL((k_strided<T, 3, 0, -1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
-        else
-            hipLaunchKernelGGL((k_strided<T, 3, 0, 1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
-    } else {
-        hipLaunchKernelGGL((k_strided<T, 6, 0, -1>), grd, dim3(NT), sm, s, g, grid, tw, ghat, st, axis, TX, lin, lout, chk);
-    }
-}
-
-template void launch_scatter_x<double>(int, int, const Geo&, const SiteArgs&, double2*, const double2*, hipStream_t);
-template void launch_scatter_x<float>(int, int, const Geo&, const SiteArgs&, float2*, const double2*, hipStream_t);
-template void launch_gather_x<double>(int, int, const Geo&, const SiteArgs&, const double2*, const double2*, hipStream_t);
-template void launch_gather_x<float>(int, int, const Geo&, const SiteArgs&, const float2*, const double2*, hipStream_t);
-template void launch_strided<double>(int, int, int, const Geo&, int, int, int, int, int, double2*, const double2*,
-                                     const double2*, const RhsState*, hipStream_t);
-template void launch_strided<float>(int, int, int, const Geo&, int, int, int, int, int, float2*, const double2*,
-                                    const float2*, const RhsState*, hipStream_t);
-
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s) {
-    const int XL = x_lines_per_tile(g.M[0], 6, false);
+    int XL = Tile<double>::EMAX / (6 * g.M[0]);
+    if (XL < 1) XL = 1;
     dim3 grd((g.M[1] + XL - 1) / XL, g.M[2], 1);
     hipLaunchKernelGGL(k_xgrid6, grd, dim3(NT), fft_smem<double2>(g.M[0], 6 * XL), s, g, grid, tw, XL);
 }
@@ -859,6 +553,9 @@ void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s) {
 }
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qsum, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(a.nrhs), dim3(NT), 0, s, a, kind, nblk);
 }
 
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,

@@ -1,0 +1,609 @@
+// The five passes of the FFT matrix-vector product y = A x, as kernel
+// templates instantiated per grid precision (dda_passes_f64.hip,
+// dda_passes_f32.hip).
+//
+// A = the interaction matrix of Draine (1988) plus the diagonal 1/alpha
+// ("Dipole Polarizabilities"); the product is a convolution on a zero-padded
+// grid (Goodman, Draine & Flatau 1990; "Choice of FFT Algorithm"), evaluated
+// in five pruned passes over three interleaved component grids:
+//   1. scatter + forward FFT along x of the occupied (y < ny, z < nz) lines
+//   2. forward FFT along y of the z < nz planes (inputs y < ny only)
+//   3. along z for every (x, y): forward FFT of the z < nz inputs, product
+//      with the symmetric 3x3 tensor FFT, inverse FFT, keep z < nz
+//   4. inverse FFT along y of the z < nz planes, keep y < ny
+//   5. inverse FFT along x, gather the occupied sites, add 1/alpha x.
+// Passes 1 and 5 also carry the BiCGSTAB vector updates and the partial sums
+// of the inner products that touch the same sites.
+//
+// Each kernel has two forms.  For the FFT lengths in CT_LENGTHS the length,
+// the tile shape and the radix plan are compile-time constants (index
+// arithmetic folds to shifts and multiplies); the x passes then run one
+// x-line (three components) per 64-thread workgroup.  Other lengths use the
+// runtime plan with twiddles staged in LDS.
+#pragma once
+
+#include "dda_kernels.h"
+
+namespace dda {
+namespace passes {
+
+// lengths with compile-time kernels
+#define DDA_CT_LENGTHS(X) X(32) X(48) X(64) X(80) X(96) X(128) X(256)
+
+// x columns per workgroup of a compile-time strided pass: a tile of about
+// 1536 complex values (three components per column)
+constexpr int ct_cols(int L) {
+    if (L <= 0) return 1;
+    int tx = 1536 / (3 * L);
+    int p = 1;
+    while (p * 2 <= tx && p * 2 <= 16) p *= 2;
+    return p;
+}
+constexpr int XTHR = 64;   // threads of a compile-time x-pass workgroup (one wavefront)
+
+template <typename C> __device__ __forceinline__ C to_c(double2 u) {
+    C c;
+    c.x = u.x;
+    c.y = u.y;
+    return c;
+}
+template <typename C> __device__ __forceinline__ double2 to_d(C u) {
+    double2 c;
+    c.x = (double)u.x;
+    c.y = (double)u.y;
+    return c;
+}
+
+__device__ __forceinline__ bool skip_rhs(const RhsState* st, int chk) {
+    if (chk == CHK_NONE) return false;
+    if (st->status != ST_ACTIVE) return true;
+    return chk == CHK_ACTIVE_NOT_SCONV && st->sconv;
+}
+
+inline __host__ __device__ int pad_len(int L) { return L | 1; }
+inline __host__ __device__ int even_up(int L) { return (L + 1) & ~1; }
+
+// LDS of a runtime-length kernel: [twiddles (L)][tile (nlines * Lp)][scratch];
+// of a compile-time kernel: [tile][scratch].
+template <typename C> inline size_t smem_rt(int L, int nlines) {
+    return ((size_t)even_up(L) + (size_t)nlines * pad_len(L)) * sizeof(C) + 8 * (NT / 64) * sizeof(double) + 64;
+}
+template <typename C> inline size_t smem_ct(int L, int nlines) {
+    return (size_t)nlines * pad_len(L) * sizeof(C) + 8 * (NT / 64) * sizeof(double) + 64;
+}
+
+// ------------------------------------------------------------------ pass 1
+
+template <typename T, int MODE, int LC, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename V2<T>::t* grid, const double2* tw64,
+                                                   int XLrt, int chk) {
+    using C = typename V2<T>::t;
+    constexpr bool CT = LC > 0;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int q = blockIdx.z;
+    const RhsState* st = a.st + q;
+    if (skip_rhs(st, chk)) return;
+    const int nx = g.n[0], ny = g.n[1];
+    const int Mx = CT ? LC : g.M[0];
+    const int My = g.M[1];
+    const int XL = CT ? 1 : XLrt;
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * XL;
+    const int nl = CT ? 1 : min(XL, ny - y0);
+    const int nlines = 3 * nl;
+    const int Lp = pad_len(Mx);
+    C* lds;
+    C* tws = nullptr;
+    if constexpr (CT) {
+        lds = (C*)smem;
+    } else {
+        tws = (C*)smem;
+        lds = tws + even_up(Mx);
+        load_twiddles<T, NTHR>(tws, tw64, g.ax[0]);
+    }
+    double2 beta = {0, 0}, omega = {0, 0}, alpha = {0, 0};
+    if (MODE == SC_P) { beta = st->beta; omega = st->omega; }
+    if (MODE == SC_S) alpha = st->alpha;
+    const long long vb = (long long)q * a.n3;
+    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    double ss = 0.0;
+    // forward transform of a line that is zero beyond nx: with 2 nx <= Mx the
+    // first radix pass never reads the upper half, which is then not filled
+    bool hin = false;
+    if constexpr (CT) hin = ct_half_in_ok(LC) && 2 * nx <= Mx;
+    const int ext = hin ? Mx / 2 : Mx;
+    const int tin = nl * ext * 3;
+    for (int idx = threadIdx.x; idx < tin; idx += NTHR) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % ext;
+        const int yo = rest / ext;
+        C val;
+        val.x = 0;
+        val.y = 0;
+        if (e < nx) {
+            const int s = mrow[yo * nx + e];
+            if (s >= 0) {
+                const long long i = vb + (long long)s * 3 + c;
+                double2 u;
+                if (MODE == SC_PLAIN) {
+                    u = a.in[i];
+                } else if (MODE == SC_CONJ) {
+                    u = cconj(a.in[i]);
+                } else if (MODE == SC_P) {
+                    // p = r + beta (p - omega v)
+                    u = cadd(a.r[i], cmul(beta, csub(a.p[i], cmul(omega, a.v[i]))));
+                    a.p[i] = u;
+                } else {
+                    // s = r - alpha v, stored over r
+                    u = csub(a.r[i], cmul(alpha, a.v[i]));
+                    a.r[i] = u;
+                    ss += u.x * u.x + u.y * u.y;
+                }
+                val = to_c<C>(u);
+            }
+        }
+        lds[(yo * 3 + c) * Lp + e] = val;
+    }
+    __syncthreads();
+    if constexpr (CT) {
+        if (hin) fft_lines_ct<T, -1, LC, 3, NTHR, true, false>(lds, tw64 + g.ax[0].tw);
+        else fft_lines_ct<T, -1, LC, 3, NTHR>(lds, tw64 + g.ax[0].tw);
+    } else {
+        fft_lines<T, -1, NTHR>(lds, tws, nlines, Lp, g.ax[0]);
+    }
+    C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
+    const int tot = nl * Mx * 3;
+    for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        gq[idx] = lds[(yo * 3 + c) * Lp + e];
+    }
+    if (MODE == SC_S) {
+        double v[1] = {ss};
+        double* sh = (double*)(lds + nlines * Lp);
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        publish_partial<1, NTHR>(v, a.partials + (long long)q * a.maxblk * 4, blk, sh);
+    }
+}
+
+// ------------------------------------------------------------------ pass 5
+
+template <typename T, int MODE, int LC, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const typename V2<T>::t* grid,
+                                                  const double2* tw64, int XLrt, int chk) {
+    using C = typename V2<T>::t;
+    constexpr bool CT = LC > 0;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int q = blockIdx.z;
+    const RhsState* st = a.st + q;
+    if (skip_rhs(st, chk)) return;
+    const int nx = g.n[0], ny = g.n[1];
+    const int Mx = CT ? LC : g.M[0];
+    const int My = g.M[1];
+    const int XL = CT ? 1 : XLrt;
+    const int z = blockIdx.y;
+    const int y0 = blockIdx.x * XL;
+    const int nl = CT ? 1 : min(XL, ny - y0);
+    const int nlines = 3 * nl;
+    const int Lp = pad_len(Mx);
+    C* lds;
+    C* tws = nullptr;
+    if constexpr (CT) {
+        lds = (C*)smem;
+    } else {
+        tws = (C*)smem;
+        lds = tws + even_up(Mx);
+        load_twiddles<T, NTHR>(tws, tw64, g.ax[0]);
+    }
+    const C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
+    const int tot = nl * Mx * 3;
+    for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % Mx;
+        const int yo = rest / Mx;
+        lds[(yo * 3 + c) * Lp + e] = gq[idx];
+    }
+    __syncthreads();
+    if constexpr (CT) {
+        // only e < nx is gathered: with 2 nx <= Mx the last pass skips the upper half
+        if (ct_half_out_ok(LC) && 2 * nx <= Mx) fft_lines_ct<T, 1, LC, 3, NTHR, false, true>(lds, tw64 + g.ax[0].tw);
+        else fft_lines_ct<T, 1, LC, 3, NTHR>(lds, tw64 + g.ax[0].tw);
+    } else {
+        fft_lines<T, 1, NTHR>(lds, tws, nlines, Lp, g.ax[0]);
+    }
+
+    const long long vb = (long long)q * a.n3;
+    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    const double2* ai = a.ainv + (long long)q * a.nmat * 3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int tout = nl * nx * 3;
+    for (int idx = threadIdx.x; idx < tout; idx += NTHR) {
+        const int c = idx % 3;
+        const int rest = idx / 3;
+        const int e = rest % nx;
+        const int yo = rest / nx;
+        const int s = mrow[yo * nx + e];
+        if (s < 0) continue;
+        const long long i = vb + (long long)s * 3 + c;
+        const double2 gv = to_d(lds[(yo * 3 + c) * Lp + e]);
+        const double2 d = ai[a.mat[s] * 3 + c];
+        double2 xin;
+        if (MODE == GA_PLAIN) xin = a.in[i];
+        if (MODE == GA_CONJ) xin = cconj(a.in[i]);
+        if (MODE == GA_V) xin = a.p[i];
+        if (MODE == GA_T) xin = a.r[i];
+        if (MODE == GA_RES) xin = a.x[i];
+        const double2 y = cadd(gv, cmul(d, xin));
+        if (MODE == GA_PLAIN) {
+            a.out[i] = y;
+        } else if (MODE == GA_CONJ) {
+            const double2 yc = cconj(y);
+            a.out[i] = yc;
+            acc[0] += yc.x * yc.x + yc.y * yc.y;
+        } else if (MODE == GA_V) {
+            a.v[i] = y;
+            const double2 w = cdotc(a.rhat[i], y);
+            acc[0] += w.x;
+            acc[1] += w.y;
+        } else if (MODE == GA_T) {
+            a.t[i] = y;
+            const double2 w = cdotc(y, xin);   // <t, s>
+            acc[0] += w.x;
+            acc[1] += w.y;
+            acc[2] += y.x * y.x + y.y * y.y;
+        } else {
+            const double2 rr = csub(a.b[i], y);
+            a.r[i] = rr;
+            acc[0] += rr.x * rr.x + rr.y * rr.y;
+        }
+    }
+    if (MODE != GA_PLAIN) {
+        double* sh = (double*)(lds + nlines * Lp);
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        publish_partial<3, NTHR>(acc, a.partials + (long long)q * a.maxblk * 4, blk, sh);
+    }
+}
+
+// ------------------------------------------------------------------ passes 2-4
+
+// Strided FFT along axis 1 (y, outer index = z) or 2 (z, outer index = y)
+// over TX adjacent x columns times NC components.  With GH: forward FFT, the
+// tensor product, inverse FFT.  Variants of the GH form (VAR):
+//   0  the workgroup handles every right-hand side in turn, its tensor values
+//      read once and kept in registers;
+//   1  every right-hand side in turn, tensor values re-read (cache) each time;
+//   2  one right-hand side per workgroup (grid z), tensor values read.
+// TXC is the compile-time tile width (x columns).
+template <typename T, int NC, int GH, int DIR, int LC, int TXC = 1, int VAR = 0>
+__global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, const double2* tw64,
+                                               const typename V2<T>::t* ghat, const RhsState* st, int nrhs,
+                                               int axis, int TXrt, int lin, int lout, int chk) {
+    using C = typename V2<T>::t;
+    constexpr bool CT = LC > 0;
+    constexpr bool RHS_LOOP = GH && VAR != 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Mx = g.M[0], My = g.M[1];
+    const AxisPlan& pl = g.ax[axis];
+    const int L = CT ? LC : pl.L;
+    const int TX = CT ? TXC : TXrt;
+    const int Lp = pad_len(L);
+    const int x0 = blockIdx.x * TX;
+    const int nxl = min(TX, Mx - x0);
+    const int nlines = NC * TX;   // lines beyond nxl hold zeros and are not stored
+    const int o = blockIdx.y;
+    const long long estride = (axis == 1) ? (long long)Mx * NC : (long long)My * Mx * NC;
+    const long long obase = (axis == 1) ? (long long)o * My * Mx * NC : (long long)o * Mx * NC;
+    C* lds;
+    C* tws = nullptr;
+    if constexpr (CT) {
+        lds = (C*)smem;
+    } else {
+        tws = (C*)smem;
+        lds = tws + even_up(L);
+        load_twiddles<T>(tws, tw64, pl);
+    }
+    const int nval = NC * nxl;
+    // tensor values of this thread's points (GH, compile-time form)
+    constexpr int MAXP = CT ? (TXC * LC + NT - 1) / NT : 1;
+    C G[MAXP][6];
+    const int Hx = g.H[0], Hy = g.H[1];
+    const int Mz = g.M[2];
+    const int ky = o;
+    const int fy = (ky <= My / 2) ? ky : My - ky;
+    const int sy = (ky <= My / 2) ? 1 : -1;
+    auto tensor_at = [&](int xo, int kz, C* out6) {
+        const int kx = x0 + xo;
+        const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
+        const int sx = (kx <= Mx / 2) ? 1 : -1;
+        const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
+        const int sz = (kz <= Mz / 2) ? 1 : -1;
+        const C* Gp = ghat + (((long long)fz * Hy + fy) * Hx + fx) * 6;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) out6[c] = Gp[c];
+        // diagonal components are even in every index, ab is odd in a and b
+        if (sx * sy < 0) { out6[1].x = -out6[1].x; out6[1].y = -out6[1].y; }
+        if (sx * sz < 0) { out6[2].x = -out6[2].x; out6[2].y = -out6[2].y; }
+        if (sy * sz < 0) { out6[4].x = -out6[4].x; out6[4].y = -out6[4].y; }
+    };
+    if constexpr (GH && CT && VAR == 0) {
+#pragma unroll
+        for (int i = 0; i < MAXP; ++i) {
+            const int p = threadIdx.x + i * NT;
+            if (p < TX * L) {
+                const int xo = p % TX;
+                const int kz = p / TX;
+                if (xo < nxl) tensor_at(xo, kz, G[i]);
+            }
+        }
+    }
+    const int q0 = RHS_LOOP ? 0 : blockIdx.z;
+    const int q1 = RHS_LOOP ? nrhs : blockIdx.z + 1;
+    // forward transforms with 2 lin <= L never read the upper half of a line;
+    // inverse transforms with 2 lout <= L never write it
+    bool hin = false, hout = false;
+    if constexpr (CT) {
+        hin = (GH || DIR < 0) && ct_half_in_ok(LC) && 2 * lin <= L;
+        hout = (GH || DIR > 0) && ct_half_out_ok(LC) && 2 * lout <= L;
+    }
+    for (int q = q0; q < q1; ++q) {
+        if (skip_rhs(st + q, chk)) continue;
+        C* gq = grid + (long long)q * g.npts * NC + obase + (long long)x0 * NC;
+        const int tin = nlines * (hin ? L / 2 : L);
+        for (int idx = threadIdx.x; idx < tin; idx += NT) {
+            const int inner = idx % nlines;
+            const int e = idx / nlines;
+            C v;
+            if (e < lin && inner < nval) {
+                v = gq[e * estride + inner];
+            } else {
+                v.x = 0;
+                v.y = 0;
+            }
+            lds[inner * Lp + e] = v;
+        }
+        __syncthreads();
+        if constexpr (GH) {
+            if constexpr (CT) {
+                if (hin) fft_lines_ct<T, -1, LC, NC * TXC, NT, true, false>(lds, tw64 + pl.tw);
+                else fft_lines_ct<T, -1, LC, NC * TXC, NT>(lds, tw64 + pl.tw);
+            } else {
+                fft_lines<T, -1>(lds, tws, nlines, Lp, pl);
+            }
+            // y_a = sum_b Ghat_ab x_b at (kx, ky = o, kz)
+            if constexpr (CT) {
+#pragma unroll
+                for (int i = 0; i < MAXP; ++i) {
+                    const int p = threadIdx.x + i * NT;
+                    if (p < TX * L) {
+                        const int xo = p % TX;
+                        const int kz = p / TX;
+                        if (xo < nxl) {
+                            C* px = lds + (xo * 3 + 0) * Lp + kz;
+                            C* py = lds + (xo * 3 + 1) * Lp + kz;
+                            C* pz = lds + (xo * 3 + 2) * Lp + kz;
+                            const C X = *px, Y = *py, Z = *pz;
+                            C Gl[6];
+                            if constexpr (VAR != 0) tensor_at(xo, kz, Gl);
+                            const C* Gi = VAR == 0 ? G[i] : Gl;
+                            *px = cadd(cadd(cmul(Gi[0], X), cmul(Gi[1], Y)), cmul(Gi[2], Z));
+                            *py = cadd(cadd(cmul(Gi[1], X), cmul(Gi[3], Y)), cmul(Gi[4], Z));
+                            *pz = cadd(cadd(cmul(Gi[2], X), cmul(Gi[4], Y)), cmul(Gi[5], Z));
+                        }
+                    }
+                }
+            } else {
+                for (int p = threadIdx.x; p < nxl * L; p += NT) {
+                    const int xo = p % nxl;
+                    const int kz = p / nxl;
+                    C Gi[6];
+                    tensor_at(xo, kz, Gi);
+                    C* px = lds + (xo * 3 + 0) * Lp + kz;
+                    C* py = lds + (xo * 3 + 1) * Lp + kz;
+                    C* pz = lds + (xo * 3 + 2) * Lp + kz;
+                    const C X = *px, Y = *py, Z = *pz;
+                    *px = cadd(cadd(cmul(Gi[0], X), cmul(Gi[1], Y)), cmul(Gi[2], Z));
+                    *py = cadd(cadd(cmul(Gi[1], X), cmul(Gi[3], Y)), cmul(Gi[4], Z));
+                    *pz = cadd(cadd(cmul(Gi[2], X), cmul(Gi[4], Y)), cmul(Gi[5], Z));
+                }
+            }
+            __syncthreads();
+            if constexpr (CT) {
+                if (hout) fft_lines_ct<T, 1, LC, NC * TXC, NT, false, true>(lds, tw64 + pl.tw);
+                else fft_lines_ct<T, 1, LC, NC * TXC, NT>(lds, tw64 + pl.tw);
+            } else {
+                fft_lines<T, 1>(lds, tws, nlines, Lp, pl);
+            }
+        } else {
+            if constexpr (CT) {
+                if (hin) fft_lines_ct<T, DIR, LC, NC * TXC, NT, true, false>(lds, tw64 + pl.tw);
+                else if (hout) fft_lines_ct<T, DIR, LC, NC * TXC, NT, false, true>(lds, tw64 + pl.tw);
+                else fft_lines_ct<T, DIR, LC, NC * TXC, NT>(lds, tw64 + pl.tw);
+            } else {
+                fft_lines<T, DIR>(lds, tws, nlines, Lp, pl);
+            }
+        }
+        const int tout = nlines * lout;
+        for (int idx = threadIdx.x; idx < tout; idx += NT) {
+            const int inner = idx % nlines;
+            const int e = idx / nlines;
+            if (inner < nval) gq[e * estride + inner] = lds[inner * Lp + e];
+        }
+        if (RHS_LOOP) __syncthreads();   // the next right-hand side refills the tile
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T, int MODE>
+void scatter_dispatch(int chk, const Geo& g, const SiteArgs& a, typename V2<T>::t* grid, const double2* tw,
+                      hipStream_t s) {
+    using C = typename V2<T>::t;
+    const int L = g.M[0];
+    const int XL = x_lines_per_tile(g, a.nrhs, sizeof(T) == 4);
+    dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
+    switch (L) {
+#define DDA_CASE(LL)                                                                                            \
+    case LL:                                                                                                   \
+        hipLaunchKernelGGL((k_scatter_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid, \
+                           tw, 1, chk);                                                                        \
+        return;
+        DDA_CT_LENGTHS(DDA_CASE)
+#undef DDA_CASE
+        default:
+            hipLaunchKernelGGL((k_scatter_x<T, MODE, 0, NT>), grd, dim3(NT), smem_rt<C>(L, 3 * XL), s, g, a, grid,
+                               tw, XL, chk);
+    }
+}
+
+template <typename T, int MODE>
+void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2<T>::t* grid, const double2* tw,
+                     hipStream_t s) {
+    using C = typename V2<T>::t;
+    const int L = g.M[0];
+    const int XL = x_lines_per_tile(g, a.nrhs, sizeof(T) == 4);
+    dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
+    switch (L) {
+#define DDA_CASE(LL)                                                                                            \
+    case LL:                                                                                                   \
+        hipLaunchKernelGGL((k_gather_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid,  \
+                           tw, 1, chk);                                                                        \
+        return;
+        DDA_CT_LENGTHS(DDA_CASE)
+#undef DDA_CASE
+        default:
+            hipLaunchKernelGGL((k_gather_x<T, MODE, 0, NT>), grd, dim3(NT), smem_rt<C>(L, 3 * XL), s, g, a, grid,
+                               tw, XL, chk);
+    }
+}
+
+// Compile-time variants of a strided pass: (tile width, VAR).  Index 0 is
+// the default; the autotuner of the C ABI picks among them by timing.
+constexpr int n_strided_variants(int gh) { return gh ? 5 : 3; }
+constexpr int variant_tx(int L, int gh, int v) {
+    const int base = ct_cols(L);
+    const int half = base > 1 ? base / 2 : 1;
+    const int dbl = (base < 16 && 3 * 2 * base * L <= 3072) ? base * 2 : base;
+    if (gh) return (v == 2 || v == 4) ? half : base;
+    return v == 1 ? half : (v == 2 ? dbl : base);
+}
+constexpr int variant_var(int gh, int v) {
+    if (!gh) return 0;
+    return v == 0 ? 0 : (v <= 2 ? 1 : 2);
+}
+
+template <typename T, int NC, int GH, int DIR, int LL, int V>
+void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
+                       typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
+                       const RhsState* st, hipStream_t s) {
+    using C = typename V2<T>::t;
+    constexpr int TX = variant_tx(LL, GH, V);
+    constexpr int VR = variant_var(GH, V);
+    const int gz = (GH && VR != 2) ? 1 : nrhs;
+    dim3 grd((g.M[0] + TX - 1) / TX, n_outer, gz);
+    hipLaunchKernelGGL((k_strided<T, NC, GH, DIR, LL, TX, VR>), grd, dim3(NT), smem_ct<C>(LL, NC * TX), s, g, grid,
+                       tw, ghat, st, nrhs, axis, TX, lin, lout, chk);
+}
+
+template <typename T, int NC, int GH, int DIR, int LL>
+void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
+                        typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
+                        const RhsState* st, hipStream_t s) {
+    switch (v) {
+        case 1: strided_ct_launch<T, NC, GH, DIR, LL, 1>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break;
+        case 2: strided_ct_launch<T, NC, GH, DIR, LL, 2>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break;
+        case 3:
+            if constexpr (GH) { strided_ct_launch<T, NC, GH, DIR, LL, 3>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break; }
+            [[fallthrough]];
+        case 4:
+            if constexpr (GH) { strided_ct_launch<T, NC, GH, DIR, LL, 4>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break; }
+            [[fallthrough]];
+        default: strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break;
+    }
+}
+
+template <typename T, int NC, int GH, int DIR>
+void strided_dispatch(int variant, int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
+                      typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
+                      hipStream_t s) {
+    using C = typename V2<T>::t;
+    const int L = g.M[axis];
+    if (NC == 3) {
+        switch (L) {
+#define DDA_CASE(LL)                                                                                       \
+    case LL:                                                                                              \
+        strided_ct_variant<T, NC, GH, DIR, LL>(variant, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, \
+                                               ghat, st, s);                                              \
+        return;
+            DDA_CT_LENGTHS(DDA_CASE)
+#undef DDA_CASE
+            default:
+                break;
+        }
+    }
+    const int TX = strided_cols_per_tile(L, NC, sizeof(T) == 4);
+    dim3 grd((g.M[0] + TX - 1) / TX, n_outer, GH ? 1 : nrhs);
+    hipLaunchKernelGGL((k_strided<T, NC, GH, DIR, 0>), grd, dim3(NT), smem_rt<C>(L, NC * TX), s, g, grid, tw, ghat,
+                       st, nrhs, axis, TX, lin, lout, chk);
+}
+
+}  // namespace passes
+
+// ------------------------------------------------------------------ entry points
+
+template <typename T>
+void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typename V2<T>::t* grid, const double2* tw,
+                      hipStream_t s) {
+    using namespace passes;
+    switch (mode) {
+        case SC_PLAIN: scatter_dispatch<T, SC_PLAIN>(chk, g, a, grid, tw, s); break;
+        case SC_CONJ: scatter_dispatch<T, SC_CONJ>(chk, g, a, grid, tw, s); break;
+        case SC_P: scatter_dispatch<T, SC_P>(chk, g, a, grid, tw, s); break;
+        default: scatter_dispatch<T, SC_S>(chk, g, a, grid, tw, s); break;
+    }
+}
+
+template <typename T>
+void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const typename V2<T>::t* grid,
+                     const double2* tw, hipStream_t s) {
+    using namespace passes;
+    switch (mode) {
+        case GA_PLAIN: gather_dispatch<T, GA_PLAIN>(chk, g, a, grid, tw, s); break;
+        case GA_CONJ: gather_dispatch<T, GA_CONJ>(chk, g, a, grid, tw, s); break;
+        case GA_V: gather_dispatch<T, GA_V>(chk, g, a, grid, tw, s); break;
+        case GA_T: gather_dispatch<T, GA_T>(chk, g, a, grid, tw, s); break;
+        default: gather_dispatch<T, GA_RES>(chk, g, a, grid, tw, s); break;
+    }
+}
+
+template <typename T>
+void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
+                    typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
+                    hipStream_t s, int variant) {
+    using namespace passes;
+    if (nc == 6) {
+        strided_dispatch<T, 6, 0, -1>(0, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+    } else if (ghat) {
+        strided_dispatch<T, 3, 1, -1>(variant, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+    } else if (dir < 0) {
+        strided_dispatch<T, 3, 0, -1>(variant, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+    } else {
+        strided_dispatch<T, 3, 0, 1>(variant, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+    }
+}
+
+static_assert(passes::n_strided_variants(1) == 5 && passes::n_strided_variants(0) == 3,
+              "strided_variants() in dda_kernels.h counts these variants");
+
+#define DDA_INSTANTIATE_PASSES(T)                                                                                 \
+    template void launch_scatter_x<T>(int, int, const Geo&, const SiteArgs&, V2<T>::t*, const double2*,           \
+                                      hipStream_t);                                                              \
+    template void launch_gather_x<T>(int, int, const Geo&, const SiteArgs&, const V2<T>::t*, const double2*,      \
+                                     hipStream_t);                                                               \
+    template void launch_strided<T>(int, int, int, const Geo&, int, int, int, int, int, V2<T>::t*, const double2*, \
+                                    const V2<T>::t*, const RhsState*, hipStream_t, int);
+
+}  // namespace dda

@@ -262,3 +262,14 @@ def test_adjoint_gradient_vs_dense(dda, weights):
     ref, _ = adjoint.gradient_dense(d["ijk"], d["m"], d["x"], kh, e0, *weights)
     assert adj["status"] == 0
     assert np.abs(g.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+def test_autotuned_variants_bitwise_equal_default(dda):
+    """Every compile-time tiling of the strided passes computes the same
+    numbers: the autotuned solve equals the default-tiling solve bitwise."""
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    base = dict(tol=1e-5, polarizability="GKDLDR")
+    P1, r1 = dda.solve(tgt, dda.Options.for_size_parameter(d["x"], autotune=True, **base), d["khat"], d["e0"])
+    P2, r2 = dda.solve(tgt, dda.Options.for_size_parameter(d["x"], autotune=False, **base), d["khat"], d["e0"])
+    assert torch.equal(P1, P2) and r1 == r2
