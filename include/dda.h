@@ -99,7 +99,9 @@ typedef struct {
     int32_t solver;          /* dda_solver */
     int32_t precision;       /* dda_precision */
     uint32_t flags;          /* DDA_FLAG_* */
-    int32_t reserved;
+    int32_t kernel_variant;  /* 0: automatic; v > 0 forces tiling variant v-1 of the
+                                strided FFT passes where it exists (for testing; every
+                                variant computes bitwise-identical results) */
 } dda_opts;
 
 typedef struct {
@@ -112,6 +114,8 @@ typedef struct {
     int32_t matvecs;                 /* FFT matrix-vector products in the iteration */
     int32_t status;                  /* dda_status of this right-hand side */
     int32_t restarts;                /* breakdown restarts taken (0 or 1) */
+    int32_t refinements;             /* FP64 residual refinements (DDA_FP32_MATVEC) */
+    int32_t reserved;
 } dda_result;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`

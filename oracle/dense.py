@@ -163,6 +163,28 @@ def assemble(ijk, alpha_inv_sites, k: float) -> np.ndarray:
     return blk.transpose(0, 2, 1, 3).reshape(3 * n, 3 * n)
 
 
+def apply_rows(ijk, alpha_inv_sites, k: float, x, rows) -> np.ndarray:
+    """(A x)_j for the listed sites j only, by the direct O(N) sum over l of
+    A_jl x_l (the definition of the product; used to check products of
+    targets far too large for a dense A).  Returns [len(rows), 3]."""
+    r = np.asarray(ijk, dtype=np.float64)
+    x = np.asarray(x, dtype=np.complex128)
+    a_inv = np.asarray(alpha_inv_sites, dtype=np.complex128)
+    out = np.zeros((len(rows), 3), dtype=np.complex128)
+    for i, j in enumerate(rows):
+        R = r[j] - r
+        dist = np.sqrt(np.sum(R * R, axis=1))
+        mask = dist > 0
+        R, dist, xl = R[mask], dist[mask], x[mask]
+        nhat = R / dist[:, None]
+        pref = np.exp(1j * k * dist) / dist
+        c_iso = pref * (-k * k - (1j * k * dist - 1.0) / dist ** 2)
+        c_nn = pref * (k * k + 3.0 * (1j * k * dist - 1.0) / dist ** 2)
+        ndotx = np.sum(nhat * xl, axis=1)
+        out[i] = np.sum(c_iso[:, None] * xl + (c_nn * ndotx)[:, None] * nhat, axis=0) + a_inv[j] * x[j]
+    return out
+
+
 def incident_field(ijk, k: float, khat, e0) -> np.ndarray:
     """E_inc at every site, [N, 3]: e exp(i k khat . r_j), with e = e0/|e0|
     ("Incident Polarization State": the library normalises e01).  Phase origin

@@ -47,7 +47,7 @@ class Opts(ctypes.Structure):
         ("solver", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("kernel_variant", ctypes.c_int32),
     ]
 
 
@@ -65,6 +65,8 @@ class Result(ctypes.Structure):
         ("matvecs", ctypes.c_int32),
         ("status", ctypes.c_int32),
         ("restarts", ctypes.c_int32),
+        ("refinements", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -73,6 +73,7 @@ class Options:
     recompute_green: bool = False
     final_checks: bool = True
     autotune: bool = True
+    kernel_variant: int = 0
 
     @classmethod
     def for_size_parameter(cls, x: float, **kw) -> "Options":
@@ -88,7 +89,8 @@ class Options:
         if not self.autotune:
             flags |= _abi.DDA_FLAG_NO_AUTOTUNE
         return _abi.Opts(self.wavelength, self.aeff, self.m_medium, self.tol, int(self.max_iter),
-                         _POLZ[self.polarizability], _abi.DDA_BICGSTAB, _PREC[self.precision], flags, 0)
+                         _POLZ[self.polarizability], _abi.DDA_BICGSTAB, _PREC[self.precision], flags,
+                         int(self.kernel_variant))
 
 
 def _incidences(khat, e0) -> ctypes.Array:
@@ -153,7 +155,7 @@ class Target:
 def _result_dict(r: _abi.Result) -> dict:
     return dict(qext=r.qext, qabs=r.qabs, qsca=r.qsca, qpha=r.qpha, rel_residual=r.rel_residual,
                 normal_eq_residual=r.normal_eq_residual, kd=r.kd, aeff_d=r.aeff_d, iters=r.iters,
-                matvecs=r.matvecs, status=r.status, restarts=r.restarts)
+                matvecs=r.matvecs, status=r.status, restarts=r.restarts, refinements=r.refinements)
 
 
 # ------------------------------------------------------------------ calls

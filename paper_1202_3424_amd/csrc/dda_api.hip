@@ -163,26 +163,39 @@ hipEvent_t take_event(dda_ctx* c) {
 }
 
 // Events around the launches issued in this scope, when timing is enabled.
+// The matvec-pass categories time their single kernel with the events of
+// hipExtLaunchKernelGGL (the kernel's own execution interval); the others
+// record the events on the stream around every launch in the scope.
 struct Timed {
     dda_ctx* c;
     int cat;
+    bool ext;
     hipEvent_t a = nullptr;
-    Timed(dda_ctx* c_, int cat_) : c(c_), cat(cat_) {
+    hipEvent_t b = nullptr;
+    Timed(dda_ctx* c_, int cat_) : c(c_), cat(cat_), ext(cat_ <= T_GATHER) {
         if (!(c->timing & (1 << cat))) return;
         a = take_event(c);
-        HIPCHK(hipEventRecord(a, c->stream));
+        if (ext) {
+            b = take_event(c);
+            launch_events() = LaunchEvents{a, b};
+        } else {
+            HIPCHK(hipEventRecord(a, c->stream));
+        }
     }
     ~Timed() {
         if (!a) return;
-        hipEvent_t b = nullptr;
-        if (!c->evpool.empty()) {
-            b = c->evpool.back();
-            c->evpool.pop_back();
-        } else if (hipEventCreate(&b) != hipSuccess) {
-            c->evpool.push_back(a);
-            return;
+        if (ext) {
+            launch_events() = LaunchEvents{};
+        } else {
+            if (!c->evpool.empty()) {
+                b = c->evpool.back();
+                c->evpool.pop_back();
+            } else if (hipEventCreate(&b) != hipSuccess) {
+                c->evpool.push_back(a);
+                return;
+            }
+            (void)hipEventRecord(b, c->stream);
         }
-        (void)hipEventRecord(b, c->stream);
         c->pending.push_back({cat, a, b});
     }
 };
@@ -216,6 +229,7 @@ void check_opts(const dda_opts* o) {
     if (o->polarizability != DDA_LATTDR && o->polarizability != DDA_GKDLDR) invalid("unknown polarizability");
     if (o->solver != DDA_BICGSTAB) invalid("unknown solver");
     if (o->precision != DDA_FP64 && o->precision != DDA_FP32_MATVEC) invalid("unknown precision");
+    if (o->kernel_variant < 0) invalid("kernel_variant must be >= 0");
 }
 
 // Normalised incidences packed for the device: khat [n][3], e0 [n][3].
@@ -284,8 +298,9 @@ struct Work {
         a.t = (double2*)(v + 5 * vbytes);
         a.b = (double2*)(v + 6 * vbytes);
         a.kd = kd;
-        const size_t cbytes = fp32 ? sizeof(float2) : sizeof(double2);
-        grid = c->grid.ensure((size_t)nrhs * g.npts * 3 * cbytes);
+        // FP64-sized even in the FP32-matvec mode: its residual refinement and
+        // final checks use FP64 products
+        grid = c->grid.ensure((size_t)nrhs * g.npts * 3 * sizeof(double2));
         a.st = (RhsState*)c->state.ensure((size_t)nrhs * sizeof(RhsState));
         // workgroups of every reducing kernel, per right-hand side
         pass_blocks = x_pass_blocks(g, nrhs, fp32);
@@ -318,7 +333,7 @@ struct Work {
         using C = typename V2<T>::t;
         const Geo& g = t->geo;
         C* gr = (C*)grid;
-        const C* gh = (const C*)(fp32 ? t->gh32.p : t->gh64.p);
+        const C* gh = (const C*)(sizeof(T) == 4 ? t->gh32.p : t->gh64.p);
         const double2* tw = (const double2*)t->tw.p;
         if (slot == 0)
             launch_strided<T>(1, -1, chk, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, c->stream, variant);
@@ -332,8 +347,15 @@ struct Work {
     // compile-time variant of each strided pass by timing every candidate on
     // the workspace grid (its contents are scratch at this point; all
     // variants compute bitwise-identical results).
-    void autotune(bool enabled) {
+    void autotune(bool enabled, int forced = 0) {
         const Geo& g = t->geo;
+        if (forced > 0) {
+            for (int slot = 0; slot < 3; ++slot) {
+                const int nv = strided_variants(g.M[slot == 1 ? 2 : 1], slot == 1);
+                var[slot] = forced - 1 < nv ? forced - 1 : 0;
+            }
+            return;
+        }
         auto key = std::make_tuple(g.M[0], g.M[1], g.M[2], g.n[0], g.n[1], g.n[2], nrhs, fp32 ? 1 : 0);
         auto it = c->tuned.find(key);
         if (it != c->tuned.end()) {
@@ -374,11 +396,11 @@ struct Work {
     }
 
     template <typename T>
-    void matvec_t(int sc, int ga, int chk_sc, int chk_rest) {
+    void matvec_t(int sc, int ga, int chk_sc, int chk_rest, const int* vars) {
         using C = typename V2<T>::t;
         const Geo& g = t->geo;
         C* gr = (C*)grid;
-        const C* gh = (const C*)(fp32 ? t->gh32.p : t->gh64.p);
+        const C* gh = (const C*)(sizeof(T) == 4 ? t->gh32.p : t->gh64.p);
         const double2* tw = (const double2*)t->tw.p;
         hipStream_t s = c->stream;
         {
@@ -391,15 +413,15 @@ struct Work {
         }
         {
             Timed tm(c, T_FFTY_FWD);
-            strided_slot<T>(0, chk_rest, var[0]);
+            strided_slot<T>(0, chk_rest, vars[0]);
         }
         {
             Timed tm(c, T_FFTZ_G);
-            strided_slot<T>(1, chk_rest, var[1]);
+            strided_slot<T>(1, chk_rest, vars[1]);
         }
         {
             Timed tm(c, T_FFTY_INV);
-            strided_slot<T>(2, chk_rest, var[2]);
+            strided_slot<T>(2, chk_rest, vars[2]);
         }
         {
             Timed tm(c, T_GATHER);
@@ -411,9 +433,11 @@ struct Work {
             launch_finalize(a, kind_of[ga], pass_blocks, s);
         }
     }
-    void matvec(int sc, int ga, int chk_sc, int chk_rest) {
-        if (fp32) matvec_t<float>(sc, ga, chk_sc, chk_rest);
-        else matvec_t<double>(sc, ga, chk_sc, chk_rest);
+    // fp64: force an FP64 product in the FP32-matvec mode (refinement, checks)
+    void matvec(int sc, int ga, int chk_sc, int chk_rest, bool fp64 = false) {
+        static const int defaults[3] = {0, 0, 0};
+        if (fp32 && !fp64) matvec_t<float>(sc, ga, chk_sc, chk_rest, var);
+        else matvec_t<double>(sc, ga, chk_sc, chk_rest, fp32 ? defaults : var);
         HIPCHK(hipGetLastError());
     }
 };
@@ -453,22 +477,10 @@ void fetch_state(dda_ctx* c, const Work& w) {
     flush_timing(c);
 }
 
-// BiCGSTAB on every right-hand side of w (b, ainv, state prepared); warm
-// start when x0_sorted != null (already in x).  Leaves P in w.a.x.
-void iterate(Work& w, const dda_opts* o, bool warm) {
+// BiCGSTAB iterations until no right-hand side is active (the device keeps
+// every scalar and status; the host polls once per chunk of iterations).
+void iterate_loop(Work& w, const dda_opts* o) {
     dda_ctx* c = w.c;
-    launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, c->stream);
-    if (warm) {
-        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE);  // r = b - A x0 (in = x)
-        Timed tm(c, T_KRYLOV);
-        launch_init_warm(w.a, w.site_blocks, c->stream);
-        launch_finalize(w.a, FIN_WARM, w.site_blocks, c->stream);
-    } else {
-        Timed tm(c, T_KRYLOV);
-        launch_init_cold(w.a, w.site_blocks, c->stream);
-        launch_finalize(w.a, FIN_COLD, w.site_blocks, c->stream);
-    }
-    HIPCHK(hipGetLastError());
     int launched = 0;
     const int chunk = std::min(8, o->max_iter);
     while (true) {
@@ -498,22 +510,60 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
     }
 }
 
+// BiCGSTAB on every right-hand side of w (b, ainv prepared); warm start when
+// x already holds P0.  In the FP32-matvec mode the recursive residual drifts
+// from the true one, so each converged right-hand side is checked with an
+// FP64 product r = b - A x and, if that misses the tolerance, the iteration
+// restarts from x with that residual (at most 5 refinements).  Leaves P in x.
+void iterate(Work& w, const dda_opts* o, bool warm) {
+    dda_ctx* c = w.c;
+    launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, c->stream);
+    if (warm) {
+        w.a.in = w.a.x;
+        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x0
+        Timed tm(c, T_KRYLOV);
+        launch_init_warm(w.a, w.site_blocks, c->stream);
+        launch_finalize(w.a, FIN_WARM, w.site_blocks, c->stream);
+    } else {
+        Timed tm(c, T_KRYLOV);
+        launch_init_cold(w.a, w.site_blocks, c->stream);
+        launch_finalize(w.a, FIN_COLD, w.site_blocks, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    iterate_loop(w, o);
+    if (!w.fp32) return;
+    for (int k = 0; k < 5; ++k) {
+        w.a.in = w.a.x;
+        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
+        {
+            Timed tm(c, T_KRYLOV);
+            launch_init_warm(w.a, w.site_blocks, c->stream);
+            launch_finalize(w.a, FIN_REFINE, w.site_blocks, c->stream);
+        }
+        fetch_state(c, w);
+        bool active = false;
+        for (int q = 0; q < w.nrhs; ++q) active |= c->host_state[q].status == ST_ACTIVE;
+        if (!active) break;
+        iterate_loop(w, o);
+    }
+}
+
 // true residual, eq. err_tol and the efficiency sums at x
 void final_checks(Work& w, bool normal_eq) {
     dda_ctx* c = w.c;
     SiteArgs& a = w.a;
     a.in = a.x;
-    w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE);  // r = b - A x, red[0] = |r|^2
+    w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x, red[0] = |r|^2
     if (normal_eq) {
         // A^H y = conj(A conj(y)) because A = A^T
         a.in = a.r;
         a.out = a.t;
         a.slot = 1;
-        w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE);
+        w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE, true);
         a.in = a.b;
         a.out = a.v;
         a.slot = 2;
-        w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE);
+        w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE, true);
     }
     {
         Timed tm(c, T_KRYLOV);
@@ -551,6 +601,7 @@ dda_status fill_results(const Work& w, bool normal_eq, dda_result* res) {
         r.iters = s.iters;
         r.matvecs = s.matvecs;
         r.restarts = s.restarts;
+        r.refinements = s.pad0;
         r.status = to_status(s.status);
         if (r.status != DDA_OK && (worst == DDA_OK || r.status > worst)) worst = (dda_status)r.status;
         if (res) res[q] = r;
@@ -596,7 +647,7 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     const bool fp32 = o->precision == DDA_FP32_MATVEC;
     ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
     Work w(c, t, nrhs, kd, fp32);
-    w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0);
+    w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
     w.upload_incidence(kh, e0);
     const bool warm = P0 != nullptr;
     {
@@ -809,7 +860,7 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, t, n_rhs, kd, fp32);
-        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0);
+        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
         launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)x, w.a.p, true, c->stream);
@@ -878,7 +929,7 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, t, 1, kd, fp32);
-        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0);
+        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
         double2* dainv = (double2*)c->dainv.ensure((size_t)t->nmat * 3 * sizeof(double2));

@@ -53,7 +53,8 @@ struct RhsState {
     int sconv;       // converged at the half step of the current iteration
     int max_iter;
     int restarts;
-    int pad0, pad1;
+    int pad0;        // FP64 residual refinements taken (FP32-matvec mode)
+    int pad1;
 };
 
 template <typename T> struct V2;

@@ -2,11 +2,32 @@
 // blocks they take.  Included by the kernels file and by the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "dda_device.h"
 
 namespace dda {
+
+// Start/stop events for the next matvec-pass launch on this thread: when
+// set, DDA_LAUNCH issues it with hipExtLaunchKernelGGL so that the events
+// carry the kernel's own execution timestamps, then clears them.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+LaunchEvents& launch_events();
+
+#define DDA_LAUNCH(kernel, grid, block, shmem, stream, ...)                                               \
+    do {                                                                                                \
+        ::dda::LaunchEvents& ev_ = ::dda::launch_events();                                              \
+        if (ev_.start) {                                                                                \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+            ev_ = ::dda::LaunchEvents{};                                                                \
+        } else {                                                                                        \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                        \
+        }                                                                                               \
+    } while (0)
 
 // Geometry of one target's FFT grid.
 //   n[a]  occupied bounding-box extent on axis a (x = first ijk index)
@@ -53,7 +74,7 @@ enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4 };
 // which right-hand sides a pass skips
 enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
 // what k_finalize makes of the partial sums of the kernel before it
-enum FinKind { FIN_S = 0, FIN_V, FIN_T, FIN_UPD, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ };
+enum FinKind { FIN_S = 0, FIN_V, FIN_T, FIN_UPD, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE };
 
 // FFT lengths with compile-time kernels (dda_passes.h)
 inline bool ct_length(int L) {
@@ -83,7 +104,7 @@ template <typename T>
 void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant = 0);
-inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 5 : 3) : 1; }
+inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 10 : 4) : 1; }
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);

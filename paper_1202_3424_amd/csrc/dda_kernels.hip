@@ -302,6 +302,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
         case FIN_S: case FIN_V: case FIN_UPD: run = st->status == ST_ACTIVE; break;
         case FIN_T: run = st->status == ST_ACTIVE && !st->sconv; break;
         case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
+        case FIN_REFINE: run = st->status == ST_CONVERGED; break;
         default: run = true; break;
     }
     if (!run) return;
@@ -383,6 +384,22 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             st->sconv = 0;
             st->restarts += 1;
             st->status = (acc[0] > 0.0 && isfinite(acc[0])) ? ST_ACTIVE : ST_BREAKDOWN;
+            break;
+        case FIN_REFINE:
+            // r holds the FP64 residual b - A x: keep converged or iterate on from x
+            st->matvecs += 1;
+            st->rnorm2 = acc[0];
+            if (!isfinite(acc[0])) {
+                st->status = ST_NONFINITE;
+            } else if (acc[0] > st->tol2 * st->bnorm2) {
+                st->rho = double2{acc[0], 0.0};
+                st->alpha = double2{1.0, 0.0};
+                st->omega = double2{1.0, 0.0};
+                st->beta = double2{0.0, 0.0};
+                st->sconv = 0;
+                st->pad0 += 1;
+                st->status = st->iters >= st->max_iter ? ST_MAXITER : ST_ACTIVE;
+            }
             break;
         case FIN_QSUM:
             st->red[3] = acc[0];
@@ -473,6 +490,11 @@ inline int blocks_for(long long n, int cap) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+LaunchEvents& launch_events() {
+    static thread_local LaunchEvents ev;
+    return ev;
+}
 
 int x_lines_per_tile(const Geo& g, int nrhs, bool fp32) {
     // compile-time lengths: one x-line (three components) per workgroup

@@ -436,6 +436,120 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
     }
 }
 
+// Pass 3 with the tensor read once per launch.  The workgroup owns octant
+// columns hx0 .. hx0+TX-1 of octant row hy and transforms, for every
+// right-hand side, the up to four column sets (hx or Mx-hx) x (hy or My-hy)
+// that share those tensor values; the values (with the z parity folded in)
+// stay in registers, the x and y parities are applied per column set.
+template <typename T, int LC, int TXC>
+__global__ __launch_bounds__(NT) void k_zfold(Geo g, typename V2<T>::t* grid, const double2* tw64,
+                                             const typename V2<T>::t* ghat, const RhsState* st, int nrhs, int lin,
+                                             int lout, int chk) {
+    using C = typename V2<T>::t;
+    constexpr int L = LC;
+    constexpr int TX = TXC;
+    constexpr int NL = 3 * TX;
+    constexpr int LP = L | 1;
+    constexpr int MAXP = (TX * L + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = (C*)smem;
+    const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
+    const int Hx = g.H[0], Hy = g.H[1];
+    const int hx0 = blockIdx.x * TX;
+    const int hy = blockIdx.y;
+    const double2* tw = tw64 + g.ax[2].tw;
+    C G[MAXP][6];
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) {
+        const int p = threadIdx.x + i * NT;
+        if (p < TX * L) {
+            const int xo = p % TX;
+            const int kz = p / TX;
+            const int hx = hx0 + xo;
+            if (hx < Hx) {
+                const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
+                const C* Gp = ghat + (((long long)fz * Hy + hy) * Hx + hx) * 6;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) G[i][c] = Gp[c];
+                if (kz > Mz / 2) {   // xz and yz are odd in z
+                    G[i][2].x = -G[i][2].x; G[i][2].y = -G[i][2].y;
+                    G[i][4].x = -G[i][4].x; G[i][4].y = -G[i][4].y;
+                }
+            }
+        }
+    }
+    const bool hin = ct_half_in_ok(LC) && 2 * lin <= L;
+    const bool hout = ct_half_out_ok(LC) && 2 * lout <= L;
+    const long long plane = (long long)My * Mx * 3;
+    for (int combo = 0; combo < 4; ++combo) {
+        const int mxf = combo & 1, myf = combo >> 1;
+        if (myf && !(hy >= 1 && 2 * hy != My)) continue;
+        const int ky = myf ? My - hy : hy;
+        auto col_ok = [&](int xo) {
+            const int hx = hx0 + xo;
+            return hx < Hx && (!mxf || (hx >= 1 && 2 * hx != Mx));
+        };
+        auto kx_of = [&](int xo) { return mxf ? Mx - (hx0 + xo) : hx0 + xo; };
+        bool any = false;
+#pragma unroll
+        for (int xo = 0; xo < TX; ++xo) any |= col_ok(xo);
+        if (!any) continue;
+        for (int q = 0; q < nrhs; ++q) {
+            if (skip_rhs(st + q, chk)) continue;
+            C* gq = grid + (long long)q * g.npts * 3 + (long long)ky * Mx * 3;
+            const int tin = NL * (hin ? L / 2 : L);
+            for (int idx = threadIdx.x; idx < tin; idx += NT) {
+                const int inner = idx % NL;
+                const int e = idx / NL;
+                const int xo = inner / 3, c = inner % 3;
+                C v;
+                if (e < lin && col_ok(xo)) {
+                    v = gq[e * plane + (long long)kx_of(xo) * 3 + c];
+                } else {
+                    v.x = 0;
+                    v.y = 0;
+                }
+                lds[inner * LP + e] = v;
+            }
+            __syncthreads();
+            if (hin) fft_lines_ct<T, -1, LC, NL, NT, true, false>(lds, tw);
+            else fft_lines_ct<T, -1, LC, NL, NT>(lds, tw);
+#pragma unroll
+            for (int i = 0; i < MAXP; ++i) {
+                const int p = threadIdx.x + i * NT;
+                if (p < TX * L) {
+                    const int xo = p % TX;
+                    const int kz = p / TX;
+                    if (col_ok(xo)) {
+                        C gxy = G[i][1], gxz = G[i][2], gyz = G[i][4];
+                        if (mxf != myf) { gxy.x = -gxy.x; gxy.y = -gxy.y; }
+                        if (mxf) { gxz.x = -gxz.x; gxz.y = -gxz.y; }
+                        if (myf) { gyz.x = -gyz.x; gyz.y = -gyz.y; }
+                        C* px = lds + (xo * 3 + 0) * LP + kz;
+                        C* py = lds + (xo * 3 + 1) * LP + kz;
+                        C* pz = lds + (xo * 3 + 2) * LP + kz;
+                        const C X = *px, Y = *py, Z = *pz;
+                        *px = cadd(cadd(cmul(G[i][0], X), cmul(gxy, Y)), cmul(gxz, Z));
+                        *py = cadd(cadd(cmul(gxy, X), cmul(G[i][3], Y)), cmul(gyz, Z));
+                        *pz = cadd(cadd(cmul(gxz, X), cmul(gyz, Y)), cmul(G[i][5], Z));
+                    }
+                }
+            }
+            __syncthreads();
+            if (hout) fft_lines_ct<T, 1, LC, NL, NT, false, true>(lds, tw);
+            else fft_lines_ct<T, 1, LC, NL, NT>(lds, tw);
+            const int tout = NL * lout;
+            for (int idx = threadIdx.x; idx < tout; idx += NT) {
+                const int inner = idx % NL;
+                const int e = idx / NL;
+                const int xo = inner / 3, c = inner % 3;
+                if (col_ok(xo)) gq[e * plane + (long long)kx_of(xo) * 3 + c] = lds[inner * LP + e];
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename T, int MODE>
@@ -448,13 +562,13 @@ void scatter_dispatch(int chk, const Geo& g, const SiteArgs& a, typename V2<T>::
     switch (L) {
 #define DDA_CASE(LL)                                                                                            \
     case LL:                                                                                                   \
-        hipLaunchKernelGGL((k_scatter_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid, \
+        DDA_LAUNCH((k_scatter_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid, \
                            tw, 1, chk);                                                                        \
         return;
         DDA_CT_LENGTHS(DDA_CASE)
 #undef DDA_CASE
         default:
-            hipLaunchKernelGGL((k_scatter_x<T, MODE, 0, NT>), grd, dim3(NT), smem_rt<C>(L, 3 * XL), s, g, a, grid,
+            DDA_LAUNCH((k_scatter_x<T, MODE, 0, NT>), grd, dim3(NT), smem_rt<C>(L, 3 * XL), s, g, a, grid,
                                tw, XL, chk);
     }
 }
@@ -469,29 +583,48 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
     switch (L) {
 #define DDA_CASE(LL)                                                                                            \
     case LL:                                                                                                   \
-        hipLaunchKernelGGL((k_gather_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid,  \
+        DDA_LAUNCH((k_gather_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid,  \
                            tw, 1, chk);                                                                        \
         return;
         DDA_CT_LENGTHS(DDA_CASE)
 #undef DDA_CASE
         default:
-            hipLaunchKernelGGL((k_gather_x<T, MODE, 0, NT>), grd, dim3(NT), smem_rt<C>(L, 3 * XL), s, g, a, grid,
+            DDA_LAUNCH((k_gather_x<T, MODE, 0, NT>), grd, dim3(NT), smem_rt<C>(L, 3 * XL), s, g, a, grid,
                                tw, XL, chk);
     }
 }
 
 // Compile-time variants of a strided pass: (tile width, VAR).  Index 0 is
-// the default; the autotuner of the C ABI picks among them by timing.
-constexpr int n_strided_variants(int gh) { return gh ? 5 : 3; }
-constexpr int variant_tx(int L, int gh, int v) {
+// the default; the autotuner of the C ABI picks among them by timing.  Wider
+// tiles give longer contiguous runs per plane (what large grids need); they
+// are bounded by an LDS budget of 48 KB of tile per workgroup.
+constexpr int n_strided_variants(int gh) { return gh ? 10 : 4; }
+template <typename T> constexpr int ct_budget() { return sizeof(T) == 4 ? 6144 : 3072; }
+template <typename T> constexpr int variant_tx(int L, int gh, int v) {
     const int base = ct_cols(L);
     const int half = base > 1 ? base / 2 : 1;
-    const int dbl = (base < 16 && 3 * 2 * base * L <= 3072) ? base * 2 : base;
-    if (gh) return (v == 2 || v == 4) ? half : base;
-    return v == 1 ? half : (v == 2 ? dbl : base);
+    const int dbl = (2 * base <= 32 && 3 * 2 * base * L <= ct_budget<T>()) ? 2 * base : base;
+    const int quad = (4 * base <= 32 && 3 * 4 * base * L <= ct_budget<T>()) ? 4 * base : dbl;
+    if (gh) {
+        switch (v) {
+            case 2: case 4: case 8: return half;
+            case 5: return dbl;
+            case 6: return quad;
+            case 9: return half > 1 ? half / 2 : 1;
+            default: return base;
+        }
+    }
+    switch (v) {
+        case 1: return half;
+        case 2: return dbl;
+        case 3: return quad;
+        default: return base;
+    }
 }
+// VAR 3: the octant-folded kernel k_zfold
 constexpr int variant_var(int gh, int v) {
     if (!gh) return 0;
+    if (v >= 7) return 3;
     return v == 0 ? 0 : (v <= 2 ? 1 : 2);
 }
 
@@ -500,12 +633,18 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                        typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
                        const RhsState* st, hipStream_t s) {
     using C = typename V2<T>::t;
-    constexpr int TX = variant_tx(LL, GH, V);
+    constexpr int TX = variant_tx<T>(LL, GH, V);
     constexpr int VR = variant_var(GH, V);
-    const int gz = (GH && VR != 2) ? 1 : nrhs;
-    dim3 grd((g.M[0] + TX - 1) / TX, n_outer, gz);
-    hipLaunchKernelGGL((k_strided<T, NC, GH, DIR, LL, TX, VR>), grd, dim3(NT), smem_ct<C>(LL, NC * TX), s, g, grid,
-                       tw, ghat, st, nrhs, axis, TX, lin, lout, chk);
+    if constexpr (VR == 3) {
+        dim3 grd((g.H[0] + TX - 1) / TX, g.H[1], 1);
+        DDA_LAUNCH((k_zfold<T, LL, TX>), grd, dim3(NT), smem_ct<C>(LL, 3 * TX), s, g, grid, tw, ghat, st, nrhs, lin,
+                   lout, chk);
+    } else {
+        const int gz = (GH && VR != 2) ? 1 : nrhs;
+        dim3 grd((g.M[0] + TX - 1) / TX, n_outer, gz);
+        DDA_LAUNCH((k_strided<T, NC, GH, DIR, LL, TX, VR>), grd, dim3(NT), smem_ct<C>(LL, NC * TX), s, g, grid, tw,
+                   ghat, st, nrhs, axis, TX, lin, lout, chk);
+    }
 }
 
 template <typename T, int NC, int GH, int DIR, int LL>
@@ -513,16 +652,19 @@ void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_
                         typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
                         const RhsState* st, hipStream_t s) {
     switch (v) {
-        case 1: strided_ct_launch<T, NC, GH, DIR, LL, 1>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break;
-        case 2: strided_ct_launch<T, NC, GH, DIR, LL, 2>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break;
-        case 3:
-            if constexpr (GH) { strided_ct_launch<T, NC, GH, DIR, LL, 3>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break; }
-            [[fallthrough]];
-        case 4:
-            if constexpr (GH) { strided_ct_launch<T, NC, GH, DIR, LL, 4>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break; }
-            [[fallthrough]];
-        default: strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); break;
+#define DDA_V(VV)                                                                                             \
+    case VV:                                                                                                 \
+        if constexpr (VV < n_strided_variants(GH)) {                                                         \
+            strided_ct_launch<T, NC, GH, DIR, LL, VV>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s); \
+            return;                                                                                          \
+        }                                                                                                    \
+        break;
+        DDA_V(1) DDA_V(2) DDA_V(3) DDA_V(4) DDA_V(5) DDA_V(6) DDA_V(7) DDA_V(8) DDA_V(9)
+#undef DDA_V
+        default:
+            break;
     }
+    strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
 }
 
 template <typename T, int NC, int GH, int DIR>
@@ -546,7 +688,7 @@ void strided_dispatch(int variant, int axis, int chk, const Geo& g, int nrhs, in
     }
     const int TX = strided_cols_per_tile(L, NC, sizeof(T) == 4);
     dim3 grd((g.M[0] + TX - 1) / TX, n_outer, GH ? 1 : nrhs);
-    hipLaunchKernelGGL((k_strided<T, NC, GH, DIR, 0>), grd, dim3(NT), smem_rt<C>(L, NC * TX), s, g, grid, tw, ghat,
+    DDA_LAUNCH((k_strided<T, NC, GH, DIR, 0>), grd, dim3(NT), smem_rt<C>(L, NC * TX), s, g, grid, tw, ghat,
                        st, nrhs, axis, TX, lin, lout, chk);
 }
 
@@ -595,7 +737,7 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
     }
 }
 
-static_assert(passes::n_strided_variants(1) == 5 && passes::n_strided_variants(0) == 3,
+static_assert(passes::n_strided_variants(1) == 10 && passes::n_strided_variants(0) == 4,
               "strided_variants() in dda_kernels.h counts these variants");
 
 #define DDA_INSTANTIATE_PASSES(T)                                                                                 \

@@ -273,3 +273,73 @@ def test_autotuned_variants_bitwise_equal_default(dda):
     P1, r1 = dda.solve(tgt, dda.Options.for_size_parameter(d["x"], autotune=True, **base), d["khat"], d["e0"])
     P2, r2 = dda.solve(tgt, dda.Options.for_size_parameter(d["x"], autotune=False, **base), d["khat"], d["e0"])
     assert torch.equal(P1, P2) and r1 == r2
+
+
+# ------------------------------------------------------------------ mixed precision
+
+def test_mixed_precision_matches_fp64_solve(dda):
+    """FP32 FFT matvec with FP64 recurrences and FP64 residual refinement:
+    the true (FP64) residual meets the tolerance and Q agrees with the FP64
+    solve to 1e-4."""
+    ijk = w.box_sphere(48, 24.0)
+    m = np.full(len(ijk), 1.33 + 0.01j)
+    tgt = dda.Target(ijk, m)
+    kh, e0 = w.along_x_yz()
+    o64 = dda.Options.for_size_parameter(8.0, tol=1e-5)
+    o32 = dda.Options.for_size_parameter(8.0, tol=1e-5, precision="fp32_matvec")
+    _, r64 = dda.solve(tgt, o64, kh, e0, want_P=False)
+    _, r32 = dda.solve(tgt, o32, kh, e0, want_P=False)
+    for a, b in zip(r32, r64):
+        assert a["status"] == 0 and a["rel_residual"] < 1e-5, a
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(a[key] - b[key]) <= 1e-4 * abs(b[key]), (key, a[key], b[key])
+
+
+def test_sphere1m_full_size(dda):
+    """The 1,099,136-site sphere on its 256^3 grid: sampled rows of A x in FP64
+    and FP32 against the oracle's direct sums; the FP32-matvec solve against
+    the FP64 solve (1e-4) and Mie theory (the DDA error bound per quantity)."""
+    d = w.workload("sphere1m")
+    n = len(d["ijk"])
+    tgt = dda.Target(d["ijk"], d["m"])
+    assert tgt.grid == (256, 256, 256)
+    k = dense.kd_from_size_parameter(d["x"], n)
+    ainv = dense.site_alpha_inverse(d["m"], k, d["khat"][0], d["e0"][0])
+    xv = w.random_vectors(8, (1, n, 3))
+    rows = np.random.default_rng(1).choice(n, 12, replace=False)
+    ref = dense.apply_rows(d["ijk"], ainv, k, xv[0], rows)
+    for prec, tol in (("fp64", 1e-12), ("fp32_matvec", 2e-5)):
+        o = dda.Options.for_size_parameter(d["x"], precision=prec)
+        y = dda.apply(tgt, o, d["khat"][:1], d["e0"][:1], _cuda(xv)).cpu().numpy()[0]
+        assert np.abs(y[rows] - ref).max() <= tol * np.abs(ref).max(), prec
+    o64 = dda.Options.for_size_parameter(d["x"], tol=1e-5)
+    o32 = dda.Options.for_size_parameter(d["x"], tol=1e-5, precision="fp32_matvec")
+    _, r64 = dda.solve(tgt, o64, d["khat"], d["e0"], want_P=False)
+    _, r32 = dda.solve(tgt, o32, d["khat"], d["e0"], want_P=False)
+    q_mie = mie.efficiencies(1.33 + 0.01j, d["x"])
+    for a, b in zip(r32, r64):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["rel_residual"] < 1e-5 and b["rel_residual"] < 1e-5
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(a[key] - b[key]) <= 1e-4 * abs(b[key]), (key, a[key], b[key])
+        assert abs(b["qext"] / q_mie["qext"] - 1) < 0.05
+        assert abs(b["qsca"] / q_mie["qsca"] - 1) < 0.05
+        assert abs(b["qabs"] / q_mie["qabs"] - 1) < 0.10
+
+
+@pytest.mark.parametrize("variant", range(1, 11))
+def test_every_tiling_variant_bitwise(dda, variant):
+    """Each compile-time tiling of the strided passes (including the
+    octant-folded z pass) gives the default tiling's product bitwise, on a
+    grid with odd x and y extents (mirror columns without partners) and two
+    right-hand sides."""
+    ijk = np.unique(np.random.default_rng(9).integers(0, [13, 14, 32], size=(2500, 3)), axis=0).astype(np.int32)
+    tgt = dda.Target(ijk, np.full(len(ijk), 1.4 + 0.1j))
+    assert tgt.grid == (25, 27, 64)
+    kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
+    e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
+    xv = _cuda(w.random_vectors(6, (2, len(ijk), 3)))
+    for prec in ("fp64", "fp32_matvec"):
+        ref = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=1), kh, e0, xv)
+        y = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=variant), kh, e0, xv)
+        assert torch.equal(y, ref), (prec, variant)

@@ -321,3 +321,15 @@ def test_workload_sizes():
     assert len(w.workload("sphere389")["ijk"]) == 389
     assert len(w.workload("ellipsoid51k")["ijk"]) == 51488
     assert len(w.box_sphere(128, 64.0)) == 1099136
+
+
+def test_apply_rows_matches_dense():
+    """The O(N)-per-row product equals rows of the dense product."""
+    ijk = np.unique(np.random.default_rng(4).integers(-4, 5, size=(120, 3)), axis=0)
+    k = 0.45
+    ainv = dense.site_alpha_inverse(np.full(len(ijk), 1.5 + 0.2j), k, [0, 1, 0], [1, 0, 0])
+    A = dense.assemble(ijk, ainv, k)
+    x = w.random_vectors(2, (len(ijk), 3))
+    rows = [0, 7, len(ijk) - 1]
+    ref = (A @ x.reshape(-1)).reshape(-1, 3)[rows]
+    assert np.abs(dense.apply_rows(ijk, ainv, k, x, rows) - ref).max() < 1e-12 * np.abs(ref).max()
