@@ -156,6 +156,20 @@ dda_status dda_apply(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t 
 dda_status dda_solve(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
                      const dda_incidence* inc, dda_c64* P, const dda_c64* P0, dda_result* res);
 
+/* Solve A x = b for caller-given right-hand sides (the system of "Choice of
+ * Iterative Algorithm" with any b, e.g. the localized right-hand side of a
+ * perturbed site).  A is the matrix of the given incidences (1/alpha depends
+ * on them through LATTDR/GKDLDR).
+ *   b   device [n_rhs][n_sites][3], caller order (not modified);
+ *   x   device output of the same shape;
+ *   x0  device warm start or NULL;
+ *   res host [n_rhs]: residuals, iterations and status; the efficiency fields
+ *       are zero (b is not an incident field).
+ * Returns the worst per-right-hand-side status, as dda_solve. */
+dda_status dda_solve_rhs(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
+                         const dda_incidence* inc, const dda_c64* b, dda_c64* x, const dda_c64* x0,
+                         dda_result* res);
+
 /* Solve several targets, each with its own right-hand sides, in one call.
  *   targets[n_targets], opts[n_targets];
  *   rhs_target[n_rhs] gives the target index of each right-hand side,

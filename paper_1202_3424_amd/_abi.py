@@ -81,6 +81,8 @@ SIGNATURES = {
     "dda_apply": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP]),
     "dda_solve": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP,
                                  ctypes.POINTER(Result)]),
+    "dda_solve_rhs": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP,
+                                     VP, ctypes.POINTER(Result)]),
     "dda_solve_batched": (ctypes.c_int, [VP, ctypes.c_int32, VP, ctypes.POINTER(Opts), ctypes.c_int32, VP,
                                          ctypes.POINTER(Incidence), VP, ctypes.POINTER(Result)]),
     "dda_grad_eps": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.POINTER(Incidence), VP, ctypes.c_double,

@@ -187,6 +187,23 @@ def solve(target: Target, opts: Options, khat, e0, P0: torch.Tensor | None = Non
     return P, [_result_dict(r) for r in res]
 
 
+def solve_rhs(target: Target, opts: Options, khat, e0, b: torch.Tensor, x0: torch.Tensor | None = None):
+    """Solve A x = b for caller-given right-hand sides (complex128 CUDA
+    [n_rhs, N, 3]); A is the matrix of the given incidences.  Returns (x,
+    [result dict]) (the efficiency fields are zero)."""
+    inc = _incidences(khat, e0)
+    n = len(inc)
+    b = _dev_c128(b, (n, target.n_sites, 3), "b")
+    x = torch.empty_like(b)
+    p0 = _dev_c128(x0, (n, target.n_sites, 3), "x0") if x0 is not None else None
+    res = (_abi.Result * n)()
+    o = opts.c()
+    st = _lib.dda_solve_rhs(target.ctx, target.handle, ctypes.byref(o), n, inc, b.data_ptr(), x.data_ptr(),
+                            p0.data_ptr() if p0 is not None else None, res)
+    _check(st, "dda_solve_rhs", (_abi.DDA_E_NOT_CONVERGED, _abi.DDA_E_BREAKDOWN, _abi.DDA_E_NONFINITE))
+    return x, [_result_dict(r) for r in res]
+
+
 def solve_batched(targets, opts, rhs_target, khat, e0, want_P: bool = True):
     """Several targets, each with its own right-hand sides, in one call.
     ``opts`` is one Options per target.  Returns ([P per rhs], [result dict])."""

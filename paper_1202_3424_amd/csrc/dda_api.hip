@@ -635,9 +635,11 @@ template <typename F> dda_status guarded(F&& f) {
 }
 
 // One batched solve on one target: Q's in res, P (caller order) to P_out
-// (contiguous [nrhs][n][3]) or per-right-hand-side pointers.
+// (contiguous [nrhs][n][3]) or per-right-hand-side pointers.  With b_caller
+// the right-hand sides are the caller's b instead of E_inc (no efficiencies).
 dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, const dda_incidence* inc,
-                     dda_c64* P, dda_c64* const* Pper, const dda_c64* P0, dda_result* res) {
+                     dda_c64* P, dda_c64* const* Pper, const dda_c64* P0, dda_result* res,
+                     const dda_c64* b_caller = nullptr) {
     check_opts(o);
     if (nrhs < 1) invalid("n_rhs must be >= 1");
     std::vector<double> kh;
@@ -653,7 +655,11 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     {
         Timed tm(c, T_SETUP);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
-        launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
+        if (b_caller)
+            launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)b_caller, w.a.b, true,
+                           c->stream);
+        else
+            launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
         if (warm)
             launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P0, w.a.x, true, c->stream);
     }
@@ -674,6 +680,9 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     HIPCHK(hipGetLastError());
     fetch_state(c, w);
     dda_status st = fill_results(w, ne, res);
+    if (b_caller && res) {
+        for (int q = 0; q < nrhs; ++q) res[q].qext = res[q].qabs = res[q].qsca = res[q].qpha = 0.0;
+    }
     if (st == DDA_OK) warn_validity(t, kd, o->m_medium);
     return st;
 }
@@ -879,6 +888,16 @@ dda_status dda_solve(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         if (!c || !t) invalid("NULL ctx or target");
         Scope sc(c);
         return solve_one(c, t, o, n_rhs, inc, P, nullptr, P0, res);
+    });
+}
+
+dda_status dda_solve_rhs(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs, const dda_incidence* inc,
+                         const dda_c64* b, dda_c64* x, const dda_c64* x0, dda_result* res) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !b || !x) invalid("NULL argument");
+        if ((const void*)b == (const void*)x) invalid("b and x alias");
+        Scope sc(c);
+        return solve_one(c, t, o, n_rhs, inc, x, nullptr, x0, res, b);
     });
 }
 

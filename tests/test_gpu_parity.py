@@ -343,3 +343,87 @@ def test_every_tiling_variant_bitwise(dda, variant):
         ref = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=1), kh, e0, xv)
         y = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=variant), kh, e0, xv)
         assert torch.equal(y, ref), (prec, variant)
+
+
+# ------------------------------------------------------------------ adjoint at full size
+
+def _dq_difference(P, dP, E, w_sites, w_site_new, j, cq, wq):
+    """Exact change of w_abs Q_abs + w_ext Q_ext when site j's 1/alpha changes
+    and P -> P + dP (the algebraic difference of the oracle's formulas)."""
+    w_abs, w_ext = wq
+    Pn = P + dP
+    d_abs = np.sum(w_sites * (2 * np.real(np.conj(P) * dP) + np.abs(dP) ** 2))
+    d_abs += np.sum((w_site_new - w_sites[j]) * np.abs(Pn[j]) ** 2)
+    d_ext = np.sum(np.imag(np.conj(E) * dP))
+    return cq * (w_abs * d_abs + w_ext * d_ext)
+
+
+def test_adjoint_gradient_40cubed_vs_finite_differences(dda):
+    """The 40^3 two-material target (N = 64,000): the adjoint gradient of
+    Q_abs + 0.5 Q_ext with respect to eps_j against central differences on
+    the 20 seeded sites.  Each difference solves the perturbed system for the
+    change dP with the localized right-hand side -dA_j P (the difference
+    formulation), so the finite difference is not swamped by solver error."""
+    d = w.workload("twomat40")
+    ijk, m = d["ijk"], d["m"]
+    kh, e0 = d["khat"][0], d["e0"][0]
+    n = len(ijk)
+    wq = (1.0, 0.5)
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-11)
+    tgt = dda.Target(ijk, m)
+    P, _ = dda.solve(tgt, opts, [kh], [e0])
+    g, adj = dda.grad_eps(tgt, opts, kh, e0, P[0], *wq)
+    assert adj["status"] == 0
+    g = g.cpu().numpy()
+    Pn = P[0].cpu().numpy()
+    k = dense.kd_from_size_parameter(d["x"], n)
+    cq = dense.q_prefactor(k, n)
+    ainv = dense.site_alpha_inverse(m, k, kh, e0)
+    w_sites = -np.imag(ainv) - (2.0 / 3.0) * k ** 3
+    E = dense.incident_field(ijk, k, kh, e0)
+    eps = np.asarray(m) ** 2
+    for j in w.fd_sites(0):
+        h = 1e-3 * abs(eps[j])
+        dq = []
+        for step in (h, -h, 1j * h, -1j * h):
+            m_new = m.copy()
+            m_new[j] = np.sqrt(eps[j] + step)
+            ainv_j = dense.alpha_inverse(m_new[j], k, kh, e0)
+            b = np.zeros((1, n, 3), dtype=np.complex128)
+            b[0, j] = -(ainv_j - ainv[j]) * Pn[j]
+            dP, r = dda.solve_rhs(dda.Target(ijk, m_new), opts, [kh], [e0], _cuda(b))
+            assert r[0]["status"] == 0
+            w_new = -np.imag(ainv_j) - (2.0 / 3.0) * k ** 3
+            dq.append(_dq_difference(Pn, dP.cpu().numpy()[0], E, w_sites, w_new, j, cq, wq))
+        fd = (dq[0] - dq[1]) / (2 * h) + 1j * (dq[2] - dq[3]) / (2 * h)
+        assert abs(g[j] - fd) <= 1e-5 * np.abs(g).max() + 1e-6 * abs(fd), (j, g[j], fd)
+
+
+def test_adjoint_gradient_40cubed_fp32_matvec(dda):
+    """The FP32-matvec variant of the adjoint gradient against the FP64 one."""
+    d = w.workload("twomat40")
+    kh, e0 = d["khat"][0], d["e0"][0]
+    tgt = dda.Target(d["ijk"], d["m"])
+    grads = []
+    for prec in ("fp64", "fp32_matvec"):
+        opts = dda.Options.for_size_parameter(d["x"], tol=1e-6, precision=prec)
+        P, _ = dda.solve(tgt, opts, [kh], [e0])
+        g, adj = dda.grad_eps(tgt, opts, kh, e0, P[0], 1.0, 0.0)
+        assert adj["status"] == 0
+        grads.append(g.cpu().numpy())
+    assert np.abs(grads[1] - grads[0]).max() <= 1e-4 * np.abs(grads[0]).max()
+
+
+def test_qeff_autograd_function(dda):
+    """QEff (torch.autograd.Function) on the 6^3 two-material target: the
+    values and the gradient of Q_abs + 0.3 Q_ext against the dense oracle."""
+    d = w.workload("twomat6")
+    kh, e0 = d["khat"][0], d["e0"][0]
+    eps = torch.tensor(np.asarray(d["m"]) ** 2, dtype=torch.complex128, device="cuda", requires_grad=True)
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-11)
+    q = dda.QEff.apply(eps, d["ijk"], opts, kh, e0)
+    (q[0] + 0.3 * q[1]).backward()
+    ref, sol = adjoint.gradient_dense(d["ijk"], d["m"], d["x"], kh, e0, 1.0, 0.3)
+    assert abs(q[0].item() - sol["qabs"]) <= 1e-8 * sol["qabs"]
+    assert abs(q[1].item() - sol["qext"]) <= 1e-8 * sol["qext"]
+    assert np.abs(eps.grad.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
