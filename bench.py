@@ -2,11 +2,12 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ellipsoid51k]
 
-A step is one whole solve of one target orientation (both polarizations,
-batched as two right-hand sides): interaction-tensor sampling and FFT,
+A step is one whole solve of a workload's right-hand sides (an orientation
+is two of them, the two polarizations): interaction-tensor sampling and FFT,
 polarizabilities, incident field, BiCGSTAB to the tolerance, the true and
-normal-equation residual checks and the efficiencies.  Inputs are synthetic
-(seeded lattice targets); nothing is cached between steps.
+normal-equation residual checks and the efficiencies.  Multi-target
+workloads go through one batched call.  Inputs are synthetic (seeded lattice
+targets); nothing is cached between steps.
 
 Prints one JSON line: the metric value is seconds per orientation; the
 ``roofline`` object reports the dominant kernel's algorithmic HBM bytes per
@@ -39,7 +40,29 @@ WORKLOADS = {
                  "fp64"),
     "sphere1m": ("sphere of radius 64 in a 128^3 box (N=1099136), m=1.33+0.01i, x=20, LATTDR, BiCGSTAB to 1e-5, "
                  "FFT grid 256^3", "fp64"),
+    "brick48": ("48x24x16 brick (N=18432), m=1.6+0.1i, x=4, 64 random orientations x 2 polarizations = 128 "
+                "right-hand sides in one solve, BiCGSTAB to 1e-5, FFT grid 96x48x32", "fp64"),
+    "config3": ("the 48x24x16 brick at 64 orientations x 2 polarizations plus 32 integer-site spheres with radii "
+                "U(6,20) (x=4, m=1.33+0.01i) x 2 polarizations, one batched call, BiCGSTAB to 1e-5", "fp64"),
 }
+
+
+def build_jobs(dda, w, name, seed, prec):
+    """[(target, options, khat, e0)] of a workload, and orientations per step."""
+    if name == "config3":
+        d = w.workload("brick48", seed)
+        kh_s, e0_s = w.along_x_yz()
+        jobs = [(dda.Target(d["ijk"], d["m"]),
+                 dda.Options.for_size_parameter(d["x"], tol=d["tol"], precision=prec, recompute_green=True),
+                 d["khat"], d["e0"])]
+        for s_ijk in w.sphere_batch(seed):
+            jobs.append((dda.Target(s_ijk, 1.33 + 0.01j),
+                         dda.Options.for_size_parameter(4.0, tol=1e-5, precision=prec, recompute_green=True),
+                         kh_s, e0_s))
+        return jobs, 64 + 32, d
+    d = w.workload(name, seed)
+    opts = dda.Options.for_size_parameter(d["x"], tol=d["tol"], precision=prec, recompute_green=True)
+    return [(dda.Target(d["ijk"], d["m"]), opts, d["khat"], d["e0"])], len(d["khat"]) / 2.0, d
 
 
 PASSES = ["scatter_fft_x", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x_gather"]
@@ -91,23 +114,42 @@ def load_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(d: dict, workload: str) -> dict:
-    """The oracle (FFT-BiCGSTAB, FP64) on one of the two polarizations."""
+def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
+    """The oracle (FFT-BiCGSTAB, FP64) on the first right-hand side of the
+    workload, scaled to seconds per orientation (two polarizations).  Targets
+    above 300k dipoles run a bounded number of iterations instead: two runs of
+    2 and 4 iterations give the set-up and per-iteration cost, extrapolated to
+    the iteration count the GPU solve needed for the same right-hand side."""
     workers = min(os.cpu_count() or 1, len(os.sched_getaffinity(0)), 16)
     os.environ["DDA_ORACLE_FFT_WORKERS"] = str(workers)
     import importlib
 
     from oracle import fftsolve
     importlib.reload(fftsolve)
-    t0 = time.perf_counter()
-    r = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], tol=d["tol"])
-    dt = time.perf_counter() - t0
-    n_pol = len(d["khat"])
-    return {"value": dt * n_pol, "unit": "s/orientation", "cores": workers, "kind": "oracle",
-            "sample": f"{workload}: polarization 1 of {n_pol} solved by the CPU oracle (scipy.fft FFT-BiCGSTAB, "
-                      f"FP64, tol {d['tol']:g}, {r['iters']} iterations, {r['matvecs']} matvecs) in {dt:.2f} s; "
-                      f"value = {n_pol} x that time",
-            "qext": r["qext"], "qabs": r["qabs"]}
+
+    def run(max_iter):
+        t0 = time.perf_counter()
+        r = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], tol=d["tol"],
+                                max_iter=max_iter)
+        return time.perf_counter() - t0, r
+
+    if len(d["ijk"]) <= 300_000:
+        dt, r = run(1000)
+        return {"value": 2 * dt, "unit": "s/orientation", "cores": workers, "kind": "oracle",
+                "sample": f"{workload}: the first right-hand side solved by the CPU oracle (scipy.fft FFT-BiCGSTAB, "
+                          f"FP64, tol {d['tol']:g}, {r['iters']} iterations, {r['matvecs']} matvecs) in {dt:.2f} s; "
+                          f"value = 2 polarizations x that time",
+                "qext": r["qext"], "qabs": r["qabs"]}
+    t2, _ = run(2)
+    t4, _ = run(4)
+    per_iter = (t4 - t2) / 2
+    setup = t2 - 2 * per_iter
+    est = setup + per_iter * gpu_iters
+    return {"value": 2 * est, "unit": "s/orientation", "cores": workers, "kind": "oracle",
+            "sample": f"{workload}: CPU oracle (scipy.fft FFT-BiCGSTAB, FP64) on the first right-hand side, run for "
+                      f"2 and 4 iterations ({t2:.1f} s, {t4:.1f} s): set-up {setup:.2f} s + {per_iter:.2f} s/iteration "
+                      f"x {gpu_iters} iterations (the GPU solve's count at tol {d['tol']:g}); value = 2 polarizations "
+                      f"x that estimate"}
 
 
 def main():
@@ -133,69 +175,88 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    d = w.workload(args.workload, args.seed)
     desc, prec = WORKLOADS[args.workload]
     prec = args.precision or prec
-    tgt = dda.Target(d["ijk"], d["m"])
-    opts = dda.Options.for_size_parameter(d["x"], tol=d["tol"], precision=prec, recompute_green=True)
-    kh, e0 = d["khat"], d["e0"]
-    n_rhs = len(kh)
-    log(f"workload {args.workload}: N={tgt.n_sites} box={tgt.box} grid={tgt.grid} rhs={n_rhs} prec={prec}")
+    jobs, orientations, d = build_jobs(dda, w, args.workload, args.seed, prec)
+    n_rhs = sum(len(j[2]) for j in jobs)
+    log(f"workload {args.workload}: {len(jobs)} target(s), {n_rhs} right-hand sides, prec={prec}, "
+        f"first target N={jobs[0][0].n_sites} grid={jobs[0][0].grid}")
+
+    def step():
+        if len(jobs) == 1:
+            t, o, kh, e0 = jobs[0]
+            return dda.solve(t, o, kh, e0, want_P=False)[1]
+        rt = [i for i, j in enumerate(jobs) for _ in range(len(j[2]))]
+        kh = np.vstack([j[2] for j in jobs])
+        e0 = np.vstack([j[3] for j in jobs])
+        return dda.solve_batched([j[0] for j in jobs], [j[1] for j in jobs], rt, kh, e0, want_P=False)[1]
+
+    def job_units(results):
+        """RHS-matvec units each job executed (iteration matvecs + 3 checks per RHS)."""
+        out, k = [], 0
+        for j in jobs:
+            n = len(j[2])
+            out.append(sum(r["matvecs"] for r in results[k:k + n]) + 3 * n)
+            k += n
+        return out
+
+    csize = 8 if prec == "fp32_matvec" else 16
+    bpus = [pass_bytes(j[0], j[0].n_sites, csize) for j in jobs]
+
+    def pass_traffic(name, units):
+        return sum(b[name] * u for b, u in zip(bpus, units))
 
     # warmup; the last warmup step times every kernel category to find the
     # dominant matvec pass, which alone is timed during the measured steps
-    calib = None
     for i in range(max(args.warmup, 1)):
         if i == max(args.warmup, 1) - 1:
             dda.set_timing(True)
-        _, res = dda.solve(tgt, opts, kh, e0, want_P=False)
-        log(f"warmup {i}: iters={[r['iters'] for r in res]} status={[r['status'] for r in res]}")
+        res = step()
+        log(f"warmup {i}: iters={[r['iters'] for r in res][:8]} status={set(r['status'] for r in res)}")
     calib = dda.get_timing()
     dda.set_timing(False)
+    cal_units = job_units(res)
     dominant = max(PASSES, key=lambda k: calib[k][0])
     log(f"dominant matvec kernel: {dominant} ({calib[dominant][0]:.3f} ms in the last warmup step)")
 
     dda.set_timing([dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    units = 0
+    units = [0] * len(jobs)
     results = None
     for i in range(args.steps):
-        _, results = dda.solve(tgt, opts, kh, e0, want_P=False)
-        units += sum(r["matvecs"] for r in results) + 3 * n_rhs
+        results = step()
+        units = [a + b for a, b in zip(units, job_units(results))]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timing = dda.get_timing()
     dda.set_timing(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    s_per_orientation = ms_per_step / 1e3 / (n_rhs / 2.0)
+    s_per_orientation = ms_per_step / 1e3 / orientations
     for r in results:
         if r["status"] != 0:
             raise SystemExit(f"solve did not converge: {r}")
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; results {results[0]}")
 
-    csize = 8 if prec == "fp32_matvec" else 16
-    bpu = pass_bytes(tgt, tgt.n_sites, csize)
     ms_tot, launches = timing[dominant]
-    gbs = bpu[dominant] * units / (ms_tot * 1e-3) / 1e9
-    bytes_per_launch = bpu[dominant] * units / launches
-    traffic = load_traffic(dominant)
+    bytes_tot = pass_traffic(dominant, units)
+    gbs = bytes_tot / (ms_tot * 1e-3) / 1e9
+    traffic = load_traffic(dominant) if len(jobs) == 1 else None
     roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
-                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_us": ms_tot / launches * 1e3,
+                "algorithmic_bytes_per_launch": bytes_tot / launches, "avg_launch_us": ms_tot / launches * 1e3,
                 "launches": launches}
     # every pass, from the calibration step (one warmup step with all categories timed)
-    cal_units = sum(r["matvecs"] for r in res) + 3 * n_rhs
     passes = {}
-    for name, b in bpu.items():
+    for name in PASSES:
         ms, nl = calib[name]
         if nl == 0 or ms == 0:
             continue
-        g = b * cal_units / (ms * 1e-3) / 1e9
-        passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": b, "GBps": g,
-                        "frac": g / HBM_PEAK_GBS}
-    matvec_ms = sum(calib[k][0] for k in bpu)
-    matvec_bytes = sum(bpu.values()) * cal_units
+        g = pass_traffic(name, cal_units) / (ms * 1e-3) / 1e9
+        passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": bpus[0][name],
+                        "GBps": g, "frac": g / HBM_PEAK_GBS}
+    matvec_ms = sum(calib[k][0] for k in PASSES)
+    matvec_bytes = sum(pass_traffic(k, cal_units) for k in PASSES)
     out = {
         "metric": METRIC,
         "value": s_per_orientation,
@@ -209,21 +270,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else "f32 matvec / f64 Krylov",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "n_sites": tgt.n_sites, "fft_grid": list(tgt.grid),
-                   "rhs_per_step": n_rhs, "orientations_per_step": n_rhs / 2.0, "precision": prec,
+        "config": {"workload": f"{args.workload}: {desc}", "targets": len(jobs),
+                   "n_sites": [j[0].n_sites for j in jobs][:4], "fft_grid": list(jobs[0][0].grid),
+                   "rhs_per_step": n_rhs, "orientations_per_step": orientations, "precision": prec,
                    "seed": args.seed},
         "roofline": roofline,
-        "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9, "units_per_step": units / args.steps,
-                   "passes_calibration_step": passes},
+        "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9,
+                   "units_per_step": sum(units) / args.steps, "passes_calibration_step": passes},
         "kernel_ms_calibration_step": {k: v[0] for k, v in calib.items()},
-        "solver": {"iters": [r["iters"] for r in results], "matvecs": [r["matvecs"] for r in results],
-                   "qext": [r["qext"] for r in results], "qabs": [r["qabs"] for r in results],
-                   "qsca": [r["qsca"] for r in results], "rel_residual": [r["rel_residual"] for r in results],
-                   "normal_eq_residual": [r["normal_eq_residual"] for r in results]},
+        "solver": {"iters": [r["iters"] for r in results][:8], "matvecs": [r["matvecs"] for r in results][:8],
+                   "qext": [r["qext"] for r in results][:8], "qabs": [r["qabs"] for r in results][:8],
+                   "qsca": [r["qsca"] for r in results][:8], "rel_residual": [r["rel_residual"] for r in results][:8],
+                   "normal_eq_residual": [r["normal_eq_residual"] for r in results][:8],
+                   "refinements": [r["refinements"] for r in results][:8]},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one polarization ...")
-        out["cpu_baseline"] = cpu_baseline(d, args.workload)
+        out["cpu_baseline"] = cpu_baseline(d, args.workload, results[0]["iters"])
+        if args.workload == "config3":
+            out["cpu_baseline"]["sample"] += " (the brick's orientations; the spheres are smaller)"
     print(json.dumps(out), flush=True)
 
 

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <array>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -102,12 +103,35 @@ AxisPlan make_plan(int L) {
 
 }  // namespace
 
+// Device buffers and pinned status copy of one in-flight solve, with the
+// stream it runs on.  The context's own workspace uses the context stream;
+// dda_solve_batched adds workspaces with their own (default-priority) streams
+// so that several targets iterate concurrently.
+struct Workspace {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevBuf grid, vecs, state, partials, inc, ainv, mrel;
+    RhsState* host_state = nullptr;
+    int host_state_cap = 0;
+    hipEvent_t ready = nullptr;   // recorded after the last asynchronous status copy
+    void release() {
+        for (DevBuf* b : {&grid, &vecs, &state, &partials, &inc, &ainv, &mrel}) b->release();
+        if (host_state) (void)hipHostFree(host_state);
+        host_state = nullptr;
+        host_state_cap = 0;
+        if (ready) (void)hipEventDestroy(ready);
+        ready = nullptr;
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+};
+
 struct dda_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    DevBuf grid, vecs, state, partials, inc, ainv, dainv, mrel, aux, gtmp;
-    RhsState* host_state = nullptr;
-    int host_state_cap = 0;
+    Workspace main;
+    std::vector<Workspace*> extra;
+    DevBuf dainv, aux, gtmp;
     // kernel timing (dda_ctx_set_timing)
     int timing = 0;   // bit mask of recorded categories
     struct Pending {
@@ -170,16 +194,17 @@ struct Timed {
     dda_ctx* c;
     int cat;
     bool ext;
+    hipStream_t st;
     hipEvent_t a = nullptr;
     hipEvent_t b = nullptr;
-    Timed(dda_ctx* c_, int cat_) : c(c_), cat(cat_), ext(cat_ <= T_GATHER) {
+    Timed(dda_ctx* c_, int cat_, hipStream_t st_) : c(c_), cat(cat_), ext(cat_ <= T_GATHER), st(st_) {
         if (!(c->timing & (1 << cat))) return;
         a = take_event(c);
         if (ext) {
             b = take_event(c);
             launch_events() = LaunchEvents{a, b};
         } else {
-            HIPCHK(hipEventRecord(a, c->stream));
+            HIPCHK(hipEventRecord(a, st));
         }
     }
     ~Timed() {
@@ -194,15 +219,20 @@ struct Timed {
                 c->evpool.push_back(a);
                 return;
             }
-            (void)hipEventRecord(b, c->stream);
+            (void)hipEventRecord(b, st);
         }
         c->pending.push_back({cat, a, b});
     }
 };
 
-// Accumulate the timed launches; the stream has been synchronised.
+// Accumulate the timed launches that have completed.
 void flush_timing(dda_ctx* c) {
+    std::vector<dda_ctx::Pending> keep;
     for (const auto& p : c->pending) {
+        if (hipEventQuery(p.b) == hipErrorNotReady) {
+            keep.push_back(p);
+            continue;
+        }
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             c->tms[p.cat] += ms;
@@ -211,7 +241,7 @@ void flush_timing(dda_ctx* c) {
         c->evpool.push_back(p.a);
         c->evpool.push_back(p.b);
     }
-    c->pending.clear();
+    c->pending.swap(keep);
 }
 
 double kd_of(const dda_opts* o, int nsites) {
@@ -267,6 +297,8 @@ void pack_incidence(int n, const dda_incidence* inc, std::vector<double>& kh, st
 // Everything one batched solve on one target needs on the device.
 struct Work {
     dda_ctx* c;
+    Workspace& ws;
+    hipStream_t s;
     dda_target* t;
     int nrhs;
     double kd;
@@ -279,11 +311,12 @@ struct Work {
     double* kh = nullptr;
     double2* e0 = nullptr;
 
-    Work(dda_ctx* c_, dda_target* t_, int nrhs_, double kd_, bool fp32_) : c(c_), t(t_), nrhs(nrhs_), kd(kd_), fp32(fp32_) {
+    Work(dda_ctx* c_, Workspace& ws_, dda_target* t_, int nrhs_, double kd_, bool fp32_)
+        : c(c_), ws(ws_), s(ws_.stream), t(t_), nrhs(nrhs_), kd(kd_), fp32(fp32_) {
         const Geo& g = t->geo;
         const long long n3 = 3LL * t->nsites;
         const size_t vbytes = (size_t)nrhs * n3 * sizeof(double2);
-        char* v = (char*)c->vecs.ensure(7 * vbytes);
+        char* v = (char*)ws.vecs.ensure(7 * vbytes);
         a.nsites = t->nsites;
         a.n3 = n3;
         a.nrhs = nrhs;
@@ -300,31 +333,31 @@ struct Work {
         a.kd = kd;
         // FP64-sized even in the FP32-matvec mode: its residual refinement and
         // final checks use FP64 products
-        grid = c->grid.ensure((size_t)nrhs * g.npts * 3 * sizeof(double2));
-        a.st = (RhsState*)c->state.ensure((size_t)nrhs * sizeof(RhsState));
+        grid = ws.grid.ensure((size_t)nrhs * g.npts * 3 * sizeof(double2));
+        a.st = (RhsState*)ws.state.ensure((size_t)nrhs * sizeof(RhsState));
         // workgroups of every reducing kernel, per right-hand side
         pass_blocks = x_pass_blocks(g, nrhs, fp32);
         site_blocks = site_blocks_for(n3, nrhs);
         a.maxblk = std::max(pass_blocks, site_blocks);
-        a.partials = (double*)c->partials.ensure((size_t)nrhs * a.maxblk * 4 * sizeof(double));
-        a.ainv = (const double2*)c->ainv.ensure((size_t)nrhs * t->nmat * 3 * sizeof(double2));
-        char* ib = (char*)c->inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
+        a.partials = (double*)ws.partials.ensure((size_t)nrhs * a.maxblk * 4 * sizeof(double));
+        a.ainv = (const double2*)ws.ainv.ensure((size_t)nrhs * t->nmat * 3 * sizeof(double2));
+        char* ib = (char*)ws.inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
         kh = (double*)ib;
         e0 = (double2*)(ib + (((size_t)nrhs * 3 * sizeof(double) + 15) & ~(size_t)15));
     }
 
     void upload_incidence(const std::vector<double>& khv, const std::vector<double2>& e0v) {
-        HIPCHK(hipMemcpyAsync(kh, khv.data(), khv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(e0, e0v.data(), e0v.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(kh, khv.data(), khv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(e0, e0v.data(), e0v.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     }
 
     // 1/alpha for every (right-hand side, material); scheme + 2 = derivative
     void alpha_table(int scheme, double m_medium, double2* out) {
         std::vector<double2> mrel(t->nmat);
         for (int i = 0; i < t->nmat; ++i) mrel[i] = double2{t->mats[i].x / m_medium, t->mats[i].y / m_medium};
-        double2* dm = (double2*)c->mrel.ensure(mrel.size() * sizeof(double2));
-        HIPCHK(hipMemcpyAsync(dm, mrel.data(), mrel.size() * sizeof(double2), hipMemcpyHostToDevice, c->stream));
-        launch_alpha(nrhs, t->nmat, dm, kh, e0, kd, scheme, out, c->stream);
+        double2* dm = (double2*)ws.mrel.ensure(mrel.size() * sizeof(double2));
+        HIPCHK(hipMemcpyAsync(dm, mrel.data(), mrel.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        launch_alpha(nrhs, t->nmat, dm, kh, e0, kd, scheme, out, s);
     }
 
     // the three strided passes: 0 = y forward, 1 = z with the tensor product, 2 = y inverse
@@ -336,11 +369,11 @@ struct Work {
         const C* gh = (const C*)(sizeof(T) == 4 ? t->gh32.p : t->gh64.p);
         const double2* tw = (const double2*)t->tw.p;
         if (slot == 0)
-            launch_strided<T>(1, -1, chk, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, c->stream, variant);
+            launch_strided<T>(1, -1, chk, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, s, variant);
         else if (slot == 1)
-            launch_strided<T>(2, 0, chk, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, c->stream, variant);
+            launch_strided<T>(2, 0, chk, g, nrhs, 3, g.M[1], g.n[2], g.n[2], gr, tw, gh, a.st, s, variant);
         else
-            launch_strided<T>(1, 1, chk, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, c->stream, variant);
+            launch_strided<T>(1, 1, chk, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, s, variant);
     }
 
     // Pick, once per (grid, box, right-hand sides, precision), the fastest
@@ -375,9 +408,9 @@ struct Work {
                         else strided_slot<double>(slot, CHK_NONE, v);
                     };
                     run();
-                    HIPCHK(hipEventRecord(e0, c->stream));
+                    HIPCHK(hipEventRecord(e0, s));
                     for (int k = 0; k < 3; ++k) run();
-                    HIPCHK(hipEventRecord(e1, c->stream));
+                    HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
                     float ms = 0.f;
                     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
@@ -402,34 +435,33 @@ struct Work {
         C* gr = (C*)grid;
         const C* gh = (const C*)(sizeof(T) == 4 ? t->gh32.p : t->gh64.p);
         const double2* tw = (const double2*)t->tw.p;
-        hipStream_t s = c->stream;
         {
-            Timed tm(c, T_SCATTER);
+            Timed tm(c, T_SCATTER, s);
             launch_scatter_x<T>(sc, chk_sc, g, a, gr, tw, s);
         }
         if (sc == SC_S) {
-            Timed tm(c, T_KRYLOV);
+            Timed tm(c, T_KRYLOV, s);
             launch_finalize(a, FIN_S, pass_blocks, s);
         }
         {
-            Timed tm(c, T_FFTY_FWD);
+            Timed tm(c, T_FFTY_FWD, s);
             strided_slot<T>(0, chk_rest, vars[0]);
         }
         {
-            Timed tm(c, T_FFTZ_G);
+            Timed tm(c, T_FFTZ_G, s);
             strided_slot<T>(1, chk_rest, vars[1]);
         }
         {
-            Timed tm(c, T_FFTY_INV);
+            Timed tm(c, T_FFTY_INV, s);
             strided_slot<T>(2, chk_rest, vars[2]);
         }
         {
-            Timed tm(c, T_GATHER);
+            Timed tm(c, T_GATHER, s);
             launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
         }
         if (ga != GA_PLAIN) {
             static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES};
-            Timed tm(c, T_KRYLOV);
+            Timed tm(c, T_KRYLOV, s);
             launch_finalize(a, kind_of[ga], pass_blocks, s);
         }
     }
@@ -449,7 +481,7 @@ void ensure_green(dda_ctx* c, dda_target* t, double kd, bool fp32, bool force) {
     const Geo& g = t->geo;
     double2* G = (double2*)c->gtmp.ensure((size_t)g.npts * 6 * sizeof(double2));
     const double2* tw = (const double2*)t->tw.p;
-    Timed tm(c, T_GREEN);
+    Timed tm(c, T_GREEN, c->stream);
     launch_green_sample(g, kd, G, c->stream);
     launch_xgrid6(g, G, tw, c->stream);
     launch_strided<double>(1, -1, CHK_NONE, g, 1, 6, g.M[2], g.M[1], g.M[1], G, tw, nullptr, nullptr, c->stream);
@@ -465,49 +497,99 @@ void ensure_green(dda_ctx* c, dda_target* t, double kd, bool fp32, bool force) {
     if (fp32) t->have32 = true;
 }
 
-void fetch_state(dda_ctx* c, const Work& w) {
-    if (c->host_state_cap < w.nrhs) {
-        if (c->host_state) (void)hipHostFree(c->host_state);
-        c->host_state = nullptr;
-        HIPCHK(hipHostMalloc((void**)&c->host_state, (size_t)w.nrhs * sizeof(RhsState), hipHostMallocDefault));
-        c->host_state_cap = w.nrhs;
+// Asynchronous copy of every right-hand side's status to pinned host memory;
+// ws.ready completes with it.
+void post_state(Work& w) {
+    Workspace& ws = w.ws;
+    if (ws.host_state_cap < w.nrhs) {
+        if (ws.host_state) (void)hipHostFree(ws.host_state);
+        ws.host_state = nullptr;
+        HIPCHK(hipHostMalloc((void**)&ws.host_state, (size_t)w.nrhs * sizeof(RhsState), hipHostMallocDefault));
+        ws.host_state_cap = w.nrhs;
     }
-    HIPCHK(hipMemcpyAsync(c->host_state, w.a.st, (size_t)w.nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!ws.ready) HIPCHK(hipEventCreateWithFlags(&ws.ready, hipEventDisableTiming));
+    HIPCHK(hipMemcpyAsync(ws.host_state, w.a.st, (size_t)w.nrhs * sizeof(RhsState), hipMemcpyDeviceToHost, w.s));
+    HIPCHK(hipEventRecord(ws.ready, w.s));
+}
+
+void fetch_state(dda_ctx* c, Work& w) {
+    post_state(w);
+    HIPCHK(hipEventSynchronize(w.ws.ready));
     flush_timing(c);
 }
 
 // BiCGSTAB iterations until no right-hand side is active (the device keeps
 // every scalar and status; the host polls once per chunk of iterations).
+// After a status copy: restart broken-down right-hand sides (once); true if
+// any right-hand side still iterates.
+bool any_active_after_restart(Work& w) {
+    bool active = false, restart = false;
+    for (int q = 0; q < w.nrhs; ++q) {
+        const RhsState& st = w.ws.host_state[q];
+        if (st.status == ST_ACTIVE) active = true;
+        if (st.status == ST_BREAKDOWN && st.restarts == 0) restart = true;
+    }
+    if (restart) {
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_restart(w.a, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_RESTART, w.site_blocks, w.s);
+        active = true;
+    }
+    return active;
+}
+
+// One chunk of BiCGSTAB iterations (every scalar and status stays on the
+// device; right-hand sides that have stopped skip the work).
+void launch_chunk(Work& w, int chunk) {
+    for (int k = 0; k < chunk; ++k) {
+        w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
+        w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_update(w.a, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_UPD, w.site_blocks, w.s);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+// BiCGSTAB iterations until no right-hand side is active (the host polls
+// once per chunk of iterations).
 void iterate_loop(Work& w, const dda_opts* o) {
     dda_ctx* c = w.c;
     int launched = 0;
     const int chunk = std::min(8, o->max_iter);
     while (true) {
         fetch_state(c, w);
-        bool active = false, restart = false;
-        for (int q = 0; q < w.nrhs; ++q) {
-            const RhsState& s = c->host_state[q];
-            if (s.status == ST_ACTIVE) active = true;
-            if (s.status == ST_BREAKDOWN && s.restarts == 0) restart = true;
-        }
-        if (restart) {
-            Timed tm(c, T_KRYLOV);
-            launch_restart(w.a, w.site_blocks, c->stream);
-            launch_finalize(w.a, FIN_RESTART, w.site_blocks, c->stream);
-            active = true;
-        }
-        if (!active || launched > o->max_iter + 2 * chunk) break;
-        for (int k = 0; k < chunk; ++k) {
-            w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
-            w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
-            Timed tm(c, T_KRYLOV);
-            launch_update(w.a, w.site_blocks, c->stream);
-            launch_finalize(w.a, FIN_UPD, w.site_blocks, c->stream);
-        }
-        HIPCHK(hipGetLastError());
+        if (!any_active_after_restart(w) || launched > o->max_iter + 2 * chunk) break;
+        launch_chunk(w, chunk);
         launched += chunk;
     }
+}
+
+// Start of BiCGSTAB: state, then r and rhat from b (cold) or b - A x (warm).
+void start_iteration(Work& w, const dda_opts* o, bool warm) {
+    launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, w.s);
+    if (warm) {
+        w.a.in = w.a.x;
+        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x0
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_init_warm(w.a, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_WARM, w.site_blocks, w.s);
+    } else {
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_init_cold(w.a, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_COLD, w.site_blocks, w.s);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+// FP64 residual r = b - A x of every converged right-hand side; those that
+// miss the tolerance iterate on from x (FP32-matvec mode).
+void launch_refinement(Work& w) {
+    w.a.in = w.a.x;
+    w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
+    Timed tm(w.c, T_KRYLOV, w.s);
+    launch_init_warm(w.a, w.site_blocks, w.s);
+    launch_finalize(w.a, FIN_REFINE, w.site_blocks, w.s);
 }
 
 // BiCGSTAB on every right-hand side of w (b, ainv prepared); warm start when
@@ -516,33 +598,14 @@ void iterate_loop(Work& w, const dda_opts* o) {
 // FP64 product r = b - A x and, if that misses the tolerance, the iteration
 // restarts from x with that residual (at most 5 refinements).  Leaves P in x.
 void iterate(Work& w, const dda_opts* o, bool warm) {
-    dda_ctx* c = w.c;
-    launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, c->stream);
-    if (warm) {
-        w.a.in = w.a.x;
-        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x0
-        Timed tm(c, T_KRYLOV);
-        launch_init_warm(w.a, w.site_blocks, c->stream);
-        launch_finalize(w.a, FIN_WARM, w.site_blocks, c->stream);
-    } else {
-        Timed tm(c, T_KRYLOV);
-        launch_init_cold(w.a, w.site_blocks, c->stream);
-        launch_finalize(w.a, FIN_COLD, w.site_blocks, c->stream);
-    }
-    HIPCHK(hipGetLastError());
+    start_iteration(w, o, warm);
     iterate_loop(w, o);
     if (!w.fp32) return;
     for (int k = 0; k < 5; ++k) {
-        w.a.in = w.a.x;
-        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
-        {
-            Timed tm(c, T_KRYLOV);
-            launch_init_warm(w.a, w.site_blocks, c->stream);
-            launch_finalize(w.a, FIN_REFINE, w.site_blocks, c->stream);
-        }
-        fetch_state(c, w);
+        launch_refinement(w);
+        fetch_state(w.c, w);
         bool active = false;
-        for (int q = 0; q < w.nrhs; ++q) active |= c->host_state[q].status == ST_ACTIVE;
+        for (int q = 0; q < w.nrhs; ++q) active |= w.ws.host_state[q].status == ST_ACTIVE;
         if (!active) break;
         iterate_loop(w, o);
     }
@@ -550,7 +613,6 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
 
 // true residual, eq. err_tol and the efficiency sums at x
 void final_checks(Work& w, bool normal_eq) {
-    dda_ctx* c = w.c;
     SiteArgs& a = w.a;
     a.in = a.x;
     w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x, red[0] = |r|^2
@@ -566,9 +628,9 @@ void final_checks(Work& w, bool normal_eq) {
         w.matvec(SC_CONJ, GA_CONJ, CHK_NONE, CHK_NONE, true);
     }
     {
-        Timed tm(c, T_KRYLOV);
-        launch_qsum(a, w.site_blocks, c->stream);
-        launch_finalize(a, FIN_QSUM, w.site_blocks, c->stream);
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_qsum(a, w.site_blocks, w.s);
+        launch_finalize(a, FIN_QSUM, w.site_blocks, w.s);
     }
     HIPCHK(hipGetLastError());
 }
@@ -588,7 +650,7 @@ dda_status fill_results(const Work& w, bool normal_eq, dda_result* res) {
     const double cq = 4.0 * M_PI * w.kd / (M_PI * a * a);
     dda_status worst = DDA_OK;
     for (int q = 0; q < w.nrhs; ++q) {
-        const RhsState& s = w.c->host_state[q];
+        const RhsState& s = w.ws.host_state[q];
         dda_result r{};
         r.qext = cq * s.red[3];
         r.qabs = cq * s.red[4];
@@ -648,33 +710,32 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     const double kd = kd_of(o, t->nsites);
     const bool fp32 = o->precision == DDA_FP32_MATVEC;
     ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
-    Work w(c, t, nrhs, kd, fp32);
+    Work w(c, c->main, t, nrhs, kd, fp32);
     w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
     w.upload_incidence(kh, e0);
     const bool warm = P0 != nullptr;
     {
-        Timed tm(c, T_SETUP);
+        Timed tm(c, T_SETUP, w.s);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
         if (b_caller)
-            launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)b_caller, w.a.b, true,
-                           c->stream);
+            launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)b_caller, w.a.b, true, w.s);
         else
-            launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, c->stream);
+            launch_einc(w.a, (const int*)t->coords.p, w.kh, w.e0, w.s);
         if (warm)
-            launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P0, w.a.x, true, c->stream);
+            launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P0, w.a.x, true, w.s);
     }
     w.a.in = w.a.x;
     iterate(w, o, warm);
     const bool ne = (o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0;
     final_checks(w, ne);
     {
-        Timed tm(c, T_SETUP);
-        if (P) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, w.a.x, (double2*)P, false, c->stream);
+        Timed tm(c, T_SETUP, w.s);
+        if (P) launch_permute(nrhs, t->nsites, 3, (const int*)t->perm.p, w.a.x, (double2*)P, false, w.s);
         if (Pper) {
             for (int q = 0; q < nrhs; ++q)
                 if (Pper[q])
                     launch_permute(1, t->nsites, 3, (const int*)t->perm.p, w.a.x + (size_t)q * w.a.n3,
-                                   (double2*)Pper[q], false, c->stream);
+                                   (double2*)Pper[q], false, w.s);
         }
     }
     HIPCHK(hipGetLastError());
@@ -685,6 +746,147 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     }
     if (st == DDA_OK) warn_validity(t, kd, o->m_medium);
     return st;
+}
+
+// ---------------------------------------------------------------- many targets
+
+// One target of a dda_solve_batched call and its progress.
+struct Job {
+    enum Phase { PENDING, ITER, REFINE, FINAL, DONE };
+    dda_target* t = nullptr;
+    const dda_opts* o = nullptr;
+    std::vector<int> idx;                 // caller indices of its right-hand sides
+    std::vector<double> kh;
+    std::vector<double2> e0;
+    std::vector<dda_c64*> P;
+    double kd = 0;
+    bool fp32 = false;
+    std::unique_ptr<Work> w;
+    Phase phase = PENDING;
+    int launched = 0;
+    int refines = 0;
+};
+
+// Every job's targets iterate concurrently, one workspace and stream per
+// job in flight (at most 4; the hardware runs that many queues at once).
+// The host never blocks on one job while another can make progress: after
+// each chunk of iterations a job posts an asynchronous status copy and the
+// host moves on to the next job whose copy has landed.
+dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
+    for (Job& j : jobs) {
+        check_opts(j.o);
+        j.kd = kd_of(j.o, j.t->nsites);
+        j.fp32 = j.o->precision == DDA_FP32_MATVEC;
+        ensure_green(c, j.t, j.kd, j.fp32, (j.o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+    }
+    const int nslot = (int)std::min<size_t>(4, jobs.size());
+    while ((int)c->extra.size() < nslot - 1) {
+        auto* ws = new Workspace();
+        c->extra.push_back(ws);
+        HIPCHK(hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking));
+        ws->own_stream = true;
+    }
+    std::vector<Workspace*> slots{&c->main};
+    for (int i = 0; i < nslot - 1; ++i) slots.push_back(c->extra[i]);
+    // the other streams start after the tensor FFTs built on the context stream
+    hipEvent_t green_done = take_event(c);
+    HIPCHK(hipEventRecord(green_done, c->stream));
+    for (int i = 1; i < nslot; ++i) HIPCHK(hipStreamWaitEvent(slots[i]->stream, green_done, 0));
+    c->evpool.push_back(green_done);
+
+    std::vector<Job*> in_slot(nslot, nullptr);
+    size_t next = 0;
+    dda_status worst = DDA_OK;
+    auto start = [&](Job& j, Workspace& ws) {
+        const int nrhs = (int)j.idx.size();
+        j.w.reset(new Work(c, ws, j.t, nrhs, j.kd, j.fp32));
+        Work& w = *j.w;
+        w.autotune((j.o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, j.o->kernel_variant);
+        w.upload_incidence(j.kh, j.e0);
+        {
+            Timed tm(c, T_SETUP, w.s);
+            w.alpha_table(j.o->polarizability, j.o->m_medium, (double2*)w.a.ainv);
+            launch_einc(w.a, (const int*)j.t->coords.p, w.kh, w.e0, w.s);
+        }
+        w.a.in = w.a.x;
+        start_iteration(w, j.o, false);
+        post_state(w);
+        j.phase = Job::ITER;
+    };
+    auto finish = [&](Job& j) {
+        Work& w = *j.w;
+        final_checks(w, (j.o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0);
+        {
+            Timed tm(c, T_SETUP, w.s);
+            for (size_t q = 0; q < j.idx.size(); ++q)
+                if (j.P[q])
+                    launch_permute(1, j.t->nsites, 3, (const int*)j.t->perm.p, w.a.x + (size_t)q * w.a.n3,
+                                   (double2*)j.P[q], false, w.s);
+        }
+        HIPCHK(hipGetLastError());
+        post_state(w);
+        j.phase = Job::FINAL;
+    };
+    int live = 0;
+    while (true) {
+        for (int sl = 0; sl < nslot; ++sl) {
+            if (!in_slot[sl] && next < jobs.size()) {
+                in_slot[sl] = &jobs[next++];
+                start(*in_slot[sl], *slots[sl]);
+                ++live;
+            }
+        }
+        if (live == 0) break;
+        bool progress = false;
+        for (int sl = 0; sl < nslot; ++sl) {
+            Job* jp = in_slot[sl];
+            if (!jp) continue;
+            Job& j = *jp;
+            Work& w = *j.w;
+            const hipError_t q = hipEventQuery(w.ws.ready);
+            if (q == hipErrorNotReady) continue;
+            HIPCHK(q);
+            progress = true;
+            const int chunk = std::min(8, j.o->max_iter);
+            if (j.phase == Job::ITER || j.phase == Job::REFINE) {
+                const bool active = any_active_after_restart(w);
+                if (active && j.launched <= j.o->max_iter + 2 * chunk) {
+                    launch_chunk(w, chunk);
+                    j.launched += chunk;
+                    j.phase = Job::ITER;
+                    post_state(w);
+                } else if (j.phase == Job::ITER && j.fp32 && j.refines < 5) {
+                    launch_refinement(w);
+                    ++j.refines;
+                    j.phase = Job::REFINE;
+                    post_state(w);
+                } else {
+                    finish(j);
+                }
+            } else if (j.phase == Job::FINAL) {
+                std::vector<dda_result> r(j.idx.size());
+                const dda_status st = fill_results(w, (j.o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0, r.data());
+                for (size_t k = 0; k < j.idx.size(); ++k)
+                    if (res) res[j.idx[k]] = r[k];
+                if (st != DDA_OK && (worst == DDA_OK || st > worst)) worst = st;
+                j.phase = Job::DONE;
+                j.w.reset();
+                in_slot[sl] = nullptr;
+                --live;
+            }
+        }
+        if (!progress) {
+            // wait for the first in-flight job instead of spinning
+            for (int sl = 0; sl < nslot; ++sl)
+                if (in_slot[sl]) {
+                    HIPCHK(hipEventSynchronize(in_slot[sl]->w->ws.ready));
+                    break;
+                }
+        }
+    }
+    for (int i = 1; i < nslot; ++i) HIPCHK(hipStreamSynchronize(slots[i]->stream));
+    flush_timing(c);
+    return worst;
 }
 
 }  // namespace
@@ -703,6 +905,7 @@ dda_status dda_ctx_create(int device, void* hip_stream, dda_ctx** out) {
         auto* c = new dda_ctx();
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
+        c->main.stream = c->stream;
         *out = c;
         return DDA_OK;
     });
@@ -714,10 +917,13 @@ dda_status dda_ctx_destroy(dda_ctx* c) {
         {
             Scope sc(c);
             (void)hipStreamSynchronize(c->stream);
-            for (DevBuf* b : {&c->grid, &c->vecs, &c->state, &c->partials, &c->inc, &c->ainv, &c->dainv,
-                              &c->mrel, &c->aux, &c->gtmp})
-                b->release();
-            if (c->host_state) (void)hipHostFree(c->host_state);
+            for (Workspace* ws : c->extra) {
+                if (ws->stream) (void)hipStreamSynchronize(ws->stream);
+                ws->release();
+                delete ws;
+            }
+            c->main.release();
+            for (DevBuf* b : {&c->dainv, &c->aux, &c->gtmp}) b->release();
             for (const auto& p : c->pending) {
                 (void)hipEventDestroy(p.a);
                 (void)hipEventDestroy(p.b);
@@ -868,7 +1074,7 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         const double kd = kd_of(o, t->nsites);
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
-        Work w(c, t, n_rhs, kd, fp32);
+        Work w(c, c->main, t, n_rhs, kd, fp32);
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
@@ -910,27 +1116,24 @@ dda_status dda_solve_batched(dda_ctx* c, int32_t n_targets, dda_target* const* t
         Scope sc(c);
         for (int q = 0; q < n_rhs; ++q)
             if (rhs_target[q] < 0 || rhs_target[q] >= n_targets) invalid("rhs_target out of range");
-        dda_status worst = DDA_OK;
+        std::vector<Job> jobs;
         for (int ti = 0; ti < n_targets; ++ti) {
-            std::vector<int> idx;
+            Job j;
             for (int q = 0; q < n_rhs; ++q)
-                if (rhs_target[q] == ti) idx.push_back(q);
-            if (idx.empty()) continue;
+                if (rhs_target[q] == ti) j.idx.push_back(q);
+            if (j.idx.empty()) continue;
             if (!targets[ti]) invalid("NULL target");
-            std::vector<dda_incidence> sub(idx.size());
-            std::vector<dda_c64*> sp(idx.size());
-            std::vector<dda_result> sr(idx.size());
-            for (size_t i = 0; i < idx.size(); ++i) {
-                sub[i] = inc[idx[i]];
-                sp[i] = P ? P[idx[i]] : nullptr;
+            j.t = targets[ti];
+            j.o = &opts[ti];
+            std::vector<dda_incidence> sub(j.idx.size());
+            for (size_t i = 0; i < j.idx.size(); ++i) {
+                sub[i] = inc[j.idx[i]];
+                j.P.push_back(P ? P[j.idx[i]] : nullptr);
             }
-            const dda_status st = solve_one(c, targets[ti], &opts[ti], (int)idx.size(), sub.data(), nullptr,
-                                            sp.data(), nullptr, sr.data());
-            for (size_t i = 0; i < idx.size(); ++i)
-                if (res) res[idx[i]] = sr[i];
-            if (st != DDA_OK && (worst == DDA_OK || st > worst)) worst = st;
+            pack_incidence((int)sub.size(), sub.data(), j.kh, j.e0);
+            jobs.push_back(std::move(j));
         }
-        return worst;
+        return solve_many(c, jobs, res);
     });
 }
 
@@ -947,7 +1150,7 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         const double kd = kd_of(o, t->nsites);
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
-        Work w(c, t, 1, kd, fp32);
+        Work w(c, c->main, t, 1, kd, fp32);
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);

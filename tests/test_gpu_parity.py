@@ -427,3 +427,62 @@ def test_qeff_autograd_function(dda):
     assert abs(q[0].item() - sol["qabs"]) <= 1e-8 * sol["qabs"]
     assert abs(q[1].item() - sol["qext"]) <= 1e-8 * sol["qext"]
     assert np.abs(eps.grad.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ batched / ragged
+
+def test_solve_batched_matches_separate_solves(dda):
+    """A ragged batch (a brick with 16 right-hand sides and six spheres of
+    different grids, two each) solved concurrently in one call gives every
+    right-hand side bitwise the result of solving its target alone."""
+    d = w.workload("brick48")
+    brick = dda.Target(d["ijk"], d["m"])
+    radii = w.sphere_radii(0)[:6]
+    spheres = [dda.Target(w.sphere_integer(r), 1.33 + 0.01j) for r in radii]
+    kh_s, e0_s = w.along_x_yz()
+    targets = [brick] + spheres
+    opts = [dda.Options.for_size_parameter(d["x"], tol=1e-5)] + \
+           [dda.Options.for_size_parameter(4.0, tol=1e-5) for _ in spheres]
+    kh = np.vstack([d["khat"][:16]] + [kh_s] * len(spheres))
+    e0 = np.vstack([d["e0"][:16]] + [e0_s] * len(spheres))
+    rt = [0] * 16 + [1 + i // 2 for i in range(2 * len(spheres))]
+    Ps, res = dda.solve_batched(targets, opts, rt, kh, e0)
+    P0, r0 = dda.solve(brick, opts[0], d["khat"][:16], d["e0"][:16])
+    for q in range(16):
+        assert torch.equal(Ps[q], P0[q]) and res[q] == r0[q]
+    q_mie = mie.efficiencies(1.33 + 0.01j, 4.0)
+    for i, t in enumerate(spheres):
+        Pi, ri = dda.solve(t, opts[1 + i], kh_s, e0_s)
+        for k in range(2):
+            g = 16 + 2 * i + k
+            assert torch.equal(Ps[g], Pi[k]) and res[g] == ri[k]
+            assert res[g]["status"] == 0
+            assert abs(res[g]["qext"] / q_mie["qext"] - 1) < 0.05
+            assert abs(res[g]["qsca"] / q_mie["qsca"] - 1) < 0.05
+
+
+def test_config3_batch_full(dda):
+    """The whole batched workload: the 48x24x16 brick at 64 random
+    orientations x 2 polarizations and 32 ragged spheres x 2, one call.
+    Spheres within 5% of Mie; two brick right-hand sides against the
+    oracle's FFT-BiCGSTAB to 1e-4."""
+    d = w.workload("brick48")
+    brick = dda.Target(d["ijk"], d["m"])
+    spheres = [dda.Target(s, 1.33 + 0.01j) for s in w.sphere_batch(0)]
+    kh_s, e0_s = w.along_x_yz()
+    targets = [brick] + spheres
+    opts = [dda.Options.for_size_parameter(d["x"], tol=1e-5)] + \
+           [dda.Options.for_size_parameter(4.0, tol=1e-5) for _ in spheres]
+    kh = np.vstack([d["khat"]] + [kh_s] * len(spheres))
+    e0 = np.vstack([d["e0"]] + [e0_s] * len(spheres))
+    rt = [0] * 128 + [1 + i // 2 for i in range(64)]
+    _, res = dda.solve_batched(targets, opts, rt, kh, e0, want_P=False)
+    assert all(r["status"] == 0 and r["rel_residual"] < 1e-5 for r in res)
+    q_mie = mie.efficiencies(1.33 + 0.01j, 4.0)
+    for r in res[128:]:
+        assert abs(r["qext"] / q_mie["qext"] - 1) < 0.05
+        assert abs(r["qsca"] / q_mie["qsca"] - 1) < 0.05
+    for q in (0, 77):
+        o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-9)
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(res[q][key] - o[key]) <= 1e-4 * abs(o[key]), (q, key)
