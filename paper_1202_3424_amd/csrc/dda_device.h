@@ -252,21 +252,57 @@ __device__ void fft_lines(typename V2<T>::t* lds, const typename V2<T>::t* tw, i
 }
 
 // ------------------------------------------------ compile-time FFT lengths
-// The radix sequence the host's planner uses (powers of two as 8s and 4s,
-// one 2 only when unavoidable, then 3s, then 5s): ct_plan(L, -1) is the
-// number of passes, ct_plan(L, s) the radix of pass s.
+// Radix sequence of each compile-time length: ct_plan(L, -1) is the number
+// of passes, ct_plan(L, s) the radix of pass s.  The passes fall into two
+// groups, the first with radix product P = ct_split(L) >= Q = L / P and Q
+// dividing P: the register-resident transform runs the first group on a
+// thread's own subsequence x[t + Q m] and the second on a thread's own
+// residue classes of the first group's output (see rf_group_a/rf_group_b).
+// Every form of the transform (LDS and register-resident) runs exactly these
+// passes, so they give bitwise-identical results.
 constexpr int ct_plan(int L, int s) {
-    int r[16] = {};
-    int n = 0, m = L, e2 = 0;
-    while (m % 2 == 0) { m /= 2; ++e2; }
-    if (e2 % 3 == 1 && e2 >= 4) { r[n++] = 4; r[n++] = 4; e2 -= 4; }
-    if (e2 % 3 == 2) { r[n++] = 4; e2 -= 2; }
-    if (e2 % 3 == 1) { r[n++] = 2; e2 -= 1; }
-    while (e2 >= 3) { r[n++] = 8; e2 -= 3; }
-    while (m % 3 == 0) { r[n++] = 3; m /= 3; }
-    while (m % 5 == 0) { r[n++] = 5; m /= 5; }
+    int r[6] = {};
+    int n = 0;
+    switch (L) {
+        case 32: r[0] = 8; r[1] = 4; n = 2; break;
+        case 48: r[0] = 4; r[1] = 3; r[2] = 4; n = 3; break;
+        case 64: r[0] = 8; r[1] = 8; n = 2; break;
+        case 80: r[0] = 4; r[1] = 5; r[2] = 4; n = 3; break;
+        case 96: r[0] = 8; r[1] = 3; r[2] = 4; n = 3; break;
+        case 128: r[0] = 4; r[1] = 4; r[2] = 8; n = 3; break;
+        case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; n = 4; break;
+        default: break;
+    }
     return s < 0 ? n : r[s];
 }
+constexpr int ct_split(int L) {
+    switch (L) {
+        case 32: return 8;
+        case 48: return 12;
+        case 64: return 8;
+        case 80: return 20;
+        case 96: return 24;
+        case 128: return 16;
+        case 256: return 16;
+        default: return 0;
+    }
+}
+// passes in the first group
+constexpr int ct_split_passes(int L) {
+    int p = 1, s = 0;
+    while (p < ct_split(L)) p *= ct_plan(L, s++);
+    return s;
+}
+constexpr bool ct_plan_ok(int L) {
+    int p = 1;
+    for (int s = 0; s < ct_plan(L, -1); ++s) p *= ct_plan(L, s);
+    int pa = 1;
+    for (int s = 0; s < ct_split_passes(L); ++s) pa *= ct_plan(L, s);
+    return p == L && pa == ct_split(L) && ct_split(L) % (L / ct_split(L)) == 0;
+}
+static_assert(ct_plan_ok(32) && ct_plan_ok(48) && ct_plan_ok(64) && ct_plan_ok(80) && ct_plan_ok(96) &&
+                  ct_plan_ok(128) && ct_plan_ok(256),
+              "radix plans must factor L with the split P >= Q, Q | P");
 
 // One radix-R pass over NL lines of compile-time length L (same in-place
 // scheme as fft_pass; the twiddles W_L^t are read from the FP64 table in
@@ -356,6 +392,111 @@ __device__ __forceinline__ void fft_lines_ct(typename V2<T>::t* lds, const doubl
 // last pass (inverse) has an even radix.
 constexpr bool ct_half_in_ok(int L) { return ct_plan(L, 0) % 2 == 0; }
 constexpr bool ct_half_out_ok(int L) { return ct_plan(L, ct_plan(L, -1) - 1) % 2 == 0; }
+
+// ------------------------------------------------ register-resident passes
+// The passes of ct_plan(L) on data held in registers.  Stockham indices: after
+// the passes with radix product NS, element j*NS + f is frequency f of the
+// NS-point transform of the subsequence x[j + (L/NS) m].  A pass only combines
+// elements whose subsequence index agrees modulo Q = L/P (first group) or
+// whose frequency agrees modulo P (second group), which is what lets a thread
+// run a whole group on its own registers.
+
+// First group on one subsequence, thread index t: on entry v[m] = x[t + Q m];
+// on exit v[f] = element t*P + f.  HIN: x[e] = 0 for e >= L/2 (the first pass
+// reads only its lower inputs, as fft_pass_ct does).
+template <typename T, int DIR, int L, bool HIN, int S = 0, int NS = 1>
+__device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[ct_split(L)], const double2* tw) {
+    using C = typename V2<T>::t;
+    constexpr int P = ct_split(L);
+    if constexpr (NS < P) {
+        constexpr int R = ct_plan(L, S);
+        constexpr int TSTEP = L / (NS * R);
+        constexpr bool HI = HIN && S == 0;
+        C o[P];
+#pragma unroll
+        for (int u0 = 0; u0 < P / (NS * R); ++u0) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                C b[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (HI && 2 * r >= R) {
+                        b[r].x = 0;
+                        b[r].y = 0;
+                    } else {
+                        b[r] = v[u0 * NS + k + r * (P / R)];
+                    }
+                }
+                if constexpr (NS > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        const double2 w = tw[r * k * TSTEP];
+                        C c;
+                        c.x = (decltype(c.x))w.x;
+                        c.y = (decltype(c.y))(DIR > 0 ? -w.y : w.y);
+                        b[r] = cmul(b[r], c);
+                    }
+                }
+                Dft<R, DIR, C>::run(b);
+#pragma unroll
+                for (int q = 0; q < R; ++q) o[u0 * NS * R + k + q * NS] = b[q];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = o[i];
+        rf_group_a<T, DIR, L, HIN, S + 1, NS * R>(v, tw);
+    }
+}
+
+// Second group on residue classes kappa_c = t + Q c (c < P/Q) of the first
+// group's frequency: on entry v[c*Q + jj] = element jj*P + kappa_c; on exit
+// v[c*Q + g] = X[kappa_c + P g].  HOUT: only X[e], e < L/2, is wanted (the
+// last pass computes only its lower outputs, as fft_pass_ct does).
+template <typename T, int DIR, int L, bool HOUT, int S = ct_split_passes(L), int NS = ct_split(L)>
+__device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[ct_split(L)], int t, const double2* tw) {
+    using C = typename V2<T>::t;
+    constexpr int P = ct_split(L);
+    constexpr int Q = L / P;
+    constexpr int NST = ct_plan(L, -1);
+    if constexpr (S < NST) {
+        constexpr int R = ct_plan(L, S);
+        constexpr int TSTEP = L / (NS * R);
+        constexpr bool HO = HOUT && S == NST - 1;
+        constexpr int G = NS / P;
+        C o[P];
+#pragma unroll
+        for (int c = 0; c < P / Q; ++c) {
+            const int kappa = t + Q * c;
+#pragma unroll
+            for (int jh = 0; jh < L / (NS * R); ++jh) {
+#pragma unroll
+                for (int gk = 0; gk < G; ++gk) {
+                    const int ks = kappa + P * gk;
+                    C b[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) b[r] = v[c * Q + (jh + r * (L / (R * NS))) * G + gk];
+#pragma unroll
+                    for (int r = 1; r < R; ++r) {
+                        const double2 w = tw[r * ks * TSTEP];
+                        C cw;
+                        cw.x = (decltype(cw.x))w.x;
+                        cw.y = (decltype(cw.y))(DIR > 0 ? -w.y : w.y);
+                        b[r] = cmul(b[r], cw);
+                    }
+                    Dft<R, DIR, C>::run(b);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        if (!HO || 2 * q < R) o[c * Q + jh * G * R + gk + q * G] = b[q];
+                        else o[c * Q + jh * G * R + gk + q * G] = b[0];   // never stored
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = o[i];
+        rf_group_b<T, DIR, L, HOUT, S + 1, NS * R>(v, t, tw);
+    }
+}
 
 // Stage the W_L^t table of an axis into LDS (FP64 table converted to T).
 template <typename T, int NTHR = NT>

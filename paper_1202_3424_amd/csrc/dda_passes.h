@@ -22,6 +22,8 @@
 // runtime plan with twiddles staged in LDS.
 #pragma once
 
+#include <type_traits>
+
 #include "dda_kernels.h"
 
 namespace dda {
@@ -550,6 +552,299 @@ __global__ __launch_bounds__(NT) void k_zfold(Geo g, typename V2<T>::t* grid, co
     }
 }
 
+// Passes 2-4 in register-resident form.  Each line is handled by Q = L/P
+// threads: thread t loads the subsequence e = t + Q m (m < P) of its lines,
+// runs the first pass group in registers, the tile is exchanged once through
+// LDS, and the thread then runs the remaining passes on its residue classes
+// and stores X[kappa + P g] directly.  With GH the three components of a
+// column stay in one thread, so the tensor product is applied in registers;
+// a second exchange brings the product back to subsequences for the inverse
+// transform.  The passes are those of fft_lines_ct (bitwise-identical
+// results to k_strided); only the data movement differs.  One right-hand
+// side per workgroup (grid z).  XR: the exchange runs in XR rounds over the
+// tile's lines (LDS of 3 TX / XR lines).  HIN / HOUT: the half-line pruning
+// of the forward input / inverse output (the host launches this kernel only
+// where the pass allows it).
+// nct: component lines per thread (3: pass 3 with the product in registers)
+constexpr int rf_threads(int L, int TX, int nct) { return (nct == 3 ? TX : 3 * TX) * (L / ct_split(L)); }
+template <int L> constexpr int rf_line_stride() { return ((L / ct_split(L)) * (ct_split(L) + 1)) | 1; }
+template <typename T, int L, int TX, int XR> constexpr size_t rf_smem() {
+    return (size_t)(3 * TX / XR) * rf_line_stride<L>() * sizeof(typename V2<T>::t);
+}
+
+// SPLIT (pass 3 only): one component line per thread, like passes 2 and 4
+// (coalesced loads, fewer registers); the tensor product is then applied
+// during the middle exchange, each thread reading the three components of
+// its column from LDS and forming its own component of the product.  The
+// exchange rounds then go over columns (TX / XR columns per round).
+// XG (pass 3 only): the grid is one-dimensional and ordered so that the
+// workgroups sharing tensor values -- the column tiles x and Mx - x, the rows
+// y and My - y, every right-hand side -- run consecutively on one XCD
+// (workgroups go to the eight XCDs round-robin), so each XCD's L2 serves
+// the repeats and the tensor is read from HBM about once per launch.
+constexpr int N_XCD = 8;
+// Occupancy asked of the compiler for one line per thread: four waves per
+// SIMD (128 VGPRs) when the line data take at most 32 VGPRs, three (168)
+// up to 64, two (256) for the four-pass length 256 (no spills in any case);
+// otherwise the compiler's own choice stands.
+template <typename T> constexpr int rf_waves(int L, int nct) {
+    const int d = ct_split(L) * (int)(2 * sizeof(T) / 4);
+    if (nct != 1) return 1;
+    if (L == 256) return 2;
+    return d <= 32 ? 4 : (d <= 64 ? 3 : 1);
+}
+template <typename T, int GH, int DIR, int L, int TX, int XR, bool HIN, bool HOUT, bool XG = false, bool SPLIT = false>
+__global__ __launch_bounds__(rf_threads(L, TX, GH && !SPLIT ? 3 : 1))
+__attribute__((amdgpu_waves_per_eu(rf_waves<T>(L, GH && !SPLIT ? 3 : 1)))) void k_strided_rf(Geo g, typename V2<T>::t* grid,
+                                                                       const double2* tw64,
+                                                                       const typename V2<T>::t* ghat,
+                                                                       const RhsState* st, int axis, int lin,
+                                                                       int lout, int chk, int nrhs) {
+    using C = typename V2<T>::t;
+    constexpr int P = ct_split(L);
+    constexpr int Q = L / P;
+    constexpr int NCT = (GH && !SPLIT) ? 3 : 1;   // component lines per thread
+    constexpr int NIN = NCT == 3 ? TX : 3 * TX;   // threads across the tile's lines
+    constexpr int LS = rf_line_stride<L>();
+    static_assert((SPLIT ? TX : 3 * TX) % XR == 0, "exchange rounds must split the tile's lines");
+    // exchange round and LDS row of line ln
+    auto round_of = [](int ln) { return SPLIT ? (ln / 3) % XR : ln % XR; };
+    auto slot_of = [](int ln) { return SPLIT ? ((ln / 3) / XR) * 3 + ln % 3 : ln / XR; };
+    // scheduling fence between the steps of the split product (register pressure)
+    constexpr bool FENCE = SPLIT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = (C*)smem;
+    const int Mx = g.M[0], My = g.M[1];
+    int q, o, xt;
+    if constexpr (XG) {
+        const int ntx = (Mx + TX - 1) / TX;
+        const int nxp = (ntx + 1) / 2, nyp = My / 2 + 1;
+        const int mg = 4 * nrhs;
+        const int w = blockIdx.x;
+        const int local = w / N_XCD;
+        const int gi = (local / mg) * N_XCD + w % N_XCD;
+        const int m = local % mg;
+        if (gi >= nxp * nyp) return;
+        const int xi = gi % nxp, yi = gi / nxp;
+        const int mir = m / nrhs;
+        q = m % nrhs;
+        xt = (mir & 1) ? ntx - 1 - xi : xi;
+        o = (mir & 2) ? (My - yi) % My : yi;
+        if (((mir & 1) && xt == xi) || ((mir & 2) && o == yi)) return;   // self-mirrored: done by mir 0
+    } else {
+        q = blockIdx.z;
+        o = blockIdx.y;
+        xt = blockIdx.x;
+    }
+    if (skip_rhs(st + q, chk)) return;
+    const int in = threadIdx.x % NIN;
+    const int t = threadIdx.x / NIN;
+    const int x0 = xt * TX;
+    const double2* tw = tw64 + g.ax[axis].tw;
+    const long long estride = (axis == 1) ? (long long)Mx * 3 : (long long)My * Mx * 3;
+    const long long obase = (axis == 1) ? (long long)o * My * Mx * 3 : (long long)o * Mx * 3;
+    C* gq = grid + (long long)q * g.npts * 3 + obase + (long long)x0 * 3;
+    const int nval = 3 * min(TX, Mx - x0);
+    // line (column * 3 + component) of this thread's component a
+    auto line_of = [&](int a) { return NCT == 3 ? in * 3 + a : in; };
+
+    C v[NCT][P];
+#pragma unroll
+    for (int a = 0; a < NCT; ++a) {
+        const int ln = line_of(a);
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const int e = t + Q * m;
+            if ((!HIN || 2 * m < P) && e < lin && ln < nval) {
+                v[a][m] = gq[(long long)e * estride + ln];
+            } else {
+                v[a][m].x = 0;
+                v[a][m].y = 0;
+            }
+        }
+    }
+    // first group -> exchange -> second group (one transform of every line)
+    auto transform = [&](auto dir_tag, auto hin_tag, auto hout_tag) {
+        constexpr int D = decltype(dir_tag)::value;
+        constexpr bool HI = decltype(hin_tag)::value;
+        constexpr bool HO = decltype(hout_tag)::value;
+#pragma unroll
+        for (int a = 0; a < NCT; ++a) rf_group_a<T, D, L, HI>(v[a], tw);
+#pragma unroll
+        for (int rd = 0; rd < XR; ++rd) {
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NCT; ++a) {
+                const int ln = line_of(a);
+                if (round_of(ln) == rd) {
+                    C* row = lds + slot_of(ln) * LS + t * (P + 1);
+#pragma unroll
+                    for (int f = 0; f < P; ++f) row[f] = v[a][f];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NCT; ++a) {
+                const int ln = line_of(a);
+                if (round_of(ln) == rd) {
+                    const C* row = lds + slot_of(ln) * LS;
+#pragma unroll
+                    for (int c = 0; c < P / Q; ++c) {
+#pragma unroll
+                        for (int jj = 0; jj < Q; ++jj) v[a][c * Q + jj] = row[jj * (P + 1) + t + Q * c];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NCT; ++a) rf_group_b<T, D, L, HO>(v[a], t, tw);
+    };
+    using Fwd = std::integral_constant<int, GH ? -1 : DIR>;
+    transform(Fwd{}, std::integral_constant<bool, HIN>{},
+              std::integral_constant<bool, GH ? false : HOUT>{});
+    if constexpr (GH && SPLIT) {
+        // exchange to subsequences with the product: thread (column, a, t)
+        // forms y_a = sum_b Ghat_ab x_b at kz = t + Q m from the three
+        // component rows of its column
+        const int Mz = g.M[2];
+        const int Hx = g.H[0], Hy = g.H[1];
+        const int ln = in;
+        const int a = ln % 3;
+        const int kx = x0 + ln / 3;
+        const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
+        const int sx = (kx <= Mx / 2) ? 1 : -1;
+        const int fy = (o <= My / 2) ? o : My - o;
+        const int sy = (o <= My / 2) ? 1 : -1;
+        // tensor row a: components (a, i1, i2) of (xx, xy, xz, yy, yz, zz)
+        const int i1 = a == 0 ? 1 : (a == 1 ? 3 : 4);
+        const int i2 = a == 0 ? 2 : (a == 1 ? 4 : 5);
+#pragma unroll
+        for (int rd = 0; rd < XR; ++rd) {
+            __syncthreads();
+            if (round_of(ln) == rd) {
+                C* row = lds + slot_of(ln) * LS;
+#pragma unroll
+                for (int c = 0; c < P / Q; ++c) {
+#pragma unroll
+                    for (int gg = 0; gg < Q; ++gg) row[t + Q * c + P * gg] = v[0][c * Q + gg];
+                }
+            }
+            __syncthreads();
+            if (round_of(ln) == rd && ln < nval) {
+                const C* r0 = lds + slot_of(ln - a) * LS;
+                const C* r1 = r0 + LS;
+                const C* r2 = r1 + LS;
+                // xy is odd in x and y, xz in x and z, yz in y and z; the flips
+                // are selects (no branches)
+                const bool fxy = sx * sy < 0;
+                const bool a0 = a == 0, a1 = a == 1, a2 = a == 2;
+                auto flip = [](C u, bool f) {
+                    C r;
+                    r.x = f ? -u.x : u.x;
+                    r.y = f ? -u.y : u.y;
+                    return r;
+                };
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const int kz = t + Q * m;
+                    const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
+                    const bool zneg = kz > Mz / 2;
+                    const bool fxz = (sx < 0) != zneg, fyz = (sy < 0) != zneg;
+                    const C* Gp = ghat + (((long long)fz * Hy + fy) * Hx + fx) * 6;
+                    const C g0 = flip(Gp[a], (a1 & fxy) | (a2 & fxz));
+                    const C g1 = flip(Gp[i1], (a0 & fxy) | (a2 & fyz));
+                    const C g2 = flip(Gp[i2], (a0 & fxz) | (a1 & fyz));
+                    const C X = r0[kz], Y = r1[kz], Z = r2[kz];
+                    v[0][m] = cadd(cadd(cmul(g0, X), cmul(g1, Y)), cmul(g2, Z));
+                    if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        transform(std::integral_constant<int, 1>{}, std::integral_constant<bool, false>{},
+                  std::integral_constant<bool, HOUT>{});
+    } else if constexpr (GH) {
+        // y_a = sum_b Ghat_ab x_b at (kx = x0 + in, ky = o, kz = kappa + P g)
+        const int Mz = g.M[2];
+        const int Hx = g.H[0], Hy = g.H[1];
+        const int kx = x0 + in;
+        if (3 * in < nval) {
+            const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
+            const int sx = (kx <= Mx / 2) ? 1 : -1;
+            const int fy = (o <= My / 2) ? o : My - o;
+            const int sy = (o <= My / 2) ? 1 : -1;
+#pragma unroll
+            for (int c = 0; c < P / Q; ++c) {
+#pragma unroll
+                for (int gg = 0; gg < Q; ++gg) {
+                    const int kz = t + Q * c + P * gg;
+                    const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
+                    const int sz = (kz <= Mz / 2) ? 1 : -1;
+                    const C* Gp = ghat + (((long long)fz * Hy + fy) * Hx + fx) * 6;
+                    C G6[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) G6[k] = Gp[k];
+                    // parity flips as selects (no branches)
+                    const bool f1 = sx * sy < 0, f2 = sx * sz < 0, f4 = sy * sz < 0;
+                    G6[1].x = f1 ? -G6[1].x : G6[1].x;
+                    G6[1].y = f1 ? -G6[1].y : G6[1].y;
+                    G6[2].x = f2 ? -G6[2].x : G6[2].x;
+                    G6[2].y = f2 ? -G6[2].y : G6[2].y;
+                    G6[4].x = f4 ? -G6[4].x : G6[4].x;
+                    G6[4].y = f4 ? -G6[4].y : G6[4].y;
+                    const int sl = c * Q + gg;
+                    const C X = v[0][sl], Y = v[NCT > 1 ? 1 : 0][sl], Z = v[NCT > 2 ? 2 : 0][sl];
+                    v[0][sl] = cadd(cadd(cmul(G6[0], X), cmul(G6[1], Y)), cmul(G6[2], Z));
+                    v[NCT > 1 ? 1 : 0][sl] = cadd(cadd(cmul(G6[1], X), cmul(G6[3], Y)), cmul(G6[4], Z));
+                    v[NCT > 2 ? 2 : 0][sl] = cadd(cadd(cmul(G6[2], X), cmul(G6[4], Y)), cmul(G6[5], Z));
+                }
+            }
+        }
+        // back to subsequences: X[kappa + P g] -> thread t holds X[t + Q m]
+#pragma unroll
+        for (int rd = 0; rd < XR; ++rd) {
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NCT; ++a) {
+                const int ln = line_of(a);
+                if (round_of(ln) == rd) {
+                    C* row = lds + slot_of(ln) * LS;
+#pragma unroll
+                    for (int c = 0; c < P / Q; ++c) {
+#pragma unroll
+                        for (int gg = 0; gg < Q; ++gg) row[t + Q * c + P * gg] = v[a][c * Q + gg];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NCT; ++a) {
+                const int ln = line_of(a);
+                if (round_of(ln) == rd) {
+                    const C* row = lds + slot_of(ln) * LS;
+#pragma unroll
+                    for (int m = 0; m < P; ++m) v[a][m] = row[t + Q * m];
+                }
+            }
+        }
+        transform(std::integral_constant<int, 1>{}, std::integral_constant<bool, false>{},
+                  std::integral_constant<bool, HOUT>{});
+    }
+#pragma unroll
+    for (int a = 0; a < NCT; ++a) {
+        const int ln = line_of(a);
+        if (ln < nval) {
+#pragma unroll
+            for (int c = 0; c < P / Q; ++c) {
+#pragma unroll
+                for (int gg = 0; gg < (HOUT ? Q / 2 : Q); ++gg) {
+                    const int e = t + Q * c + P * gg;
+                    if (e < lout) gq[(long long)e * estride + ln] = v[a][c * Q + gg];
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename T, int MODE>
@@ -594,11 +889,16 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
     }
 }
 
-// Compile-time variants of a strided pass: (tile width, VAR).  Index 0 is
-// the default; the autotuner of the C ABI picks among them by timing.  Wider
-// tiles give longer contiguous runs per plane (what large grids need); they
-// are bounded by an LDS budget of 48 KB of tile per workgroup.
-constexpr int n_strided_variants(int gh) { return gh ? 10 : 4; }
+// Compile-time variants of a strided pass.  LDS form (k_strided, k_zfold):
+// (tile width, VAR), indices 0 .. n_lds_variants - 1, index 0 the default.
+// Register-resident form (k_strided_rf): (tile width, exchange rounds),
+// the following rf_variants indices.  The autotuner of the C ABI picks among
+// them by timing; all give bitwise-identical results.  Wider tiles give
+// longer contiguous runs per plane (what large grids need); LDS tiles are
+// bounded by 48 KB per workgroup.
+constexpr int n_lds_variants(int gh) { return gh ? 10 : 4; }
+constexpr int rf_variants(int gh) { return gh ? 12 : 4; }
+constexpr int n_strided_variants(int gh) { return n_lds_variants(gh) + rf_variants(gh); }
 template <typename T> constexpr int ct_budget() { return sizeof(T) == 4 ? 6144 : 3072; }
 template <typename T> constexpr int variant_tx(int L, int gh, int v) {
     const int base = ct_cols(L);
@@ -627,23 +927,75 @@ constexpr int variant_var(int gh, int v) {
     if (v >= 7) return 3;
     return v == 0 ? 0 : (v <= 2 ? 1 : 2);
 }
+// register-resident variant r (0 .. rf_variants-1): tile width, rounds,
+// (pass 3) the XCD-grouped workgroup order for r >= 4 (not r = 11) and one
+// component line per thread for r >= 8
+constexpr int rf_tx(int gh, int r) {
+    if (gh && r >= 8) return r < 10 ? 16 : 8;
+    return gh ? (r % 2 == 0 ? 16 : 8) : (r == 1 ? 16 : (r == 3 ? 4 : 8));
+}
+constexpr int rf_xr(int gh, int r) {
+    if (gh && r >= 8) return r == 8 ? 2 : (r == 9 ? 4 : (r == 10 ? 1 : 2));
+    return gh ? (r % 4 < 2 ? 3 : 1) : (r == 2 ? 3 : 1);
+}
+constexpr bool rf_xg(int gh, int r) { return gh && r >= 4 && r != 11; }
+constexpr bool rf_split(int gh, int r) { return gh && r >= 8; }
+constexpr int rf_nct(int gh, int r) { return gh && !rf_split(gh, r) ? 3 : 1; }
+// a register-resident variant exists where its data fit: at most 192 VGPRs
+// of line data per thread, 512 threads and 64 KB of LDS per workgroup
+template <typename T> constexpr bool rf_feasible(int L, int gh, int r) {
+    const int P = ct_split(L);
+    const int vgpr = rf_nct(gh, r) * P * (int)(2 * sizeof(T) / 4);
+    const int thr = rf_threads(L, rf_tx(gh, r), rf_nct(gh, r));
+    const size_t lds = (size_t)(3 * rf_tx(gh, r) / rf_xr(gh, r)) * (((L / P) * (P + 1)) | 1) * 2 * sizeof(T);
+    return P > 0 && vgpr <= 192 && thr <= 512 && lds <= 65536;
+}
 
 template <typename T, int NC, int GH, int DIR, int LL, int V>
 void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
                        typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
                        const RhsState* st, hipStream_t s) {
     using C = typename V2<T>::t;
-    constexpr int TX = variant_tx<T>(LL, GH, V);
-    constexpr int VR = variant_var(GH, V);
-    if constexpr (VR == 3) {
-        dim3 grd((g.H[0] + TX - 1) / TX, g.H[1], 1);
-        DDA_LAUNCH((k_zfold<T, LL, TX>), grd, dim3(NT), smem_ct<C>(LL, 3 * TX), s, g, grid, tw, ghat, st, nrhs, lin,
-                   lout, chk);
+    if constexpr (V >= n_lds_variants(GH)) {
+        constexpr int R = V - n_lds_variants(GH);
+        constexpr int TX = rf_tx(GH, R), XR = rf_xr(GH, R);
+        constexpr bool XG = rf_xg(GH, R);
+        constexpr bool SP = rf_split(GH, R);
+        const bool hin = (GH || DIR < 0) && 2 * lin <= LL;
+        const bool hout = (GH || DIR > 0) && 2 * lout <= LL;
+        // the instantiated pruning: both halves for pass 3, the input half of
+        // a forward and the output half of an inverse y pass
+        const bool pruned = GH ? (hin && hout) : (DIR < 0 ? hin : hout);
+        if constexpr (NC == 3 && rf_feasible<T>(LL, GH, R)) {
+            if (pruned) {
+                constexpr bool HI = GH || DIR < 0, HO = GH || DIR > 0;
+                const int ntx = (g.M[0] + TX - 1) / TX;
+                dim3 grd(ntx, n_outer, nrhs);
+                if (XG) {
+                    const long long groups = (long long)((ntx + 1) / 2) * (g.M[1] / 2 + 1);
+                    grd = dim3((unsigned)(((groups + N_XCD - 1) / N_XCD) * N_XCD * 4 * nrhs));
+                }
+                const dim3 blk(rf_threads(LL, TX, rf_nct(GH, R)));
+                const size_t shm = rf_smem<T, LL, TX, XR>();
+                DDA_LAUNCH((k_strided_rf<T, GH, DIR, LL, TX, XR, HI, HO, XG, SP>), grd, blk, shm, s, g, grid, tw,
+                           ghat, st, axis, lin, lout, chk, nrhs);
+                return;
+            }
+        }
+        strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
     } else {
-        const int gz = (GH && VR != 2) ? 1 : nrhs;
-        dim3 grd((g.M[0] + TX - 1) / TX, n_outer, gz);
-        DDA_LAUNCH((k_strided<T, NC, GH, DIR, LL, TX, VR>), grd, dim3(NT), smem_ct<C>(LL, NC * TX), s, g, grid, tw,
-                   ghat, st, nrhs, axis, TX, lin, lout, chk);
+        constexpr int TX = variant_tx<T>(LL, GH, V);
+        constexpr int VR = variant_var(GH, V);
+        if constexpr (VR == 3) {
+            dim3 grd((g.H[0] + TX - 1) / TX, g.H[1], 1);
+            DDA_LAUNCH((k_zfold<T, LL, TX>), grd, dim3(NT), smem_ct<C>(LL, 3 * TX), s, g, grid, tw, ghat, st, nrhs,
+                       lin, lout, chk);
+        } else {
+            const int gz = (GH && VR != 2) ? 1 : nrhs;
+            dim3 grd((g.M[0] + TX - 1) / TX, n_outer, gz);
+            DDA_LAUNCH((k_strided<T, NC, GH, DIR, LL, TX, VR>), grd, dim3(NT), smem_ct<C>(LL, NC * TX), s, g, grid,
+                       tw, ghat, st, nrhs, axis, TX, lin, lout, chk);
+        }
     }
 }
 
@@ -659,7 +1011,8 @@ void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_
             return;                                                                                          \
         }                                                                                                    \
         break;
-        DDA_V(1) DDA_V(2) DDA_V(3) DDA_V(4) DDA_V(5) DDA_V(6) DDA_V(7) DDA_V(8) DDA_V(9)
+        DDA_V(1) DDA_V(2) DDA_V(3) DDA_V(4) DDA_V(5) DDA_V(6) DDA_V(7) DDA_V(8) DDA_V(9) DDA_V(10) DDA_V(11)
+        DDA_V(12) DDA_V(13) DDA_V(14) DDA_V(15) DDA_V(16) DDA_V(17) DDA_V(18) DDA_V(19) DDA_V(20) DDA_V(21)
 #undef DDA_V
         default:
             break;
@@ -673,7 +1026,7 @@ void strided_dispatch(int variant, int axis, int chk, const Geo& g, int nrhs, in
                       hipStream_t s) {
     using C = typename V2<T>::t;
     const int L = g.M[axis];
-    if (NC == 3) {
+    if constexpr (NC == 3) {
         switch (L) {
 #define DDA_CASE(LL)                                                                                       \
     case LL:                                                                                              \
@@ -737,7 +1090,7 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
     }
 }
 
-static_assert(passes::n_strided_variants(1) == 10 && passes::n_strided_variants(0) == 4,
+static_assert(passes::n_strided_variants(1) == 22 && passes::n_strided_variants(0) == 8,
               "strided_variants() in dda_kernels.h counts these variants");
 
 #define DDA_INSTANTIATE_PASSES(T)                                                                                 \

@@ -327,22 +327,37 @@ def test_sphere1m_full_size(dda):
         assert abs(b["qabs"] / q_mie["qabs"] - 1) < 0.10
 
 
-@pytest.mark.parametrize("variant", range(1, 11))
+# boxes whose padded grids put every compile-time FFT length on the y and
+# the z axis (x extents small and ragged: partial column tiles)
+VARIANT_BOXES = [(13, 14, 32), (5, 24, 16), (5, 40, 48), (3, 64, 40), (3, 32, 128), (3, 128, 64)]
+
+
+def _box_target(dda, box, seed):
+    rng = np.random.default_rng(seed)
+    ijk = np.argwhere(rng.random(box) < 0.3).astype(np.int32)
+    ijk = np.unique(np.vstack([ijk, [[0, 0, 0], [b - 1 for b in box]]]), axis=0).astype(np.int32)
+    return dda.Target(ijk, np.full(len(ijk), 1.4 + 0.1j))
+
+
+@pytest.mark.parametrize("variant", range(2, 23))
 def test_every_tiling_variant_bitwise(dda, variant):
-    """Each compile-time tiling of the strided passes (including the
-    octant-folded z pass) gives the default tiling's product bitwise, on a
-    grid with odd x and y extents (mirror columns without partners) and two
-    right-hand sides."""
-    ijk = np.unique(np.random.default_rng(9).integers(0, [13, 14, 32], size=(2500, 3)), axis=0).astype(np.int32)
-    tgt = dda.Target(ijk, np.full(len(ijk), 1.4 + 0.1j))
-    assert tgt.grid == (25, 27, 64)
+    """Each compile-time form of the strided passes (LDS tilings, the
+    octant-folded z pass, the register-resident passes) gives the default
+    form's product bitwise, for every compile-time length on the y and z
+    axes, with ragged x tiles and two right-hand sides."""
     kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
     e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
-    xv = _cuda(w.random_vectors(6, (2, len(ijk), 3)))
-    for prec in ("fp64", "fp32_matvec"):
-        ref = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=1), kh, e0, xv)
-        y = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=variant), kh, e0, xv)
-        assert torch.equal(y, ref), (prec, variant)
+    seen = set()
+    for bi, box in enumerate(VARIANT_BOXES):
+        tgt = _box_target(dda, box, 90 + bi)
+        seen.update(tgt.grid[1:])
+        xv = _cuda(w.random_vectors(6 + bi, (2, tgt.n_sites, 3)))
+        for prec in ("fp64", "fp32_matvec"):
+            ref = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=1), kh, e0, xv)
+            y = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=variant), kh, e0,
+                          xv)
+            assert torch.equal(y, ref), (prec, variant, box, tgt.grid)
+    assert {32, 48, 64, 80, 96, 128, 256} <= seen
 
 
 # ------------------------------------------------------------------ adjoint at full size
