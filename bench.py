@@ -73,8 +73,9 @@ def log(*a):
 
 
 def kernel_source_digest() -> str:
+    """Digest of the sources that define the FFT pass kernels."""
     h = hashlib.sha256()
-    for f in ("dda_kernels.hip", "dda_device.h", "dda_passes.h", "dda_kernels.h"):
+    for f in ("dda_device.h", "dda_passes.h", "dda_kernels.h"):
         with open(os.path.join(ROOT, "paper_1202_3424_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -101,15 +102,22 @@ def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
     }
 
 
-def load_traffic(kernel: str):
+SLOT_OF_PASS = {"fft_y_fwd": 0, "fft_z_green": 1, "fft_y_inv": 2}
+
+
+def load_traffic(kernel: str, workload: str, precision: str, variants):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    this kernel and workload, if it was taken on the current kernel sources
+    and with the variant the autotuner chose in this run."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    slot = SLOT_OF_PASS.get(kernel)
+    if slot is not None and (variants is None or rec.get("variant") != variants[slot]):
         return None
     return rec.get("bytes_per_launch")
 
@@ -152,6 +160,47 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
                       f"x that estimate"}
 
 
+def plain_reference(dda, np, torch, jobs, results, ms_per_step):
+    """The plain method on the same workload: every right-hand side solved
+    alone, FP64 matvec, same tolerance, one after another, the tensor FFT of
+    each target reused (outside the timed region).  Returns its time, the speedup of the measured step and the
+    largest relative difference of each efficiency from it."""
+    import dataclasses
+    # the tensor FFT is computed once per target and reused by its solves
+    opts64 = [dataclasses.replace(o, precision="fp64", recompute_green=False) for _, o, _, _ in jobs]
+    def run():
+        out = []
+        for (t, o, kh, e0), o64 in zip(jobs, opts64):
+            for q in range(len(kh)):
+                out.append(dda.solve(t, o64, kh[q:q + 1], e0[q:q + 1], want_P=False)[1][0])
+        return out
+    run()   # tensor FFTs and autotuning, as in the measured warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    diff = {}
+    for k in ("qext", "qabs", "qsca"):
+        diff[k] = max(abs(r[k] - p[k]) / abs(p[k]) for r, p in zip(results, ref))
+    return {"ms": ms, "speedup": ms / ms_per_step, "max_rel_diff": diff,
+            "note": "each right-hand side solved alone with the FP64 matvec at the same tolerance, tensor FFT "
+                    "reused; max_rel_diff compares the measured step's efficiencies with these"}
+
+
+def copy_probe(mib: int = 1024, reps: int = 4):
+    """A plain device-to-device copy of known size (torch's copy kernel), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "copies": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,8 +209,14 @@ def main():
     ap.add_argument("--workload", default="ellipsoid51k", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32_matvec"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 single-RHS comparison")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
               "right-hand sides is a design note, not part of this build", file=sys.stderr)
@@ -241,7 +296,8 @@ def main():
     ms_tot, launches = timing[dominant]
     bytes_tot = pass_traffic(dominant, units)
     gbs = bytes_tot / (ms_tot * 1e-3) / 1e9
-    traffic = load_traffic(dominant) if len(jobs) == 1 else None
+    variants = dda.tuned_variants(jobs[0][0], len(jobs[0][2]), prec) if len(jobs) == 1 else None
+    traffic = load_traffic(dominant, args.workload, prec, variants) if len(jobs) == 1 else None
     roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
                 "algorithmic_bytes_per_launch": bytes_tot / launches, "avg_launch_us": ms_tot / launches * 1e3,
@@ -275,6 +331,7 @@ def main():
                    "rhs_per_step": n_rhs, "orientations_per_step": orientations, "precision": prec,
                    "seed": args.seed},
         "roofline": roofline,
+        "autotuned_variants": variants,
         "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9,
                    "units_per_step": sum(units) / args.steps, "passes_calibration_step": passes},
         "kernel_ms_calibration_step": {k: v[0] for k, v in calib.items()},
@@ -284,6 +341,9 @@ def main():
                    "normal_eq_residual": [r["normal_eq_residual"] for r in results][:8],
                    "refinements": [r["refinements"] for r in results][:8]},
     }
+    if not args.no_plain:
+        log("timing the plain FP64 single-right-hand-side solves of the same workload ...")
+        out["vs_plain_fp64_single_rhs"] = plain_reference(dda, np, torch, jobs, results, ms_per_step)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one polarization ...")
         out["cpu_baseline"] = cpu_baseline(d, args.workload, results[0]["iters"])

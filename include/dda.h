@@ -207,6 +207,15 @@ typedef struct {
 dda_status dda_ctx_set_timing(dda_ctx* ctx, int mask);
 dda_status dda_ctx_get_timing(dda_ctx* ctx, dda_timing* out);
 
+/* The strided-pass variants the autotuner chose for this context, target,
+ * right-hand-side count and precision: variants[0] forward y pass,
+ * variants[1] z pass with the tensor product, variants[2] inverse y pass
+ * (each the value opts->kernel_variant - 1 would force).  All three are -1
+ * when no solve with these parameters has been tuned yet.
+ * E_INVALID for NULL arguments, n_rhs < 1 or an unknown precision. */
+dda_status dda_ctx_tuned_variants(dda_ctx* ctx, const dda_target* t, int32_t n_rhs, dda_precision precision,
+                                  int32_t variants[3]);
+
 /* Description of the last error or warning on this thread ("" if none).
  * Valid until the next library call on the thread.  |m|kd >= 1 (the validity
  * bound of "Applicability of the DDA") is reported here as a warning. */

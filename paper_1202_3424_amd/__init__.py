@@ -12,7 +12,7 @@ The public names below load libdda.so on first use and raise ImportError if
 it has not been built: there is no fallback implementation.
 """
 _PUBLIC = ("DDAError", "Options", "QEff", "Target", "apply", "context", "get_timing", "grad_eps", "last_error",
-           "set_timing", "solve", "solve_batched", "solve_rhs")
+           "set_timing", "solve", "solve_batched", "solve_rhs", "tuned_variants")
 
 __all__ = list(_PUBLIC)
 

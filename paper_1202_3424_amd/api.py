@@ -285,6 +285,16 @@ def set_timing(categories=True, device: int | None = None) -> None:
     _check(_lib.dda_ctx_set_timing(context(device), mask), "dda_ctx_set_timing")
 
 
+def tuned_variants(target: "Target", n_rhs: int, precision: str = "fp64") -> tuple:
+    """(y forward, z with tensor, y inverse) strided-pass variants the
+    autotuner chose for this target, right-hand-side count and precision, or
+    (-1, -1, -1) before any such solve."""
+    out = (ctypes.c_int32 * 3)()
+    _check(_lib.dda_ctx_tuned_variants(target.ctx, target._h, int(n_rhs), _PREC[precision], out),
+           "dda_ctx_tuned_variants")
+    return tuple(int(v) for v in out)
+
+
 def get_timing(device: int | None = None) -> dict:
     """{category: (total ms, launches)} accumulated since set_timing(True)."""
     t = _abi.Timing()

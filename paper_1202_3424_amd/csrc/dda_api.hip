@@ -1210,6 +1210,21 @@ dda_status dda_ctx_get_timing(dda_ctx* c, dda_timing* out) {
     });
 }
 
+dda_status dda_ctx_tuned_variants(dda_ctx* c, const dda_target* t, int32_t n_rhs, dda_precision precision,
+                                  int32_t variants[3]) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !variants) invalid("NULL argument");
+        if (n_rhs < 1) invalid("n_rhs must be >= 1");
+        if (precision != DDA_FP64 && precision != DDA_FP32_MATVEC) invalid("unknown precision");
+        const Geo& g = t->geo;
+        auto key = std::make_tuple(g.M[0], g.M[1], g.M[2], g.n[0], g.n[1], g.n[2], (int)n_rhs,
+                                   precision == DDA_FP32_MATVEC ? 1 : 0);
+        auto it = c->tuned.find(key);
+        for (int i = 0; i < 3; ++i) variants[i] = it == c->tuned.end() ? -1 : it->second[i];
+        return DDA_OK;
+    });
+}
+
 const char* dda_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

@@ -401,59 +401,70 @@ constexpr bool ct_half_out_ok(int L) { return ct_plan(L, ct_plan(L, -1) - 1) % 2
 // whose frequency agrees modulo P (second group), which is what lets a thread
 // run a whole group on its own registers.
 
-// First group on one subsequence, thread index t: on entry v[m] = x[t + Q m];
-// on exit v[f] = element t*P + f.  HIN: x[e] = 0 for e >= L/2 (the first pass
-// reads only its lower inputs, as fft_pass_ct does).
-template <typename T, int DIR, int L, bool HIN, int S = 0, int NS = 1>
-__device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[ct_split(L)], const double2* tw) {
+// First group on NCL lines of one subsequence each (the lines share the
+// twiddles), thread index t: on entry v[a][m] = x_a[t + Q m]; on exit
+// v[a][f] = element t*P + f of line a.  HIN: x[e] = 0 for e >= L/2 (the
+// first pass reads only its lower inputs, as fft_pass_ct does).
+template <typename T, int DIR, int L, bool HIN, int NCL, int S = 0, int NS = 1>
+__device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[NCL][ct_split(L)], const double2* tw) {
     using C = typename V2<T>::t;
     constexpr int P = ct_split(L);
     if constexpr (NS < P) {
         constexpr int R = ct_plan(L, S);
         constexpr int TSTEP = L / (NS * R);
         constexpr bool HI = HIN && S == 0;
-        C o[P];
+        C o[NCL][P];
 #pragma unroll
         for (int u0 = 0; u0 < P / (NS * R); ++u0) {
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                C b[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (HI && 2 * r >= R) {
-                        b[r].x = 0;
-                        b[r].y = 0;
-                    } else {
-                        b[r] = v[u0 * NS + k + r * (P / R)];
-                    }
-                }
+                C w[R];
                 if constexpr (NS > 1) {
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
-                        const double2 w = tw[r * k * TSTEP];
-                        C c;
-                        c.x = (decltype(c.x))w.x;
-                        c.y = (decltype(c.y))(DIR > 0 ? -w.y : w.y);
-                        b[r] = cmul(b[r], c);
+                        const double2 t = tw[r * k * TSTEP];
+                        w[r].x = (decltype(w[r].x))t.x;
+                        w[r].y = (decltype(w[r].y))(DIR > 0 ? -t.y : t.y);
                     }
                 }
-                Dft<R, DIR, C>::run(b);
 #pragma unroll
-                for (int q = 0; q < R; ++q) o[u0 * NS * R + k + q * NS] = b[q];
+                for (int a = 0; a < NCL; ++a) {
+                    C b[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (HI && 2 * r >= R) {
+                            b[r].x = 0;
+                            b[r].y = 0;
+                        } else {
+                            b[r] = v[a][u0 * NS + k + r * (P / R)];
+                        }
+                    }
+                    if constexpr (NS > 1) {
+#pragma unroll
+                        for (int r = 1; r < R; ++r) b[r] = cmul(b[r], w[r]);
+                    }
+                    Dft<R, DIR, C>::run(b);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) o[a][u0 * NS * R + k + q * NS] = b[q];
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < P; ++i) v[i] = o[i];
-        rf_group_a<T, DIR, L, HIN, S + 1, NS * R>(v, tw);
+        for (int a = 0; a < NCL; ++a) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) v[a][i] = o[a][i];
+        }
+        rf_group_a<T, DIR, L, HIN, NCL, S + 1, NS * R>(v, tw);
     }
 }
 
 // Second group on residue classes kappa_c = t + Q c (c < P/Q) of the first
-// group's frequency: on entry v[c*Q + jj] = element jj*P + kappa_c; on exit
-// v[c*Q + g] = X[kappa_c + P g].  HOUT: only X[e], e < L/2, is wanted (the
-// last pass computes only its lower outputs, as fft_pass_ct does).
-template <typename T, int DIR, int L, bool HOUT, int S = ct_split_passes(L), int NS = ct_split(L)>
-__device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[ct_split(L)], int t, const double2* tw) {
+// group's frequency, NCL lines sharing the twiddles: on entry
+// v[a][c*Q + jj] = element jj*P + kappa_c of line a; on exit
+// v[a][c*Q + g] = X_a[kappa_c + P g].  HOUT: only X[e], e < L/2, is wanted
+// (the last pass computes only its lower outputs, as fft_pass_ct does).
+template <typename T, int DIR, int L, bool HOUT, int NCL, int S = ct_split_passes(L), int NS = ct_split(L)>
+__device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[NCL][ct_split(L)], int t, const double2* tw) {
     using C = typename V2<T>::t;
     constexpr int P = ct_split(L);
     constexpr int Q = L / P;
@@ -463,7 +474,7 @@ __device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[ct_split(L)], 
         constexpr int TSTEP = L / (NS * R);
         constexpr bool HO = HOUT && S == NST - 1;
         constexpr int G = NS / P;
-        C o[P];
+        C o[NCL][P];
 #pragma unroll
         for (int c = 0; c < P / Q; ++c) {
             const int kappa = t + Q * c;
@@ -472,29 +483,36 @@ __device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[ct_split(L)], 
 #pragma unroll
                 for (int gk = 0; gk < G; ++gk) {
                     const int ks = kappa + P * gk;
-                    C b[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) b[r] = v[c * Q + (jh + r * (L / (R * NS))) * G + gk];
+                    C w[R];
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
-                        const double2 w = tw[r * ks * TSTEP];
-                        C cw;
-                        cw.x = (decltype(cw.x))w.x;
-                        cw.y = (decltype(cw.y))(DIR > 0 ? -w.y : w.y);
-                        b[r] = cmul(b[r], cw);
+                        const double2 tt = tw[r * ks * TSTEP];
+                        w[r].x = (decltype(w[r].x))tt.x;
+                        w[r].y = (decltype(w[r].y))(DIR > 0 ? -tt.y : tt.y);
                     }
-                    Dft<R, DIR, C>::run(b);
 #pragma unroll
-                    for (int q = 0; q < R; ++q) {
-                        if (!HO || 2 * q < R) o[c * Q + jh * G * R + gk + q * G] = b[q];
-                        else o[c * Q + jh * G * R + gk + q * G] = b[0];   // never stored
+                    for (int a = 0; a < NCL; ++a) {
+                        C b[R];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) b[r] = v[a][c * Q + (jh + r * (L / (R * NS))) * G + gk];
+#pragma unroll
+                        for (int r = 1; r < R; ++r) b[r] = cmul(b[r], w[r]);
+                        Dft<R, DIR, C>::run(b);
+#pragma unroll
+                        for (int q = 0; q < R; ++q) {
+                            if (!HO || 2 * q < R) o[a][c * Q + jh * G * R + gk + q * G] = b[q];
+                            else o[a][c * Q + jh * G * R + gk + q * G] = b[0];   // never stored
+                        }
                     }
                 }
             }
         }
 #pragma unroll
-        for (int i = 0; i < P; ++i) v[i] = o[i];
-        rf_group_b<T, DIR, L, HOUT, S + 1, NS * R>(v, t, tw);
+        for (int a = 0; a < NCL; ++a) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) v[a][i] = o[a][i];
+        }
+        rf_group_b<T, DIR, L, HOUT, NCL, S + 1, NS * R>(v, t, tw);
     }
 }
 

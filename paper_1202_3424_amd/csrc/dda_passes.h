@@ -572,30 +572,24 @@ template <typename T, int L, int TX, int XR> constexpr size_t rf_smem() {
     return (size_t)(3 * TX / XR) * rf_line_stride<L>() * sizeof(typename V2<T>::t);
 }
 
-// SPLIT (pass 3 only): one component line per thread, like passes 2 and 4
-// (coalesced loads, fewer registers); the tensor product is then applied
-// during the middle exchange, each thread reading the three components of
-// its column from LDS and forming its own component of the product.  The
-// exchange rounds then go over columns (TX / XR columns per round).
 // XG (pass 3 only): the grid is one-dimensional and ordered so that the
 // workgroups sharing tensor values -- the column tiles x and Mx - x, the rows
 // y and My - y, every right-hand side -- run consecutively on one XCD
 // (workgroups go to the eight XCDs round-robin), so each XCD's L2 serves
 // the repeats and the tensor is read from HBM about once per launch.
 constexpr int N_XCD = 8;
-// Occupancy asked of the compiler for one line per thread: four waves per
-// SIMD (128 VGPRs) when the line data take at most 32 VGPRs, three (168)
-// up to 64, two (256) for the four-pass length 256 (no spills in any case);
-// otherwise the compiler's own choice stands.
-template <typename T> constexpr int rf_waves(int L, int nct) {
+// Occupancy asked of the compiler for passes 2 and 4 (one line per thread):
+// four waves per SIMD (128 VGPRs) when the line data take at most 32 VGPRs,
+// three (168) up to 64, two (256) for the four-pass length 256 -- none of
+// which spills.  For pass 3 the occupancy is a tuning choice (WV).
+template <typename T> constexpr int rf_waves(int L) {
     const int d = ct_split(L) * (int)(2 * sizeof(T) / 4);
-    if (nct != 1) return 1;
     if (L == 256) return 2;
     return d <= 32 ? 4 : (d <= 64 ? 3 : 1);
 }
-template <typename T, int GH, int DIR, int L, int TX, int XR, bool HIN, bool HOUT, bool XG = false, bool SPLIT = false>
-__global__ __launch_bounds__(rf_threads(L, TX, GH && !SPLIT ? 3 : 1))
-__attribute__((amdgpu_waves_per_eu(rf_waves<T>(L, GH && !SPLIT ? 3 : 1)))) void k_strided_rf(Geo g, typename V2<T>::t* grid,
+template <typename T, int GH, int DIR, int L, int TX, int XR, bool HIN, bool HOUT, bool XG, int WV>
+__global__ __launch_bounds__(rf_threads(L, TX, GH ? 3 : 1))
+__attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf(Geo g, typename V2<T>::t* grid,
                                                                        const double2* tw64,
                                                                        const typename V2<T>::t* ghat,
                                                                        const RhsState* st, int axis, int lin,
@@ -603,15 +597,13 @@ __attribute__((amdgpu_waves_per_eu(rf_waves<T>(L, GH && !SPLIT ? 3 : 1)))) void 
     using C = typename V2<T>::t;
     constexpr int P = ct_split(L);
     constexpr int Q = L / P;
-    constexpr int NCT = (GH && !SPLIT) ? 3 : 1;   // component lines per thread
+    constexpr int NCT = GH ? 3 : 1;               // component lines per thread
     constexpr int NIN = NCT == 3 ? TX : 3 * TX;   // threads across the tile's lines
     constexpr int LS = rf_line_stride<L>();
-    static_assert((SPLIT ? TX : 3 * TX) % XR == 0, "exchange rounds must split the tile's lines");
+    static_assert((3 * TX) % XR == 0, "exchange rounds must split the tile's lines");
     // exchange round and LDS row of line ln
-    auto round_of = [](int ln) { return SPLIT ? (ln / 3) % XR : ln % XR; };
-    auto slot_of = [](int ln) { return SPLIT ? ((ln / 3) / XR) * 3 + ln % 3 : ln / XR; };
-    // scheduling fence between the steps of the split product (register pressure)
-    constexpr bool FENCE = SPLIT;
+    auto round_of = [](int ln) { return ln % XR; };
+    auto slot_of = [](int ln) { return ln / XR; };
     extern __shared__ __align__(16) unsigned char smem[];
     C* lds = (C*)smem;
     const int Mx = g.M[0], My = g.M[1];
@@ -668,8 +660,7 @@ __attribute__((amdgpu_waves_per_eu(rf_waves<T>(L, GH && !SPLIT ? 3 : 1)))) void 
         constexpr int D = decltype(dir_tag)::value;
         constexpr bool HI = decltype(hin_tag)::value;
         constexpr bool HO = decltype(hout_tag)::value;
-#pragma unroll
-        for (int a = 0; a < NCT; ++a) rf_group_a<T, D, L, HI>(v[a], tw);
+        rf_group_a<T, D, L, HI, NCT>(v, tw);
 #pragma unroll
         for (int rd = 0; rd < XR; ++rd) {
             __syncthreads();
@@ -696,73 +687,12 @@ __attribute__((amdgpu_waves_per_eu(rf_waves<T>(L, GH && !SPLIT ? 3 : 1)))) void 
                 }
             }
         }
-#pragma unroll
-        for (int a = 0; a < NCT; ++a) rf_group_b<T, D, L, HO>(v[a], t, tw);
+        rf_group_b<T, D, L, HO, NCT>(v, t, tw);
     };
     using Fwd = std::integral_constant<int, GH ? -1 : DIR>;
     transform(Fwd{}, std::integral_constant<bool, HIN>{},
               std::integral_constant<bool, GH ? false : HOUT>{});
-    if constexpr (GH && SPLIT) {
-        // exchange to subsequences with the product: thread (column, a, t)
-        // forms y_a = sum_b Ghat_ab x_b at kz = t + Q m from the three
-        // component rows of its column
-        const int Mz = g.M[2];
-        const int Hx = g.H[0], Hy = g.H[1];
-        const int ln = in;
-        const int a = ln % 3;
-        const int kx = x0 + ln / 3;
-        const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
-        const int sx = (kx <= Mx / 2) ? 1 : -1;
-        const int fy = (o <= My / 2) ? o : My - o;
-        const int sy = (o <= My / 2) ? 1 : -1;
-        // tensor row a: components (a, i1, i2) of (xx, xy, xz, yy, yz, zz)
-        const int i1 = a == 0 ? 1 : (a == 1 ? 3 : 4);
-        const int i2 = a == 0 ? 2 : (a == 1 ? 4 : 5);
-#pragma unroll
-        for (int rd = 0; rd < XR; ++rd) {
-            __syncthreads();
-            if (round_of(ln) == rd) {
-                C* row = lds + slot_of(ln) * LS;
-#pragma unroll
-                for (int c = 0; c < P / Q; ++c) {
-#pragma unroll
-                    for (int gg = 0; gg < Q; ++gg) row[t + Q * c + P * gg] = v[0][c * Q + gg];
-                }
-            }
-            __syncthreads();
-            if (round_of(ln) == rd && ln < nval) {
-                const C* r0 = lds + slot_of(ln - a) * LS;
-                const C* r1 = r0 + LS;
-                const C* r2 = r1 + LS;
-                // xy is odd in x and y, xz in x and z, yz in y and z; the flips
-                // are selects (no branches)
-                const bool fxy = sx * sy < 0;
-                const bool a0 = a == 0, a1 = a == 1, a2 = a == 2;
-                auto flip = [](C u, bool f) {
-                    C r;
-                    r.x = f ? -u.x : u.x;
-                    r.y = f ? -u.y : u.y;
-                    return r;
-                };
-#pragma unroll
-                for (int m = 0; m < P; ++m) {
-                    const int kz = t + Q * m;
-                    const int fz = (kz <= Mz / 2) ? kz : Mz - kz;
-                    const bool zneg = kz > Mz / 2;
-                    const bool fxz = (sx < 0) != zneg, fyz = (sy < 0) != zneg;
-                    const C* Gp = ghat + (((long long)fz * Hy + fy) * Hx + fx) * 6;
-                    const C g0 = flip(Gp[a], (a1 & fxy) | (a2 & fxz));
-                    const C g1 = flip(Gp[i1], (a0 & fxy) | (a2 & fyz));
-                    const C g2 = flip(Gp[i2], (a0 & fxz) | (a1 & fyz));
-                    const C X = r0[kz], Y = r1[kz], Z = r2[kz];
-                    v[0][m] = cadd(cadd(cmul(g0, X), cmul(g1, Y)), cmul(g2, Z));
-                    if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
-        transform(std::integral_constant<int, 1>{}, std::integral_constant<bool, false>{},
-                  std::integral_constant<bool, HOUT>{});
-    } else if constexpr (GH) {
+    if constexpr (GH) {
         // y_a = sum_b Ghat_ab x_b at (kx = x0 + in, ky = o, kz = kappa + P g)
         const int Mz = g.M[2];
         const int Hx = g.H[0], Hy = g.H[1];
@@ -927,26 +857,23 @@ constexpr int variant_var(int gh, int v) {
     if (v >= 7) return 3;
     return v == 0 ? 0 : (v <= 2 ? 1 : 2);
 }
-// register-resident variant r (0 .. rf_variants-1): tile width, rounds,
-// (pass 3) the XCD-grouped workgroup order for r >= 4 (not r = 11) and one
-// component line per thread for r >= 8
-constexpr int rf_tx(int gh, int r) {
-    if (gh && r >= 8) return r < 10 ? 16 : 8;
-    return gh ? (r % 2 == 0 ? 16 : 8) : (r == 1 ? 16 : (r == 3 ? 4 : 8));
+// register-resident variant r (0 .. rf_variants-1): tile width and rounds;
+// for pass 3 also the XCD-grouped workgroup order (r >= 4) and an occupancy
+// of three waves per SIMD asked of the compiler (r >= 8, where the line data
+// take at most 96 VGPRs; a few spilled registers are the price)
+constexpr int rf_tx(int gh, int r) { return gh ? (r % 2 == 0 ? 16 : 8) : (r == 1 ? 16 : (r == 3 ? 4 : 8)); }
+constexpr int rf_xr(int gh, int r) { return gh ? (r % 4 < 2 ? 3 : 1) : (r == 2 ? 3 : 1); }
+constexpr bool rf_xg(int gh, int r) { return gh && r >= 4; }
+template <typename T> constexpr int rf_wv(int L, int gh, int r) {
+    return (gh && r >= 8 && 3 * ct_split(L) * (int)(2 * sizeof(T) / 4) <= 96) ? 3 : 1;
 }
-constexpr int rf_xr(int gh, int r) {
-    if (gh && r >= 8) return r == 8 ? 2 : (r == 9 ? 4 : (r == 10 ? 1 : 2));
-    return gh ? (r % 4 < 2 ? 3 : 1) : (r == 2 ? 3 : 1);
-}
-constexpr bool rf_xg(int gh, int r) { return gh && r >= 4 && r != 11; }
-constexpr bool rf_split(int gh, int r) { return gh && r >= 8; }
-constexpr int rf_nct(int gh, int r) { return gh && !rf_split(gh, r) ? 3 : 1; }
+constexpr int rf_nct(int gh) { return gh ? 3 : 1; }
 // a register-resident variant exists where its data fit: at most 192 VGPRs
 // of line data per thread, 512 threads and 64 KB of LDS per workgroup
 template <typename T> constexpr bool rf_feasible(int L, int gh, int r) {
     const int P = ct_split(L);
-    const int vgpr = rf_nct(gh, r) * P * (int)(2 * sizeof(T) / 4);
-    const int thr = rf_threads(L, rf_tx(gh, r), rf_nct(gh, r));
+    const int vgpr = rf_nct(gh) * P * (int)(2 * sizeof(T) / 4);
+    const int thr = rf_threads(L, rf_tx(gh, r), rf_nct(gh));
     const size_t lds = (size_t)(3 * rf_tx(gh, r) / rf_xr(gh, r)) * (((L / P) * (P + 1)) | 1) * 2 * sizeof(T);
     return P > 0 && vgpr <= 192 && thr <= 512 && lds <= 65536;
 }
@@ -960,7 +887,7 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
         constexpr int R = V - n_lds_variants(GH);
         constexpr int TX = rf_tx(GH, R), XR = rf_xr(GH, R);
         constexpr bool XG = rf_xg(GH, R);
-        constexpr bool SP = rf_split(GH, R);
+        constexpr int WV = rf_wv<T>(LL, GH, R);
         const bool hin = (GH || DIR < 0) && 2 * lin <= LL;
         const bool hout = (GH || DIR > 0) && 2 * lout <= LL;
         // the instantiated pruning: both halves for pass 3, the input half of
@@ -975,9 +902,9 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                     const long long groups = (long long)((ntx + 1) / 2) * (g.M[1] / 2 + 1);
                     grd = dim3((unsigned)(((groups + N_XCD - 1) / N_XCD) * N_XCD * 4 * nrhs));
                 }
-                const dim3 blk(rf_threads(LL, TX, rf_nct(GH, R)));
+                const dim3 blk(rf_threads(LL, TX, rf_nct(GH)));
                 const size_t shm = rf_smem<T, LL, TX, XR>();
-                DDA_LAUNCH((k_strided_rf<T, GH, DIR, LL, TX, XR, HI, HO, XG, SP>), grd, blk, shm, s, g, grid, tw,
+                DDA_LAUNCH((k_strided_rf<T, GH, DIR, LL, TX, XR, HI, HO, XG, WV>), grd, blk, shm, s, g, grid, tw,
                            ghat, st, axis, lin, lout, chk, nrhs);
                 return;
             }
