@@ -232,7 +232,11 @@ def main():
     torch.cuda.set_device(0)
     desc, prec = WORKLOADS[args.workload]
     prec = args.precision or prec
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
     jobs, orientations, d = build_jobs(dda, w, args.workload, args.seed, prec)
+    torch.cuda.synchronize()
+    target_create_ms = (time.perf_counter() - t_create) * 1e3
     n_rhs = sum(len(j[2]) for j in jobs)
     log(f"workload {args.workload}: {len(jobs)} target(s), {n_rhs} right-hand sides, prec={prec}, "
         f"first target N={jobs[0][0].n_sites} grid={jobs[0][0].grid}")
@@ -332,6 +336,7 @@ def main():
                    "seed": args.seed},
         "roofline": roofline,
         "autotuned_variants": variants,
+        "target_create_ms": target_create_ms,
         "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9,
                    "units_per_step": sum(units) / args.steps, "passes_calibration_step": passes},
         "kernel_ms_calibration_step": {k: v[0] for k, v in calib.items()},
