@@ -17,6 +17,7 @@ BiCGSTAB is van der Vorst (1992), the PBCGST option of "Choice of Iterative
 Algorithm", with x0 = 0 (the guide's usual starting guess), shadow residual
 r^ = r0 and conjugated inner products <u, v> = sum conj(u) v.  It stops when
 |E - A P| / |E| < tol, checked after the half step (s) and after the full step.
+``qmr_sym`` is the QMRCCG option of the same section (see its docstring).
 """
 from __future__ import annotations
 
@@ -171,8 +172,72 @@ def bicgstab(apply, b, tol: float, max_iter: int, x0=None):
     return x, dict(iters=max_iter, matvecs=matvecs, rel_residual=float(rn), converged=False)
 
 
+def qmr_sym(apply, b, tol: float, max_iter: int, x0=None, trace=None):
+    """QMR for complex-symmetric A (the guide's QMRCCG option of "Choice of
+    Iterative Algorithm"), read as conjugate orthogonal CG (COCG; van der
+    Vorst & Melissen 1990) followed by quasi-minimal-residual smoothing
+    (Zhou & Walker 1994) of its iterates and residuals.
+
+    COCG is CG with the unconjugated bilinear form u^T v, which A = A^T makes
+    a valid Petrov-Galerkin condition: rho_k = r_k^T r_k, p_k = r_k +
+    (rho_k / rho_{k-1}) p_{k-1}, alpha_k = rho_k / (p_k^T A p_k), x_{k+1} =
+    x_k + alpha_k p_k, r_{k+1} = r_k - alpha_k A p_k.  The smoothing keeps
+    tau_k (1/tau_k^2 = 1/tau_{k-1}^2 + 1/|r_k|^2, tau_0 = |r_0|) and replaces
+    (y, s) by the convex combination (tau_k^2/tau_{k-1}^2)(y, s) +
+    (tau_k^2/|r_k|^2)(x_k, r_k), so that s_k = b - A y_k.  It stops when
+    |s_k| / |b| < tol and returns y.  ``trace``, if a list, receives
+    dict(r, s, y, tau2) after every step (for the pins).
+
+    Returns (y, info) with info = dict(iters, matvecs, rel_residual (of s),
+    converged)."""
+    b = np.asarray(b, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    matvecs = 0
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - apply(x)
+        matvecs += 1
+    y = x.copy()
+    s = r.copy()
+    tau2 = float(np.vdot(r, r).real)
+    if trace is not None:
+        trace.append(dict(r=r.copy(), s=s.copy(), y=y.copy(), tau2=tau2))
+    sn = np.sqrt(tau2) / bnorm
+    if sn < tol:
+        return y, dict(iters=0, matvecs=matvecs, rel_residual=float(sn), converged=True)
+    p = np.zeros_like(b)
+    rho_old = None
+    for it in range(1, max_iter + 1):
+        rho = np.sum(r * r)
+        beta = 0.0 if rho_old is None else rho / rho_old
+        p = r + beta * p
+        q = apply(p)
+        matvecs += 1
+        alpha = rho / np.sum(p * q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rho_old = rho
+        nu2 = float(np.vdot(r, r).real)
+        tau2_new = 1.0 / (1.0 / tau2 + 1.0 / nu2)
+        w_old, w_new = tau2_new / tau2, tau2_new / nu2
+        s = w_old * s + w_new * r
+        y = w_old * y + w_new * x
+        tau2 = tau2_new
+        if trace is not None:
+            trace.append(dict(r=r.copy(), s=s.copy(), y=y.copy(), tau2=tau2))
+        sn = np.linalg.norm(s) / bnorm
+        if sn < tol:
+            return y, dict(iters=it, matvecs=matvecs, rel_residual=float(sn), converged=True)
+    return y, dict(iters=max_iter, matvecs=matvecs, rel_residual=float(sn), converged=False)
+
+
+SOLVERS = {"bicgstab": bicgstab, "qmr": qmr_sym}
+
+
 def solve_case(ijk, m_sites, x: float, khat, e0, tol: float, scheme: str = dense.LATTDR,
-               m_medium: float = 1.0, max_iter: int = 1000) -> dict:
+               m_medium: float = 1.0, max_iter: int = 1000, solver: str = "bicgstab") -> dict:
     """FFT-BiCGSTAB solve of one right-hand side; returns P, E, the Q's and
     solver counts (Q_sca = Q_ext - Q_abs here; the closed form is O(N^2))."""
     n = len(ijk)
@@ -181,7 +246,7 @@ def solve_case(ijk, m_sites, x: float, khat, e0, tol: float, scheme: str = dense
     ainv = dense.site_alpha_inverse(m_rel, k, khat, e0, scheme)
     op = FFTOperator(ijk, ainv, k)
     E = dense.incident_field(ijk, k, khat, e0)
-    P, info = bicgstab(op.apply, E, tol, max_iter)
+    P, info = SOLVERS[solver](op.apply, E, tol, max_iter)
     qe, qa = dense.q_ext(E, P, k), dense.q_abs(P, ainv, k)
     true_res = float(np.linalg.norm(E - op.apply(P)) / np.linalg.norm(E))
     return dict(P=P, E=E, alpha_inv=ainv, k=k, op=op, qext=qe, qabs=qa, qsca=qe - qa,

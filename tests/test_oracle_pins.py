@@ -263,6 +263,56 @@ def test_bicgstab_matches_lu():
     assert abs(it["qext"] - lu["qext"]) < 1e-9
 
 
+def test_qmr_matches_lu():
+    """QMR (COCG with quasi-minimal-residual smoothing) reaches the LU
+    solution of the same system."""
+    d = w.workload("sphere389")
+    lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][1], d["e0"][1], with_qsca=False)
+    it = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][1], d["e0"][1], tol=1e-10, solver="qmr")
+    assert it["converged"] and it["true_residual"] < 1e-9
+    assert np.abs(it["P"] - lu["P"]).max() < 1e-8 * np.abs(lu["P"]).max()
+    assert abs(it["qext"] - lu["qext"]) < 1e-9
+
+
+def _qmr_trace(name="sphere389", pol=0, steps=12):
+    d = w.workload(name)
+    k = dense.kd_from_size_parameter(d["x"], len(d["ijk"]))
+    ainv = dense.site_alpha_inverse(d["m"], k, d["khat"][pol], d["e0"][pol], dense.LATTDR)
+    A = dense.assemble(d["ijk"], ainv, k)
+    E = dense.incident_field(d["ijk"], k, d["khat"][pol], d["e0"][pol])
+    trace = []
+    fftsolve.qmr_sym(lambda v: (A @ v.reshape(-1)).reshape(v.shape), E, 1e-14, steps, trace=trace)
+    return A, E, trace
+
+
+def test_qmr_smoothed_residual_is_residual_of_smoothed_iterate():
+    """The smoothing must carry (y, s) together: s_k = E - A y_k at every
+    step, and tau_k decreases with |s_k| <= sqrt(k+1) tau_k (the
+    quasi-minimal residual bound)."""
+    A, E, trace = _qmr_trace()
+    en = np.linalg.norm(E)
+    for k, t in enumerate(trace):
+        res = E.reshape(-1) - A @ t["y"].reshape(-1)
+        assert np.linalg.norm(res - t["s"].reshape(-1)) < 1e-11 * en, k
+        assert np.linalg.norm(t["s"]) <= math.sqrt(k + 1) * math.sqrt(t["tau2"]) * (1 + 1e-12), k
+        if k:
+            assert t["tau2"] < trace[k - 1]["tau2"]
+
+
+def test_cocg_residuals_are_bilinearly_orthogonal():
+    """COCG's residuals are orthogonal in the unconjugated form u^T v (the
+    Galerkin condition that A = A^T permits), not in the Hermitian one."""
+    A, E, trace = _qmr_trace(steps=8)
+    rs = [t["r"].reshape(-1) for t in trace]
+    herm = 0.0
+    for j in range(len(rs)):
+        for k in range(j + 1, len(rs)):
+            scale = np.linalg.norm(rs[j]) * np.linalg.norm(rs[k])
+            assert abs(np.sum(rs[j] * rs[k])) < 1e-9 * scale, (j, k)
+            herm = max(herm, abs(np.vdot(rs[j], rs[k])) / scale)
+    assert herm > 1e-3
+
+
 def test_normal_equation_residual_definition():
     """eq. err_tol: |A^H A P - A^H E| / |A^H E| is zero at the exact solution
     and equals the explicit expression for a perturbed P."""
