@@ -57,15 +57,23 @@ typedef enum {
     DDA_E_NOMEM = 2,          /* device or host allocation failed */
     DDA_E_DEVICE = 3,         /* a HIP call failed */
     DDA_E_NOT_CONVERGED = 4,  /* max_iter reached; best iterate returned */
-    DDA_E_BREAKDOWN = 5,      /* Krylov breakdown persisted after one restart */
+    DDA_E_BREAKDOWN = 5,      /* Krylov breakdown (BiCGSTAB: after one restart) */
     DDA_E_NONFINITE = 6       /* NaN or Inf met in the iteration */
 } dda_status;
 
 /* Polarizability prescription ("Dipole Polarizabilities"). */
 typedef enum { DDA_LATTDR = 0, DDA_GKDLDR = 1 } dda_polarizability;
 
-/* Iterative method ("Choice of Iterative Algorithm"): PBCGST = BiCGSTAB. */
-typedef enum { DDA_BICGSTAB = 0 } dda_solver;
+/* Iterative method ("Choice of Iterative Algorithm"):
+ *   DDA_BICGSTAB  PBCGST: BiCGSTAB (van der Vorst 1992), two products per
+ *                 iteration; one automatic restart after a breakdown.
+ *   DDA_QMR_SYM   QMRCCG: QMR for complex-symmetric A, read as COCG (van der
+ *                 Vorst & Melissen 1990) with quasi-minimal-residual smoothing
+ *                 (Zhou & Walker 1994); one product per iteration; stops on
+ *                 the smoothed residual |E - A P| / |E| < tol and returns the
+ *                 smoothed iterate; a breakdown (P^T A P = 0 or r^T r = 0) ends
+ *                 the solve with DDA_E_BREAKDOWN and that iterate (no restart). */
+typedef enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1 } dda_solver;
 
 /* Arithmetic of the FFT matrix-vector product.  The Krylov recurrences,
  * inner products, diagonal term and residual checks are FP64 in both modes

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NOT_
 DDA_LATTDR = 0
 DDA_GKDLDR = 1
 DDA_BICGSTAB = 0
+DDA_QMR_SYM = 1
 DDA_FP64 = 0
 DDA_FP32_MATVEC = 1
 DDA_FLAG_RECOMPUTE_GREEN = 1

@@ -57,6 +57,7 @@ def context(device: int | None = None) -> ctypes.c_void_p:
 
 _POLZ = {"LATTDR": _abi.DDA_LATTDR, "GKDLDR": _abi.DDA_GKDLDR}
 _PREC = {"fp64": _abi.DDA_FP64, "fp32_matvec": _abi.DDA_FP32_MATVEC}
+_SOLVER = {"bicgstab": _abi.DDA_BICGSTAB, "qmr": _abi.DDA_QMR_SYM}
 
 
 @dataclass
@@ -70,6 +71,7 @@ class Options:
     max_iter: int = 1000
     polarizability: str = "LATTDR"
     precision: str = "fp64"
+    solver: str = "bicgstab"
     recompute_green: bool = False
     final_checks: bool = True
     autotune: bool = True
@@ -89,7 +91,7 @@ class Options:
         if not self.autotune:
             flags |= _abi.DDA_FLAG_NO_AUTOTUNE
         return _abi.Opts(self.wavelength, self.aeff, self.m_medium, self.tol, int(self.max_iter),
-                         _POLZ[self.polarizability], _abi.DDA_BICGSTAB, _PREC[self.precision], flags,
+                         _POLZ[self.polarizability], _SOLVER[self.solver], _PREC[self.precision], flags,
                          int(self.kernel_variant))
 
 

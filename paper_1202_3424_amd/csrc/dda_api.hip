@@ -257,7 +257,7 @@ void check_opts(const dda_opts* o) {
     if (!(o->tol > 0) || !std::isfinite(o->tol)) invalid("tol must be > 0");
     if (o->max_iter < 1) invalid("max_iter must be >= 1");
     if (o->polarizability != DDA_LATTDR && o->polarizability != DDA_GKDLDR) invalid("unknown polarizability");
-    if (o->solver != DDA_BICGSTAB) invalid("unknown solver");
+    if (o->solver != DDA_BICGSTAB && o->solver != DDA_QMR_SYM) invalid("unknown solver");
     if (o->precision != DDA_FP64 && o->precision != DDA_FP32_MATVEC) invalid("unknown precision");
     if (o->kernel_variant < 0) invalid("kernel_variant must be >= 0");
 }
@@ -303,6 +303,7 @@ struct Work {
     int nrhs;
     double kd;
     bool fp32;
+    bool qmr = false;   // QMR for complex-symmetric A instead of BiCGSTAB
     SiteArgs a{};
     int site_blocks = 1;
     int pass_blocks = 1;
@@ -460,7 +461,7 @@ struct Work {
             launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
         }
         if (ga != GA_PLAIN) {
-            static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES};
+            static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES, FIN_QV};
             Timed tm(c, T_KRYLOV, s);
             launch_finalize(a, kind_of[ga], pass_blocks, s);
         }
@@ -527,7 +528,8 @@ bool any_active_after_restart(Work& w) {
     for (int q = 0; q < w.nrhs; ++q) {
         const RhsState& st = w.ws.host_state[q];
         if (st.status == ST_ACTIVE) active = true;
-        if (st.status == ST_BREAKDOWN && st.restarts == 0) restart = true;
+        // QMR stops at a breakdown and returns its smoothed iterate
+        if (!w.qmr && st.status == ST_BREAKDOWN && st.restarts == 0) restart = true;
     }
     if (restart) {
         Timed tm(w.c, T_KRYLOV, w.s);
@@ -541,6 +543,18 @@ bool any_active_after_restart(Work& w) {
 // One chunk of BiCGSTAB iterations (every scalar and status stays on the
 // device; right-hand sides that have stopped skip the work).
 void launch_chunk(Work& w, int chunk) {
+    if (w.qmr) {
+        // one product per iteration: p, the pending smoothing step, v = A p
+        // and alpha; then x, r and the next smoothing step, beta, status
+        for (int k = 0; k < chunk; ++k) {
+            w.matvec(SC_Q, GA_Q, CHK_ACTIVE, CHK_ACTIVE);
+            Timed tm(w.c, T_KRYLOV, w.s);
+            launch_qmr_update(w.a, w.site_blocks, w.s);
+            launch_finalize(w.a, FIN_QUPD, w.site_blocks, w.s);
+        }
+        HIPCHK(hipGetLastError());
+        return;
+    }
     for (int k = 0; k < chunk; ++k) {
         w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
         w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
@@ -568,6 +582,17 @@ void iterate_loop(Work& w, const dda_opts* o) {
 // Start of BiCGSTAB: state, then r and rhat from b (cold) or b - A x (warm).
 void start_iteration(Work& w, const dda_opts* o, bool warm) {
     launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, w.s);
+    if (w.qmr) {
+        if (warm) {
+            w.a.in = w.a.x;
+            w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x0
+        }
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_qmr_init(w.a, !warm, w.site_blocks, w.s);
+        launch_finalize(w.a, warm ? FIN_QWARM : FIN_QCOLD, w.site_blocks, w.s);
+        HIPCHK(hipGetLastError());
+        return;
+    }
     if (warm) {
         w.a.in = w.a.x;
         w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x0
@@ -584,7 +609,24 @@ void start_iteration(Work& w, const dda_opts* o, bool warm) {
 
 // FP64 residual r = b - A x of every converged right-hand side; those that
 // miss the tolerance iterate on from x (FP32-matvec mode).
+// x <- QMR's smoothed iterate (idempotent; nothing for BiCGSTAB).
+void qmr_solution(Work& w) {
+    if (!w.qmr) return;
+    Timed tm(w.c, T_KRYLOV, w.s);
+    launch_qmr_final(w.a, w.site_blocks, w.s);
+    launch_finalize(w.a, FIN_QFINAL, 0, w.s);
+}
+
 void launch_refinement(Work& w) {
+    if (w.qmr) {
+        qmr_solution(w);
+        w.a.in = w.a.x;
+        w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
+        Timed tm(w.c, T_KRYLOV, w.s);
+        launch_qmr_init(w.a, false, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_QREFINE, w.site_blocks, w.s);
+        return;
+    }
     w.a.in = w.a.x;
     w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
     Timed tm(w.c, T_KRYLOV, w.s);
@@ -600,15 +642,17 @@ void launch_refinement(Work& w) {
 void iterate(Work& w, const dda_opts* o, bool warm) {
     start_iteration(w, o, warm);
     iterate_loop(w, o);
-    if (!w.fp32) return;
-    for (int k = 0; k < 5; ++k) {
-        launch_refinement(w);
-        fetch_state(w.c, w);
-        bool active = false;
-        for (int q = 0; q < w.nrhs; ++q) active |= w.ws.host_state[q].status == ST_ACTIVE;
-        if (!active) break;
-        iterate_loop(w, o);
+    if (w.fp32) {
+        for (int k = 0; k < 5; ++k) {
+            launch_refinement(w);
+            fetch_state(w.c, w);
+            bool active = false;
+            for (int q = 0; q < w.nrhs; ++q) active |= w.ws.host_state[q].status == ST_ACTIVE;
+            if (!active) break;
+            iterate_loop(w, o);
+        }
     }
+    qmr_solution(w);
 }
 
 // true residual, eq. err_tol and the efficiency sums at x
@@ -711,6 +755,7 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     const bool fp32 = o->precision == DDA_FP32_MATVEC;
     ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
     Work w(c, c->main, t, nrhs, kd, fp32);
+    w.qmr = o->solver == DDA_QMR_SYM;
     w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
     w.upload_incidence(kh, e0);
     const bool warm = P0 != nullptr;
@@ -801,6 +846,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
         const int nrhs = (int)j.idx.size();
         j.w.reset(new Work(c, ws, j.t, nrhs, j.kd, j.fp32));
         Work& w = *j.w;
+        w.qmr = j.o->solver == DDA_QMR_SYM;
         w.autotune((j.o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, j.o->kernel_variant);
         w.upload_incidence(j.kh, j.e0);
         {
@@ -815,6 +861,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
     };
     auto finish = [&](Job& j) {
         Work& w = *j.w;
+        qmr_solution(w);
         final_checks(w, (j.o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0);
         {
             Timed tm(c, T_SETUP, w.s);
@@ -1075,6 +1122,7 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, c->main, t, n_rhs, kd, fp32);
+        w.qmr = o->solver == DDA_QMR_SYM;
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
@@ -1151,6 +1199,7 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         const bool fp32 = o->precision == DDA_FP32_MATVEC;
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, c->main, t, 1, kd, fp32);
+        w.qmr = o->solver == DDA_QMR_SYM;
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);

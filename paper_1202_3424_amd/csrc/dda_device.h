@@ -36,16 +36,20 @@ enum RhsStatus : int {
 };
 
 // Per right-hand-side solver state, device resident.  Scalars of BiCGSTAB
-// (van der Vorst 1992) and the reductions that produce them.
+// (van der Vorst 1992) or of QMR for complex-symmetric A (COCG with
+// quasi-minimal-residual smoothing) and the reductions that produce them.
 struct RhsState {
-    double2 rho;     // <rhat, r>
+    double2 rho;     // <rhat, r> (BiCGSTAB) or r^T r (QMR)
     double2 alpha;
     double2 omega;
     double2 beta;
     double bnorm2;   // |E|^2
     double rnorm2;   // |r|^2 of the latest residual
-    double snorm2;   // |s|^2 of the latest half step
+    double snorm2;   // |s|^2 of the latest half step (BiCGSTAB) or smoothed residual (QMR)
     double tol2;     // tol^2
+    double tau2;     // QMR: squared quasi-residual norm
+    double w_old;    // QMR: weights of the pending smoothing step (y, s) <- w_old (y, s) + w_new (x, r)
+    double w_new;
     double red[8];   // end-of-solve reductions (see kernels)
     int status;
     int iters;
@@ -54,7 +58,7 @@ struct RhsState {
     int max_iter;
     int restarts;
     int pad0;        // FP64 residual refinements taken (FP32-matvec mode)
-    int pad1;
+    int pend;        // QMR: the smoothing step (w_old, w_new) has not been applied yet
 };
 
 template <typename T> struct V2;

@@ -69,12 +69,20 @@ struct SiteArgs {
     double kd;
 };
 
-enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3 };
-enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4 };
+// SC_Q / GA_Q: the QMR iteration (p = r + beta p with the pending smoothing
+// step; v = A p with p^T v)
+enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3, SC_Q = 4 };
+enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4, GA_Q = 5 };
 // which right-hand sides a pass skips
 enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
 // what k_finalize makes of the partial sums of the kernel before it
-enum FinKind { FIN_S = 0, FIN_V, FIN_T, FIN_UPD, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE };
+enum FinKind {
+    FIN_S = 0, FIN_V, FIN_T, FIN_UPD, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE,
+    // QMR: after the product (alpha), after the update (smoothing, beta,
+    // status), after the cold / warm start, after an FP64 refinement residual
+    // and after k_qmr_final (clears the pending smoothing step)
+    FIN_QV, FIN_QUPD, FIN_QCOLD, FIN_QWARM, FIN_QREFINE, FIN_QFINAL
+};
 
 // FFT lengths with compile-time kernels (dda_passes.h)
 inline bool ct_length(int L) {
@@ -116,6 +124,11 @@ void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s);
+// QMR: start (cold: r = b, x = 0; warm: r holds b - A x), update, and the
+// pending smoothing step applied to x (x <- the smoothed iterate)
+void launch_qmr_init(const SiteArgs& a, bool cold, int site_blocks, hipStream_t s);
+void launch_qmr_update(const SiteArgs& a, int site_blocks, hipStream_t s);
+void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]

@@ -266,6 +266,108 @@ __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
     publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
 }
 
+// ------------------------------------------------------------------ QMR
+// QMR for complex-symmetric A ("Choice of Iterative Algorithm", QMRCCG): COCG
+// (van der Vorst & Melissen 1990) -- CG with the bilinear form u^T v -- whose
+// iterates and residuals are smoothed (Zhou & Walker 1994) so that the
+// smoothed residual s = b - A y has quasi-minimal norm.  Vectors: x, r, p
+// (COCG), v = A p, rhat = s, t = y.  A smoothing step (w_old, w_new) is
+// computed by the finalize after an update and applied by the next scatter
+// (or by k_qmr_final); pend marks it as not yet applied.
+
+// Start: cold r = b, x = 0 (warm: r = b - A x already).  p = 0, s = r,
+// y = x; sums r^T r, |r|^2, |b|^2.
+__global__ __launch_bounds__(NT) void k_qmr_init(SiteArgs a, int cold) {
+    __shared__ double sh[8 * NT / 64];
+    const int q = blockIdx.y;
+    const long long vb = (long long)q * a.n3;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 bb = a.b[vb + i];
+        double2 rr;
+        if (cold) {
+            rr = bb;
+            a.r[vb + i] = rr;
+            a.x[vb + i] = double2{0.0, 0.0};
+        } else {
+            rr = a.r[vb + i];
+        }
+        a.p[vb + i] = double2{0.0, 0.0};
+        a.rhat[vb + i] = rr;
+        a.t[vb + i] = cold ? double2{0.0, 0.0} : a.x[vb + i];
+        acc[0] += rr.x * rr.x - rr.y * rr.y;
+        acc[1] += 2.0 * rr.x * rr.y;
+        acc[2] += rr.x * rr.x + rr.y * rr.y;
+        acc[3] += bb.x * bb.x + bb.y * bb.y;
+    }
+    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+}
+
+// x += alpha p, r -= alpha v; sums r^T r, |r|^2 and Re <s, r> (for the
+// norm of the next smoothed residual).
+__global__ __launch_bounds__(NT) void k_qmr_update(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    const int q = blockIdx.y;
+    const RhsState* st = a.st + q;
+    if (st->status != ST_ACTIVE) return;
+    const double2 alpha = st->alpha;
+    const long long vb = (long long)q * a.n3;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        a.x[vb + i] = cadd(a.x[vb + i], cmul(alpha, a.p[vb + i]));
+        const double2 rr = csub(a.r[vb + i], cmul(alpha, a.v[vb + i]));
+        a.r[vb + i] = rr;
+        const double2 sm = a.rhat[vb + i];
+        acc[0] += rr.x * rr.x - rr.y * rr.y;
+        acc[1] += 2.0 * rr.x * rr.y;
+        acc[2] += rr.x * rr.x + rr.y * rr.y;
+        acc[3] += sm.x * rr.x + sm.y * rr.y;
+    }
+    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+}
+
+// x and y <- the smoothed iterate: w_old y + w_new x if a step is pending,
+// else y.  A FIN_QFINAL finalize then clears the pending flag, so applying
+// both again leaves x unchanged.
+__global__ __launch_bounds__(NT) void k_qmr_final(SiteArgs a) {
+    const int q = blockIdx.y;
+    const RhsState* st = a.st + q;
+    const bool pend = st->pend != 0;
+    const double wo = st->w_old, wn = st->w_new;
+    const long long vb = (long long)q * a.n3;
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        double2 y = a.t[vb + i];
+        if (pend) {
+            const double2 xx = a.x[vb + i];
+            y = double2{wo * y.x + wn * xx.x, wo * y.y + wn * xx.y};
+            a.t[vb + i] = y;
+        }
+        a.x[vb + i] = y;
+    }
+}
+
+// QMR state from the start sums: r^T r = (acc0, acc1), |r|^2 = acc2, |b|^2 =
+// acc3.  The first smoothing step is (0, 1): y = x, s = r.
+__device__ void qmr_start(RhsState* st, const double* acc) {
+    st->bnorm2 = acc[3];
+    st->rnorm2 = acc[2];
+    st->snorm2 = acc[2];
+    st->tau2 = acc[2];
+    st->rho = double2{acc[0], acc[1]};
+    st->beta = double2{0.0, 0.0};
+    st->w_old = 0.0;
+    st->w_new = 1.0;
+    st->pend = 1;
+    st->sconv = 0;
+    if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2]) || !isfinite(acc[3])) {
+        st->status = ST_NONFINITE;
+    } else if (acc[2] <= st->tol2 * acc[3]) {
+        st->status = ST_CONVERGED;
+    } else {
+        st->status = (acc[0] == 0.0 && acc[1] == 0.0) ? ST_BREAKDOWN : ST_ACTIVE;
+    }
+}
+
 // Efficiency sums at the solution x (Draine 1988):
 //   red[3] = sum Im(E* . P), red[4] = sum (-Im(1/alpha) - (2/3) k^3) |P|^2,
 //   red[5] = sum Re(E* . P).
@@ -302,12 +404,22 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
         case FIN_S: case FIN_V: case FIN_UPD: run = st->status == ST_ACTIVE; break;
         case FIN_T: run = st->status == ST_ACTIVE && !st->sconv; break;
         case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
-        case FIN_REFINE: run = st->status == ST_CONVERGED; break;
+        case FIN_REFINE: case FIN_QREFINE: run = st->status == ST_CONVERGED; break;
+        case FIN_QV: case FIN_QUPD: run = st->status == ST_ACTIVE; break;
         default: run = true; break;
     }
     if (!run) return;
-    double acc[3];
-    sum_partials<3>(acc, part, nblk, sh);
+    const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (four) {
+        sum_partials<4>(acc, part, nblk, sh);
+    } else {
+        double a3[3];
+        sum_partials<3>(a3, part, nblk, sh);
+        acc[0] = a3[0];
+        acc[1] = a3[1];
+        acc[2] = a3[2];
+    }
     if (threadIdx.x != 0) return;
     switch (kind) {
         case FIN_S:
@@ -399,6 +511,72 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                 st->sconv = 0;
                 st->pad0 += 1;
                 st->status = st->iters >= st->max_iter ? ST_MAXITER : ST_ACTIVE;
+            }
+            break;
+        case FIN_QV: {
+            // mu = p^T A p; the scatter has applied the pending smoothing step
+            const double2 mu = {acc[0], acc[1]};
+            st->matvecs += 1;
+            st->pend = 0;
+            if (!finite2(mu)) st->status = ST_NONFINITE;
+            else if (mu.x == 0.0 && mu.y == 0.0) st->status = ST_BREAKDOWN;
+            else st->alpha = cdiv(st->rho, mu);
+            break;
+        }
+        case FIN_QUPD: {
+            // next smoothing step: 1/tau^2 += 1/|r|^2, weights tau^2/tau_old^2
+            // and tau^2/|r|^2; |s_next|^2 from |s|^2, Re <s, r>, |r|^2
+            const double2 rho_new = {acc[0], acc[1]};
+            const double nu2 = acc[2], sr = acc[3];
+            st->iters += 1;
+            st->rnorm2 = nu2;
+            if (!finite2(rho_new) || !isfinite(nu2) || !isfinite(sr)) {
+                st->status = ST_NONFINITE;
+                break;
+            }
+            double wo = 0.0, wn = 1.0, t2 = 0.0;
+            if (nu2 > 0.0) {
+                t2 = 1.0 / (1.0 / st->tau2 + 1.0 / nu2);
+                wo = t2 / st->tau2;
+                wn = t2 / nu2;
+            }
+            const double s2 = fmax(wo * wo * st->snorm2 + 2.0 * wo * wn * sr + wn * wn * nu2, 0.0);
+            st->tau2 = t2;
+            st->w_old = wo;
+            st->w_new = wn;
+            st->pend = 1;
+            st->snorm2 = s2;
+            if (s2 <= st->tol2 * st->bnorm2) {
+                st->status = ST_CONVERGED;
+            } else if (rho_new.x == 0.0 && rho_new.y == 0.0) {
+                st->status = ST_BREAKDOWN;
+            } else {
+                st->beta = cdiv(rho_new, st->rho);
+                st->rho = rho_new;
+            }
+            if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
+            break;
+        }
+        case FIN_QFINAL:
+            st->pend = 0;
+            break;
+        case FIN_QCOLD:
+        case FIN_QWARM:
+            qmr_start(st, acc);
+            st->iters = 0;
+            st->matvecs = kind == FIN_QWARM ? 1 : 0;
+            st->restarts = 0;
+            break;
+        case FIN_QREFINE:
+            // r holds the FP64 residual b - A x of a converged solution
+            st->matvecs += 1;
+            st->rnorm2 = acc[2];
+            if (!isfinite(acc[2])) {
+                st->status = ST_NONFINITE;
+            } else if (acc[2] > st->tol2 * st->bnorm2) {
+                qmr_start(st, acc);
+                st->pad0 += 1;
+                if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
             }
             break;
         case FIN_QSUM:
@@ -572,6 +750,15 @@ void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
 }
 void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_restart, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_qmr_init(const SiteArgs& a, bool cold, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_qmr_init, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a, cold ? 1 : 0);
+}
+void launch_qmr_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_qmr_update, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_qmr_final, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qsum, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);

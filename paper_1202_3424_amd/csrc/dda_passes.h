@@ -104,8 +104,10 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         load_twiddles<T, NTHR>(tws, tw64, g.ax[0]);
     }
     double2 beta = {0, 0}, omega = {0, 0}, alpha = {0, 0};
+    double w_old = 0.0, w_new = 0.0;
     if (MODE == SC_P) { beta = st->beta; omega = st->omega; }
     if (MODE == SC_S) alpha = st->alpha;
+    if (MODE == SC_Q) { beta = st->beta; w_old = st->w_old; w_new = st->w_new; }
     const long long vb = (long long)q * a.n3;
     const int* mrow = a.map + ((long long)z * ny + y0) * nx;
     double ss = 0.0;
@@ -136,6 +138,15 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
                     // p = r + beta (p - omega v)
                     u = cadd(a.r[i], cmul(beta, csub(a.p[i], cmul(omega, a.v[i]))));
                     a.p[i] = u;
+                } else if (MODE == SC_Q) {
+                    // QMR: p = r + beta p, and the pending smoothing step
+                    // (y, s) <- w_old (y, s) + w_new (x, r)
+                    const double2 rr = a.r[i];
+                    u = cadd(rr, cmul(beta, a.p[i]));
+                    a.p[i] = u;
+                    const double2 sm = a.rhat[i], ym = a.t[i], xx = a.x[i];
+                    a.rhat[i] = double2{w_old * sm.x + w_new * rr.x, w_old * sm.y + w_new * rr.y};
+                    a.t[i] = double2{w_old * ym.x + w_new * xx.x, w_old * ym.y + w_new * xx.y};
                 } else {
                     // s = r - alpha v, stored over r
                     u = csub(a.r[i], cmul(alpha, a.v[i]));
@@ -239,6 +250,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         if (MODE == GA_V) xin = a.p[i];
         if (MODE == GA_T) xin = a.r[i];
         if (MODE == GA_RES) xin = a.x[i];
+        if (MODE == GA_Q) xin = a.p[i];
         const double2 y = cadd(gv, cmul(d, xin));
         if (MODE == GA_PLAIN) {
             a.out[i] = y;
@@ -257,6 +269,10 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             acc[0] += w.x;
             acc[1] += w.y;
             acc[2] += y.x * y.x + y.y * y.y;
+        } else if (MODE == GA_Q) {
+            a.v[i] = y;
+            acc[0] += xin.x * y.x - xin.y * y.y;   // p^T v (bilinear)
+            acc[1] += xin.x * y.y + xin.y * y.x;
         } else {
             const double2 rr = csub(a.b[i], y);
             a.r[i] = rr;
@@ -984,6 +1000,7 @@ void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typena
         case SC_PLAIN: scatter_dispatch<T, SC_PLAIN>(chk, g, a, grid, tw, s); break;
         case SC_CONJ: scatter_dispatch<T, SC_CONJ>(chk, g, a, grid, tw, s); break;
         case SC_P: scatter_dispatch<T, SC_P>(chk, g, a, grid, tw, s); break;
+        case SC_Q: scatter_dispatch<T, SC_Q>(chk, g, a, grid, tw, s); break;
         default: scatter_dispatch<T, SC_S>(chk, g, a, grid, tw, s); break;
     }
 }
@@ -997,6 +1014,7 @@ void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const t
         case GA_CONJ: gather_dispatch<T, GA_CONJ>(chk, g, a, grid, tw, s); break;
         case GA_V: gather_dispatch<T, GA_V>(chk, g, a, grid, tw, s); break;
         case GA_T: gather_dispatch<T, GA_T>(chk, g, a, grid, tw, s); break;
+        case GA_Q: gather_dispatch<T, GA_Q>(chk, g, a, grid, tw, s); break;
         default: gather_dispatch<T, GA_RES>(chk, g, a, grid, tw, s); break;
     }
 }

@@ -501,3 +501,118 @@ def test_config3_batch_full(dda):
         o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-9)
         for key in ("qext", "qabs", "qsca"):
             assert abs(res[q][key] - o[key]) <= 1e-4 * abs(o[key]), (q, key)
+
+
+# ------------------------------------------------------------------ QMR (complex-symmetric)
+
+def test_qmr_sphere389_vs_lu_and_oracle(dda):
+    """QMR on the GPU reaches the LU solution, with the oracle's QMR
+    iteration count (the smoothed-residual test decided on the device from
+    its norm recurrence, on the CPU from the vector)."""
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8, solver="qmr")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P = P.cpu().numpy()
+    for q in range(2):
+        lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], with_qsca=False)
+        o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-8, solver="qmr")
+        r = res[q]
+        assert r["status"] == 0 and r["rel_residual"] < 1e-8
+        assert abs(r["iters"] - o["iters"]) <= 1 and r["matvecs"] == r["iters"]
+        assert np.abs(P[q] - lu["P"]).max() <= 1e-7 * np.abs(lu["P"]).max()
+        assert np.abs(P[q] - o["P"]).max() <= 1e-7 * np.abs(lu["P"]).max()
+        for key in ("qext", "qabs", "qpha"):
+            assert abs(r[key] - lu[key]) <= 1e-7 * abs(lu[key]), key
+
+
+@pytest.mark.parametrize("scheme", ["LATTDR", "GKDLDR"])
+def test_qmr_two_material_vs_lu(dda, scheme):
+    d = w.workload("twomat6")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-10, polarizability=scheme, solver="qmr")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], scheme=scheme, with_qsca=False)
+    assert res[0]["status"] == 0
+    assert np.abs(P[0].cpu().numpy() - lu["P"]).max() <= 1e-8 * np.abs(lu["P"]).max()
+
+
+def test_qmr_worked_example(dda):
+    """The guide's printed gold brick solved with QMR (GKDLDR, TOL 1e-5)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_au_brick.json")))
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(g["x"], tol=1e-5, polarizability="GKDLDR", solver="qmr")
+    _, res = dda.solve(tgt, opts, d["khat"], d["e0"], want_P=False)
+    for r in res:
+        assert r["status"] == 0 and r["rel_residual"] < 1e-5
+        for key in ("qext", "qabs", "qsca", "qpha"):
+            assert abs(r[key] - g[key]) <= 1e-4 * abs(g[key]) + 5e-6, (key, r[key])
+
+
+def test_qmr_full_size_ellipsoid_vs_oracle(dda):
+    """The 51,488-site ellipsoid with QMR at tol 1e-5: Q within 1e-4 of the
+    oracle (tight solve), iterations within one of the oracle's QMR."""
+    d = w.workload("ellipsoid51k")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5, solver="qmr")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P = P.cpu().numpy()
+    sample = np.random.default_rng(1).choice(len(d["ijk"]), 500, replace=False)
+    for q in range(2):
+        o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-9)
+        oq = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-5, solver="qmr")
+        r = res[q]
+        assert r["status"] == 0 and r["rel_residual"] < 1e-5
+        assert abs(r["iters"] - oq["iters"]) <= 1
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(r[key] - o[key]) <= 1e-4 * abs(o[key]), (key, r[key], o[key])
+        assert np.abs(P[q][sample] - o["P"][sample]).max() <= 1e-3 * np.abs(o["P"]).max()
+
+
+def test_qmr_batched_deterministic_and_warm(dda):
+    """QMR batches equal single solves bitwise, repeat bitwise, and a warm
+    start at the solution takes no iteration."""
+    d = w.workload("brick48")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5, solver="qmr")
+    kh, e0 = d["khat"][:4], d["e0"][:4]
+    Pb, rb = dda.solve(tgt, opts, kh, e0)
+    Pb2, rb2 = dda.solve(tgt, opts, kh, e0)
+    assert torch.equal(Pb, Pb2) and rb == rb2
+    for q in (0, 3):
+        Ps, rs = dda.solve(tgt, opts, kh[q:q + 1], e0[q:q + 1])
+        assert torch.equal(Pb[q], Ps[0]) and rb[q]["iters"] == rs[0]["iters"]
+    Pw, rw = dda.solve(tgt, opts, kh, e0, P0=Pb)
+    assert all(r["iters"] == 0 and r["status"] == 0 for r in rw)
+    assert torch.equal(Pw, Pb)
+
+
+def test_qmr_fp32_matvec_matches_fp64(dda):
+    """FP32-matvec QMR (with FP64 residual refinement) against FP64 QMR on
+    the ellipsoid: the same residual bound and Q within 1e-4."""
+    d = w.workload("ellipsoid51k")
+    tgt = dda.Target(d["ijk"], d["m"])
+    o64 = dda.Options.for_size_parameter(d["x"], tol=1e-5, solver="qmr")
+    o32 = dda.Options.for_size_parameter(d["x"], tol=1e-5, solver="qmr", precision="fp32_matvec")
+    _, r64 = dda.solve(tgt, o64, d["khat"], d["e0"], want_P=False)
+    _, r32 = dda.solve(tgt, o32, d["khat"], d["e0"], want_P=False)
+    for a, b in zip(r32, r64):
+        assert a["status"] == 0 and a["rel_residual"] < 1e-5
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(a[key] - b[key]) <= 1e-4 * abs(b[key]), key
+
+
+def test_qmr_adjoint_gradient_vs_dense(dda):
+    """The adjoint solve run with QMR gives the dense adjoint gradient."""
+    d = w.workload("twomat6")
+    kh, e0 = d["khat"][0], d["e0"][0]
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-11, solver="qmr")
+    P, _ = dda.solve(tgt, opts, [kh], [e0])
+    g, adj = dda.grad_eps(tgt, opts, kh, e0, P[0], 1.0, 0.5)
+    ref, _ = adjoint.gradient_dense(d["ijk"], d["m"], d["x"], kh, e0, 1.0, 0.5)
+    assert adj["status"] == 0
+    assert np.abs(g.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
