@@ -17,7 +17,8 @@ BiCGSTAB is van der Vorst (1992), the PBCGST option of "Choice of Iterative
 Algorithm", with x0 = 0 (the guide's usual starting guess), shadow residual
 r^ = r0 and conjugated inner products <u, v> = sum conj(u) v.  It stops when
 |E - A P| / |E| < tol, checked after the half step (s) and after the full step.
-``qmr_sym`` is the QMRCCG option of the same section (see its docstring).
+``qmr_sym`` is the QMRCCG option and ``bicgstab_l`` (l = 2) the PBCGS2
+option of the same section (see their docstrings).
 """
 from __future__ import annotations
 
@@ -233,7 +234,89 @@ def qmr_sym(apply, b, tol: float, max_iter: int, x0=None, trace=None):
     return y, dict(iters=max_iter, matvecs=matvecs, rel_residual=float(sn), converged=False)
 
 
-SOLVERS = {"bicgstab": bicgstab, "qmr": qmr_sym}
+def bicgstab_l(apply, b, tol: float, max_iter: int, ell: int = 2, x0=None, trace=None):
+    """BiCGstab(l) (Sleijpen & Fokkema 1993; the guide's PBCGS2 option of
+    "Choice of Iterative Algorithm" is l = 2), conjugated inner products,
+    shadow residual r~ = r0.  One outer iteration takes l BiCG steps, each
+    extending the search vectors u_0..u_j and residuals r_0..r_j by one
+    product, then a minimal-residual step: r_0 - sum_j gamma_j r_j is
+    minimised over gamma by modified Gram-Schmidt on r_1..r_l.  Stops when
+    |r| / |b| < tol after an outer iteration.  ``trace``, if a list, receives
+    dict(x, r, r_bicg) after every outer iteration, r_bicg being the BiCG
+    residual the minimal-residual step started from (for the pins).
+
+    Returns (x, info) with info = dict(iters (outer), matvecs, rel_residual,
+    converged)."""
+    b = np.asarray(b, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    matvecs = 0
+    if x0 is None:
+        r = b.copy()
+    else:
+        r = b - apply(x)
+        matvecs += 1
+    rt = r.copy()
+    u = np.zeros_like(b)
+    rho0, alpha, omega = 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+    rn = np.linalg.norm(r) / bnorm
+    if rn < tol:
+        return x, dict(iters=0, matvecs=matvecs, rel_residual=float(rn), converged=True)
+    for it in range(1, max_iter + 1):
+        rs = [r] + [None] * ell
+        us = [u] + [None] * ell
+        rho0 = -omega * rho0
+        # BiCG part
+        for j in range(ell):
+            rho1 = np.vdot(rt, rs[j])
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                us[i] = rs[i] - beta * us[i]
+            us[j + 1] = apply(us[j])
+            matvecs += 1
+            alpha = rho0 / np.vdot(rt, us[j + 1])
+            for i in range(j + 1):
+                rs[i] = rs[i] - alpha * us[i + 1]
+            rs[j + 1] = apply(rs[j])
+            matvecs += 1
+            x = x + alpha * us[0]
+        r_bicg = rs[0]
+        # minimal-residual part (modified Gram-Schmidt)
+        tau = np.zeros((ell + 1, ell + 1), dtype=np.complex128)
+        sigma = np.zeros(ell + 1)
+        gp = np.zeros(ell + 1, dtype=np.complex128)
+        for j in range(1, ell + 1):
+            for i in range(1, j):
+                tau[i, j] = np.vdot(rs[i], rs[j]) / sigma[i]
+                rs[j] = rs[j] - tau[i, j] * rs[i]
+            sigma[j] = np.vdot(rs[j], rs[j]).real
+            gp[j] = np.vdot(rs[j], rs[0]) / sigma[j]
+        g = np.zeros(ell + 1, dtype=np.complex128)
+        g[ell] = gp[ell]
+        omega = g[ell]
+        for j in range(ell - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, ell + 1))
+        gpp = np.zeros(ell + 1, dtype=np.complex128)
+        for j in range(1, ell):
+            gpp[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, ell))
+        x = x + g[1] * rs[0]
+        rs[0] = rs[0] - gp[ell] * rs[ell]
+        us[0] = us[0] - g[ell] * us[ell]
+        for j in range(1, ell):
+            us[0] = us[0] - g[j] * us[j]
+            x = x + gpp[j] * rs[j]
+            rs[0] = rs[0] - gp[j] * rs[j]
+        r, u = rs[0], us[0]
+        if trace is not None:
+            trace.append(dict(x=x.copy(), r=r.copy(), r_bicg=r_bicg.copy()))
+        rn = np.linalg.norm(r) / bnorm
+        if rn < tol:
+            return x, dict(iters=it, matvecs=matvecs, rel_residual=float(rn), converged=True)
+    return x, dict(iters=max_iter, matvecs=matvecs, rel_residual=float(rn), converged=False)
+
+
+SOLVERS = {"bicgstab": bicgstab, "qmr": qmr_sym, "bicgstab2": bicgstab_l}
 
 
 def solve_case(ijk, m_sites, x: float, khat, e0, tol: float, scheme: str = dense.LATTDR,

@@ -112,7 +112,7 @@ template <typename T>
 void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant = 0);
-inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 22 : 8) : 1; }
+inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 24 : 8) : 1; }
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);

@@ -288,15 +288,45 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
 
 // ------------------------------------------------------------------ passes 2-4
 
+// XCD-grouped workgroup order of pass 3: the grid is one-dimensional and
+// ordered so that the workgroups sharing tensor values -- the column tiles x
+// and Mx - x, the rows y and My - y, every right-hand side -- run
+// consecutively on one XCD (workgroups go to the eight XCDs round-robin),
+// so each XCD's L2 serves the repeats and the tensor is read from HBM about
+// once per launch.  Returns false for the padding workgroups and for the
+// mirror copies of self-mirrored tiles (done by the unmirrored one).
+constexpr int N_XCD = 8;
+__device__ __forceinline__ bool xcd_tile(int Mx, int My, int TX, int nrhs, int& xt, int& o, int& q) {
+    const int ntx = (Mx + TX - 1) / TX;
+    const int nxp = (ntx + 1) / 2, nyp = My / 2 + 1;
+    const int mg = 4 * nrhs;
+    const int w = blockIdx.x;
+    const int local = w / N_XCD;
+    const int gi = (local / mg) * N_XCD + w % N_XCD;
+    const int m = local % mg;
+    if (gi >= nxp * nyp) return false;
+    const int xi = gi % nxp, yi = gi / nxp;
+    const int mir = m / nrhs;
+    q = m % nrhs;
+    xt = (mir & 1) ? ntx - 1 - xi : xi;
+    o = (mir & 2) ? (My - yi) % My : yi;
+    return !(((mir & 1) && xt == xi) || ((mir & 2) && o == yi));
+}
+inline unsigned xcd_grid(int Mx, int My, int TX, int nrhs) {
+    const long long groups = (long long)(((Mx + TX - 1) / TX + 1) / 2) * (My / 2 + 1);
+    return (unsigned)(((groups + N_XCD - 1) / N_XCD) * N_XCD * 4 * nrhs);
+}
+
 // Strided FFT along axis 1 (y, outer index = z) or 2 (z, outer index = y)
 // over TX adjacent x columns times NC components.  With GH: forward FFT, the
 // tensor product, inverse FFT.  Variants of the GH form (VAR):
 //   0  the workgroup handles every right-hand side in turn, its tensor values
 //      read once and kept in registers;
 //   1  every right-hand side in turn, tensor values re-read (cache) each time;
-//   2  one right-hand side per workgroup (grid z), tensor values read.
+//   2  one right-hand side per workgroup (grid z, or the XCD-grouped order
+//      of xcd_tile with XG), tensor values read.
 // TXC is the compile-time tile width (x columns).
-template <typename T, int NC, int GH, int DIR, int LC, int TXC = 1, int VAR = 0>
+template <typename T, int NC, int GH, int DIR, int LC, int TXC = 1, int VAR = 0, bool XG = false>
 __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, const double2* tw64,
                                                const typename V2<T>::t* ghat, const RhsState* st, int nrhs,
                                                int axis, int TXrt, int lin, int lout, int chk) {
@@ -309,10 +339,14 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
     const int L = CT ? LC : pl.L;
     const int TX = CT ? TXC : TXrt;
     const int Lp = pad_len(L);
-    const int x0 = blockIdx.x * TX;
+    int xt = blockIdx.x, o = blockIdx.y, qx = blockIdx.z;
+    if constexpr (XG) {
+        static_assert(!XG || (GH && VAR == 2 && LC > 0), "XCD order: pass 3, one right-hand side per workgroup");
+        if (!xcd_tile(Mx, My, TX, nrhs, xt, o, qx)) return;
+    }
+    const int x0 = xt * TX;
     const int nxl = min(TX, Mx - x0);
     const int nlines = NC * TX;   // lines beyond nxl hold zeros and are not stored
-    const int o = blockIdx.y;
     const long long estride = (axis == 1) ? (long long)Mx * NC : (long long)My * Mx * NC;
     const long long obase = (axis == 1) ? (long long)o * My * Mx * NC : (long long)o * Mx * NC;
     C* lds;
@@ -358,8 +392,8 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
             }
         }
     }
-    const int q0 = RHS_LOOP ? 0 : blockIdx.z;
-    const int q1 = RHS_LOOP ? nrhs : blockIdx.z + 1;
+    const int q0 = RHS_LOOP ? 0 : qx;
+    const int q1 = RHS_LOOP ? nrhs : qx + 1;
     // forward transforms with 2 lin <= L never read the upper half of a line;
     // inverse transforms with 2 lout <= L never write it
     bool hin = false, hout = false;
@@ -588,12 +622,7 @@ template <typename T, int L, int TX, int XR> constexpr size_t rf_smem() {
     return (size_t)(3 * TX / XR) * rf_line_stride<L>() * sizeof(typename V2<T>::t);
 }
 
-// XG (pass 3 only): the grid is one-dimensional and ordered so that the
-// workgroups sharing tensor values -- the column tiles x and Mx - x, the rows
-// y and My - y, every right-hand side -- run consecutively on one XCD
-// (workgroups go to the eight XCDs round-robin), so each XCD's L2 serves
-// the repeats and the tensor is read from HBM about once per launch.
-constexpr int N_XCD = 8;
+// XG (pass 3 only): the XCD-grouped workgroup order of xcd_tile.
 // Occupancy asked of the compiler for passes 2 and 4 (one line per thread):
 // four waves per SIMD (128 VGPRs) when the line data take at most 32 VGPRs,
 // three (168) up to 64, two (256) for the four-pass length 256 -- none of
@@ -625,20 +654,7 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
     const int Mx = g.M[0], My = g.M[1];
     int q, o, xt;
     if constexpr (XG) {
-        const int ntx = (Mx + TX - 1) / TX;
-        const int nxp = (ntx + 1) / 2, nyp = My / 2 + 1;
-        const int mg = 4 * nrhs;
-        const int w = blockIdx.x;
-        const int local = w / N_XCD;
-        const int gi = (local / mg) * N_XCD + w % N_XCD;
-        const int m = local % mg;
-        if (gi >= nxp * nyp) return;
-        const int xi = gi % nxp, yi = gi / nxp;
-        const int mir = m / nrhs;
-        q = m % nrhs;
-        xt = (mir & 1) ? ntx - 1 - xi : xi;
-        o = (mir & 2) ? (My - yi) % My : yi;
-        if (((mir & 1) && xt == xi) || ((mir & 2) && o == yi)) return;   // self-mirrored: done by mir 0
+        if (!xcd_tile(Mx, My, TX, nrhs, xt, o, q)) return;
     } else {
         q = blockIdx.z;
         o = blockIdx.y;
@@ -836,13 +852,14 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
 }
 
 // Compile-time variants of a strided pass.  LDS form (k_strided, k_zfold):
-// (tile width, VAR), indices 0 .. n_lds_variants - 1, index 0 the default.
+// (tile width, VAR, XCD order), indices 0 .. n_lds_variants - 1, index 0 the
+// default.
 // Register-resident form (k_strided_rf): (tile width, exchange rounds),
 // the following rf_variants indices.  The autotuner of the C ABI picks among
 // them by timing; all give bitwise-identical results.  Wider tiles give
 // longer contiguous runs per plane (what large grids need); LDS tiles are
 // bounded by 48 KB per workgroup.
-constexpr int n_lds_variants(int gh) { return gh ? 10 : 4; }
+constexpr int n_lds_variants(int gh) { return gh ? 12 : 4; }
 constexpr int rf_variants(int gh) { return gh ? 12 : 4; }
 constexpr int n_strided_variants(int gh) { return n_lds_variants(gh) + rf_variants(gh); }
 template <typename T> constexpr int ct_budget() { return sizeof(T) == 4 ? 6144 : 3072; }
@@ -853,7 +870,7 @@ template <typename T> constexpr int variant_tx(int L, int gh, int v) {
     const int quad = (4 * base <= 32 && 3 * 4 * base * L <= ct_budget<T>()) ? 4 * base : dbl;
     if (gh) {
         switch (v) {
-            case 2: case 4: case 8: return half;
+            case 2: case 4: case 8: case 11: return half;
             case 5: return dbl;
             case 6: return quad;
             case 9: return half > 1 ? half / 2 : 1;
@@ -867,12 +884,15 @@ template <typename T> constexpr int variant_tx(int L, int gh, int v) {
         default: return base;
     }
 }
-// VAR 3: the octant-folded kernel k_zfold
+// VAR 3: the octant-folded kernel k_zfold; variants 10 and 11: VAR 2 in the
+// XCD-grouped order
 constexpr int variant_var(int gh, int v) {
     if (!gh) return 0;
+    if (v >= 10) return 2;
     if (v >= 7) return 3;
     return v == 0 ? 0 : (v <= 2 ? 1 : 2);
 }
+constexpr bool variant_xg(int gh, int v) { return gh && v >= 10; }
 // register-resident variant r (0 .. rf_variants-1): tile width and rounds;
 // for pass 3 also the XCD-grouped workgroup order (r >= 4) and an occupancy
 // of three waves per SIMD asked of the compiler (r >= 8, where the line data
@@ -914,10 +934,7 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                 constexpr bool HI = GH || DIR < 0, HO = GH || DIR > 0;
                 const int ntx = (g.M[0] + TX - 1) / TX;
                 dim3 grd(ntx, n_outer, nrhs);
-                if (XG) {
-                    const long long groups = (long long)((ntx + 1) / 2) * (g.M[1] / 2 + 1);
-                    grd = dim3((unsigned)(((groups + N_XCD - 1) / N_XCD) * N_XCD * 4 * nrhs));
-                }
+                if (XG) grd = dim3(xcd_grid(g.M[0], g.M[1], TX, nrhs));
                 const dim3 blk(rf_threads(LL, TX, rf_nct(GH)));
                 const size_t shm = rf_smem<T, LL, TX, XR>();
                 DDA_LAUNCH((k_strided_rf<T, GH, DIR, LL, TX, XR, HI, HO, XG, WV>), grd, blk, shm, s, g, grid, tw,
@@ -933,6 +950,10 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
             dim3 grd((g.H[0] + TX - 1) / TX, g.H[1], 1);
             DDA_LAUNCH((k_zfold<T, LL, TX>), grd, dim3(NT), smem_ct<C>(LL, 3 * TX), s, g, grid, tw, ghat, st, nrhs,
                        lin, lout, chk);
+        } else if constexpr (variant_xg(GH, V)) {
+            const dim3 grd(xcd_grid(g.M[0], g.M[1], TX, nrhs));
+            DDA_LAUNCH((k_strided<T, NC, GH, DIR, LL, TX, VR, true>), grd, dim3(NT), smem_ct<C>(LL, NC * TX), s, g,
+                       grid, tw, ghat, st, nrhs, axis, TX, lin, lout, chk);
         } else {
             const int gz = (GH && VR != 2) ? 1 : nrhs;
             dim3 grd((g.M[0] + TX - 1) / TX, n_outer, gz);
@@ -956,6 +977,7 @@ void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_
         break;
         DDA_V(1) DDA_V(2) DDA_V(3) DDA_V(4) DDA_V(5) DDA_V(6) DDA_V(7) DDA_V(8) DDA_V(9) DDA_V(10) DDA_V(11)
         DDA_V(12) DDA_V(13) DDA_V(14) DDA_V(15) DDA_V(16) DDA_V(17) DDA_V(18) DDA_V(19) DDA_V(20) DDA_V(21)
+        DDA_V(22) DDA_V(23)
 #undef DDA_V
         default:
             break;
@@ -1035,7 +1057,7 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
     }
 }
 
-static_assert(passes::n_strided_variants(1) == 22 && passes::n_strided_variants(0) == 8,
+static_assert(passes::n_strided_variants(1) == 24 && passes::n_strided_variants(0) == 8,
               "strided_variants() in dda_kernels.h counts these variants");
 
 #define DDA_INSTANTIATE_PASSES(T)                                                                                 \

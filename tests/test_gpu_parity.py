@@ -339,7 +339,7 @@ def _box_target(dda, box, seed):
     return dda.Target(ijk, np.full(len(ijk), 1.4 + 0.1j))
 
 
-@pytest.mark.parametrize("variant", range(2, 23))
+@pytest.mark.parametrize("variant", range(2, 25))
 def test_every_tiling_variant_bitwise(dda, variant):
     """Each compile-time form of the strided passes (LDS tilings, the
     octant-folded z pass, the register-resident passes) gives the default

@@ -313,6 +313,41 @@ def test_cocg_residuals_are_bilinearly_orthogonal():
     assert herm > 1e-3
 
 
+def test_bicgstab2_matches_lu():
+    d = w.workload("sphere389")
+    lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][1], d["e0"][1], with_qsca=False)
+    it = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][1], d["e0"][1], tol=1e-10, solver="bicgstab2")
+    assert it["converged"] and it["true_residual"] < 1e-9
+    assert np.abs(it["P"] - lu["P"]).max() < 1e-8 * np.abs(lu["P"]).max()
+
+
+def test_bicgstab_l_with_l1_is_bicgstab():
+    """BiCGstab(1) is BiCGSTAB (van der Vorst 1992): the same iterates, step
+    by step, from an independent formulation of the recurrences."""
+    A, E, _ = _qmr_trace(steps=1)
+    op = lambda v: (A @ v.reshape(-1)).reshape(v.shape)
+    tr = []
+    fftsolve.bicgstab_l(op, E, 1e-14, 6, ell=1, trace=tr)
+    for k in range(1, 7):
+        xk, _ = fftsolve.bicgstab(op, E, 1e-30, k)
+        assert np.linalg.norm(tr[k - 1]["x"] - xk) <= 1e-9 * np.linalg.norm(xk), k
+
+
+def test_bicgstab2_residual_consistent_and_minimal():
+    """After every outer iteration of BiCGstab(2) the recursive residual is
+    E - A x, and it is no larger than the BiCG residual the minimal-residual
+    step started from."""
+    A, E, _ = _qmr_trace(steps=1)
+    op = lambda v: (A @ v.reshape(-1)).reshape(v.shape)
+    tr = []
+    fftsolve.bicgstab_l(op, E, 1e-14, 5, ell=2, trace=tr)
+    en = np.linalg.norm(E)
+    for t in tr:
+        res = E.reshape(-1) - A @ t["x"].reshape(-1)
+        assert np.linalg.norm(res - t["r"].reshape(-1)) < 1e-10 * en
+        assert np.linalg.norm(t["r"]) <= np.linalg.norm(t["r_bicg"]) * (1 + 1e-12)
+
+
 def test_normal_equation_residual_definition():
     """eq. err_tol: |A^H A P - A^H E| / |A^H E| is zero at the exact solution
     and equals the explicit expression for a perturbed P."""
