@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 single-RHS comparison")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "qmr"])
+    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "qmr", "bicgstab2"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()

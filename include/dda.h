@@ -72,8 +72,12 @@ typedef enum { DDA_LATTDR = 0, DDA_GKDLDR = 1 } dda_polarizability;
  *                 (Zhou & Walker 1994); one product per iteration; stops on
  *                 the smoothed residual |E - A P| / |E| < tol and returns the
  *                 smoothed iterate; a breakdown (P^T A P = 0 or r^T r = 0) ends
- *                 the solve with DDA_E_BREAKDOWN and that iterate (no restart). */
-typedef enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1 } dda_solver;
+ *                 the solve with DDA_E_BREAKDOWN and that iterate (no restart).
+ *   DDA_BICGSTAB2 PBCGS2: BiCGstab(l) with l = 2 (Sleijpen & Fokkema 1993), four
+ *                 products per iteration (iters counts these iterations);
+ *                 stops on |E - A P| / |E| < tol after an iteration; one
+ *                 automatic restart after a breakdown. */
+typedef enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1, DDA_BICGSTAB2 = 2 } dda_solver;
 
 /* Arithmetic of the FFT matrix-vector product.  The Krylov recurrences,
  * inner products, diagonal term and residual checks are FP64 in both modes

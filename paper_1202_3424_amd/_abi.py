@@ -22,6 +22,7 @@ DDA_LATTDR = 0
 DDA_GKDLDR = 1
 DDA_BICGSTAB = 0
 DDA_QMR_SYM = 1
+DDA_BICGSTAB2 = 2
 DDA_FP64 = 0
 DDA_FP32_MATVEC = 1
 DDA_FLAG_RECOMPUTE_GREEN = 1

@@ -57,7 +57,7 @@ def context(device: int | None = None) -> ctypes.c_void_p:
 
 _POLZ = {"LATTDR": _abi.DDA_LATTDR, "GKDLDR": _abi.DDA_GKDLDR}
 _PREC = {"fp64": _abi.DDA_FP64, "fp32_matvec": _abi.DDA_FP32_MATVEC}
-_SOLVER = {"bicgstab": _abi.DDA_BICGSTAB, "qmr": _abi.DDA_QMR_SYM}
+_SOLVER = {"bicgstab": _abi.DDA_BICGSTAB, "qmr": _abi.DDA_QMR_SYM, "bicgstab2": _abi.DDA_BICGSTAB2}
 
 
 @dataclass

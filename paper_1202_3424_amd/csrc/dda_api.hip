@@ -257,7 +257,8 @@ void check_opts(const dda_opts* o) {
     if (!(o->tol > 0) || !std::isfinite(o->tol)) invalid("tol must be > 0");
     if (o->max_iter < 1) invalid("max_iter must be >= 1");
     if (o->polarizability != DDA_LATTDR && o->polarizability != DDA_GKDLDR) invalid("unknown polarizability");
-    if (o->solver != DDA_BICGSTAB && o->solver != DDA_QMR_SYM) invalid("unknown solver");
+    if (o->solver != DDA_BICGSTAB && o->solver != DDA_QMR_SYM && o->solver != DDA_BICGSTAB2)
+        invalid("unknown solver");
     if (o->precision != DDA_FP64 && o->precision != DDA_FP32_MATVEC) invalid("unknown precision");
     if (o->kernel_variant < 0) invalid("kernel_variant must be >= 0");
 }
@@ -304,6 +305,7 @@ struct Work {
     double kd;
     bool fp32;
     bool qmr = false;   // QMR for complex-symmetric A instead of BiCGSTAB
+    bool b2 = false;    // BiCGstab(2) instead of BiCGSTAB
     SiteArgs a{};
     int site_blocks = 1;
     int pass_blocks = 1;
@@ -317,7 +319,7 @@ struct Work {
         const Geo& g = t->geo;
         const long long n3 = 3LL * t->nsites;
         const size_t vbytes = (size_t)nrhs * n3 * sizeof(double2);
-        char* v = (char*)ws.vecs.ensure(7 * vbytes);
+        char* v = (char*)ws.vecs.ensure(9 * vbytes);
         a.nsites = t->nsites;
         a.n3 = n3;
         a.nrhs = nrhs;
@@ -331,6 +333,8 @@ struct Work {
         a.v = (double2*)(v + 4 * vbytes);
         a.t = (double2*)(v + 5 * vbytes);
         a.b = (double2*)(v + 6 * vbytes);
+        a.u2 = (double2*)(v + 7 * vbytes);
+        a.r2 = (double2*)(v + 8 * vbytes);
         a.kd = kd;
         // FP64-sized even in the FP32-matvec mode: its residual refinement and
         // final checks use FP64 products
@@ -340,7 +344,7 @@ struct Work {
         pass_blocks = x_pass_blocks(g, nrhs, fp32);
         site_blocks = site_blocks_for(n3, nrhs);
         a.maxblk = std::max(pass_blocks, site_blocks);
-        a.partials = (double*)ws.partials.ensure((size_t)nrhs * a.maxblk * 4 * sizeof(double));
+        a.partials = (double*)ws.partials.ensure((size_t)nrhs * a.maxblk * PSTRIDE * sizeof(double));
         a.ainv = (const double2*)ws.ainv.ensure((size_t)nrhs * t->nmat * 3 * sizeof(double2));
         char* ib = (char*)ws.inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
         kh = (double*)ib;
@@ -461,7 +465,7 @@ struct Work {
             launch_gather_x<T>(ga, chk_rest, g, a, gr, tw, s);
         }
         if (ga != GA_PLAIN) {
-            static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES, FIN_QV};
+            static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES, FIN_QV, FIN_B_BETA, FIN_V, FIN_B_MR};
             Timed tm(c, T_KRYLOV, s);
             launch_finalize(a, kind_of[ga], pass_blocks, s);
         }
@@ -543,6 +547,21 @@ bool any_active_after_restart(Work& w) {
 // One chunk of BiCGSTAB iterations (every scalar and status stays on the
 // device; right-hand sides that have stopped skip the work).
 void launch_chunk(Work& w, int chunk) {
+    if (w.b2) {
+        // BiCGstab(2): two BiCG steps of two products each, then the
+        // minimal-residual combination
+        for (int k = 0; k < chunk; ++k) {
+            w.matvec(SC_B0, GA_V, CHK_ACTIVE, CHK_ACTIVE);    // u_1 = A u_0, alpha
+            w.matvec(SC_B1, GA_B1, CHK_ACTIVE, CHK_ACTIVE);   // r_1 = A r_0, beta
+            w.matvec(SC_B2, GA_B2, CHK_ACTIVE, CHK_ACTIVE);   // u_2 = A u_1, alpha
+            w.matvec(SC_B3, GA_B3, CHK_ACTIVE, CHK_ACTIVE);   // r_2 = A r_1, g1, g2
+            Timed tm(w.c, T_KRYLOV, w.s);
+            launch_b2_update(w.a, w.site_blocks, w.s);
+            launch_finalize(w.a, FIN_B_UPD, w.site_blocks, w.s);
+        }
+        HIPCHK(hipGetLastError());
+        return;
+    }
     if (w.qmr) {
         // one product per iteration: p, the pending smoothing step, v = A p
         // and alpha; then x, r and the next smoothing step, beta, status
@@ -756,6 +775,7 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
     Work w(c, c->main, t, nrhs, kd, fp32);
     w.qmr = o->solver == DDA_QMR_SYM;
+    w.b2 = o->solver == DDA_BICGSTAB2;
     w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
     w.upload_incidence(kh, e0);
     const bool warm = P0 != nullptr;
@@ -847,6 +867,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
         j.w.reset(new Work(c, ws, j.t, nrhs, j.kd, j.fp32));
         Work& w = *j.w;
         w.qmr = j.o->solver == DDA_QMR_SYM;
+        w.b2 = j.o->solver == DDA_BICGSTAB2;
         w.autotune((j.o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, j.o->kernel_variant);
         w.upload_incidence(j.kh, j.e0);
         {
@@ -1123,6 +1144,7 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, c->main, t, n_rhs, kd, fp32);
         w.qmr = o->solver == DDA_QMR_SYM;
+        w.b2 = o->solver == DDA_BICGSTAB2;
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
@@ -1200,6 +1222,7 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         ensure_green(c, t, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
         Work w(c, c->main, t, 1, kd, fp32);
         w.qmr = o->solver == DDA_QMR_SYM;
+        w.b2 = o->solver == DDA_BICGSTAB2;
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);

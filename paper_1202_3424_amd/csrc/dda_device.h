@@ -36,10 +36,11 @@ enum RhsStatus : int {
 };
 
 // Per right-hand-side solver state, device resident.  Scalars of BiCGSTAB
-// (van der Vorst 1992) or of QMR for complex-symmetric A (COCG with
-// quasi-minimal-residual smoothing) and the reductions that produce them.
+// (van der Vorst 1992), BiCGstab(2) (Sleijpen & Fokkema 1993) or QMR for
+// complex-symmetric A (COCG with quasi-minimal-residual smoothing) and the
+// reductions that produce them.
 struct RhsState {
-    double2 rho;     // <rhat, r> (BiCGSTAB) or r^T r (QMR)
+    double2 rho;     // <rhat, r> (BiCGSTAB, BiCGstab(2): rho_0) or r^T r (QMR)
     double2 alpha;
     double2 omega;
     double2 beta;
@@ -50,6 +51,8 @@ struct RhsState {
     double tau2;     // QMR: squared quasi-residual norm
     double w_old;    // QMR: weights of the pending smoothing step (y, s) <- w_old (y, s) + w_new (x, r)
     double w_new;
+    double2 g1;      // BiCGstab(2): minimal-residual coefficients of r_1 and r_2
+    double2 g2;
     double red[8];   // end-of-solve reductions (see kernels)
     int status;
     int iters;
@@ -563,14 +566,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
     __syncthreads();
 }
 
-// This workgroup's sums go to partials[blk * 4 + i] (no atomics, no fences:
-// the consumer is a later kernel on the same stream).
+// Doubles of partial sums per workgroup and right-hand side.
+constexpr int PSTRIDE = 8;
+
+// This workgroup's sums go to partials[blk * PSTRIDE + i] (no atomics, no
+// fences: the consumer is a later kernel on the same stream).
 template <int NV, int NTHR = NT>
 __device__ __forceinline__ void publish_partial(double (&v)[NV], double* partials, int blk, double* sh) {
     block_sum<NV, NTHR>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) partials[(long)blk * 4 + i] = v[i];
+        for (int i = 0; i < NV; ++i) partials[(long)blk * PSTRIDE + i] = v[i];
     }
 }
 
@@ -581,7 +587,7 @@ __device__ __forceinline__ void sum_partials(double (&acc)[NV], const double* pa
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += NT) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += partials[(long)b * 4 + i];
+        for (int i = 0; i < NV; ++i) acc[i] += partials[(long)b * PSTRIDE + i];
     }
     block_sum<NV>(acc, sh);
 }

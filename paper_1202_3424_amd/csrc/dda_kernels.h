@@ -60,6 +60,8 @@ struct SiteArgs {
     double2* v;
     double2* t;
     double2* b;
+    double2* u2;           // BiCGstab(2): third search vector
+    double2* r2;           // BiCGstab(2): third residual
     const double2* in;     // input of the plain / conjugated product
     double2* out;          // output of the plain / conjugated product
     RhsState* st;          // [nrhs]
@@ -70,9 +72,11 @@ struct SiteArgs {
 };
 
 // SC_Q / GA_Q: the QMR iteration (p = r + beta p with the pending smoothing
-// step; v = A p with p^T v)
-enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3, SC_Q = 4 };
-enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4, GA_Q = 5 };
+// step; v = A p with p^T v).  SC_B0..SC_B3 / GA_B1..GA_B3: the four products
+// of a BiCGstab(2) iteration (vectors: r_0 = r, r_1 = t, r_2 = r2, u_0 = p,
+// u_1 = v, u_2 = u2, shadow residual rhat; GA_V serves the first product).
+enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3, SC_Q = 4, SC_B0 = 5, SC_B1 = 6, SC_B2 = 7, SC_B3 = 8 };
+enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4, GA_Q = 5, GA_B1 = 6, GA_B2 = 7, GA_B3 = 8 };
 // which right-hand sides a pass skips
 enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
 // what k_finalize makes of the partial sums of the kernel before it
@@ -81,7 +85,10 @@ enum FinKind {
     // QMR: after the product (alpha), after the update (smoothing, beta,
     // status), after the cold / warm start, after an FP64 refinement residual
     // and after k_qmr_final (clears the pending smoothing step)
-    FIN_QV, FIN_QUPD, FIN_QCOLD, FIN_QWARM, FIN_QREFINE, FIN_QFINAL
+    FIN_QV, FIN_QUPD, FIN_QCOLD, FIN_QWARM, FIN_QREFINE, FIN_QFINAL,
+    // BiCGstab(2): beta after the second product, the minimal-residual
+    // coefficients after the fourth, status and beta after the update
+    FIN_B_BETA, FIN_B_MR, FIN_B_UPD
 };
 
 // FFT lengths with compile-time kernels (dda_passes.h)
@@ -129,6 +136,8 @@ void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qmr_init(const SiteArgs& a, bool cold, int site_blocks, hipStream_t s);
 void launch_qmr_update(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s);
+// BiCGstab(2): x += g1 r + g2 t, r -= g1 t + g2 r2, p -= g1 v + g2 u2
+void launch_b2_update(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_init_cold(SiteArgs a) {
         a.v[vb + i] = double2{0.0, 0.0};
         acc[0] += bb.x * bb.x + bb.y * bb.y;
     }
-    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // Warm start: x already holds P0 and r = b - A P0.  rhat = r, p = v = 0.
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
         acc[0] += rr.x * rr.x + rr.y * rr.y;
         acc[1] += bb.x * bb.x + bb.y * bb.y;
     }
-    publish_partial<2>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<2>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // End of a BiCGSTAB iteration: x += alpha p + omega s, r = s - omega t (or,
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_update(SiteArgs a) {
         acc[1] += w.y;
         acc[2] += rr.x * rr.x + rr.y * rr.y;
     }
-    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // One restart after a breakdown: rhat = r, p = v = 0, rho = |r|^2.
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
         a.v[vb + i] = double2{0.0, 0.0};
         acc[0] += rr.x * rr.x + rr.y * rr.y;
     }
-    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------ QMR
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(NT) void k_qmr_init(SiteArgs a, int cold) {
         acc[2] += rr.x * rr.x + rr.y * rr.y;
         acc[3] += bb.x * bb.x + bb.y * bb.y;
     }
-    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // x += alpha p, r -= alpha v; sums r^T r, |r|^2 and Re <s, r> (for the
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_qmr_update(SiteArgs a) {
         acc[2] += rr.x * rr.x + rr.y * rr.y;
         acc[3] += sm.x * rr.x + sm.y * rr.y;
     }
-    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // x and y <- the smoothed iterate: w_old y + w_new x if a step is pending,
@@ -368,6 +368,33 @@ __device__ void qmr_start(RhsState* st, const double* acc) {
     }
 }
 
+// ------------------------------------------------------------------ BiCGstab(2)
+// End of a BiCGstab(2) iteration ("Choice of Iterative Algorithm", PBCGS2;
+// Sleijpen & Fokkema 1993): the minimal-residual combination
+// x += g1 r_0 + g2 r_1, r_0 -= g1 r_1 + g2 r_2, u_0 -= g1 u_1 + g2 u_2;
+// sums <rhat, r_0> and |r_0|^2 for the next iteration.
+__global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
+    __shared__ double sh[8 * NT / 64];
+    const int q = blockIdx.y;
+    const RhsState* st = a.st + q;
+    if (st->status != ST_ACTIVE) return;
+    const double2 g1 = st->g1, g2 = st->g2;
+    const long long vb = (long long)q * a.n3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+        const double2 r0 = a.r[vb + i], r1 = a.t[vb + i];
+        a.x[vb + i] = cadd(a.x[vb + i], cadd(cmul(g1, r0), cmul(g2, r1)));
+        const double2 rn = csub(r0, cadd(cmul(g1, r1), cmul(g2, a.r2[vb + i])));
+        a.r[vb + i] = rn;
+        a.p[vb + i] = csub(a.p[vb + i], cadd(cmul(g1, a.v[vb + i]), cmul(g2, a.u2[vb + i])));
+        const double2 w = cdotc(a.rhat[vb + i], rn);
+        acc[0] += w.x;
+        acc[1] += w.y;
+        acc[2] += rn.x * rn.x + rn.y * rn.y;
+    }
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+}
+
 // Efficiency sums at the solution x (Draine 1988):
 //   red[3] = sum Im(E* . P), red[4] = sum (-Im(1/alpha) - (2/3) k^3) |P|^2,
 //   red[5] = sum Re(E* . P).
@@ -388,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
         acc[1] += (-d.y - rr) * (P.x * P.x + P.y * P.y);
         acc[2] += w.x;
     }
-    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * 4, blockIdx.x, sh);
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // Turn the partial sums of a producer kernel into the right-hand side's
@@ -398,21 +425,27 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     __shared__ double sh[8 * NT / 64];
     const int q = blockIdx.x;
     RhsState* st = a.st + q;
-    const double* part = a.partials + (long long)q * a.maxblk * 4;
+    const double* part = a.partials + (long long)q * a.maxblk * PSTRIDE;
     bool run;
     switch (kind) {
         case FIN_S: case FIN_V: case FIN_UPD: run = st->status == ST_ACTIVE; break;
         case FIN_T: run = st->status == ST_ACTIVE && !st->sconv; break;
         case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
         case FIN_REFINE: case FIN_QREFINE: run = st->status == ST_CONVERGED; break;
-        case FIN_QV: case FIN_QUPD: run = st->status == ST_ACTIVE; break;
+        case FIN_QV: case FIN_QUPD: case FIN_B_BETA: case FIN_B_MR: case FIN_B_UPD:
+            run = st->status == ST_ACTIVE;
+            break;
         default: run = true; break;
     }
     if (!run) return;
     const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (four) {
-        sum_partials<4>(acc, part, nblk, sh);
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (kind == FIN_B_MR) {
+        sum_partials<8>(acc, part, nblk, sh);
+    } else if (four) {
+        double a4[4];
+        sum_partials<4>(a4, part, nblk, sh);
+        for (int i = 0; i < 4; ++i) acc[i] = a4[i];
     } else {
         double a3[3];
         sum_partials<3>(a3, part, nblk, sh);
@@ -560,6 +593,70 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
         case FIN_QFINAL:
             st->pend = 0;
             break;
+        case FIN_B_BETA: {
+            // rho_1 = <rhat, r_1>: beta = alpha rho_1 / rho_0, rho_0 <- rho_1
+            const double2 rho1 = {acc[0], acc[1]};
+            st->matvecs += 1;
+            if (!finite2(rho1)) st->status = ST_NONFINITE;
+            else if (rho1.x == 0.0 && rho1.y == 0.0) st->status = ST_BREAKDOWN;
+            else {
+                st->beta = cmul(st->alpha, cdiv(rho1, st->rho));
+                st->rho = rho1;
+            }
+            break;
+        }
+        case FIN_B_MR: {
+            // modified Gram-Schmidt on r_1, r_2: tau = <r_1,r_2>/s1,
+            // s2 = |r_2 - tau r_1|^2, g'1 = <r_1,r_0>/s1,
+            // g'2 = <r_2 - tau r_1, r_0>/s2; g2 = g'2, g1 = g'1 - tau g2
+            st->matvecs += 1;
+            bool ok = true;
+            for (int i = 0; i < 8; ++i) ok = ok && isfinite(acc[i]);
+            if (!ok) {
+                st->status = ST_NONFINITE;
+                break;
+            }
+            const double s1 = acc[0];
+            const double2 c12 = {acc[1], acc[2]}, c10 = {acc[4], acc[5]}, c20 = {acc[6], acc[7]};
+            if (!(s1 > 0.0)) {
+                st->status = ST_BREAKDOWN;
+                break;
+            }
+            const double2 tau = {c12.x / s1, c12.y / s1};
+            const double s2 = acc[3] - (c12.x * c12.x + c12.y * c12.y) / s1;
+            if (!(s2 > 0.0)) {
+                st->status = ST_BREAKDOWN;
+                break;
+            }
+            const double2 gp1 = {c10.x / s1, c10.y / s1};
+            const double2 num = csub(c20, cmul(cconj(tau), c10));
+            const double2 g2 = {num.x / s2, num.y / s2};
+            st->g2 = g2;
+            st->g1 = csub(gp1, cmul(tau, g2));
+            st->omega = g2;
+            break;
+        }
+        case FIN_B_UPD: {
+            // convergence on |r_0|; rho_0 <- -omega rho_0, then the first
+            // BiCG step's beta = alpha <rhat, r_0> / rho_0
+            const double2 rho1 = {acc[0], acc[1]};
+            const double2 om = st->omega;
+            st->iters += 1;
+            st->rnorm2 = acc[2];
+            if (!isfinite(acc[2]) || !finite2(rho1)) {
+                st->status = ST_NONFINITE;
+            } else if (acc[2] <= st->tol2 * st->bnorm2) {
+                st->status = ST_CONVERGED;
+            } else if ((rho1.x == 0.0 && rho1.y == 0.0) || (om.x == 0.0 && om.y == 0.0)) {
+                st->status = ST_BREAKDOWN;
+            } else {
+                const double2 rho0 = cmul(double2{-om.x, -om.y}, st->rho);
+                st->beta = cmul(st->alpha, cdiv(rho1, rho0));
+                st->rho = rho1;
+            }
+            if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
+            break;
+        }
         case FIN_QCOLD:
         case FIN_QWARM:
             qmr_start(st, acc);
@@ -756,6 +853,9 @@ void launch_qmr_init(const SiteArgs& a, bool cold, int site_blocks, hipStream_t 
 }
 void launch_qmr_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qmr_update, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_b2_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_b2_update, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
 void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qmr_final, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);

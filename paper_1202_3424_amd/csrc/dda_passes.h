@@ -108,6 +108,8 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
     if (MODE == SC_P) { beta = st->beta; omega = st->omega; }
     if (MODE == SC_S) alpha = st->alpha;
     if (MODE == SC_Q) { beta = st->beta; w_old = st->w_old; w_new = st->w_new; }
+    if (MODE == SC_B0 || MODE == SC_B2) beta = st->beta;
+    if (MODE == SC_B1 || MODE == SC_B3) alpha = st->alpha;
     const long long vb = (long long)q * a.n3;
     const int* mrow = a.map + ((long long)z * ny + y0) * nx;
     double ss = 0.0;
@@ -138,6 +140,26 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
                     // p = r + beta (p - omega v)
                     u = cadd(a.r[i], cmul(beta, csub(a.p[i], cmul(omega, a.v[i]))));
                     a.p[i] = u;
+                } else if (MODE == SC_B0) {
+                    // BiCGstab(2), first BiCG step: u_0 = r_0 - beta u_0
+                    u = csub(a.r[i], cmul(beta, a.p[i]));
+                    a.p[i] = u;
+                } else if (MODE == SC_B1) {
+                    // r_0 -= alpha u_1, x += alpha u_0; product of r_0
+                    u = csub(a.r[i], cmul(alpha, a.v[i]));
+                    a.r[i] = u;
+                    a.x[i] = cadd(a.x[i], cmul(alpha, a.p[i]));
+                } else if (MODE == SC_B2) {
+                    // second BiCG step: u_0 = r_0 - beta u_0, u_1 = r_1 - beta u_1; product of u_1
+                    a.p[i] = csub(a.r[i], cmul(beta, a.p[i]));
+                    u = csub(a.t[i], cmul(beta, a.v[i]));
+                    a.v[i] = u;
+                } else if (MODE == SC_B3) {
+                    // r_0 -= alpha u_1, r_1 -= alpha u_2, x += alpha u_0; product of r_1
+                    a.r[i] = csub(a.r[i], cmul(alpha, a.v[i]));
+                    u = csub(a.t[i], cmul(alpha, a.u2[i]));
+                    a.t[i] = u;
+                    a.x[i] = cadd(a.x[i], cmul(alpha, a.p[i]));
                 } else if (MODE == SC_Q) {
                     // QMR: p = r + beta p, and the pending smoothing step
                     // (y, s) <- w_old (y, s) + w_new (x, r)
@@ -178,7 +200,7 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         double v[1] = {ss};
         double* sh = (double*)(lds + nlines * Lp);
         const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        publish_partial<1, NTHR>(v, a.partials + (long long)q * a.maxblk * 4, blk, sh);
+        publish_partial<1, NTHR>(v, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
     }
 }
 
@@ -232,7 +254,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
     const long long vb = (long long)q * a.n3;
     const int* mrow = a.map + ((long long)z * ny + y0) * nx;
     const double2* ai = a.ainv + (long long)q * a.nmat * 3;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const int tout = nl * nx * 3;
     for (int idx = threadIdx.x; idx < tout; idx += NTHR) {
         const int c = idx % 3;
@@ -251,6 +273,9 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         if (MODE == GA_T) xin = a.r[i];
         if (MODE == GA_RES) xin = a.x[i];
         if (MODE == GA_Q) xin = a.p[i];
+        if (MODE == GA_B1) xin = a.r[i];
+        if (MODE == GA_B2) xin = a.v[i];
+        if (MODE == GA_B3) xin = a.t[i];
         const double2 y = cadd(gv, cmul(d, xin));
         if (MODE == GA_PLAIN) {
             a.out[i] = y;
@@ -273,6 +298,27 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             a.v[i] = y;
             acc[0] += xin.x * y.x - xin.y * y.y;   // p^T v (bilinear)
             acc[1] += xin.x * y.y + xin.y * y.x;
+        } else if (MODE == GA_B1 || MODE == GA_B2) {
+            // r_1 = A r_0 or u_2 = A u_1, and <rhat, .>
+            if (MODE == GA_B1) a.t[i] = y;
+            else a.u2[i] = y;
+            const double2 w = cdotc(a.rhat[i], y);
+            acc[0] += w.x;
+            acc[1] += w.y;
+        } else if (MODE == GA_B3) {
+            // r_2 = A r_1 and the minimal-residual sums |r_1|^2, <r_1, r_2>,
+            // |r_2|^2, <r_1, r_0>, <r_2, r_0>
+            a.r2[i] = y;
+            const double2 r0 = a.r[i];
+            const double2 w12 = cdotc(xin, y), w10 = cdotc(xin, r0), w20 = cdotc(y, r0);
+            acc[0] += xin.x * xin.x + xin.y * xin.y;
+            acc[1] += w12.x;
+            acc[2] += w12.y;
+            acc[3] += y.x * y.x + y.y * y.y;
+            acc[4] += w10.x;
+            acc[5] += w10.y;
+            acc[6] += w20.x;
+            acc[7] += w20.y;
         } else {
             const double2 rr = csub(a.b[i], y);
             a.r[i] = rr;
@@ -282,7 +328,12 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
     if (MODE != GA_PLAIN) {
         double* sh = (double*)(lds + nlines * Lp);
         const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        publish_partial<3, NTHR>(acc, a.partials + (long long)q * a.maxblk * 4, blk, sh);
+        if constexpr (MODE == GA_B3) {
+            publish_partial<8, NTHR>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        } else {
+            double a3[3] = {acc[0], acc[1], acc[2]};
+            publish_partial<3, NTHR>(a3, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        }
     }
 }
 
@@ -1023,6 +1074,10 @@ void launch_scatter_x(int mode, int chk, const Geo& g, const SiteArgs& a, typena
         case SC_CONJ: scatter_dispatch<T, SC_CONJ>(chk, g, a, grid, tw, s); break;
         case SC_P: scatter_dispatch<T, SC_P>(chk, g, a, grid, tw, s); break;
         case SC_Q: scatter_dispatch<T, SC_Q>(chk, g, a, grid, tw, s); break;
+        case SC_B0: scatter_dispatch<T, SC_B0>(chk, g, a, grid, tw, s); break;
+        case SC_B1: scatter_dispatch<T, SC_B1>(chk, g, a, grid, tw, s); break;
+        case SC_B2: scatter_dispatch<T, SC_B2>(chk, g, a, grid, tw, s); break;
+        case SC_B3: scatter_dispatch<T, SC_B3>(chk, g, a, grid, tw, s); break;
         default: scatter_dispatch<T, SC_S>(chk, g, a, grid, tw, s); break;
     }
 }
@@ -1037,6 +1092,9 @@ void launch_gather_x(int mode, int chk, const Geo& g, const SiteArgs& a, const t
         case GA_V: gather_dispatch<T, GA_V>(chk, g, a, grid, tw, s); break;
         case GA_T: gather_dispatch<T, GA_T>(chk, g, a, grid, tw, s); break;
         case GA_Q: gather_dispatch<T, GA_Q>(chk, g, a, grid, tw, s); break;
+        case GA_B1: gather_dispatch<T, GA_B1>(chk, g, a, grid, tw, s); break;
+        case GA_B2: gather_dispatch<T, GA_B2>(chk, g, a, grid, tw, s); break;
+        case GA_B3: gather_dispatch<T, GA_B3>(chk, g, a, grid, tw, s); break;
         default: gather_dispatch<T, GA_RES>(chk, g, a, grid, tw, s); break;
     }
 }

@@ -616,3 +616,72 @@ def test_qmr_adjoint_gradient_vs_dense(dda):
     ref, _ = adjoint.gradient_dense(d["ijk"], d["m"], d["x"], kh, e0, 1.0, 0.5)
     assert adj["status"] == 0
     assert np.abs(g.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ BiCGstab(2)
+
+def test_bicgstab2_sphere389_vs_lu_and_oracle(dda):
+    """BiCGstab(2) on the GPU reaches the LU solution with the oracle's
+    iteration count (four products per iteration)."""
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8, solver="bicgstab2")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    P = P.cpu().numpy()
+    for q in range(2):
+        lu = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], with_qsca=False)
+        o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-8, solver="bicgstab2")
+        r = res[q]
+        assert r["status"] == 0 and r["rel_residual"] < 1e-8
+        assert abs(r["iters"] - o["iters"]) <= 1 and r["matvecs"] == 4 * r["iters"]
+        assert np.abs(P[q] - lu["P"]).max() <= 1e-7 * np.abs(lu["P"]).max()
+        for key in ("qext", "qabs", "qpha"):
+            assert abs(r[key] - lu[key]) <= 1e-7 * abs(lu[key]), key
+
+
+def test_bicgstab2_worked_example(dda):
+    """The guide's printed gold brick with its own solver choice (PBCGS2):
+    the printed Q's, and iterations within 3 of the printed 18."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_au_brick.json")))
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(g["x"], tol=1e-5, polarizability="GKDLDR", solver="bicgstab2")
+    _, res = dda.solve(tgt, opts, d["khat"], d["e0"], want_P=False)
+    for r, it in zip(res, g["pbcgs2_iterations"]):
+        assert r["status"] == 0 and r["rel_residual"] < 1e-5
+        assert abs(r["iters"] - it) <= 3
+        for key in ("qext", "qabs", "qsca", "qpha"):
+            assert abs(r[key] - g[key]) <= 1e-4 * abs(g[key]) + 5e-6, (key, r[key])
+
+
+def test_bicgstab2_full_size_and_modes(dda):
+    """The ellipsoid with BiCGstab(2): Q within 1e-4 of the oracle; batched
+    equals single bitwise; FP32-matvec mode within 1e-4 of FP64; the adjoint
+    solve with BiCGstab(2) gives the dense adjoint gradient."""
+    d = w.workload("ellipsoid51k")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5, solver="bicgstab2")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    for q in range(2):
+        o = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-9)
+        assert res[q]["status"] == 0 and res[q]["rel_residual"] < 1e-5
+        for key in ("qext", "qabs", "qsca"):
+            assert abs(res[q][key] - o[key]) <= 1e-4 * abs(o[key]), key
+    P1, r1 = dda.solve(tgt, opts, d["khat"][1:], d["e0"][1:])
+    assert torch.equal(P1[0], P[1]) and r1[0]["iters"] == res[1]["iters"]
+    o32 = dda.Options.for_size_parameter(d["x"], tol=1e-5, solver="bicgstab2", precision="fp32_matvec")
+    _, r32 = dda.solve(tgt, o32, d["khat"], d["e0"], want_P=False)
+    for a, b in zip(r32, res):
+        assert a["status"] == 0 and a["rel_residual"] < 1e-5
+        assert abs(a["qext"] - b["qext"]) <= 1e-4 * abs(b["qext"])
+    t = w.workload("twomat6")
+    kh, e0 = t["khat"][0], t["e0"][0]
+    tt = dda.Target(t["ijk"], t["m"])
+    ot = dda.Options.for_size_parameter(t["x"], tol=1e-11, solver="bicgstab2")
+    Pt, _ = dda.solve(tt, ot, [kh], [e0])
+    g, adj = dda.grad_eps(tt, ot, kh, e0, Pt[0], 1.0, 0.5)
+    ref, _ = adjoint.gradient_dense(t["ijk"], t["m"], t["x"], kh, e0, 1.0, 0.5)
+    assert adj["status"] == 0
+    assert np.abs(g.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
