@@ -431,3 +431,94 @@ def test_bicgstab2_iterations_near_the_printed_worked_example():
     assert r["converged"] and abs(r["iters"] - g["pbcgs2_iterations"][0]) <= 3
     for key in ("qext", "qabs"):
         assert abs(r[key] - g[key]) <= 1e-4 * abs(g[key]) + 5e-6
+
+
+# ---------------------------------------------------------------- far field
+
+from oracle import farfield  # noqa: E402
+
+
+def _au_brick_P(tol=1e-9):
+    d = w.workload("au_brick")
+    Ps, k = [], None
+    for q in range(2):
+        r = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=tol, scheme=dense.GKDLDR)
+        Ps.append(r["P"])
+        k = r["k"]
+    return d, Ps, k
+
+
+def test_worked_example_mueller_matrix_matches_printed():
+    """The guide's printed Mueller elements of the gold brick at 74
+    directions (phi = 0 and 90 deg), its polarization column and Q_bk."""
+    g = json.load(open(os.path.join(GOLDEN, "worked_example_au_brick_mueller.json")))
+    rows = np.array(g["rows"])
+    d, Ps, k = _au_brick_P()
+    n, th, ph = farfield.lab_directions(rows[:, 0], rows[:, 1])
+    A1 = farfield.amplitude_vectors(d["ijk"], Ps[0], k, n)
+    A2 = farfield.amplitude_vectors(d["ijk"], Ps[1], k, n)
+    M = farfield.mueller(farfield.amplitude_matrix(farfield.f_matrix(A1, A2, th, ph), d["e0"][0], d["e0"][1],
+                                                   rows[:, 1]))
+    s11 = rows[:, 3]
+    assert np.all(np.abs(M["S11"] - s11) <= 2e-4 * s11)
+    assert np.all(np.abs(M["S12"] - rows[:, 4]) <= 2e-4 * s11)
+    assert np.all(np.abs(M["S21"] - rows[:, 5]) <= 1e-3 * s11)
+    assert np.all(np.abs(M["S22"] - rows[:, 6]) <= 1e-3 * s11)
+    assert np.all(np.abs(-M["S12"] / M["S11"] - rows[:, 2]) <= 1e-4)
+    assert np.all(np.abs(M["S31"]) <= 1e-4) and np.all(np.abs(M["S41"]) <= 1e-4)
+    a = dense.aeff_over_d(len(d["ijk"]))
+    nb, thb, phb = farfield.lab_directions([180.0], [0.0])
+    for P in Ps:
+        qbk = farfield.q_bk(farfield.amplitude_vectors(d["ijk"], P, k, nb)[0], thb[0], phb[0], k, a)
+        assert abs(qbk - g["qbk"]) <= 2e-4 * g["qbk"]
+
+
+def test_forward_amplitude_gives_q_ext():
+    """Optical theorem: Q_ext = 4 Im(e0* . A(k)) / (k^2 a^2) from the forward
+    amplitude equals the extinction sum over dipoles (oblique, elliptical)."""
+    d = w.workload("sphere389")
+    kh = np.array([0.36, 0.48, 0.8])
+    e0 = np.array([0.8, -0.6, 0]) + 1j * np.cross(kh, [0.8, -0.6, 0])
+    e0 = e0 / np.linalg.norm(e0)
+    s = dense.solve_case(d["ijk"], d["m"], d["x"], kh, e0, with_qsca=False)
+    A = farfield.amplitude_vectors(d["ijk"], s["P"], s["k"], kh[None, :])[0]
+    a = dense.aeff_over_d(len(d["ijk"]))
+    qe = 4 * np.imag(np.vdot(e0, A)) / (s["k"] ** 2 * a ** 2)
+    assert abs(qe - s["qext"]) < 1e-12 * abs(s["qext"])
+
+
+def test_angular_integral_of_far_field_is_q_sca():
+    """The differential cross section (|f_1|^2 + |f_2|^2)/k^2 integrated
+    over all directions (Gauss-Legendre in cos theta, uniform in phi) equals
+    the closed-form Q_sca."""
+    d = w.workload("sphere389")
+    s = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0])
+    mu, wmu = np.polynomial.legendre.leggauss(48)
+    phis = np.arange(64) * 2 * np.pi / 64
+    T, Pp = np.meshgrid(np.degrees(np.arccos(mu)), np.degrees(phis), indexing="ij")
+    n, th, ph = farfield.lab_directions(T.ravel(), Pp.ravel())
+    A = farfield.amplitude_vectors(d["ijk"], s["P"], s["k"], n)
+    dcs = (np.abs(np.sum(th * A, axis=1)) ** 2 + np.abs(np.sum(ph * A, axis=1)) ** 2) / s["k"] ** 2
+    csca = np.sum(dcs.reshape(T.shape) * wmu[:, None]) * (2 * np.pi / 64)
+    a = dense.aeff_over_d(len(d["ijk"]))
+    assert abs(csca / (np.pi * a ** 2) - s["qsca"]) < 1e-8 * s["qsca"]
+
+
+def test_mueller_elements_match_the_stokes_construction():
+    """Each of the 16 element formulas against the matrix construction
+    M = T (J kron J*) T^-1, with J = (S2 S3; S4 S1) acting on (E_par, E_perp)
+    and T the map from E (x) E* to the Stokes vector (I, Q, U, V); a Mueller
+    matrix of one amplitude matrix is non-depolarizing, sum S_ij^2 = 4 S11^2."""
+    rng = np.random.default_rng(3)
+    S = rng.normal(size=(20, 2, 2)) + 1j * rng.normal(size=(20, 2, 2))
+    M = farfield.mueller(S)
+    T = np.array([[1, 0, 0, 1], [1, 0, 0, -1], [0, 1, 1, 0], [0, 1j, -1j, 0]])
+    Ti = np.linalg.inv(T)
+    for n in range(len(S)):
+        Mk = T @ np.kron(S[n], np.conj(S[n])) @ Ti
+        assert np.abs(Mk.imag).max() < 1e-12
+        for i in range(4):
+            for j in range(4):
+                assert abs(M[f"S{i + 1}{j + 1}"][n] - Mk[i, j].real) < 1e-12 * max(1.0, abs(Mk[0, 0])), (i, j)
+        frob = sum(M[f"S{i + 1}{j + 1}"][n] ** 2 for i in range(4) for j in range(4))
+        assert abs(frob - 4 * M["S11"][n] ** 2) < 1e-10 * M["S11"][n] ** 2
