@@ -201,6 +201,37 @@ dda_status dda_grad_eps(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const
                         const dda_c64* P, double w_qabs, double w_qext, dda_c64* grad,
                         dda_result* adj);
 
+/* Far-field scattering amplitudes ("Scattering by Finite Targets: The Mueller
+ * Matrix"; Draine 1988).  For each right-hand side q and direction d:
+ *   A = k^3 sum_j P_qj exp(-i k n_d . r_j)  (lattice units, r_j = the ijk of
+ *   dda_target_create, k = kd of opts),
+ *   f[q][d][0] = theta_d . A, f[q][d][1] = phi_d . A  (the guide's f_ml with
+ *   m = 1, 2 for the scattered polarizations theta_d, phi_d),
+ *   dcs[q][d] = (|f_0|^2 + |f_1|^2) / k^2  (differential scattering cross
+ *   section per steradian, in units of d^2; over pi a_eff^2 at theta = 180
+ *   deg this is Q_bk).
+ * P: device [n_rhs][n_sites][3] in the caller's site order (as dda_solve
+ * writes it).  n_hat, theta_hat, phi_hat: host [n_dir][3] orthonormal unit
+ * vectors in the target frame.  f: host [n_rhs][n_dir][2], dcs: host
+ * [n_rhs][n_dir]; either may be NULL.  E_INVALID for NULL inputs, counts
+ * outside 1..65535, or direction vectors that are not unit (1e-6) and
+ * mutually orthogonal (1e-6). */
+dda_status dda_far_field(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs, const dda_c64* P,
+                         int32_t n_dir, const double* n_hat, const double* theta_hat, const double* phi_hat,
+                         dda_c64* f, double* dcs);
+
+/* The 4x4 Mueller matrix ("Scattering by Finite Targets: The Mueller
+ * Matrix") in the Lab Frame (incidence along x_LF) from the amplitudes of
+ * the two incident polarizations e01, e02 (Lab Frame, as solved): f1, f2
+ * host [n_dir][2] (dda_far_field's f of each, with theta_d, phi_d the
+ * Lab-Frame unit vectors of direction d), phi_deg host [n_dir] the
+ * scattering-plane angle of direction d (phi = 0: the x-y plane).  Builds the
+ * amplitude matrix (S2 S3; S4 S1) of Bohren & Huffman (1983) from f by the
+ * guide's relation and returns its 16 Mueller elements, row-major
+ * S[d][4 (i-1) + (j-1)] = S_ij (host).  Host computation; no device use. */
+dda_status dda_mueller(int32_t n_dir, const dda_c64* f1, const dda_c64* f2, const dda_c64* e01, const dda_c64* e02,
+                       const double* phi_deg, double* S);
+
 /* Kernel timing on the context stream (HIP events around every launch of
  * the solver's kernels, read back at the stream synchronisations the calls
  * already make).  Categories (index into dda_timing arrays):

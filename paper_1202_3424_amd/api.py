@@ -287,6 +287,57 @@ def set_timing(categories=True, device: int | None = None) -> None:
     _check(_lib.dda_ctx_set_timing(context(device), mask), "dda_ctx_set_timing")
 
 
+def lab_directions(theta_deg, phi_deg):
+    """Scattering directions for incidence along x (the guide's Lab Frame):
+    n = x cos t + (y cos p + z sin p) sin t and the unit vectors theta_s,
+    phi_s of the scattered polarizations (phi = 0: the x-y scattering plane).
+    Returns three float64 arrays [n_dir, 3]."""
+    t = np.radians(np.asarray(theta_deg, dtype=np.float64).reshape(-1))
+    p = np.radians(np.asarray(phi_deg, dtype=np.float64).reshape(-1))
+    n = np.stack([np.cos(t), np.sin(t) * np.cos(p), np.sin(t) * np.sin(p)], axis=-1)
+    th = np.stack([-np.sin(t), np.cos(t) * np.cos(p), np.cos(t) * np.sin(p)], axis=-1)
+    ph = np.stack([np.zeros_like(t), -np.sin(p), np.cos(p)], axis=-1)
+    return n, th, ph
+
+
+def far_field(target: "Target", opts: Options, P: torch.Tensor, n_hat, theta_hat, phi_hat):
+    """Scattering amplitudes f [n_rhs, n_dir, 2] (complex128: theta, phi
+    components) and differential cross sections dcs [n_rhs, n_dir] of the
+    solution P [n_rhs, n_sites, 3] (device, complex128) for the given
+    orthonormal direction frames (dda_far_field)."""
+    if P.dim() == 2:
+        P = P.unsqueeze(0)
+    P = P.to(torch.complex128).contiguous()
+    nh = np.ascontiguousarray(np.asarray(n_hat, dtype=np.float64).reshape(-1, 3))
+    th = np.ascontiguousarray(np.asarray(theta_hat, dtype=np.float64).reshape(-1, 3))
+    ph = np.ascontiguousarray(np.asarray(phi_hat, dtype=np.float64).reshape(-1, 3))
+    n_rhs, n_dir = P.shape[0], nh.shape[0]
+    f = np.zeros((n_rhs, n_dir, 2), dtype=np.complex128)
+    dcs = np.zeros((n_rhs, n_dir), dtype=np.float64)
+    o = opts.c()
+    _check(_lib.dda_far_field(target.ctx, target.handle, ctypes.byref(o), n_rhs, P.data_ptr(), n_dir,
+                              nh.ctypes.data, th.ctypes.data, ph.ctypes.data, f.ctypes.data, dcs.ctypes.data),
+           "dda_far_field")
+    return f, dcs
+
+
+def mueller(f1, f2, e01, e02, phi_deg) -> np.ndarray:
+    """Mueller matrices [n_dir, 4, 4] in the Lab Frame from the amplitudes
+    f1, f2 [n_dir, 2] of the incident polarizations e01, e02 (dda_mueller)."""
+    f1 = np.ascontiguousarray(np.asarray(f1, dtype=np.complex128).reshape(-1, 2))
+    f2 = np.ascontiguousarray(np.asarray(f2, dtype=np.complex128).reshape(-1, 2))
+    e1 = np.ascontiguousarray(np.asarray(e01, dtype=np.complex128).reshape(3))
+    e2 = np.ascontiguousarray(np.asarray(e02, dtype=np.complex128).reshape(3))
+    ph = np.ascontiguousarray(np.asarray(phi_deg, dtype=np.float64).reshape(-1))
+    n_dir = f1.shape[0]
+    if f2.shape[0] != n_dir or ph.shape[0] != n_dir:
+        raise ValueError("f1, f2 and phi_deg must have the same number of directions")
+    S = np.zeros((n_dir, 16), dtype=np.float64)
+    _check(_lib.dda_mueller(n_dir, f1.ctypes.data, f2.ctypes.data, e1.ctypes.data, e2.ctypes.data, ph.ctypes.data,
+                            S.ctypes.data), "dda_mueller")
+    return S.reshape(n_dir, 4, 4)
+
+
 def tuned_variants(target: "Target", n_rhs: int, precision: str = "fp64") -> tuple:
     """(y forward, z with tensor, y inverse) strided-pass variants the
     autotuner chose for this target, right-hand-side count and precision, or

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <array>
 #include <map>
@@ -132,6 +133,7 @@ struct dda_ctx {
     Workspace main;
     std::vector<Workspace*> extra;
     DevBuf dainv, aux, gtmp;
+    DevBuf ffbuf;   // far-field amplitudes: sorted P, directions, results
     // kernel timing (dda_ctx_set_timing)
     int timing = 0;   // bit mask of recorded categories
     struct Pending {
@@ -1293,6 +1295,97 @@ dda_status dda_ctx_tuned_variants(dda_ctx* c, const dda_target* t, int32_t n_rhs
                                    precision == DDA_FP32_MATVEC ? 1 : 0);
         auto it = c->tuned.find(key);
         for (int i = 0; i < 3; ++i) variants[i] = it == c->tuned.end() ? -1 : it->second[i];
+        return DDA_OK;
+    });
+}
+
+dda_status dda_far_field(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs, const dda_c64* P,
+                         int32_t n_dir, const double* n_hat, const double* theta_hat, const double* phi_hat,
+                         dda_c64* f, double* dcs) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !P || !n_hat || !theta_hat || !phi_hat) invalid("NULL argument");
+        if (n_rhs < 1 || n_dir < 1) invalid("n_rhs and n_dir must be >= 1");
+        if (n_dir > 65535 || n_rhs > 65535) invalid("n_rhs and n_dir must be <= 65535");
+        check_opts(o);
+        std::vector<double> dirs((size_t)n_dir * 9);
+        for (int d = 0; d < n_dir; ++d) {
+            const double* v[3] = {n_hat + 3 * d, theta_hat + 3 * d, phi_hat + 3 * d};
+            for (int i = 0; i < 3; ++i) {
+                double nn = 0.0;
+                for (int m = 0; m < 3; ++m) {
+                    if (!std::isfinite(v[i][m])) invalid("non-finite direction " + std::to_string(d));
+                    nn += v[i][m] * v[i][m];
+                    dirs[(size_t)d * 9 + 3 * i + m] = v[i][m];
+                }
+                if (std::fabs(nn - 1.0) > 1e-6) invalid("direction vectors must be unit vectors (" + std::to_string(d) + ")");
+            }
+            for (int i = 0; i < 3; ++i)
+                for (int j = i + 1; j < 3; ++j) {
+                    const double dot = v[i][0] * v[j][0] + v[i][1] * v[j][1] + v[i][2] * v[j][2];
+                    if (std::fabs(dot) > 1e-6) invalid("n, theta, phi must be orthogonal (" + std::to_string(d) + ")");
+                }
+        }
+        Scope sc(c);
+        const double kd = kd_of(o, t->nsites);
+        const size_t n3 = 3 * (size_t)t->nsites;
+        const size_t pb = (size_t)n_rhs * n3 * sizeof(double2), db = dirs.size() * sizeof(double);
+        const size_t fb = (size_t)n_rhs * n_dir * 2 * sizeof(double2), cb = (size_t)n_rhs * n_dir * sizeof(double);
+        char* buf = (char*)c->ffbuf.ensure(pb + db + fb + cb + 256);
+        double2* Ps = (double2*)buf;
+        double* ddev = (double*)(buf + pb);
+        double2* fdev = (double2*)(buf + pb + db);
+        double* cdev = (double*)(buf + pb + db + fb);
+        HIPCHK(hipMemcpyAsync(ddev, dirs.data(), db, hipMemcpyHostToDevice, c->stream));
+        launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P, Ps, true, c->stream);
+        launch_farfield(t->nsites, (const int*)t->coords.p, Ps, n_rhs, ddev, n_dir, kd, fdev, cdev, c->stream);
+        HIPCHK(hipGetLastError());
+        if (f) HIPCHK(hipMemcpyAsync(f, fdev, fb, hipMemcpyDeviceToHost, c->stream));
+        if (dcs) HIPCHK(hipMemcpyAsync(dcs, cdev, cb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return DDA_OK;
+    });
+}
+
+dda_status dda_mueller(int32_t n_dir, const dda_c64* f1, const dda_c64* f2, const dda_c64* e01, const dda_c64* e02,
+                       const double* phi_deg, double* S) {
+    return guarded([&]() -> dda_status {
+        if (!f1 || !f2 || !e01 || !e02 || !phi_deg || !S) invalid("NULL argument");
+        if (n_dir < 1) invalid("n_dir must be >= 1");
+        typedef std::complex<double> cd;
+        auto C = [](const dda_c64& z) { return cd(z.re, z.im); };
+        // rows: incident e01, e02 projected on y and z of the Lab Frame
+        const cd a = std::conj(C(e01[1])), b = std::conj(C(e01[2]));
+        const cd cc = std::conj(C(e02[1])), d = std::conj(C(e02[2]));
+        const cd mi(0.0, -1.0);
+        for (int k = 0; k < n_dir; ++k) {
+            const double p = phi_deg[k] * (M_PI / 180.0);
+            const double cp = std::cos(p), sp = std::sin(p);
+            // F = (f11 f12; -f21 -f22), then F (a b; c d) R with R = (cp sp; sp -cp)
+            const cd F11 = C(f1[2 * k + 0]), F12 = C(f2[2 * k + 0]);
+            const cd F21 = -C(f1[2 * k + 1]), F22 = -C(f2[2 * k + 1]);
+            const cd G11 = F11 * a + F12 * cc, G12 = F11 * b + F12 * d;
+            const cd G21 = F21 * a + F22 * cc, G22 = F21 * b + F22 * d;
+            const cd S2 = mi * (G11 * cp + G12 * sp), S3 = mi * (G11 * sp - G12 * cp);
+            const cd S4 = mi * (G21 * cp + G22 * sp), S1 = mi * (G21 * sp - G22 * cp);
+            const double a1 = std::norm(S1), a2 = std::norm(S2), a3 = std::norm(S3), a4 = std::norm(S4);
+            double* M = S + (size_t)k * 16;
+            M[0] = 0.5 * (a2 + a3 + a4 + a1);
+            M[1] = 0.5 * (a2 - a3 + a4 - a1);
+            M[2] = std::real(S2 * std::conj(S3) + S1 * std::conj(S4));
+            M[3] = std::imag(S2 * std::conj(S3) - S1 * std::conj(S4));
+            M[4] = 0.5 * (a2 + a3 - a4 - a1);
+            M[5] = 0.5 * (a2 - a3 - a4 + a1);
+            M[6] = std::real(S2 * std::conj(S3) - S1 * std::conj(S4));
+            M[7] = std::imag(S2 * std::conj(S3) + S1 * std::conj(S4));
+            M[8] = std::real(S2 * std::conj(S4) + S1 * std::conj(S3));
+            M[9] = std::real(S2 * std::conj(S4) - S1 * std::conj(S3));
+            M[10] = std::real(S1 * std::conj(S2) + S3 * std::conj(S4));
+            M[11] = std::imag(S2 * std::conj(S1) + S4 * std::conj(S3));
+            M[12] = std::imag(S4 * std::conj(S2) + S1 * std::conj(S3));
+            M[13] = std::imag(S4 * std::conj(S2) - S1 * std::conj(S3));
+            M[14] = std::imag(S1 * std::conj(S2) - S3 * std::conj(S4));
+            M[15] = std::real(S1 * std::conj(S2) - S3 * std::conj(S4));
+        }
         return DDA_OK;
     });
 }

@@ -139,6 +139,10 @@ void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s);
 // BiCGstab(2): x += g1 r + g2 t, r -= g1 t + g2 r2, p -= g1 v + g2 u2
 void launch_b2_update(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
+// far-field amplitudes: P sorted [nrhs][nsites][3], dirs [ndir][9] (n, theta,
+// phi), f [nrhs][ndir][2], dcs [nrhs][ndir]
+void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
+                     double k, double2* f, double* dcs, hipStream_t s);
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,

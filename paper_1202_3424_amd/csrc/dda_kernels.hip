@@ -395,6 +395,49 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
     publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
+// ------------------------------------------------------------------ far field
+// Scattering amplitudes ("Scattering by Finite Targets: The Mueller Matrix";
+// Draine 1988): per direction n and right-hand side, A = k^3 sum_j P_j
+// exp(-i k n . r_j), then f_1 = theta . A, f_2 = phi . A and the differential
+// cross section (|f_1|^2 + |f_2|^2) / k^2.  dirs holds n, theta, phi per
+// direction; one workgroup per (direction, right-hand side), deterministic
+// sums.
+__global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, const double2* P, long long n3,
+                                                 const double* dirs, double k, double2* f, double* dcs, int ndir) {
+    __shared__ double sh[8 * NT / 64];
+    const int d = blockIdx.x, q = blockIdx.y;
+    const double* dv = dirs + (long long)d * 9;
+    const double nx = dv[0], ny = dv[1], nz = dv[2];
+    const double2* Pq = P + (long long)q * n3;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int s = threadIdx.x; s < nsites; s += NT) {
+        const double ph = -k * (nx * coords[s * 3 + 0] + ny * coords[s * 3 + 1] + nz * coords[s * 3 + 2]);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double2 w = {cs, sn};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 v = cmul(Pq[(long long)s * 3 + c], w);
+            acc[2 * c] += v.x;
+            acc[2 * c + 1] += v.y;
+        }
+    }
+    block_sum<6>(acc, sh);
+    if (threadIdx.x != 0) return;
+    const double k3 = k * k * k;
+    double2 f1 = {0.0, 0.0}, f2 = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double2 A = {k3 * acc[2 * c], k3 * acc[2 * c + 1]};
+        f1 = cadd(f1, double2{dv[3 + c] * A.x, dv[3 + c] * A.y});
+        f2 = cadd(f2, double2{dv[6 + c] * A.x, dv[6 + c] * A.y});
+    }
+    const long long o = (long long)q * ndir + d;
+    f[o * 2 + 0] = f1;
+    f[o * 2 + 1] = f2;
+    dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
+}
+
 // Efficiency sums at the solution x (Draine 1988):
 //   red[3] = sum Im(E* . P), red[4] = sum (-Im(1/alpha) - (2/3) k^3) |P|^2,
 //   red[5] = sum Re(E* . P).
@@ -859,6 +902,11 @@ void launch_b2_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
 }
 void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qmr_final, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+}
+void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
+                     double k, double2* f, double* dcs, hipStream_t s) {
+    hipLaunchKernelGGL(k_farfield, dim3(ndir, nrhs), dim3(NT), 0, s, nsites, coords, P, 3LL * nsites, dirs, k, f, dcs,
+                       ndir);
 }
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qsum, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);

@@ -685,3 +685,70 @@ def test_bicgstab2_full_size_and_modes(dda):
     ref, _ = adjoint.gradient_dense(t["ijk"], t["m"], t["x"], kh, e0, 1.0, 0.5)
     assert adj["status"] == 0
     assert np.abs(g.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ far field
+
+def _random_frames(rng, n):
+    v = rng.normal(size=(n, 3))
+    nh = v / np.linalg.norm(v, axis=1, keepdims=True)
+    u = np.cross(nh, rng.normal(size=(n, 3)))
+    th = u / np.linalg.norm(u, axis=1, keepdims=True)
+    return nh, th, np.cross(nh, th)
+
+
+def test_far_field_amplitudes_match_oracle(dda):
+    """dda_far_field against the oracle's direct sum on the same P, at
+    random directions and frames, oblique elliptical incidence included."""
+    from oracle import farfield
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
+    e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-10)
+    P, res = dda.solve(tgt, opts, kh, e0)
+    nh, th, ph = _random_frames(np.random.default_rng(4), 50)
+    f, dcs = dda.far_field(tgt, opts, P, nh, th, ph)
+    Pn = P.cpu().numpy()
+    for q in range(2):
+        A = farfield.amplitude_vectors(d["ijk"], Pn[q], res[q]["kd"], nh)
+        ref = np.stack([np.sum(th * A, axis=1), np.sum(ph * A, axis=1)], axis=1)
+        assert np.abs(f[q] - ref).max() <= 1e-12 * np.abs(ref).max()
+        rd = (np.abs(ref[:, 0]) ** 2 + np.abs(ref[:, 1]) ** 2) / res[q]["kd"] ** 2
+        assert np.abs(dcs[q] - rd).max() <= 1e-12 * rd.max()
+    with pytest.raises(dda.DDAError):
+        dda.far_field(tgt, opts, P, nh, th, nh)
+
+
+def test_worked_example_mueller_and_qbk_on_gpu(dda):
+    """The guide's printed gold brick end to end on the GPU: solve (GKDLDR),
+    far field at the 74 printed directions, Mueller elements from
+    dda_mueller against the printed table and against the oracle's formulas
+    on the same amplitudes, Q_bk against the printed value."""
+    import json
+    import os
+    from oracle import farfield
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_au_brick_mueller.json")))
+    rows = np.array(g["rows"])
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8, polarizability="GKDLDR")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    nh, th, ph = dda.lab_directions(rows[:, 0], rows[:, 1])
+    f, _ = dda.far_field(tgt, opts, P, nh, th, ph)
+    M = dda.mueller(f[0], f[1], d["e0"][0], d["e0"][1], rows[:, 1])
+    s11 = rows[:, 3]
+    assert np.all(np.abs(M[:, 0, 0] - s11) <= 2e-4 * s11)
+    assert np.all(np.abs(M[:, 0, 1] - rows[:, 4]) <= 2e-4 * s11)
+    assert np.all(np.abs(M[:, 1, 0] - rows[:, 5]) <= 1e-3 * s11)
+    assert np.all(np.abs(M[:, 1, 1] - rows[:, 6]) <= 1e-3 * s11)
+    assert np.all(np.abs(M[:, 2, 0]) <= 1e-4) and np.all(np.abs(M[:, 3, 0]) <= 1e-4)
+    ref = farfield.mueller(farfield.amplitude_matrix(f.transpose(1, 2, 0), d["e0"][0], d["e0"][1], rows[:, 1]))
+    for i in range(4):
+        for j in range(4):
+            assert np.abs(M[:, i, j] - ref[f"S{i + 1}{j + 1}"]).max() <= 1e-12 * s11.max(), (i, j)
+    nb, tb, pb = dda.lab_directions([180.0], [0.0])
+    _, dcs = dda.far_field(tgt, opts, P, nb, tb, pb)
+    for q in range(2):
+        qbk = dcs[q, 0] / (np.pi * res[q]["aeff_d"] ** 2)
+        assert abs(qbk - g["qbk"]) <= 2e-4 * g["qbk"]
