@@ -220,6 +220,22 @@ dda_status dda_far_field(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int3
                          int32_t n_dir, const double* n_hat, const double* theta_hat, const double* phi_hat,
                          dda_c64* f, double* dcs);
 
+/* Averages over scattering directions ("Averaging over Scattering
+ * Directions"): for each right-hand side q, with theta the angle between the
+ * scattering direction and khat of inc[q],
+ *   out[q][0] = Q_sca = (1 / pi a_eff^2) int dC_sca/dOmega dOmega,
+ *   out[q][1] = g = <cos theta>,  out[q][2] = <cos^2 theta>,
+ * the cross section dC_sca/dOmega being dda_far_field's dcs, integrated with
+ * n_theta Gauss-Legendre nodes in cos theta times n_phi equally spaced
+ * azimuths (the far field is band limited, so the rule converges quickly;
+ * 48 x 64 is ample for targets of size parameter up to about 5).  P: device
+ * [n_rhs][n_sites][3], caller order.  out: host [n_rhs][3].  E_INVALID for
+ * NULL arguments, bad incidences, n_theta < 2, n_phi < 1 or
+ * n_theta * n_phi > 65535. */
+dda_status dda_scattering_averages(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
+                                   const dda_incidence* inc, const dda_c64* P, int32_t n_theta, int32_t n_phi,
+                                   double* out);
+
 /* The 4x4 Mueller matrix ("Scattering by Finite Targets: The Mueller
  * Matrix") in the Lab Frame (incidence along x_LF) from the amplitudes of
  * the two incident polarizations e01, e02 (Lab Frame, as solved): f1, f2

@@ -92,3 +92,30 @@ def q_bk(A_back, theta_hat, phi_hat, k: float, a_eff_over_d: float) -> float:
     f1 = np.sum(theta_hat * A_back)
     f2 = np.sum(phi_hat * A_back)
     return float((abs(f1) ** 2 + abs(f2) ** 2) / k ** 2 / (np.pi * a_eff_over_d ** 2))
+
+
+def angular_averages(ijk, P, k: float, khat, a_eff_over_d: float, n_theta: int = 48, n_phi: int = 64):
+    """Q_sca, g = <cos theta> and <cos^2 theta> of one incident polarization
+    (the guide's "Averaging over Scattering Directions" quantities): the
+    differential cross section (|f_1|^2 + |f_2|^2)/k^2 integrated over all
+    directions n = cos t khat + sin t (cos p u + sin p v) with Gauss-Legendre
+    nodes in cos t and n_phi equally spaced p (exact for the band-limited
+    far field once the nodes resolve it)."""
+    kh = np.asarray(khat, dtype=np.float64)
+    kh = kh / np.linalg.norm(kh)
+    u = np.cross(kh, [1.0, 0.0, 0.0] if abs(kh[0]) < 0.9 else [0.0, 1.0, 0.0])
+    u = u / np.linalg.norm(u)
+    v = np.cross(kh, u)
+    mu, wmu = np.polynomial.legendre.leggauss(n_theta)
+    p = np.arange(n_phi) * 2 * np.pi / n_phi
+    MU, PP = np.meshgrid(mu, p, indexing="ij")
+    st = np.sqrt(1 - MU ** 2)
+    n = (MU[..., None] * kh + st[..., None] * (np.cos(PP)[..., None] * u + np.sin(PP)[..., None] * v)).reshape(-1, 3)
+    A = amplitude_vectors(ijk, P, k, n)
+    # |f_1|^2 + |f_2|^2 = |A|^2 - |n . A|^2 (the transverse part)
+    dcs = (np.sum(np.abs(A) ** 2, axis=1) - np.abs(np.sum(n * A, axis=1)) ** 2) / k ** 2
+    w = (wmu[:, None] * np.full(n_phi, 2 * np.pi / n_phi)[None, :]).reshape(-1)
+    csca = np.sum(w * dcs)
+    g = np.sum(w * dcs * MU.reshape(-1)) / csca
+    c2 = np.sum(w * dcs * MU.reshape(-1) ** 2) / csca
+    return float(csca / (np.pi * a_eff_over_d ** 2)), float(g), float(c2)

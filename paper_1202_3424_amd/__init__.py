@@ -12,7 +12,8 @@ The public names below load libdda.so on first use and raise ImportError if
 it has not been built: there is no fallback implementation.
 """
 _PUBLIC = ("DDAError", "Options", "QEff", "Target", "apply", "context", "far_field", "get_timing", "grad_eps",
-           "lab_directions", "last_error", "mueller", "set_timing", "solve", "solve_batched", "solve_rhs",
+           "lab_directions", "last_error", "mueller", "scattering_averages", "set_timing", "solve", "solve_batched",
+           "solve_rhs",
            "tuned_variants")
 
 __all__ = list(_PUBLIC)

@@ -126,5 +126,8 @@ SIGNATURES["dda_ctx_set_timing"] = (ctypes.c_int, [VP, ctypes.c_int])
 SIGNATURES["dda_ctx_get_timing"] = (ctypes.c_int, [VP, ctypes.POINTER(Timing)])
 SIGNATURES["dda_far_field"] = (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, VP, ctypes.c_int32, VP,
                                               VP, VP, VP, VP])
+SIGNATURES["dda_scattering_averages"] = (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32,
+                                                        ctypes.POINTER(Incidence), VP, ctypes.c_int32,
+                                                        ctypes.c_int32, VP])
 SIGNATURES["dda_mueller"] = (ctypes.c_int, [ctypes.c_int32, VP, VP, VP, VP, VP, VP])
 SIGNATURES["dda_ctx_tuned_variants"] = (ctypes.c_int, [VP, VP, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)])

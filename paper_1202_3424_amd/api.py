@@ -321,6 +321,22 @@ def far_field(target: "Target", opts: Options, P: torch.Tensor, n_hat, theta_hat
     return f, dcs
 
 
+def scattering_averages(target: "Target", opts: Options, khat, e0, P: torch.Tensor, n_theta: int = 48,
+                        n_phi: int = 64) -> list:
+    """[{qsca, g, cos2}] per right-hand side: Q_sca, <cos theta> and
+    <cos^2 theta> by quadrature of the far field (dda_scattering_averages)."""
+    if P.dim() == 2:
+        P = P.unsqueeze(0)
+    P = P.to(torch.complex128).contiguous()
+    inc = _incidences(khat, e0)
+    n = len(inc)
+    out = np.zeros((n, 3), dtype=np.float64)
+    o = opts.c()
+    _check(_lib.dda_scattering_averages(target.ctx, target.handle, ctypes.byref(o), n, inc, P.data_ptr(),
+                                        int(n_theta), int(n_phi), out.ctypes.data), "dda_scattering_averages")
+    return [dict(qsca=float(r[0]), g=float(r[1]), cos2=float(r[2])) for r in out]
+
+
 def mueller(f1, f2, e01, e02, phi_deg) -> np.ndarray:
     """Mueller matrices [n_dir, 4, 4] in the Lab Frame from the amplitudes
     f1, f2 [n_dir, 2] of the incident polarizations e01, e02 (dda_mueller)."""

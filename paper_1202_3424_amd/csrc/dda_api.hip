@@ -1346,6 +1346,113 @@ dda_status dda_far_field(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n
     });
 }
 
+}  // extern "C"
+
+namespace {
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n from
+// the Chebyshev-like first guess, P_n and P_n' by the three-term recurrence.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double pn = n == 1 ? z : p1, pm = n == 1 ? 1.0 : p0;
+            dp = n * (z * pn - pm) / (z * z - 1.0);
+            const double dz = pn / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+}  // namespace
+
+extern "C" {
+
+dda_status dda_scattering_averages(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs,
+                                   const dda_incidence* inc, const dda_c64* P, int32_t n_theta, int32_t n_phi,
+                                   double* out) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !inc || !P || !out) invalid("NULL argument");
+        if (n_rhs < 1 || n_rhs > 65535) invalid("n_rhs must be in 1..65535");
+        if (n_theta < 2 || n_phi < 1 || (long long)n_theta * n_phi > 65535) invalid("need n_theta >= 2, n_phi >= 1 and n_theta * n_phi <= 65535");
+        check_opts(o);
+        std::vector<double> kh;
+        std::vector<double2> e0;
+        pack_incidence(n_rhs, inc, kh, e0);
+        Scope sc(c);
+        const double kd = kd_of(o, t->nsites);
+        const double a = aeff_over_d(t->nsites);
+        std::vector<double> mu, wmu;
+        gauss_legendre(n_theta, mu, wmu);
+        const int nd = n_theta * n_phi;
+        const size_t n3 = 3 * (size_t)t->nsites;
+        const size_t pb = (size_t)n_rhs * n3 * sizeof(double2), db = (size_t)nd * 9 * sizeof(double);
+        const size_t fb = (size_t)nd * 2 * sizeof(double2), cb = (size_t)nd * sizeof(double);
+        char* buf = (char*)c->ffbuf.ensure(pb + db + fb + cb + 256);
+        double2* Ps = (double2*)buf;
+        double* ddev = (double*)(buf + pb);
+        double2* fdev = (double2*)(buf + pb + db);
+        double* cdev = (double*)(buf + pb + db + fb);
+        launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P, Ps, true, c->stream);
+        std::vector<double> dirs((size_t)nd * 9), dcs(nd);
+        for (int q = 0; q < n_rhs; ++q) {
+            // frame (khat, u, v) and directions n = mu khat + sqrt(1-mu^2)(cos p u + sin p v)
+            const double* k = kh.data() + 3 * q;
+            double u[3], v[3];
+            const double ref[3] = {std::fabs(k[0]) < 0.9 ? 1.0 : 0.0, std::fabs(k[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+            u[0] = k[1] * ref[2] - k[2] * ref[1];
+            u[1] = k[2] * ref[0] - k[0] * ref[2];
+            u[2] = k[0] * ref[1] - k[1] * ref[0];
+            const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (double& x : u) x /= un;
+            v[0] = k[1] * u[2] - k[2] * u[1];
+            v[1] = k[2] * u[0] - k[0] * u[2];
+            v[2] = k[0] * u[1] - k[1] * u[0];
+            for (int i = 0; i < n_theta; ++i) {
+                const double ct = mu[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+                for (int j = 0; j < n_phi; ++j) {
+                    const double p = 2.0 * M_PI * j / n_phi, cp = std::cos(p), sp = std::sin(p);
+                    double* D = dirs.data() + ((size_t)i * n_phi + j) * 9;
+                    for (int m = 0; m < 3; ++m) {
+                        D[m] = ct * k[m] + st * (cp * u[m] + sp * v[m]);
+                        D[3 + m] = ct * (cp * u[m] + sp * v[m]) - st * k[m];
+                        D[6 + m] = -sp * u[m] + cp * v[m];
+                    }
+                }
+            }
+            HIPCHK(hipMemcpyAsync(ddev, dirs.data(), db, hipMemcpyHostToDevice, c->stream));
+            launch_farfield(t->nsites, (const int*)t->coords.p, Ps + (size_t)q * n3, 1, ddev, nd, kd, fdev, cdev,
+                            c->stream);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(dcs.data(), cdev, cb, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int i = 0; i < n_theta; ++i)
+                for (int j = 0; j < n_phi; ++j) {
+                    const double wgt = wmu[i] * (2.0 * M_PI / n_phi) * dcs[(size_t)i * n_phi + j];
+                    s0 += wgt;
+                    s1 += wgt * mu[i];
+                    s2 += wgt * mu[i] * mu[i];
+                }
+            out[3 * q + 0] = s0 / (M_PI * a * a);
+            out[3 * q + 1] = s0 > 0 ? s1 / s0 : 0.0;
+            out[3 * q + 2] = s0 > 0 ? s2 / s0 : 0.0;
+        }
+        return DDA_OK;
+    });
+}
+
 dda_status dda_mueller(int32_t n_dir, const dda_c64* f1, const dda_c64* f2, const dda_c64* e01, const dda_c64* e02,
                        const double* phi_deg, double* S) {
     return guarded([&]() -> dda_status {

@@ -752,3 +752,27 @@ def test_worked_example_mueller_and_qbk_on_gpu(dda):
     for q in range(2):
         qbk = dcs[q, 0] / (np.pi * res[q]["aeff_d"] ** 2)
         assert abs(qbk - g["qbk"]) <= 2e-4 * g["qbk"]
+
+
+def test_scattering_averages_on_gpu(dda):
+    """dda_scattering_averages on the gold brick: against the oracle's
+    quadrature on the same P (1e-10), Q_sca against Q_ext - Q_abs, and g,
+    <cos^2> within 0.3% of the guide's printed (962-direction) values."""
+    import json
+    import os
+    from oracle import dense as odense, farfield
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_au_brick.json")))
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8, polarizability="GKDLDR")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    av = dda.scattering_averages(tgt, opts, d["khat"], d["e0"], P, 32, 48)
+    a = odense.aeff_over_d(len(d["ijk"]))
+    Pn = P.cpu().numpy()
+    for q in range(2):
+        qs, gg, c2 = farfield.angular_averages(d["ijk"], Pn[q], res[q]["kd"], d["khat"][q], a, 32, 48)
+        assert abs(av[q]["qsca"] - qs) <= 1e-10 * qs
+        assert abs(av[q]["g"] - gg) <= 1e-10 and abs(av[q]["cos2"] - c2) <= 1e-10
+        assert abs(av[q]["qsca"] - res[q]["qsca"]) <= 1e-6 * res[q]["qsca"]
+        assert abs(av[q]["g"] - g["g1"]) <= 3e-3 * g["g1"]
+        assert abs(av[q]["cos2"] - g["cos2"]) <= 3e-3 * g["cos2"]
