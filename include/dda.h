@@ -100,6 +100,12 @@ typedef struct {
 #define DDA_FLAG_NO_FINAL_CHECKS 2u  /* skip the true-residual and eq. err_tol matvecs */
 #define DDA_FLAG_NO_AUTOTUNE 4u      /* use the default kernel tiling instead of timing the
                                         variants once per grid shape (results are identical) */
+#define DDA_FLAG_NO_GRAPH 8u         /* dda_solve_batched: launch the Krylov iterations one kernel at
+                                        a time instead of replaying a captured HIP graph of each
+                                        chunk of iterations (with several targets in flight the
+                                        host's launch rate is the limit; single-target calls always
+                                        launch directly; with kernel timing on, one chunk in the
+                                        timing sample period runs as direct launches) */
 
 typedef struct {
     double wavelength;   /* vacuum wavelength (any physical unit) > 0 */
@@ -260,11 +266,19 @@ dda_status dda_mueller(int32_t n_dir, const dda_c64* f1, const dda_c64* f2, cons
  * dda_ctx_get_timing copies the totals accumulated so far. */
 #define DDA_TIMING_CATEGORIES 8
 typedef struct {
-    double ms[DDA_TIMING_CATEGORIES];        /* summed kernel time */
-    int64_t launches[DDA_TIMING_CATEGORIES];  /* kernel launches timed */
+    double ms[DDA_TIMING_CATEGORIES];            /* summed kernel time of the timed launches */
+    int64_t launches[DDA_TIMING_CATEGORIES];     /* kernel launches timed */
+    int64_t all_launches[DDA_TIMING_CATEGORIES]; /* launches of the category, timed or not */
 } dda_timing;
 dda_status dda_ctx_set_timing(dda_ctx* ctx, int mask);
 dda_status dda_ctx_get_timing(dda_ctx* ctx, dda_timing* out);
+/* Record events on every `every`-th launch of each recorded category only (a
+ * systematic sample that keeps the event overhead off most launches);
+ * every = 1 (the default) times every launch.  In batched solves that replay
+ * graphs, one chunk of iterations in `every` runs as direct launches (and is
+ * sampled as above); all_launches still counts every launch.  E_INVALID for
+ * every < 1. */
+dda_status dda_ctx_set_timing_sample(dda_ctx* ctx, int every);
 
 /* The strided-pass variants the autotuner chose for this context, target,
  * right-hand-side count and precision: variants[0] forward y pass,

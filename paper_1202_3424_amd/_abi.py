@@ -28,6 +28,7 @@ DDA_FP32_MATVEC = 1
 DDA_FLAG_RECOMPUTE_GREEN = 1
 DDA_FLAG_NO_FINAL_CHECKS = 2
 DDA_FLAG_NO_AUTOTUNE = 4
+DDA_FLAG_NO_GRAPH = 8
 
 
 class C64(ctypes.Structure):
@@ -119,11 +120,13 @@ TIMING_NAMES = ["scatter_fft_x", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * DDA_TIMING_CATEGORIES), ("launches", ctypes.c_int64 * DDA_TIMING_CATEGORIES)]
+    _fields_ = [("ms", ctypes.c_double * DDA_TIMING_CATEGORIES), ("launches", ctypes.c_int64 * DDA_TIMING_CATEGORIES),
+                ("all_launches", ctypes.c_int64 * DDA_TIMING_CATEGORIES)]
 
 
 SIGNATURES["dda_ctx_set_timing"] = (ctypes.c_int, [VP, ctypes.c_int])
 SIGNATURES["dda_ctx_get_timing"] = (ctypes.c_int, [VP, ctypes.POINTER(Timing)])
+SIGNATURES["dda_ctx_set_timing_sample"] = (ctypes.c_int, [VP, ctypes.c_int])
 SIGNATURES["dda_far_field"] = (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, VP, ctypes.c_int32, VP,
                                               VP, VP, VP, VP])
 SIGNATURES["dda_scattering_averages"] = (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32,

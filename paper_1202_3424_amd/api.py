@@ -75,6 +75,7 @@ class Options:
     recompute_green: bool = False
     final_checks: bool = True
     autotune: bool = True
+    graphs: bool = True
     kernel_variant: int = 0
 
     @classmethod
@@ -90,6 +91,8 @@ class Options:
             flags |= _abi.DDA_FLAG_NO_FINAL_CHECKS
         if not self.autotune:
             flags |= _abi.DDA_FLAG_NO_AUTOTUNE
+        if not self.graphs:
+            flags |= _abi.DDA_FLAG_NO_GRAPH
         return _abi.Opts(self.wavelength, self.aeff, self.m_medium, self.tol, int(self.max_iter),
                          _POLZ[self.polarizability], _SOLVER[self.solver], _PREC[self.precision], flags,
                          int(self.kernel_variant))
@@ -365,7 +368,13 @@ def tuned_variants(target: "Target", n_rhs: int, precision: str = "fp64") -> tup
 
 
 def get_timing(device: int | None = None) -> dict:
-    """{category: (total ms, launches)} accumulated since set_timing(True)."""
+    """{category: (total ms of the timed launches, timed launches, all
+    launches)} accumulated since set_timing."""
     t = _abi.Timing()
     _check(_lib.dda_ctx_get_timing(context(device), ctypes.byref(t)), "dda_ctx_get_timing")
-    return {name: (t.ms[i], int(t.launches[i])) for i, name in enumerate(_abi.TIMING_NAMES)}
+    return {name: (t.ms[i], int(t.launches[i]), int(t.all_launches[i])) for i, name in enumerate(_abi.TIMING_NAMES)}
+
+
+def set_timing_sample(every: int, device: int | None = None) -> None:
+    """Time every ``every``-th launch of each recorded category only."""
+    _check(_lib.dda_ctx_set_timing_sample(context(device), int(every)), "dda_ctx_set_timing_sample")

@@ -115,7 +115,28 @@ struct Workspace {
     RhsState* host_state = nullptr;
     int host_state_cap = 0;
     hipEvent_t ready = nullptr;   // recorded after the last asynchronous status copy
+    // captured chunks of Krylov iterations, keyed by every value their kernel
+    // arguments hold; replayed on `stream`, or on the side stream `gstream`
+    // when `stream` is the null stream (which cannot be captured)
+    struct Graph {
+        hipGraphExec_t exec;
+        long long launches[DDA_TIMING_CATEGORIES];   // launches per category in the chunk
+    };
+    std::map<std::string, Graph> graphs;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second.exec);
+        graphs.clear();
+    }
     void release() {
+        drop_graphs();
+        if (gstream) (void)hipStreamDestroy(gstream);
+        gstream = nullptr;
+        for (hipEvent_t& e : gev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
         for (DevBuf* b : {&grid, &vecs, &state, &partials, &inc, &ainv, &mrel}) b->release();
         if (host_state) (void)hipHostFree(host_state);
         host_state = nullptr;
@@ -136,6 +157,11 @@ struct dda_ctx {
     DevBuf ffbuf;   // far-field amplitudes: sorted P, directions, results
     // kernel timing (dda_ctx_set_timing)
     int timing = 0;   // bit mask of recorded categories
+    int tsample = 1;  // events on every tsample-th launch of a category (dda_ctx_set_timing_sample)
+    long long tall[DDA_TIMING_CATEGORIES] = {};   // every launch of each recorded category
+    bool tsuppress = false;   // inside a graph capture: count launches (tcap), record no events
+    long long tcap[DDA_TIMING_CATEGORIES] = {};
+    long long tchunk = 0;     // Krylov chunks run while timing (graph replays sample chunks)
     struct Pending {
         int cat;
         hipEvent_t a, b;
@@ -200,7 +226,14 @@ struct Timed {
     hipEvent_t a = nullptr;
     hipEvent_t b = nullptr;
     Timed(dda_ctx* c_, int cat_, hipStream_t st_) : c(c_), cat(cat_), ext(cat_ <= T_GATHER), st(st_) {
+        if (c->tsuppress) {   // captured into a graph: counted, never timed
+            ++c->tcap[cat];
+            return;
+        }
         if (!(c->timing & (1 << cat))) return;
+        const long long n = c->tall[cat]++;
+        // systematic sample: events on every tsample-th launch of the category
+        if (n % c->tsample != 0) return;
         a = take_event(c);
         if (ext) {
             b = take_event(c);
@@ -308,6 +341,7 @@ struct Work {
     bool fp32;
     bool qmr = false;   // QMR for complex-symmetric A instead of BiCGSTAB
     bool b2 = false;    // BiCGstab(2) instead of BiCGSTAB
+    bool graphs = false; // replay captured iteration chunks (batched solves, unless DDA_FLAG_NO_GRAPH)
     SiteArgs a{};
     int site_blocks = 1;
     int pass_blocks = 1;
@@ -586,6 +620,75 @@ void launch_chunk(Work& w, int chunk) {
     HIPCHK(hipGetLastError());
 }
 
+// A chunk of iterations as a captured graph: the launch sequence of
+// launch_chunk depends only on values fixed for a workspace, target and
+// solve configuration, so one capture serves every later chunk with the
+// same key.  With kernel timing on, one chunk in tsample runs as plain
+// launches carrying the timing events and the others replay the graph; the
+// launch counts recorded at capture keep the per-category totals exact.
+template <typename T> void key_bytes(std::string& k, const T& v) {
+    k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+void run_chunk(Work& w, int chunk) {
+    dda_ctx* c = w.c;
+    if (!w.graphs || (c->timing != 0 && c->tchunk++ % c->tsample == 0)) {
+        launch_chunk(w, chunk);
+        return;
+    }
+    Workspace& ws = w.ws;
+    std::string key;
+    key_bytes(key, w.a);
+    key_bytes(key, w.grid);
+    key_bytes(key, w.t->geo);
+    key_bytes(key, w.t->gh64.p);
+    key_bytes(key, w.t->gh32.p);
+    key_bytes(key, w.t->tw.p);
+    key_bytes(key, w.var);
+    key_bytes(key, w.site_blocks);
+    key_bytes(key, w.pass_blocks);
+    const int flags[4] = {chunk, w.fp32 ? 1 : 0, w.qmr ? 1 : 0, w.b2 ? 1 : 0};
+    key_bytes(key, flags);
+    hipStream_t gs = w.s;
+    if (!gs) {
+        if (!ws.gstream) HIPCHK(hipStreamCreateWithFlags(&ws.gstream, hipStreamNonBlocking));
+        gs = ws.gstream;
+    }
+    for (hipEvent_t& e : ws.gev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (gs != w.s) {
+        HIPCHK(hipEventRecord(ws.gev[0], w.s));
+        HIPCHK(hipStreamWaitEvent(gs, ws.gev[0], 0));
+    }
+    auto it = ws.graphs.find(key);
+    if (it == ws.graphs.end()) {
+        if (ws.graphs.size() >= 32) ws.drop_graphs();
+        Workspace::Graph gr{};
+        for (long long& n : c->tcap) n = 0;
+        const hipStream_t keep = w.s;
+        w.s = gs;
+        c->tsuppress = true;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        launch_chunk(w, chunk);
+        const hipError_t ce = hipStreamEndCapture(gs, &g);
+        c->tsuppress = false;
+        w.s = keep;
+        HIPCHK(ce);
+        for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) gr.launches[i] = c->tcap[i];
+        const hipError_t ie = hipGraphInstantiateWithFlags(&gr.exec, g, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ie);
+        it = ws.graphs.emplace(key, gr).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second.exec, gs));
+    for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i)
+        if (c->timing & (1 << i)) c->tall[i] += it->second.launches[i];
+    if (gs != w.s) {
+        HIPCHK(hipEventRecord(ws.gev[1], gs));
+        HIPCHK(hipStreamWaitEvent(w.s, ws.gev[1], 0));
+    }
+}
+
 // BiCGSTAB iterations until no right-hand side is active (the host polls
 // once per chunk of iterations).
 void iterate_loop(Work& w, const dda_opts* o) {
@@ -595,7 +698,7 @@ void iterate_loop(Work& w, const dda_opts* o) {
     while (true) {
         fetch_state(c, w);
         if (!any_active_after_restart(w) || launched > o->max_iter + 2 * chunk) break;
-        launch_chunk(w, chunk);
+        run_chunk(w, chunk);
         launched += chunk;
     }
 }
@@ -778,6 +881,7 @@ dda_status solve_one(dda_ctx* c, dda_target* t, const dda_opts* o, int nrhs, con
     Work w(c, c->main, t, nrhs, kd, fp32);
     w.qmr = o->solver == DDA_QMR_SYM;
     w.b2 = o->solver == DDA_BICGSTAB2;
+    w.graphs = false;   // one stream: replays are slower than launches
     w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
     w.upload_incidence(kh, e0);
     const bool warm = P0 != nullptr;
@@ -870,6 +974,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
         Work& w = *j.w;
         w.qmr = j.o->solver == DDA_QMR_SYM;
         w.b2 = j.o->solver == DDA_BICGSTAB2;
+        w.graphs = (j.o->flags & DDA_FLAG_NO_GRAPH) == 0;
         w.autotune((j.o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, j.o->kernel_variant);
         w.upload_incidence(j.kh, j.e0);
         {
@@ -921,7 +1026,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
             if (j.phase == Job::ITER || j.phase == Job::REFINE) {
                 const bool active = any_active_after_restart(w);
                 if (active && j.launched <= j.o->max_iter + 2 * chunk) {
-                    launch_chunk(w, chunk);
+                    run_chunk(w, chunk);
                     j.launched += chunk;
                     j.phase = Job::ITER;
                     post_state(w);
@@ -1147,6 +1252,7 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         Work w(c, c->main, t, n_rhs, kd, fp32);
         w.qmr = o->solver == DDA_QMR_SYM;
         w.b2 = o->solver == DDA_BICGSTAB2;
+        w.graphs = false;   // one stream: replays are slower than launches
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
@@ -1225,6 +1331,7 @@ dda_status dda_grad_eps(dda_ctx* c, dda_target* t, const dda_opts* o, const dda_
         Work w(c, c->main, t, 1, kd, fp32);
         w.qmr = o->solver == DDA_QMR_SYM;
         w.b2 = o->solver == DDA_BICGSTAB2;
+        w.graphs = false;   // one stream: replays are slower than launches
         w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
         w.upload_incidence(kh, e0);
         w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
@@ -1263,7 +1370,9 @@ dda_status dda_ctx_set_timing(dda_ctx* c, int mask) {
             for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) {
                 c->tms[i] = 0.0;
                 c->tlaunch[i] = 0;
+                c->tall[i] = 0;
             }
+            c->tchunk = 0;
         }
         c->timing = mask & ((1 << DDA_TIMING_CATEGORIES) - 1);
         return DDA_OK;
@@ -1279,7 +1388,17 @@ dda_status dda_ctx_get_timing(dda_ctx* c, dda_timing* out) {
         for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) {
             out->ms[i] = c->tms[i];
             out->launches[i] = c->tlaunch[i];
+            out->all_launches[i] = c->tall[i];
         }
+        return DDA_OK;
+    });
+}
+
+dda_status dda_ctx_set_timing_sample(dda_ctx* c, int every) {
+    return guarded([&]() -> dda_status {
+        if (!c) invalid("ctx is NULL");
+        if (every < 1) invalid("every must be >= 1");
+        c->tsample = every;
         return DDA_OK;
     });
 }
