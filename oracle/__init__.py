@@ -15,11 +15,16 @@ names a result, the published source it names):
                  interaction tensor, dense assembly and LU solve, incident
                  field, Q_ext / Q_abs / Q_pha, closed-form Q_sca, the
                  normal-equation residual of the guide's stopping test.
-* ``fftsolve`` -- the FFT embedding of the interaction matrix and plain
-                 BiCGSTAB, for targets too large for dense LU.
+* ``fftsolve`` -- the FFT embedding of the interaction matrix and the Krylov
+                 solvers (BiCGSTAB, QMR for complex-symmetric A,
+                 BiCGstab(2)), for targets too large for dense LU.
 * ``mie``     -- Mie theory for a homogeneous sphere.
 * ``adjoint`` -- gradients of Q_abs and Q_ext with respect to the per-site
                  permittivity, by the adjoint of the dense solve.
+* ``farfield`` -- far-field amplitudes, the amplitude and Mueller matrices,
+                 backscattering and averages over scattering directions.
+* ``nearfield`` -- E_inc and the field of the dipoles on an extended lattice
+                 volume, and the field along a line between lattice points.
 
 Pins (``tests/test_oracle_*.py``, run with ``-m "not gpu"``) tie each function
 to something other than itself: the guide's printed worked example, closed

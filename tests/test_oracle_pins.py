@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from oracle import adjoint, dense, fftsolve, mie
+from oracle import adjoint, dense, farfield, fftsolve, mie, nearfield
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -435,8 +435,6 @@ def test_bicgstab2_iterations_near_the_printed_worked_example():
 
 # ---------------------------------------------------------------- far field
 
-from oracle import farfield  # noqa: E402
-
 
 def _au_brick_P(tol=1e-9):
     d = w.workload("au_brick")
@@ -538,3 +536,123 @@ def test_worked_example_angular_averages_near_printed():
         assert abs(gg - g["g1"]) <= 3e-3 * g["g1"]
         assert abs(c2 - g["cos2"]) <= 3e-3 * g["cos2"]
         assert abs(qs - g["qsca"]) <= 2e-4 * g["qsca"]
+
+
+# ---------------------------------------------------------------- near field
+
+def _nf_track():
+    with open(os.path.join(GOLDEN, "nearfield_au_sphere_track.json")) as f:
+        return json.load(f)
+
+
+def test_nearfield_example_lattice_and_extended_volume():
+    """The near-field example's header: N = 59728 sites in the 48^3 box, the
+    printed kd = 0.20619 and d = 1.6408e-2 um at a_eff = 0.39789 um, and the
+    extended volume of 96^3 points for r = 0.5 on every side."""
+    g = _nf_track()
+    d = w.workload("au_sphere_nf")
+    assert len(d["ijk"]) == g["header"]["n_sites"]
+    assert abs(dense.kd_from_size_parameter(d["x"], len(d["ijk"])) - g["header"]["kd"][0]) < 5e-6
+    # half a unit in the last printed place (1.6408E-02)
+    assert abs(g["header"]["aeff_um"] / dense.aeff_over_d(len(d["ijk"])) - g["header"]["d_um"]) < 5e-7
+    origin, dims = nearfield.extended_box(d["ijk"], d["nf_ext"])
+    assert list(dims) == g["header"]["dims"] and list(origin) == [-24, -24, -24]
+
+
+def _au_sphere_solution():
+    d = w.workload("au_sphere_nf")
+    res = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], 1e-5,
+                              scheme=dense.GKDLDR, solver="bicgstab2")
+    return d, res
+
+
+def test_nearfield_printed_readnf_track():
+    """E = E_inc + E_sca along the x_TF axis through the gold sphere (the
+    guide's printed readnf output, 52 rows): GKDLDR solve to tol 1e-5, then
+    the direct-sum near field, trilinear between lattice points.  Positions:
+    lattice = x_TF / d + 23.5 (the box centre), E_inc phase 1 at the centre.
+    The nearest-lattice-point reading misses the printed values by 1e-2."""
+    g = _nf_track()
+    d, res = _au_sphere_solution()
+    k = res["k"]
+    dl = g["header"]["aeff_um"] / dense.aeff_over_d(len(d["ijk"]))
+    c = 23.5
+    a = np.array(g["line_um"]["a"]) / dl + c
+    b = np.array(g["line_um"]["b"]) / dl + c
+    rows = np.array(g["rows"])
+    printed = rows[:, 3::2] + 1j * rows[:, 4::2]
+    E = nearfield.line_field(d["ijk"], res["P"], k, d["khat"][0], d["e0"][0], a, b, len(rows))
+    E *= np.exp(-1j * k * c)           # phase origin at the sphere's centre
+    assert np.abs(E - printed).max() < 3e-4
+    # positions as printed (4 digits) agree too, within their rounding
+    pts = nearfield.line_points(a, b, len(rows))
+    assert np.abs(pts[:, 0] - (rows[:, 0] / dl + c)).max() < 0.01
+    near = nearfield.incident_field(np.rint(pts), k, d["khat"][0], d["e0"][0]) + \
+        nearfield.scattered_field(d["ijk"], res["P"], k, np.rint(pts))
+    assert np.abs(near * np.exp(-1j * k * c) - printed).max() > 1e-2
+
+
+def test_nearfield_satisfies_the_dda_equations_at_the_sites():
+    """At every target site the field of the others plus E_inc is the local
+    field that polarizes it: P_j = alpha_j (E_inc,j + E_sca,j) for the LU
+    solution (the system A P = E, stated point by point), two materials and
+    an oblique elliptical incidence."""
+    ijk = w.brick(4, 3, 3)
+    mask = np.arange(len(ijk)) % 3 == 0
+    m = np.where(mask, 1.5 + 0.02j, 2.2 + 0.4j)
+    kh = np.array([0.6, 0.0, 0.8])
+    e0 = np.array([0.8, 0.3j, -0.6])
+    case = dense.solve_case(ijk, m, 1.1, kh, e0, scheme=dense.LATTDR)
+    k, P = case["k"], case["P"]
+    E = nearfield.incident_field(ijk, k, kh, e0) + nearfield.scattered_field(ijk, P, k, ijk)
+    assert np.abs(case["alpha_inv"] * P - E).max() < 1e-11 * np.abs(E).max()
+    # on the extended volume the target's own sites carry the same fields
+    origin, dims, Ei, Es = nearfield.nearfield(ijk, P, k, kh, e0, (0.5, 0.25, 0.0, 1.0, 0.4, 0.4))
+    pts = nearfield.box_points(origin, dims)
+    flat = (Ei + Es).reshape(-1, 3)
+    idx = [int(np.flatnonzero((pts == s).all(axis=1))[0]) for s in ijk]
+    assert np.abs(flat[idx] - E).max() < 1e-12 * np.abs(E).max()
+    assert list(dims) == [4 + 2 + 1, 3 + 0 + 3, 3 + 1 + 1]
+
+
+def test_nearfield_far_zone_is_the_far_field_amplitude():
+    """Far away along n the dipole sum becomes (e^{ikR} / kR) (I - n n) A(n)
+    / k^2 ... i.e. E_sca R e^{-ikR} -> (I - n n) A(n) / k, with A(n) the
+    far-field amplitude vector pinned by the guide's printed Mueller table."""
+    ijk = w.sphere_integer(2.5)
+    kh, e0 = w.along_x_yz()
+    case = dense.solve_case(ijk, np.full(len(ijk), 1.4 + 0.05j), 0.8, kh[0], e0[0])
+    k, P = case["k"], case["P"]
+    n = np.array([0.36, -0.48, 0.8])
+    R = 1e7
+    E = nearfield.scattered_field(ijk, P, k, (R * n)[None, :])[0] * R * np.exp(-1j * k * R)
+    A = farfield.amplitude_vectors(ijk, P, k, n[None, :])[0]
+    expect = (A - n * (n @ A)) / k
+    assert np.abs(E - expect).max() < 1e-5 * np.abs(expect).max()
+
+
+def test_nearfield_static_dipole_and_interaction_tensor():
+    """k -> 0: one dipole's field is (3 n (n.P) - P) / r^3 (electrostatics).
+    At finite k the field equals -A_jl P_l with the interaction block that
+    finite differences of exp(ikr)/r pin."""
+    P = np.array([[0.3, -0.2 + 0.1j, 0.5]])
+    site = np.array([[0, 0, 0]])
+    r = np.array([[2.0, -1.0, 3.0]])
+    rn = np.linalg.norm(r[0])
+    n = r[0] / rn
+    E0 = nearfield.scattered_field(site, P, 1e-9, r)[0]
+    assert np.abs(E0 - (3 * n * (n @ P[0]) - P[0]) / rn ** 3).max() < 1e-12
+    E1 = nearfield.scattered_field(site, P, 0.7, r)[0]
+    assert np.abs(E1 + dense.interaction_block(r[0], 0.7) @ P[0]).max() < 1e-14
+    # no self term: the field at the dipole's own site is zero
+    assert not nearfield.scattered_field(site, P, 0.7, site).any()
+
+
+def test_trilinear_reproduces_linear_fields():
+    """Trilinear interpolation is exact for a field linear in position."""
+    B = np.array([[1.0, 2.0j, -0.5], [0.3, 0.0, 1j], [2.0, -1.0, 0.25]])
+    c0 = np.array([0.1, -2j, 3.0])
+    lin = lambda q: c0[None, :] + np.asarray(q, float) @ B
+    pts = nearfield.line_points([-1.3, 0.25, 2.0], [4.7, 3.5, -1.1], 23)
+    assert np.abs(nearfield.trilinear(lin, pts) - lin(pts)).max() < 1e-12
+    assert np.allclose(pts[0], [-1.3, 0.25, 2.0]) and np.allclose(pts[-1], [4.7, 3.5, -1.1])

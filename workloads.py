@@ -164,7 +164,8 @@ def workload(name: str, seed: int = 0) -> dict:
     'brick48' (48x24x16 brick, x=4, 64 random orientations x 2 polarizations),
     'sphere1m' (radius-64 sphere in a 128^3 box, x=20, tol 1e-5),
     'twomat40' (40^3 two-material brick, x=6), 'twomat6' (its 6^3 instance,
-    same kd as the 40^3 case), 'au_brick' (16x32x32 gold brick, x=3.093665)."""
+    same kd as the 40^3 case), 'au_brick' (16x32x32 gold brick, x=3.093665),
+    'au_sphere_nf' (gold pseudosphere of the near-field example, N = 59728)."""
     if name == "sphere389":
         ijk = sphere_integer(4.5)
         kh, e0 = along_x_yz()
@@ -200,6 +201,14 @@ def workload(name: str, seed: int = 0) -> dict:
         kh, e0 = along_x_yz()
         m = np.full(len(ijk), 0.9656 + 1.8628j)
         return dict(ijk=ijk, m=m, x=3.093665, khat=kh, e0=e0, tol=1e-5)
+    if name == "au_sphere_nf":
+        # the guide's near-field example: a 48^3-box pseudosphere of diameter
+        # 48.49 sites (N = 59728), m = 0.96+1.01i, x = 5, extended by half
+        # the box on every side
+        ijk = box_sphere(48, 48.49 / 2)
+        kh, e0 = along_x_yz()
+        m = np.full(len(ijk), 0.96 + 1.01j)
+        return dict(ijk=ijk, m=m, x=5.0, khat=kh, e0=e0, tol=1e-5, nf_ext=(0.5,) * 6)
     raise KeyError(name)
 
 
