@@ -207,6 +207,47 @@ dda_status dda_grad_eps(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const
                         const dda_c64* P, double w_qabs, double w_qext, dda_c64* grad,
                         dda_result* adj);
 
+/* Near field ("Near-Field Calculations"; the volume of "Additional
+ * Nearfield Calculation?").  The volume is the target's bounding box grown by
+ * round(r_i * n_a) lattice points on each side, ext = (r1, r2, r3, r4, r5, r6)
+ * for -x, +x, -y, +y, -z, +z and n_a the box's extent in sites on axis a;
+ * 0 <= r_i <= 16, and each grown extent must allow a padded FFT extent of at
+ * most 341 (E_INVALID otherwise).  dda_nearfield_volume writes the lattice
+ * coordinates of the volume's first point (origin) and its extents (dims). */
+dda_status dda_nearfield_volume(const dda_target* t, const double ext[6], int32_t origin[3], int32_t dims[3]);
+
+/* At every point j of that volume: the incident field E_inc,j = e exp(i kd
+ * khat . r_j) (phase origin at lattice index (0, 0, 0), as in dda_solve) and
+ * the field of the target's dipoles, the dipole at j itself excluded:
+ *   E_sca,j = - sum_{l != j} A_jl P_l
+ * (the guide's E_sca; the total field is E_inc + E_sca, and at a target site
+ * P_j = alpha_j (E_inc,j + E_sca,j) holds to the solve's tolerance).  It is
+ * one FFT product on the volume with a zero diagonal, in the precision of
+ * opts (FP32_MATVEC: FP32 product).  kd is the target's (opts and its site
+ * count).
+ *   inc    host [n_rhs] incidences (for E_inc)
+ *   P      device [n_rhs][n_sites][3], caller order (as dda_solve writes it)
+ *   E_inc  device [n_rhs][dims z][dims y][dims x][3] output, or NULL
+ *   E_sca  device, same shape, output
+ * Enqueued on the context's stream (no host synchronisation).  The volume's
+ * site map and tensor FFT are built on the first call for an extension and
+ * kept with the target until another extension is asked for or the target is
+ * destroyed. */
+dda_status dda_nearfield(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const double ext[6], int32_t n_rhs,
+                         const dda_incidence* inc, const dda_c64* P, dda_c64* E_inc, dda_c64* E_sca);
+
+/* Values of a lattice field along a line (the guide's readnf program, section
+ * "The Program readnf"): n_points equally spaced points from a to b inclusive
+ * (lattice coordinates; a alone when n_points = 1), each the trilinear
+ * interpolation of the 8 surrounding lattice points (the guide does not state
+ * readnf's interpolation; trilinear reproduces its printed track).
+ *   E    device [n_rhs][dims z][dims y][dims x][3], first point at origin
+ *   out  device [n_rhs][n_points][3] output
+ * E_INVALID if a or b lies outside the box [origin, origin + dims - 1].
+ * Enqueued on the context's stream. */
+dda_status dda_field_line(dda_ctx* ctx, int32_t n_rhs, const int32_t origin[3], const int32_t dims[3],
+                          const dda_c64* E, const double a[3], const double b[3], int32_t n_points, dda_c64* out);
+
 /* Far-field scattering amplitudes ("Scattering by Finite Targets: The Mueller
  * Matrix"; Draine 1988).  For each right-hand side q and direction d:
  *   A = k^3 sum_j P_qj exp(-i k n_d . r_j)  (lattice units, r_j = the ijk of

@@ -133,4 +133,8 @@ SIGNATURES["dda_scattering_averages"] = (ctypes.c_int, [VP, VP, ctypes.POINTER(O
                                                         ctypes.POINTER(Incidence), VP, ctypes.c_int32,
                                                         ctypes.c_int32, VP])
 SIGNATURES["dda_mueller"] = (ctypes.c_int, [ctypes.c_int32, VP, VP, VP, VP, VP, VP])
+SIGNATURES["dda_nearfield_volume"] = (ctypes.c_int, [VP, VP, VP, VP])
+SIGNATURES["dda_nearfield"] = (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), VP, ctypes.c_int32,
+                                              ctypes.POINTER(Incidence), VP, VP, VP])
+SIGNATURES["dda_field_line"] = (ctypes.c_int, [VP, ctypes.c_int32, VP, VP, VP, VP, VP, ctypes.c_int32, VP])
 SIGNATURES["dda_ctx_tuned_variants"] = (ctypes.c_int, [VP, VP, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)])

@@ -340,6 +340,58 @@ def scattering_averages(target: "Target", opts: Options, khat, e0, P: torch.Tens
     return [dict(qsca=float(r[0]), g=float(r[1]), cos2=float(r[2])) for r in out]
 
 
+def nearfield_volume(target: "Target", ext) -> tuple[np.ndarray, np.ndarray]:
+    """(origin, dims) of the near-field volume: the target's bounding box
+    grown by round(r_i n_a) points per side, ext = (r1..r6) for -x, +x, -y,
+    +y, -z, +z (dda_nearfield_volume)."""
+    r = np.ascontiguousarray(np.asarray(ext, dtype=np.float64).reshape(6))
+    org = np.zeros(3, dtype=np.int32)
+    dims = np.zeros(3, dtype=np.int32)
+    _check(_lib.dda_nearfield_volume(target.handle, r.ctypes.data, org.ctypes.data, dims.ctypes.data),
+           "dda_nearfield_volume")
+    return org, dims
+
+
+def nearfield(target: "Target", opts: Options, ext, khat, e0, P: torch.Tensor, incident: bool = True):
+    """E_inc and E_sca [n_rhs, dims z, dims y, dims x, 3] (device, complex128)
+    on the near-field volume for the solution P [n_rhs, n_sites, 3]; returns
+    (origin, dims, E_inc or None, E_sca) (dda_nearfield)."""
+    if P.dim() == 2:
+        P = P.unsqueeze(0)
+    P = P.to(torch.complex128).contiguous()
+    inc = _incidences(khat, e0)
+    n = len(inc)
+    _dev_c128(P, (n, target.n_sites, 3), "P")
+    org, dims = nearfield_volume(target, ext)
+    shape = (n, int(dims[2]), int(dims[1]), int(dims[0]), 3)
+    esca = torch.empty(shape, dtype=torch.complex128, device=P.device)
+    einc = torch.empty(shape, dtype=torch.complex128, device=P.device) if incident else None
+    r = np.ascontiguousarray(np.asarray(ext, dtype=np.float64).reshape(6))
+    o = opts.c()
+    _check(_lib.dda_nearfield(target.ctx, target.handle, ctypes.byref(o), r.ctypes.data, n, inc, P.data_ptr(),
+                              einc.data_ptr() if einc is not None else None, esca.data_ptr()), "dda_nearfield")
+    return org, dims, einc, esca
+
+
+def field_line(E: torch.Tensor, origin, a, b, n_points: int, device: int | None = None) -> torch.Tensor:
+    """Trilinear values [n_rhs, n_points, 3] of the lattice field E [n_rhs,
+    dims z, dims y, dims x, 3] (first point at ``origin``) at n_points equally
+    spaced points from a to b (lattice coordinates; dda_field_line)."""
+    if E.dim() == 4:
+        E = E.unsqueeze(0)
+    n, nz, ny, nx, _ = E.shape
+    E = _dev_c128(E, (n, nz, ny, nx, 3), "E")
+    org = np.ascontiguousarray(np.asarray(origin, dtype=np.int32).reshape(3))
+    dims = np.array([nx, ny, nz], dtype=np.int32)
+    pa = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(3))
+    pb = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(3))
+    out = torch.empty((n, int(n_points), 3), dtype=torch.complex128, device=E.device)
+    _check(_lib.dda_field_line(context(E.device.index if device is None else device), n, org.ctypes.data,
+                               dims.ctypes.data, E.data_ptr(), pa.ctypes.data, pb.ctypes.data, int(n_points),
+                               out.data_ptr()), "dda_field_line")
+    return out
+
+
 def mueller(f1, f2, e01, e02, phi_deg) -> np.ndarray:
     """Mueller matrices [n_dir, 4, 4] in the Lab Frame from the amplitudes
     f1, f2 [n_dir, 2] of the incident polarizations e01, e02 (dda_mueller)."""

@@ -185,6 +185,11 @@ struct dda_target {
     double green_kd = -1.0;
     bool have64 = false, have32 = false;
     DevBuf gh64, gh32;
+    int lo[3] = {0, 0, 0};             // lattice coordinates of the bounding box's first point
+    // near field: the last extended volume (every point a site), keyed by the
+    // points added below and above the box on each axis
+    dda_target* nf = nullptr;
+    int nf_key[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -1064,6 +1069,154 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
     return worst;
 }
 
+// Sorted device copies of a target's sites (throws on invalid input; the
+// caller has made the context's device current).
+dda_target* create_target(dda_ctx* c, int64_t n_sites, const int32_t* ijk, const dda_c64* m_site) {
+    if (n_sites < 1 || n_sites > (int64_t)1 << 30) invalid("n_sites out of range");
+    if (!ijk || !m_site) invalid("ijk or m_site is NULL");
+    const int n = (int)n_sites;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = ijk[a]; hi[a] = ijk[a]; }
+    for (int j = 0; j < n; ++j)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], ijk[3 * j + a]);
+            hi[a] = std::max(hi[a], ijk[3 * j + a]);
+        }
+    Geo g{};
+    for (int a = 0; a < 3; ++a) {
+        const long long ext = (long long)hi[a] - lo[a] + 1;
+        if (ext > 4096) invalid("target extent above 4096 sites on an axis");
+        g.n[a] = (int)ext;
+        g.M[a] = padded_extent(g.n[a]);
+        g.H[a] = g.M[a] / 2 + 1;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (6 * g.M[a] > Tile<double>::EMAX)
+            invalid("padded FFT extent " + std::to_string(g.M[a]) + " above the supported 341");
+    g.npts = (long long)g.M[0] * g.M[1] * g.M[2];
+    const long long boxv = (long long)g.n[0] * g.n[1] * g.n[2];
+    if (boxv > ((long long)1 << 31) - 1) invalid("bounding box too large");
+    // sort sites in box-scan order (x fastest), reject duplicates
+    std::vector<std::pair<long long, int>> key(n);
+    for (int j = 0; j < n; ++j) {
+        const long long x = ijk[3 * j] - lo[0], y = ijk[3 * j + 1] - lo[1], z = ijk[3 * j + 2] - lo[2];
+        key[j] = {(z * g.n[1] + y) * g.n[0] + x, j};
+    }
+    std::sort(key.begin(), key.end());
+    for (int j = 1; j < n; ++j)
+        if (key[j].first == key[j - 1].first)
+            invalid("duplicate lattice site (" + std::to_string(ijk[3 * key[j].second]) + "," +
+                    std::to_string(ijk[3 * key[j].second + 1]) + "," + std::to_string(ijk[3 * key[j].second + 2]) +
+                    ")");
+    auto* t = new dda_target();
+    t->ctx = c;
+    t->nsites = n;
+    std::vector<int> map((size_t)boxv, -1), perm(n), mat(n), coords((size_t)n * 3);
+    std::map<std::pair<double, double>, int> mid;
+    try {
+        for (int s = 0; s < n; ++s) {
+            const int j = key[s].second;
+            map[(size_t)key[s].first] = s;
+            perm[s] = j;
+            for (int a = 0; a < 3; ++a) coords[(size_t)s * 3 + a] = ijk[3 * j + a];
+            const dda_c64 m = m_site[j];
+            if (!std::isfinite(m.re) || !std::isfinite(m.im)) invalid("non-finite refractive index");
+            if (m.re == 1.0 && m.im == 0.0) invalid("refractive index 1 (vacuum) on an occupied site");
+            auto it = mid.find({m.re, m.im});
+            if (it == mid.end()) {
+                if (mid.size() >= 65535) invalid("more than 65535 distinct materials");
+                it = mid.emplace(std::make_pair(m.re, m.im), (int)mid.size()).first;
+                t->mats.push_back(double2{m.re, m.im});
+            }
+            mat[s] = it->second;
+        }
+        t->nmat = (int)t->mats.size();
+        // FFT plans and their twiddle tables W_L^t = exp(-2 pi i t / L)
+        std::vector<double2> tw;
+        std::map<int, int> twoff;
+        for (int a = 0; a < 3; ++a) {
+            g.ax[a] = make_plan(g.M[a]);
+            auto it = twoff.find(g.M[a]);
+            if (it == twoff.end()) {
+                const int off = (int)tw.size();
+                for (int i = 0; i < g.M[a]; ++i) {
+                    const double ang = -2.0 * M_PI * (double)i / (double)g.M[a];
+                    tw.push_back(double2{std::cos(ang), std::sin(ang)});
+                }
+                it = twoff.emplace(g.M[a], off).first;
+            }
+            g.ax[a].tw = it->second;
+        }
+        t->geo = g;
+        auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+            b.ensure(bytes);
+            HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        up(t->map, map.data(), map.size() * sizeof(int));
+        up(t->perm, perm.data(), perm.size() * sizeof(int));
+        up(t->mat, mat.data(), mat.size() * sizeof(int));
+        up(t->coords, coords.data(), coords.size() * sizeof(int));
+        up(t->tw, tw.data(), tw.size() * sizeof(double2));
+        for (int a = 0; a < 3; ++a) t->lo[a] = lo[a];
+    } catch (...) {
+        for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw}) b->release();
+        delete t;
+        throw;
+    }
+    return t;
+}
+
+// Release a target's device memory (and its extended near-field volume).
+void free_target(dda_target* t) {
+    if (!t) return;
+    free_target(t->nf);
+    t->nf = nullptr;
+    for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->gh64, &t->gh32}) b->release();
+    delete t;
+}
+
+// Points the near-field volume adds below (e[2a]) and above (e[2a+1]) the
+// bounding box on axis a: round(r * n) for the fractions r1..r6 of the box
+// extents n ("Additional Nearfield Calculation?").
+void nf_extension(const dda_target* t, const double* r, int e[6], int org[3], int dims[3]) {
+    if (!r) invalid("ext is NULL");
+    for (int i = 0; i < 6; ++i) {
+        if (!std::isfinite(r[i]) || r[i] < 0.0 || r[i] > 16.0) invalid("ext fractions must lie in [0, 16]");
+        e[i] = (int)std::floor(r[i] * t->geo.n[i / 2] + 0.5);
+    }
+    for (int a = 0; a < 3; ++a) {
+        org[a] = t->lo[a] - e[2 * a];
+        dims[a] = t->geo.n[a] + e[2 * a] + e[2 * a + 1];
+        if (padded_extent(dims[a]) > Tile<double>::EMAX / 6)
+            invalid("near-field volume of " + std::to_string(dims[a]) + " points on axis " + std::to_string(a) +
+                    " needs a padded FFT extent above the supported 341");
+    }
+}
+
+// The extended volume as a target whose sites are all of its points, in
+// box-scan order (cached on t for the last extension asked for).
+dda_target* nf_target(dda_ctx* c, dda_target* t, const int e[6], const int org[3], const int dims[3]) {
+    if (t->nf && std::equal(e, e + 6, t->nf_key)) return t->nf;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    free_target(t->nf);
+    t->nf = nullptr;
+    const long long n = (long long)dims[0] * dims[1] * dims[2];
+    std::vector<int32_t> ijk((size_t)n * 3);
+    long long i = 0;
+    for (int z = 0; z < dims[2]; ++z)
+        for (int y = 0; y < dims[1]; ++y)
+            for (int x = 0; x < dims[0]; ++x, ++i) {
+                ijk[(size_t)i * 3 + 0] = org[0] + x;
+                ijk[(size_t)i * 3 + 1] = org[1] + y;
+                ijk[(size_t)i * 3 + 2] = org[2] + z;
+            }
+    // one placeholder material: the product runs with a zero diagonal
+    const std::vector<dda_c64> m((size_t)n, dda_c64{2.0, 0.0});
+    t->nf = create_target(c, n, ijk.data(), m.data());
+    std::copy(e, e + 6, t->nf_key);
+    return t->nf;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1115,98 +1268,8 @@ dda_status dda_target_create(dda_ctx* c, int64_t n_sites, const int32_t* ijk, co
     return guarded([&]() -> dda_status {
         if (!c || !out) invalid("ctx or out is NULL");
         *out = nullptr;
-        if (n_sites < 1 || n_sites > (int64_t)1 << 30) invalid("n_sites out of range");
-        if (!ijk || !m_site) invalid("ijk or m_site is NULL");
         Scope sc(c);
-        const int n = (int)n_sites;
-        int lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) { lo[a] = ijk[a]; hi[a] = ijk[a]; }
-        for (int j = 0; j < n; ++j)
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = std::min(lo[a], ijk[3 * j + a]);
-                hi[a] = std::max(hi[a], ijk[3 * j + a]);
-            }
-        Geo g{};
-        for (int a = 0; a < 3; ++a) {
-            const long long ext = (long long)hi[a] - lo[a] + 1;
-            if (ext > 4096) invalid("target extent above 4096 sites on an axis");
-            g.n[a] = (int)ext;
-            g.M[a] = padded_extent(g.n[a]);
-            g.H[a] = g.M[a] / 2 + 1;
-        }
-        for (int a = 0; a < 3; ++a)
-            if (6 * g.M[a] > Tile<double>::EMAX)
-                invalid("padded FFT extent " + std::to_string(g.M[a]) + " above the supported 341");
-        g.npts = (long long)g.M[0] * g.M[1] * g.M[2];
-        const long long boxv = (long long)g.n[0] * g.n[1] * g.n[2];
-        if (boxv > ((long long)1 << 31) - 1) invalid("bounding box too large");
-        // sort sites in box-scan order (x fastest), reject duplicates
-        std::vector<std::pair<long long, int>> key(n);
-        for (int j = 0; j < n; ++j) {
-            const long long x = ijk[3 * j] - lo[0], y = ijk[3 * j + 1] - lo[1], z = ijk[3 * j + 2] - lo[2];
-            key[j] = {(z * g.n[1] + y) * g.n[0] + x, j};
-        }
-        std::sort(key.begin(), key.end());
-        for (int j = 1; j < n; ++j)
-            if (key[j].first == key[j - 1].first)
-                invalid("duplicate lattice site (" + std::to_string(ijk[3 * key[j].second]) + "," +
-                        std::to_string(ijk[3 * key[j].second + 1]) + "," + std::to_string(ijk[3 * key[j].second + 2]) +
-                        ")");
-        auto* t = new dda_target();
-        t->ctx = c;
-        t->nsites = n;
-        std::vector<int> map((size_t)boxv, -1), perm(n), mat(n), coords((size_t)n * 3);
-        std::map<std::pair<double, double>, int> mid;
-        try {
-            for (int s = 0; s < n; ++s) {
-                const int j = key[s].second;
-                map[(size_t)key[s].first] = s;
-                perm[s] = j;
-                for (int a = 0; a < 3; ++a) coords[(size_t)s * 3 + a] = ijk[3 * j + a];
-                const dda_c64 m = m_site[j];
-                if (!std::isfinite(m.re) || !std::isfinite(m.im)) invalid("non-finite refractive index");
-                if (m.re == 1.0 && m.im == 0.0) invalid("refractive index 1 (vacuum) on an occupied site");
-                auto it = mid.find({m.re, m.im});
-                if (it == mid.end()) {
-                    if (mid.size() >= 65535) invalid("more than 65535 distinct materials");
-                    it = mid.emplace(std::make_pair(m.re, m.im), (int)mid.size()).first;
-                    t->mats.push_back(double2{m.re, m.im});
-                }
-                mat[s] = it->second;
-            }
-            t->nmat = (int)t->mats.size();
-            // FFT plans and their twiddle tables W_L^t = exp(-2 pi i t / L)
-            std::vector<double2> tw;
-            std::map<int, int> twoff;
-            for (int a = 0; a < 3; ++a) {
-                g.ax[a] = make_plan(g.M[a]);
-                auto it = twoff.find(g.M[a]);
-                if (it == twoff.end()) {
-                    const int off = (int)tw.size();
-                    for (int i = 0; i < g.M[a]; ++i) {
-                        const double ang = -2.0 * M_PI * (double)i / (double)g.M[a];
-                        tw.push_back(double2{std::cos(ang), std::sin(ang)});
-                    }
-                    it = twoff.emplace(g.M[a], off).first;
-                }
-                g.ax[a].tw = it->second;
-            }
-            t->geo = g;
-            auto up = [&](DevBuf& b, const void* src, size_t bytes) {
-                b.ensure(bytes);
-                HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
-            };
-            up(t->map, map.data(), map.size() * sizeof(int));
-            up(t->perm, perm.data(), perm.size() * sizeof(int));
-            up(t->mat, mat.data(), mat.size() * sizeof(int));
-            up(t->coords, coords.data(), coords.size() * sizeof(int));
-            up(t->tw, tw.data(), tw.size() * sizeof(double2));
-        } catch (...) {
-            for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw}) b->release();
-            delete t;
-            throw;
-        }
-        *out = t;
+        *out = create_target(c, n_sites, ijk, m_site);
         return DDA_OK;
     });
 }
@@ -1217,9 +1280,8 @@ dda_status dda_target_destroy(dda_target* t) {
         {
             Scope sc(t->ctx);
             (void)hipStreamSynchronize(t->ctx->stream);
-            for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->gh64, &t->gh32}) b->release();
+            free_target(t);
         }
-        delete t;
         return DDA_OK;
     });
 }
@@ -1612,6 +1674,75 @@ dda_status dda_mueller(int32_t n_dir, const dda_c64* f1, const dda_c64* f2, cons
             M[14] = std::imag(S1 * std::conj(S2) - S3 * std::conj(S4));
             M[15] = std::real(S1 * std::conj(S2) - S3 * std::conj(S4));
         }
+        return DDA_OK;
+    });
+}
+
+dda_status dda_nearfield_volume(const dda_target* t, const double ext[6], int32_t origin[3], int32_t dims[3]) {
+    return guarded([&]() -> dda_status {
+        if (!t || !origin || !dims) invalid("NULL argument");
+        int e[6], org[3], dm[3];
+        nf_extension(t, ext, e, org, dm);
+        for (int a = 0; a < 3; ++a) {
+            origin[a] = org[a];
+            dims[a] = dm[a];
+        }
+        return DDA_OK;
+    });
+}
+
+dda_status dda_nearfield(dda_ctx* c, dda_target* t, const dda_opts* o, const double ext[6], int32_t n_rhs,
+                         const dda_incidence* inc, const dda_c64* P, dda_c64* E_inc, dda_c64* E_sca) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !P || !E_sca) invalid("NULL argument");
+        if (n_rhs < 1 || n_rhs > 65535) invalid("n_rhs must lie in 1..65535");
+        check_opts(o);
+        int e[6], org[3], dims[3];
+        nf_extension(t, ext, e, org, dims);
+        Scope sc(c);
+        std::vector<double> kh;
+        std::vector<double2> e0;
+        pack_incidence(n_rhs, inc, kh, e0);
+        // k d of the target itself (a_eff counts its sites, not the volume's)
+        const double kd = kd_of(o, t->nsites);
+        const bool fp32 = o->precision == DDA_FP32_MATVEC;
+        dda_target* x = nf_target(c, t, e, org, dims);
+        ensure_green(c, x, kd, fp32, (o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+        Work w(c, c->main, x, n_rhs, kd, fp32);
+        w.autotune((o->flags & DDA_FLAG_NO_AUTOTUNE) == 0, o->kernel_variant);
+        w.upload_incidence(kh, e0);
+        launch_fill((double2*)w.a.ainv, (long long)n_rhs * x->nmat * 3, w.s);
+        launch_fill(w.a.p, (long long)n_rhs * w.a.n3, w.s);
+        launch_nf_place(t->nsites, (const int*)t->perm.p, (const int*)t->coords.p, (const double2*)P, n_rhs, org,
+                        dims, w.a.p, w.s);
+        w.a.in = w.a.p;
+        w.a.out = w.a.v;
+        w.matvec(SC_PLAIN, GA_PLAIN, CHK_NONE, CHK_NONE);
+        launch_nf_out(n_rhs, org, dims, w.kh, w.e0, kd, w.a.v, (double2*)E_inc, (double2*)E_sca, w.s);
+        HIPCHK(hipGetLastError());
+        return DDA_OK;
+    });
+}
+
+dda_status dda_field_line(dda_ctx* c, int32_t n_rhs, const int32_t origin[3], const int32_t dims[3],
+                          const dda_c64* E, const double a[3], const double b[3], int32_t n_points, dda_c64* out) {
+    return guarded([&]() -> dda_status {
+        if (!c || !origin || !dims || !E || !a || !b || !out) invalid("NULL argument");
+        if (n_rhs < 1 || n_rhs > 65535) invalid("n_rhs must lie in 1..65535");
+        if (n_points < 1) invalid("n_points must be >= 1");
+        for (int d = 0; d < 3; ++d) {
+            if (dims[d] < 1) invalid("dims must be >= 1");
+            if (!std::isfinite(a[d]) || !std::isfinite(b[d])) invalid("non-finite line end point");
+            const double lo = origin[d], hi = (double)origin[d] + dims[d] - 1;
+            if (a[d] < lo || a[d] > hi || b[d] < lo || b[d] > hi)
+                invalid("line end points must lie inside the lattice box");
+        }
+        if ((long long)dims[0] * dims[1] * dims[2] > ((long long)1 << 31) - 1) invalid("lattice box too large");
+        Scope sc(c);
+        const int org[3] = {origin[0], origin[1], origin[2]};
+        const int dm[3] = {dims[0], dims[1], dims[2]};
+        launch_field_line(n_rhs, org, dm, (const double2*)E, a, b, n_points, (double2*)out, c->stream);
+        HIPCHK(hipGetLastError());
         return DDA_OK;
     });
 }

@@ -143,6 +143,16 @@ void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
 // phi), f [nrhs][ndir][2], dcs [nrhs][ndir]
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
                      double k, double2* f, double* dcs, hipStream_t s);
+// near field on an extended lattice box (first point org, extents dims):
+// P (caller order) into the box-scan site vector x at the target's sites;
+// E_sca = -v and E_inc at every point (either output may be null); the
+// trilinear line a..b of n points through E [nrhs][box][3]
+void launch_nf_place(int nsites, const int* perm, const int* coords, const double2* P, int nrhs, const int org[3],
+                     const int dims[3], double2* x, hipStream_t s);
+void launch_nf_out(int nrhs, const int org[3], const int dims[3], const double* khat, const double2* e0, double kd,
+                   const double2* v, double2* einc, double2* esca, hipStream_t s);
+void launch_field_line(int nrhs, const int org[3], const int dims[3], const double2* E, const double a[3],
+                       const double b[3], int n, double2* out, hipStream_t s);
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,

@@ -438,6 +438,94 @@ __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, 
     dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
 }
 
+// ------------------------------------------------------------------ near field
+// ("Near-Field Calculations".)  The extended volume is a lattice box of
+// dims[0] x dims[1] x dims[2] points starting at lattice point org, every
+// point a site of the product's target; its site vectors are in box-scan
+// order.  k_nf_place copies the solution P (caller order) into that vector
+// at the target's sites (every other point is zeroed beforehand).
+__global__ __launch_bounds__(NT) void k_nf_place(int nsites, const int* perm, const int* coords, const double2* P,
+                                                 int ox, int oy, int oz, int nx, int ny, long long n3x,
+                                                 double2* x) {
+    const int q = blockIdx.y;
+    const long long n3 = 3LL * nsites;
+    for (int s = blockIdx.x * NT + threadIdx.x; s < nsites; s += gridDim.x * NT) {
+        const long long i = ((long long)(coords[s * 3 + 2] - oz) * ny + (coords[s * 3 + 1] - oy)) * nx +
+                            (coords[s * 3 + 0] - ox);
+        const double2* src = P + (long long)q * n3 + (long long)perm[s] * 3;
+        double2* dst = x + (long long)q * n3x + i * 3;
+        for (int c = 0; c < 3; ++c) dst[c] = src[c];
+    }
+}
+
+// E_sca = -(off-diagonal product) at every point of the extended volume (v
+// holds that product: the diagonal was zero), and E_inc = e exp(i kd khat . r)
+// with r the point's lattice coordinates.  Either output may be null.
+__global__ __launch_bounds__(NT) void k_nf_out(long long npts, int ox, int oy, int oz, int nx, int ny,
+                                               const double* khat, const double2* e0, double kd, const double2* v,
+                                               double2* einc, double2* esca) {
+    const int q = blockIdx.y;
+    const double* kh = khat + q * 3;
+    const double2* e = e0 + q * 3;
+    const long long base = (long long)q * npts * 3;
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < npts; i += (long long)gridDim.x * NT) {
+        if (esca)
+            for (int c = 0; c < 3; ++c) {
+                const double2 y = v[base + i * 3 + c];
+                esca[base + i * 3 + c] = double2{-y.x, -y.y};
+            }
+        if (einc) {
+            const long long xy = (long long)nx * ny;
+            const int z = (int)(i / xy), y = (int)((i / nx) % ny), x = (int)(i % nx);
+            const double ph = kd * (kh[0] * (x + ox) + kh[1] * (y + oy) + kh[2] * (z + oz));
+            double sn, cs;
+            sincos(ph, &sn, &cs);
+            const double2 w = {cs, sn};
+            for (int c = 0; c < 3; ++c) einc[base + i * 3 + c] = cmul(e[c], w);
+        }
+    }
+}
+
+// Trilinear values of a lattice field E [nrhs][dims z][dims y][dims x][3]
+// (first point at lattice point org) at n points p_i = a + (b - a) i / (n - 1)
+// (p_0 = a when n = 1).  The host has checked that a and b lie in the box,
+// so every p_i does; the lower corner is clamped so that a point on the upper
+// face takes weight 1 on it.
+__global__ __launch_bounds__(NT) void k_field_line(const double2* E, int ox, int oy, int oz, int nx, int ny, int nz,
+                                                   double ax, double ay, double az, double bx, double by, double bz,
+                                                   int n, double2* out) {
+    const int q = blockIdx.y;
+    const long long npts = (long long)nx * ny * nz;
+    const double2* Eq = E + (long long)q * npts * 3;
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const double t = n > 1 ? (double)i / (double)(n - 1) : 0.0;
+        const double p[3] = {ax + t * (bx - ax) - ox, ay + t * (by - ay) - oy, az + t * (bz - az) - oz};
+        const int dim[3] = {nx, ny, nz};
+        int b0[3];
+        double f[3];
+        for (int d = 0; d < 3; ++d) {
+            int c = (int)floor(p[d]);
+            c = c < 0 ? 0 : c;
+            c = c > dim[d] - 2 ? (dim[d] >= 2 ? dim[d] - 2 : 0) : c;
+            b0[d] = c;
+            f[d] = dim[d] >= 2 ? p[d] - c : 0.0;
+        }
+        double2 acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        for (int corner = 0; corner < 8; ++corner) {
+            const int dx = corner & 1, dy = (corner >> 1) & 1, dz = corner >> 2;
+            if ((dx && nx < 2) || (dy && ny < 2) || (dz && nz < 2)) continue;
+            const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+            const long long j = ((long long)(b0[2] + dz) * ny + (b0[1] + dy)) * nx + (b0[0] + dx);
+            for (int c = 0; c < 3; ++c) {
+                const double2 v = Eq[j * 3 + c];
+                acc[c].x += w * v.x;
+                acc[c].y += w * v.y;
+            }
+        }
+        for (int c = 0; c < 3; ++c) out[((long long)q * n + i) * 3 + c] = acc[c];
+    }
+}
+
 // Efficiency sums at the solution x (Draine 1988):
 //   red[3] = sum Im(E* . P), red[4] = sum (-Im(1/alpha) - (2/3) k^3) |P|^2,
 //   red[5] = sum Re(E* . P).
@@ -907,6 +995,23 @@ void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, 
                      double k, double2* f, double* dcs, hipStream_t s) {
     hipLaunchKernelGGL(k_farfield, dim3(ndir, nrhs), dim3(NT), 0, s, nsites, coords, P, 3LL * nsites, dirs, k, f, dcs,
                        ndir);
+}
+void launch_nf_place(int nsites, const int* perm, const int* coords, const double2* P, int nrhs, const int org[3],
+                     const int dims[3], double2* x, hipStream_t s) {
+    const long long n3x = 3LL * dims[0] * dims[1] * dims[2];
+    hipLaunchKernelGGL(k_nf_place, dim3(blocks_for(nsites, 4096), nrhs), dim3(NT), 0, s, nsites, perm, coords, P,
+                       org[0], org[1], org[2], dims[0], dims[1], n3x, x);
+}
+void launch_nf_out(int nrhs, const int org[3], const int dims[3], const double* khat, const double2* e0, double kd,
+                   const double2* v, double2* einc, double2* esca, hipStream_t s) {
+    const long long npts = (long long)dims[0] * dims[1] * dims[2];
+    hipLaunchKernelGGL(k_nf_out, dim3(blocks_for(npts, 4096), nrhs), dim3(NT), 0, s, npts, org[0], org[1], org[2],
+                       dims[0], dims[1], khat, e0, kd, v, einc, esca);
+}
+void launch_field_line(int nrhs, const int org[3], const int dims[3], const double2* E, const double a[3],
+                       const double b[3], int n, double2* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_field_line, dim3(blocks_for(n, 1024), nrhs), dim3(NT), 0, s, E, org[0], org[1], org[2],
+                       dims[0], dims[1], dims[2], a[0], a[1], a[2], b[0], b[1], b[2], n, out);
 }
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qsum, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);

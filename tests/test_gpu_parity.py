@@ -833,3 +833,139 @@ def test_graph_replays_match_eager_launches(dda, solver):
         assert counts[1][name][2] == counts[0][name][2], name
         assert counts[1][name][1] <= counts[0][name][1], name
     assert sum(v[2] for v in counts[1].values()) > 0
+
+
+# ---------------------------------------------------------------- near field
+
+NF_CASES = {
+    # target, refractive index, extension fractions (ragged on purpose)
+    "sphere389": (lambda: w.sphere_integer(4.5), 1.33 + 0.01j, (0.5, 0.25, 0.0, 1.0, 0.4, 0.4)),
+    "ragged_9x7x13": (_ragged, 1.5 + 0.2j, (0.3, 0.3, 0.6, 0.0, 0.1, 0.2)),
+    "single_site": (lambda: np.array([[3, -2, 5]], dtype=np.int32), 1.7 + 0.3j, (2.0, 3.0, 1.0, 4.0, 0.0, 2.0)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NF_CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32_matvec"])
+def test_nearfield_matches_oracle_everywhere(dda, name, precision):
+    """dda_nearfield on every point of a ragged extended volume against the
+    oracle's direct sums on the same P (2 right-hand sides, one oblique and
+    elliptical): E_sca within 1e-12 of max|E_sca| in FP64 (2e-5 in the FP32
+    product), E_inc within 1e-13; the volume's origin and extents as the
+    oracle's."""
+    from oracle import nearfield
+    mk, mval, ext = NF_CASES[name]
+    ijk = mk()
+    n = len(ijk)
+    tgt = dda.Target(ijk, np.full(n, mval))
+    kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
+    e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
+    opts = dda.Options.for_size_parameter(1.3, precision=precision)
+    P = w.random_vectors(9, (2, n, 3))
+    org, dims, Ei, Es = dda.nearfield(tgt, opts, ext, kh, e0, _cuda(P))
+    torch.cuda.synchronize()
+    k = dense.kd_from_size_parameter(1.3, n)
+    o_ref, d_ref = nearfield.extended_box(ijk, ext)
+    assert list(org) == list(o_ref) and list(dims) == list(d_ref)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    for q in range(2):
+        _, _, ri, rs = nearfield.nearfield(ijk, P[q], k, kh[q], e0[q], ext)
+        gi, gs = Ei[q].cpu().numpy(), Es[q].cpu().numpy()
+        assert np.abs(gs - rs).max() <= tol * np.abs(rs).max(), q
+        assert np.abs(gi - ri).max() <= 1e-13, q
+    # the incident field is optional; E_sca is the same without it
+    _, _, none, Es2 = dda.nearfield(tgt, opts, ext, kh, e0, _cuda(P), incident=False)
+    assert none is None and torch.equal(Es2, Es)
+
+
+def test_nearfield_solution_satisfies_the_dda_equations(dda):
+    """On a GPU solution the total field at the target's sites is the local
+    field: |E_inc + E_sca - P / alpha| / |E_inc| over the sites equals the
+    solve's true relative residual (to rounding), and the cached volume is
+    rebuilt when another extension is asked for."""
+    d = w.workload("twomat6")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-9)
+    P, res = dda.solve(tgt, opts, d["khat"][:1], d["e0"][:1])
+    k = res[0]["kd"]
+    ainv = dense.site_alpha_inverse(np.asarray(d["m"]), k, d["khat"][0], d["e0"][0], dense.LATTDR)
+    for ext in ((0.5,) * 6, (0.0, 1.0, 0.5, 0.0, 0.0, 0.34)):
+        org, dims, Ei, Es = dda.nearfield(tgt, opts, ext, d["khat"][:1], d["e0"][:1], P)
+        Et = (Ei + Es)[0].cpu().numpy()
+        idx = d["ijk"] - np.asarray(org)
+        Es_sites = Et[idx[:, 2], idx[:, 1], idx[:, 0]]
+        Einc = Ei[0].cpu().numpy()[idx[:, 2], idx[:, 1], idx[:, 0]]
+        r = np.linalg.norm(Es_sites - ainv * P[0].cpu().numpy()) / np.linalg.norm(Einc)
+        assert r <= 1e-9 and abs(r - res[0]["rel_residual"]) <= 1e-11
+
+
+def test_field_line_matches_oracle_trilinear(dda):
+    """dda_field_line against the oracle's trilinear interpolation of the
+    same lattice field: a line with both ends on faces of the box, a single
+    point, and a box one point thick on an axis; end points outside the box
+    are rejected."""
+    from oracle import nearfield
+    rng = np.random.default_rng(12)
+    for dims, org, a, b, npt in (((7, 5, 6), (-3, 2, 0), (-3.0, 2.5, 0.2), (3.0, 6.0, 5.0), 41),
+                                 ((7, 5, 6), (-3, 2, 0), (0.3, 3.7, 4.4), (0.3, 3.7, 4.4), 1),
+                                 ((9, 1, 4), (0, 5, -2), (0.5, 5.0, -2.0), (8.0, 5.0, 1.0), 17)):
+        nx, ny, nz = dims
+        E = rng.standard_normal((2, nz, ny, nx, 3)) + 1j * rng.standard_normal((2, nz, ny, nx, 3))
+        out = dda.field_line(_cuda(E), org, a, b, npt).cpu().numpy()
+        for q in range(2):
+            def field_at(pts, q=q):
+                p = np.asarray(pts) - np.asarray(org)
+                p = np.minimum(p, np.asarray(dims) - 1)     # corners beyond a one-point axis weigh 0
+                return E[q][p[:, 2], p[:, 1], p[:, 0]]
+            ref = nearfield.trilinear(field_at, nearfield.line_points(a, b, npt))
+            assert np.abs(out[q] - ref).max() <= 1e-13 * np.abs(E).max()
+    with pytest.raises(dda.DDAError):
+        dda.field_line(_cuda(E), org, (0.0, 5.0, -2.5), b, 5)
+
+
+def test_nearfield_error_paths(dda):
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options()
+    P = _cuda(w.random_vectors(3, (1, len(d["ijk"]), 3)))
+    kh, e0 = w.along_x_yz()
+    for bad in ((-0.1, 0, 0, 0, 0, 0), (0, 0, 0, 0, 0, float("nan")), (20.0, 20.0, 0, 0, 0, 0)):
+        with pytest.raises(dda.DDAError):
+            dda.nearfield(tgt, opts, bad, kh[:1], e0[:1], P)
+
+
+def test_nearfield_gold_sphere_printed_track_on_gpu(dda):
+    """The guide's near-field example end to end on the GPU: GKDLDR solve of
+    the N = 59728 gold pseudosphere (tol 1e-5), E on the 96^3 extended
+    volume, then the readnf track along x_TF through the centre (52 points,
+    trilinear) against the printed values (3e-4, as the oracle's pin), and
+    sampled lattice points against the oracle's direct sums on the GPU's P
+    (1e-10 of max|E_sca|)."""
+    import json
+    import os
+    from oracle import nearfield
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "nearfield_au_sphere_track.json")))
+    d = w.workload("au_sphere_nf")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-5, polarizability="GKDLDR", solver="bicgstab2")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    org, dims, Ei, Es = dda.nearfield(tgt, opts, d["nf_ext"], d["khat"], d["e0"], P)
+    assert list(dims) == g["header"]["dims"]
+    k = res[0]["kd"]
+    dl = g["header"]["aeff_um"] / res[0]["aeff_d"]
+    c = 23.5
+    a = np.array(g["line_um"]["a"]) / dl + c
+    b = np.array(g["line_um"]["b"]) / dl + c
+    rows = np.array(g["rows"])
+    printed = rows[:, 3::2] + 1j * rows[:, 4::2]
+    line = dda.field_line(Ei + Es, org, a, b, len(rows)).cpu().numpy()
+    assert np.abs(line[0] * np.exp(-1j * k * c) - printed).max() < 3e-4
+    # sampled lattice points (inside, on the surface, outside, the corners)
+    rng = np.random.default_rng(21)
+    pts = np.vstack([rng.integers(0, dims, size=(12, 3)), [[0, 0, 0], list(np.asarray(dims) - 1), [47, 47, 47]]])
+    Pn = P.cpu().numpy()
+    Esn = Es.cpu().numpy()
+    for q in range(2):
+        ref = nearfield.scattered_field(d["ijk"], Pn[q], k, pts + np.asarray(org))
+        got = Esn[q][pts[:, 2], pts[:, 1], pts[:, 0]]
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(Esn[q]).max(), q
