@@ -43,6 +43,9 @@ WORKLOADS = {
                  "FFT grid 256^3", "fp64"),
     "brick48": ("48x24x16 brick (N=18432), m=1.6+0.1i, x=4, 64 random orientations x 2 polarizations = 128 "
                 "right-hand sides in one solve, BiCGSTAB to 1e-5, FFT grid 96x48x32", "fp64"),
+    "au_sphere_nf": ("the guide's near-field example: 48^3-box gold pseudosphere (N=59728), m=0.96+1.01i, x=5, "
+                     "GKDLDR, BiCGSTAB to 1e-5, FFT grid 96^3; then E on the 96^3 volume grown by half the box on "
+                     "every side (FFT grid 192^3), timed separately", "fp64"),
     "config3": ("the 48x24x16 brick at 64 orientations x 2 polarizations plus 32 integer-site spheres with radii "
                 "U(6,20) (x=4, m=1.33+0.01i) x 2 polarizations, one batched call, BiCGSTAB to 1e-5", "fp64"),
 }
@@ -65,7 +68,7 @@ def build_jobs(dda, w, name, seed, prec, solver="bicgstab"):
         return jobs, 64 + 32, d
     d = w.workload(name, seed)
     opts = dda.Options.for_size_parameter(d["x"], tol=d["tol"], precision=prec, recompute_green=True,
-                                          solver=solver)
+                                          solver=solver, polarizability=d.get("polarizability", "LATTDR"))
     return [(dda.Target(d["ijk"], d["m"]), opts, d["khat"], d["e0"])], len(d["khat"]) / 2.0, d
 
 
@@ -79,7 +82,7 @@ def log(*a):
 def kernel_source_digest() -> str:
     """Digest of the sources that define the FFT pass kernels."""
     h = hashlib.sha256()
-    for f in ("dda_device.h", "dda_passes.h", "dda_kernels.h"):
+    for f in ("dda_device.h", "dda_passes.h"):
         with open(os.path.join(ROOT, "paper_1202_3424_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -109,10 +112,12 @@ def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
 SLOT_OF_PASS = {"fft_y_fwd": 0, "fft_z_green": 1, "fft_y_inv": 2}
 
 
-def load_traffic(kernel: str, workload: str, precision: str, variants):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel and workload, if it was taken on the current kernel sources
-    and with the variant the autotuner chose in this run."""
+def load_traffic(kernel: str, workload: str, precision: str, variants, rhs_matvecs_per_launch: float):
+    """Measured HBM bytes per launch of this kernel: the committed rocprofv3
+    counter summary's bytes per right-hand-side matvec for the variant the
+    autotuner chose in this run, times this run's right-hand-side matvecs
+    per launch (launches skip right-hand sides that have converged).  None
+    unless the counters were taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -121,9 +126,152 @@ def load_traffic(kernel: str, workload: str, precision: str, variants):
     if rec.get("source_sha256") != kernel_source_digest():
         return None
     slot = SLOT_OF_PASS.get(kernel)
-    if slot is not None and (variants is None or rec.get("variant") != variants[slot]):
+    if slot is None or variants is None:
         return None
-    return rec.get("bytes_per_launch")
+    v = rec.get("by_variant", {}).get(str(variants[slot]))
+    return None if v is None else v["bytes_per_rhs_matvec"] * rhs_matvecs_per_launch
+
+
+# kernel-name patterns of each pass's compile-time family (every variant)
+PASS_PATTERNS = {
+    "scatter_fft_x": r"k_scatter_x<",
+    "fft_y_fwd": r"k_strided<(double|float), 3, 0, -1,|k_strided_rf<(double|float), 0, -1,",
+    "fft_z_green": r"k_strided<(double|float), 3, 1, -1,|k_strided_rf<(double|float), 1, -1,|k_zfold<",
+    "fft_y_inv": r"k_strided<(double|float), 3, 0, 1,|k_strided_rf<(double|float), 0, 1,",
+    "fft_x_gather": r"k_gather_x<",
+}
+AUTOTUNE_LAUNCHES = 6   # launches of each candidate while the autotuner times it
+
+
+def profile_commands(workload: str, prec: str, out: str = "/root/repo/gpurun_out/tr") -> dict:
+    """The rocprofv3 runs behind the committed summaries (run from /tmp)."""
+    wl = "" if workload == "ellipsoid51k" else f" --workload {workload}"
+    pr = "" if prec == WORKLOADS[workload][1] else f" --precision {prec}"
+    b = f"python -u /root/repo/bench.py{wl}{pr}"
+    pre = "cd /tmp && export TMPDIR=/tmp && "
+    return {
+        "trace": pre + f"timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d {out}/kt -o run "
+                       f"-- {b} --steps 20 --warmup 3 --no-cpu-baseline --no-plain",
+        "fetch": pre + f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/f -o run "
+                       f"-- {b} --steps 2 --warmup 1 --no-cpu-baseline --no-plain",
+        "write": pre + f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/w -o run "
+                       f"-- {b} --steps 2 --warmup 1 --no-cpu-baseline --no-plain",
+        "copy_fetch": pre + f"timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/cf -o run "
+                            f"-- python -u /root/repo/bench.py --copy-probe",
+        "copy_write": pre + f"timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/cw -o run "
+                            f"-- python -u /root/repo/bench.py --copy-probe",
+        "unprofiled": f"{b} --steps 20 --warmup 3 --no-cpu-baseline --no-plain",
+    }
+
+
+def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> None:
+    """Write profiles/<pass>_<workload>_<prec>_traffic.json and
+    profiles/dda_kernels_<workload>_<prec>_trace.txt from the outputs of
+    ``profile_commands`` under ``tr`` (kt/, f/, w/, cf/, cw/ and the copy
+    probe's log cf.log) and the unprofiled bench line in ``unprofiled``.
+
+    Traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) times the factor
+    that makes the same counter read the known size of a plain device copy.
+    Every candidate of the dominant pass runs AUTOTUNE_LAUNCHES times on the
+    real grid, in variant order, while the autotuner times it: those
+    dispatches give each variant's bytes per full launch."""
+    import csv
+    import re
+    import statistics
+
+    def rows(p):
+        with open(p) as fh:
+            return list(csv.DictReader(fh))
+
+    def short(n):
+        return re.sub(r"\(.*", "", n.replace("dda::passes::", "").replace("dda::(anonymous namespace)::", "")
+                      .replace("void ", ""))
+
+    with open(os.path.join(tr, "cf.log")) as fh:
+        nbytes = json.loads([ln for ln in fh if "copy_probe" in ln][0])["copy_probe_bytes_each_way"]
+    cf = [float(r["Counter_Value"]) for r in rows(os.path.join(tr, "cf", "run_counter_collection.csv"))
+          if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE"]
+    cw = [float(r["Counter_Value"]) for r in rows(os.path.join(tr, "cw", "run_counter_collection.csv"))
+          if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == "WRITE_SIZE"]
+    fscale = nbytes / (statistics.mean(cf) * 1024)
+    wscale = nbytes / (statistics.mean(cw) * 1024)
+    with open(unprofiled) as fh:
+        ub = json.loads(fh.read().strip().splitlines()[-1])
+    with open(os.path.join(tr, "kt.json")) as fh:
+        kt = json.loads(fh.read().strip().splitlines()[-1])
+    dom = ub["roofline"]["kernel"]
+    slot = SLOT_OF_PASS[dom]
+    n_rhs = ub["config"]["rhs_per_step"]
+    pat = re.compile(PASS_PATTERNS[dom])
+
+    def per_variant(path, counter, scale):
+        fam = sorted((r for r in rows(path) if r["Counter_Name"] == counter and pat.search(r["Kernel_Name"])),
+                     key=lambda r: int(r["Dispatch_Id"]))
+        out = {}
+        v = 0
+        while (v + 1) * AUTOTUNE_LAUNCHES <= len(fam):
+            grp = fam[v * AUTOTUNE_LAUNCHES:(v + 1) * AUTOTUNE_LAUNCHES]
+            names = {short(r["Kernel_Name"]) for r in grp}
+            if len(names) != 1:
+                break
+            out[v] = (names.pop(), statistics.mean(float(r["Counter_Value"]) for r in grp) * 1024 * scale)
+            v += 1
+        return out
+
+    fv = per_variant(os.path.join(tr, "f", "run_counter_collection.csv"), "FETCH_SIZE", fscale)
+    wv = per_variant(os.path.join(tr, "w", "run_counter_collection.csv"), "WRITE_SIZE", wscale)
+    alg_full = ub["matvec"]["passes_calibration_step"][dom]["bytes_per_rhs_matvec"]
+    by_variant = {}
+    for v in sorted(set(fv) & set(wv)):
+        if fv[v][0] != wv[v][0]:
+            continue
+        tot = fv[v][1] + wv[v][1]
+        by_variant[str(v)] = {"kernel_name": fv[v][0], "fetch_bytes_per_launch": fv[v][1],
+                              "write_bytes_per_launch": wv[v][1], "bytes_per_launch": tot,
+                              "bytes_per_rhs_matvec": tot / n_rhs, "over_algorithmic": tot / n_rhs / alg_full}
+    cmds = profile_commands(workload, prec)
+    chosen = ub["autotuned_variants"][slot] if ub.get("autotuned_variants") else None
+    rec = {"kernel": dom, "workload": workload, "precision": prec, "rhs_per_launch": n_rhs,
+           "variant_unprofiled_run": chosen, "algorithmic_bytes_per_rhs_matvec": alg_full,
+           "by_variant": by_variant, "fetch_scale": fscale, "write_scale": wscale,
+           "source_sha256": kernel_source_digest(), "commands": cmds,
+           "note": "bytes of one launch over all right-hand sides of the workload, from the autotuner's timing "
+                   "launches of each variant on the real grid (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, "
+                   "averaged over those launches, times the copy-probe factors)"}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}_{prec}_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    ks = sorted(rows(os.path.join(tr, "kt", "run_kernel_stats.csv")), key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel-trace summary: {workload}, {prec}",
+             f"# command: {cmds['trace']}",
+             "# source: run_kernel_stats.csv (top kernels; the autotuner's timing launches of each variant included)",
+             f"{'kernel':72s} {'calls':>6s} {'total_us':>10s} {'avg_us':>8s} {'min_us':>7s} {'max_us':>8s} {'pct':>5s}"]
+    for r in ks[:24]:
+        lines.append(f"{short(r['Name'])[:72]:72s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e3:10.1f} "
+                     f"{float(r['AverageNs']) / 1e3:8.2f} {float(r['MinNs']) / 1e3:7.2f} "
+                     f"{float(r['MaxNs']) / 1e3:8.2f} {float(r['Percentage']):5.1f}")
+    kv = kt["autotuned_variants"][slot] if kt.get("autotuned_variants") else None
+    kname = by_variant.get(str(kv), {}).get("kernel_name")
+    krow = next((r for r in ks if kname and short(r["Name"]) == kname), None)
+    rf, urf = kt["roofline"], ub["roofline"]
+    lines += ["",
+              f"# dominant pass {dom}; autotuned variants (y fwd, z, y inv): profiled run {kt.get('autotuned_variants')}, "
+              f"unprofiled run {ub.get('autotuned_variants')}",
+              f"#   profiled run: variant {kv} = {kname}: rocprofv3 average "
+              f"{float(krow['AverageNs']) / 1e3 if krow else float('nan'):.2f} us/launch over {krow['Calls'] if krow else 0} "
+              f"launches; the same run's HIP events {rf['avg_launch_us']:.2f} us/launch (profiler overhead included)",
+              f"#   unprofiled run ({cmds['unprofiled']}): HIP events {urf['avg_launch_us']:.2f} us/launch over "
+              f"{urf['launches']} launches, {urf['achieved']:.0f} GB/s algorithmic, frac {urf['frac']:.3f}; "
+              f"ms/step {ub['ms_per_step']:.3f}",
+              f"#   algorithmic bytes per right-hand-side matvec: {alg_full / 1e6:.2f} MB",
+              f"#   counter scales from the copy probe: FETCH_SIZE x {fscale:.3f}, WRITE_SIZE x {wscale:.3f}",
+              "#   measured HBM bytes per right-hand-side matvec by variant (fetch + write, x algorithmic):"]
+    for v, e in by_variant.items():
+        lines.append(f"#     {int(v):2d} {e['kernel_name'][:64]:64s} {e['fetch_bytes_per_launch'] / n_rhs / 1e6:7.2f} + "
+                     f"{e['write_bytes_per_launch'] / n_rhs / 1e6:6.2f} MB  x{e['over_algorithmic']:.2f}")
+    with open(os.path.join(ROOT, "profiles", f"dda_kernels_{workload}_{prec}_trace.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
@@ -142,7 +290,7 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
     def run(max_iter):
         t0 = time.perf_counter()
         r = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], tol=d["tol"],
-                                max_iter=max_iter)
+                                max_iter=max_iter, scheme=d.get("polarizability", "LATTDR"))
         return time.perf_counter() - t0, r
 
     if len(d["ijk"]) <= 300_000:
@@ -162,6 +310,89 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
                       f"2 and 4 iterations ({t2:.1f} s, {t4:.1f} s): set-up {setup:.2f} s + {per_iter:.2f} s/iteration "
                       f"x {gpu_iters} iterations (the GPU solve's count at tol {d['tol']:g}); value = 2 polarizations "
                       f"x that estimate"}
+
+
+def padded(n: int) -> int:
+    """The library's padded FFT extent: 2n if 2,3,5-smooth, else the smallest
+    smooth extent >= 2n - 1."""
+    def smooth(m):
+        for p in (2, 3, 5):
+            while m % p == 0:
+                m //= p
+        return m == 1
+    if smooth(2 * n):
+        return 2 * n
+    m = max(2 * n - 1, 1)
+    while not smooth(m):
+        m += 1
+    return m
+
+
+def nearfield_measurement(dda, np, torch, job, d, reps: int = 10, cpu: bool = True) -> dict:
+    """dda_nearfield on the workload's solution: wall time per call (both
+    polarizations, E_inc and E_sca), per-pass kernel times from HIP events
+    against the algorithmic bytes of the product on the grown volume, and the
+    oracle's direct sum timed on a bounded sample of points."""
+    import dataclasses
+    t, o, kh, e0 = job
+    ext = d["nf_ext"]
+    P, _ = dda.solve(t, o, kh, e0)
+    org, dims = dda.nearfield_volume(t, ext)
+    # the volume's tensor FFT, rebuilt on every call, then kept (one per kd)
+    o_new = dataclasses.replace(o, recompute_green=True)
+    o_kept = dataclasses.replace(o, recompute_green=False)
+
+    def timed(opts, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            dda.nearfield(t, opts, ext, kh, e0, P)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+    for _ in range(2):
+        dda.nearfield(t, o_new, ext, kh, e0, P)
+    ms_new = timed(o_new, reps)
+    ms_kept = timed(o_kept, reps)
+    dda.set_timing(True)
+    timed(o_kept, reps)
+    tm = dda.get_timing()
+    dda.set_timing(False)
+    ms = ms_kept
+    npts = int(np.prod(dims))
+    n_rhs = len(kh)
+
+    class Vol:   # the grown volume as the product sees it: every point a site
+        box = tuple(int(v) for v in dims)
+        grid = tuple(padded(int(v)) for v in dims)
+    bp = pass_bytes(Vol, npts, 16)
+    passes = {}
+    for name in PASSES:
+        pms, nl, _ = tm[name]
+        if nl:
+            gbs = bp[name] * n_rhs * nl / reps / (pms / reps * 1e-3) / 1e9
+            passes[name] = {"ms_per_call": pms / reps, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+    kern_ms = sum(tm[k][0] for k in PASSES) / reps
+    kern_bytes = sum(bp[k] for k in PASSES) * n_rhs
+    out = {"ms_per_call": ms, "ms_per_call_tensor_rebuilt": ms_new, "points": npts,
+           "dims": [int(v) for v in dims], "fft_grid": list(Vol.grid),
+           "n_rhs": n_rhs, "product_kernels_ms": kern_ms,
+           "product_GBps": kern_bytes / (kern_ms * 1e-3) / 1e9, "passes": passes,
+           "note": "one call = E_inc and E_sca for both polarizations on every point of the volume, the "
+                   "volume's tensor FFT kept from an earlier call (ms_per_call_tensor_rebuilt: built in the "
+                   "call); wall time includes placing P and writing both fields"}
+    if cpu:
+        from oracle import dense as odense
+        from oracle import nearfield as onf
+        Pn = P.cpu().numpy()
+        rng = np.random.default_rng(3)
+        pts = rng.integers(0, dims, size=(48, 3)) + np.asarray(org)
+        t0 = time.perf_counter()
+        onf.scattered_field(d["ijk"], Pn[0], odense.kd_from_size_parameter(d["x"], len(d["ijk"])), pts)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": dt / len(pts) * npts * n_rhs, "unit": "s/call", "cores": 1, "kind": "oracle",
+                             "sample": f"the oracle's direct sum (numpy, FP64) at 48 random points of the volume in "
+                                       f"{dt:.2f} s, scaled to {npts} points x {n_rhs} polarizations"}
+    return out
 
 
 def plain_reference(dda, np, torch, jobs, results, ms_per_step):
@@ -219,9 +450,22 @@ def main():
     ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "qmr", "bicgstab2"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--print-profile-commands", action="store_true",
+                    help="print the rocprofv3 runs behind the profiles/ summaries of --workload")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write the profiles/ summaries of --workload from those runs' outputs under DIR")
+    ap.add_argument("--unprofiled", metavar="JSON", help="with --summarize: the unprofiled bench line")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.print_profile_commands or args.summarize:
+        prec = args.precision or WORKLOADS[args.workload][1]
+        if args.summarize:
+            summarize_profiles(args.summarize, args.workload, prec, args.unprofiled)
+        else:
+            for k, c in profile_commands(args.workload, prec).items():
+                print(f"# {k}\n{c}")
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
@@ -313,7 +557,8 @@ def main():
     avg_s = ms_tot * 1e-3 / launches
     gbs = bytes_tot / all_launches / avg_s / 1e9
     variants = dda.tuned_variants(jobs[0][0], len(jobs[0][2]), prec) if len(jobs) == 1 else None
-    traffic = load_traffic(dominant, args.workload, prec, variants) if len(jobs) == 1 else None
+    traffic = (load_traffic(dominant, args.workload, prec, variants, sum(units) / all_launches)
+               if len(jobs) == 1 else None)
     roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
                 "algorithmic_bytes_per_launch": bytes_tot / all_launches, "avg_launch_us": avg_s * 1e6,
@@ -361,6 +606,9 @@ def main():
     if not args.no_plain:
         log("timing the plain FP64 single-right-hand-side solves of the same workload ...")
         out["vs_plain_fp64_single_rhs"] = plain_reference(dda, np, torch, jobs, results, ms_per_step)
+    if "nf_ext" in d:
+        log("timing the near field on the solution ...")
+        out["nearfield"] = nearfield_measurement(dda, np, torch, jobs[0], d, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on one polarization ...")
         out["cpu_baseline"] = cpu_baseline(d, args.workload, results[0]["iters"])

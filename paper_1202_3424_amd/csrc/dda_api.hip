@@ -422,10 +422,11 @@ struct Work {
             launch_strided<T>(1, 1, chk, g, nrhs, 3, g.n[2], g.M[1], g.n[1], gr, tw, nullptr, a.st, s, variant);
     }
 
-    // Pick, once per (grid, box, right-hand sides, precision), the fastest
-    // compile-time variant of each strided pass by timing every candidate on
-    // the workspace grid (its contents are scratch at this point; all
-    // variants compute bitwise-identical results).
+    // Pick, once per (grid, box, right-hand sides, precision), a compile-time
+    // variant of each strided pass by timing every candidate on the workspace
+    // grid (its contents are scratch at this point; all variants compute
+    // bitwise-identical results): the lowest-numbered variant within 3% of
+    // the fastest, so that near-ties resolve the same way from run to run.
     void autotune(bool enabled, int forced = 0) {
         const Geo& g = t->geo;
         if (forced > 0) {
@@ -447,7 +448,7 @@ struct Work {
             for (int slot = 0; slot < 3; ++slot) {
                 const int L = g.M[slot == 1 ? 2 : 1];
                 const int nv = strided_variants(L, slot == 1);
-                float best_ms = 1e30f;
+                std::vector<float> t_ms(nv, 0.f);
                 for (int v = 0; v < nv; ++v) {
                     auto run = [&]() {
                         if (fp32) strided_slot<float>(slot, CHK_NONE, v);
@@ -455,16 +456,14 @@ struct Work {
                     };
                     run();
                     HIPCHK(hipEventRecord(e0, s));
-                    for (int k = 0; k < 3; ++k) run();
+                    for (int k = 0; k < 5; ++k) run();
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best[slot] = v;
-                    }
+                    HIPCHK(hipEventElapsedTime(&t_ms[v], e0, e1));
                 }
+                const float fastest = *std::min_element(t_ms.begin(), t_ms.end());
+                for (int v = nv - 1; v >= 0; --v)
+                    if (t_ms[v] <= 1.03f * fastest) best[slot] = v;
             }
             HIPCHK(hipGetLastError());
             c->evpool.push_back(e0);

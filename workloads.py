@@ -208,7 +208,7 @@ def workload(name: str, seed: int = 0) -> dict:
         ijk = box_sphere(48, 48.49 / 2)
         kh, e0 = along_x_yz()
         m = np.full(len(ijk), 0.96 + 1.01j)
-        return dict(ijk=ijk, m=m, x=5.0, khat=kh, e0=e0, tol=1e-5, nf_ext=(0.5,) * 6)
+        return dict(ijk=ijk, m=m, x=5.0, khat=kh, e0=e0, tol=1e-5, nf_ext=(0.5,) * 6, polarizability="GKDLDR")
     raise KeyError(name)
 
 
