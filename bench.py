@@ -274,6 +274,41 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
     print("\n".join(lines))
 
 
+def host_info(workers: int) -> dict:
+    """The host the CPU baseline ran on: CPU model, threads used and visible,
+    numpy and scipy versions."""
+    import platform
+
+    import numpy
+    import scipy
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "threads_used": workers, "cpus_visible": len(os.sched_getaffinity(0)),
+            "numpy": numpy.__version__, "scipy": scipy.__version__}
+
+
+# the guide's own whole-run CPU seconds for its sample calculation nearest to
+# each workload (context on other hardware, never the target)
+GUIDE_CONTEXT = {
+    "ellipsoid51k": {"guide_run": "ELLIPSOID sample: N=59,728 sphere in 48^3, m=1.5+0.01i, x=5, 2 polarizations",
+                     "cpu_s": 63.0, "section": "Sample calculation in directory examples_exp/ELLIPSOID"},
+    "au_brick": {"guide_run": "RCTGLPRSM sample: the 16x32x32 gold brick (this workload), PBCGS2, 2 polarizations",
+                 "cpu_s": 10.0, "section": "Sample calculation in directory examples_exp/RCTGLPRSM"},
+    "au_sphere_nf": {"guide_run": "ELLIPSOID_NEARFIELD sample (this workload): solve, then E on the 96^3 volume",
+                     "cpu_s": 60.0, "nearfield_cpu_s": 9.6,
+                     "section": "Sample calculation in directory examples_exp/ELLIPSOID_NEARFIELD"},
+    "brick48": {"guide_run": "RCTGLPRSM run of 3 orientations x 2 polarizations on a 131,072-dipole brick",
+                "cpu_s": 672.0, "section": "Running DDSCAT Using the Sample ddscat.par File"},
+}
+
+
 def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
     """The oracle (FFT-BiCGSTAB, FP64) on the first right-hand side of the
     workload, scaled to seconds per orientation (two polarizations).  Targets
@@ -296,6 +331,7 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
     if len(d["ijk"]) <= 300_000:
         dt, r = run(1000)
         return {"value": 2 * dt, "unit": "s/orientation", "cores": workers, "kind": "oracle",
+                "host": host_info(workers),
                 "sample": f"{workload}: the first right-hand side solved by the CPU oracle (scipy.fft FFT-BiCGSTAB, "
                           f"FP64, tol {d['tol']:g}, {r['iters']} iterations, {r['matvecs']} matvecs) in {dt:.2f} s; "
                           f"value = 2 polarizations x that time",
@@ -306,6 +342,7 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
     setup = t2 - 2 * per_iter
     est = setup + per_iter * gpu_iters
     return {"value": 2 * est, "unit": "s/orientation", "cores": workers, "kind": "oracle",
+            "host": host_info(workers),
             "sample": f"{workload}: CPU oracle (scipy.fft FFT-BiCGSTAB, FP64) on the first right-hand side, run for "
                       f"2 and 4 iterations ({t2:.1f} s, {t4:.1f} s): set-up {setup:.2f} s + {per_iter:.2f} s/iteration "
                       f"x {gpu_iters} iterations (the GPU solve's count at tol {d['tol']:g}); value = 2 polarizations "
@@ -606,6 +643,10 @@ def main():
     if not args.no_plain:
         log("timing the plain FP64 single-right-hand-side solves of the same workload ...")
         out["vs_plain_fp64_single_rhs"] = plain_reference(dda, np, torch, jobs, results, ms_per_step)
+    if args.workload in GUIDE_CONTEXT:
+        out["guide_context"] = dict(GUIDE_CONTEXT[args.workload],
+                                    hardware="one 2.53 GHz CPU core, whole DDSCAT run (target generation, solve, "
+                                             "scattering directions), precision not stated")
     if "nf_ext" in d:
         log("timing the near field on the solution ...")
         out["nearfield"] = nearfield_measurement(dda, np, torch, jobs[0], d, cpu=not args.no_cpu_baseline)
