@@ -969,3 +969,37 @@ def test_nearfield_gold_sphere_printed_track_on_gpu(dda):
         ref = nearfield.scattered_field(d["ijk"], Pn[q], k, pts + np.asarray(org))
         got = Esn[q][pts[:, 2], pts[:, 1], pts[:, 0]]
         assert np.abs(got - ref).max() <= 1e-10 * np.abs(Esn[q]).max(), q
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_degenerate_inputs_are_rejected(dda):
+    """An empty target, a vacuum site, no right-hand sides, and a box whose
+    padded FFT extent would exceed the supported 341 are errors, not launches."""
+    with pytest.raises(dda.DDAError):
+        dda.Target(np.zeros((0, 3), dtype=np.int32), 1.5)
+    with pytest.raises(dda.DDAError):
+        dda.Target(np.array([[0, 0, 0], [1, 0, 0]]), np.array([1.5, 1.0]))
+    with pytest.raises(dda.DDAError):        # 171 sites on x: padded extent 342
+        dda.Target(np.array([[i, 0, 0] for i in range(171)]), 1.5)
+    tgt = dda.Target(w.sphere_integer(2.0), 1.5 + 0.1j)
+    with pytest.raises(dda.DDAError):
+        dda.solve(tgt, dda.Options.for_size_parameter(1.0), np.zeros((0, 3)), np.zeros((0, 3), complex))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_largest_padded_extent_matches_dense(dda, axis):
+    """A line of 160 sites has the padded extent 320, the largest 2,3,5-smooth
+    one within the supported 341 (a runtime-planned transform); on each axis
+    the product equals the dense one (1e-12 of max|y|)."""
+    ijk = np.zeros((160, 3), dtype=np.int32)
+    ijk[:, axis] = np.arange(160) - 40
+    tgt = dda.Target(ijk, 1.4 + 0.2j)
+    assert tgt.grid[axis] == 320
+    kh, e0 = [[0.0, 0.6, 0.8]], [[1.0, 0.0, 0.0]]
+    opts = dda.Options.for_size_parameter(3.0)
+    xv = w.random_vectors(13, (1, 160, 3))
+    y = dda.apply(tgt, opts, kh, e0, _cuda(xv)).cpu().numpy()
+    A = _dense_A(ijk, np.full(160, 1.4 + 0.2j), 3.0, kh[0], e0[0], "LATTDR")
+    ref = (A @ xv[0].reshape(-1)).reshape(-1, 3)
+    assert np.abs(y[0] - ref).max() <= 1e-12 * np.abs(ref).max()
