@@ -62,6 +62,17 @@ __device__ __forceinline__ bool skip_rhs(const RhsState* st, int chk) {
     return chk == CHK_ACTIVE_NOT_SCONV && st->sconv;
 }
 
+// g_a X + g_b Y + g_c Z for one row of the symmetric tensor product, each
+// part one expression so that it contracts to a multiply and five fused
+// multiply-adds (every pass-3 form uses this, so all stay bitwise identical)
+template <typename C>
+__device__ __forceinline__ C trow(const C& ga, const C& gb, const C& gc, const C& X, const C& Y, const C& Z) {
+    C r;
+    r.x = ga.x * X.x - ga.y * X.y + gb.x * Y.x - gb.y * Y.y + gc.x * Z.x - gc.y * Z.y;
+    r.y = ga.x * X.y + ga.y * X.x + gb.x * Y.y + gb.y * Y.x + gc.x * Z.y + gc.y * Z.x;
+    return r;
+}
+
 inline __host__ __device__ int pad_len(int L) { return L | 1; }
 inline __host__ __device__ int even_up(int L) { return (L + 1) & ~1; }
 
@@ -492,9 +503,9 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
                             C Gl[6];
                             if constexpr (VAR != 0) tensor_at(xo, kz, Gl);
                             const C* Gi = VAR == 0 ? G[i] : Gl;
-                            *px = cadd(cadd(cmul(Gi[0], X), cmul(Gi[1], Y)), cmul(Gi[2], Z));
-                            *py = cadd(cadd(cmul(Gi[1], X), cmul(Gi[3], Y)), cmul(Gi[4], Z));
-                            *pz = cadd(cadd(cmul(Gi[2], X), cmul(Gi[4], Y)), cmul(Gi[5], Z));
+                            *px = trow(Gi[0], Gi[1], Gi[2], X, Y, Z);
+                            *py = trow(Gi[1], Gi[3], Gi[4], X, Y, Z);
+                            *pz = trow(Gi[2], Gi[4], Gi[5], X, Y, Z);
                         }
                     }
                 }
@@ -508,9 +519,9 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
                     C* py = lds + (xo * 3 + 1) * Lp + kz;
                     C* pz = lds + (xo * 3 + 2) * Lp + kz;
                     const C X = *px, Y = *py, Z = *pz;
-                    *px = cadd(cadd(cmul(Gi[0], X), cmul(Gi[1], Y)), cmul(Gi[2], Z));
-                    *py = cadd(cadd(cmul(Gi[1], X), cmul(Gi[3], Y)), cmul(Gi[4], Z));
-                    *pz = cadd(cadd(cmul(Gi[2], X), cmul(Gi[4], Y)), cmul(Gi[5], Z));
+                    *px = trow(Gi[0], Gi[1], Gi[2], X, Y, Z);
+                    *py = trow(Gi[1], Gi[3], Gi[4], X, Y, Z);
+                    *pz = trow(Gi[2], Gi[4], Gi[5], X, Y, Z);
                 }
             }
             __syncthreads();
@@ -632,9 +643,9 @@ __global__ __launch_bounds__(NT) void k_zfold(Geo g, typename V2<T>::t* grid, co
                         C* py = lds + (xo * 3 + 1) * LP + kz;
                         C* pz = lds + (xo * 3 + 2) * LP + kz;
                         const C X = *px, Y = *py, Z = *pz;
-                        *px = cadd(cadd(cmul(G[i][0], X), cmul(gxy, Y)), cmul(gxz, Z));
-                        *py = cadd(cadd(cmul(gxy, X), cmul(G[i][3], Y)), cmul(gyz, Z));
-                        *pz = cadd(cadd(cmul(gxz, X), cmul(gyz, Y)), cmul(G[i][5], Z));
+                        *px = trow(G[i][0], gxy, gxz, X, Y, Z);
+                        *py = trow(gxy, G[i][3], gyz, X, Y, Z);
+                        *pz = trow(gxz, gyz, G[i][5], X, Y, Z);
                     }
                 }
             }
@@ -806,9 +817,9 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
                     G6[4].y = f4 ? -G6[4].y : G6[4].y;
                     const int sl = c * Q + gg;
                     const C X = v[0][sl], Y = v[NCT > 1 ? 1 : 0][sl], Z = v[NCT > 2 ? 2 : 0][sl];
-                    v[0][sl] = cadd(cadd(cmul(G6[0], X), cmul(G6[1], Y)), cmul(G6[2], Z));
-                    v[NCT > 1 ? 1 : 0][sl] = cadd(cadd(cmul(G6[1], X), cmul(G6[3], Y)), cmul(G6[4], Z));
-                    v[NCT > 2 ? 2 : 0][sl] = cadd(cadd(cmul(G6[2], X), cmul(G6[4], Y)), cmul(G6[5], Z));
+                    v[0][sl] = trow(G6[0], G6[1], G6[2], X, Y, Z);
+                    v[NCT > 1 ? 1 : 0][sl] = trow(G6[1], G6[3], G6[4], X, Y, Z);
+                    v[NCT > 2 ? 2 : 0][sl] = trow(G6[2], G6[4], G6[5], X, Y, Z);
                 }
             }
         }
