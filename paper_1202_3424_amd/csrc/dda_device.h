@@ -277,6 +277,8 @@ constexpr int ct_plan(int L, int s) {
         case 80: r[0] = 4; r[1] = 5; r[2] = 4; n = 3; break;
         case 96: r[0] = 8; r[1] = 3; r[2] = 4; n = 3; break;
         case 128: r[0] = 4; r[1] = 4; r[2] = 8; n = 3; break;
+        case 160: r[0] = 8; r[1] = 5; r[2] = 4; n = 3; break;
+        case 192: r[0] = 8; r[1] = 3; r[2] = 8; n = 3; break;
         case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; n = 4; break;
         default: break;
     }
@@ -290,6 +292,8 @@ constexpr int ct_split(int L) {
         case 80: return 20;
         case 96: return 24;
         case 128: return 16;
+        case 160: return 40;
+        case 192: return 24;
         case 256: return 16;
         default: return 0;
     }
@@ -308,7 +312,7 @@ constexpr bool ct_plan_ok(int L) {
     return p == L && pa == ct_split(L) && ct_split(L) % (L / ct_split(L)) == 0;
 }
 static_assert(ct_plan_ok(32) && ct_plan_ok(48) && ct_plan_ok(64) && ct_plan_ok(80) && ct_plan_ok(96) &&
-                  ct_plan_ok(128) && ct_plan_ok(256),
+                  ct_plan_ok(128) && ct_plan_ok(160) && ct_plan_ok(192) && ct_plan_ok(256),
               "radix plans must factor L with the split P >= Q, Q | P");
 
 // One radix-R pass over NL lines of compile-time length L (same in-place

@@ -93,7 +93,7 @@ enum FinKind {
 
 // FFT lengths with compile-time kernels (dda_passes.h)
 inline bool ct_length(int L) {
-    return L == 32 || L == 48 || L == 64 || L == 80 || L == 96 || L == 128 || L == 256;
+    return L == 32 || L == 48 || L == 64 || L == 80 || L == 96 || L == 128 || L == 160 || L == 192 || L == 256;
 }
 
 // tile sizes chosen by the host: x-lines (along y) per workgroup of the x

@@ -30,7 +30,7 @@ namespace dda {
 namespace passes {
 
 // lengths with compile-time kernels
-#define DDA_CT_LENGTHS(X) X(32) X(48) X(64) X(80) X(96) X(128) X(256)
+#define DDA_CT_LENGTHS(X) X(32) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256)
 
 // x columns per workgroup of a compile-time strided pass: a tile of about
 // 1536 complex values (three components per column)

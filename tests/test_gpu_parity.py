@@ -50,6 +50,10 @@ MATVEC_CASES = {
     "line_z9": lambda: (np.array([[0, 0, i] for i in range(9)], dtype=np.int32), 2.0 + 0.5j),
     "single_site": lambda: (np.array([[3, -2, 5]], dtype=np.int32), 1.7 + 0.3j),
     "box_8x3x40": lambda: (w.brick(8, 3, 40), 1.6 + 0.1j),
+    # three perpendicular lines: padded extents 192 (x, z) and 160 (y)
+    "lines_96_80_96": lambda: (np.unique(np.vstack([[[i, 0, 0] for i in range(96)], [[0, j, 0] for j in range(80)],
+                                                    [[0, 0, k] for k in range(96)]]), axis=0).astype(np.int32),
+                               1.5 + 0.05j),
 }
 
 
@@ -329,7 +333,8 @@ def test_sphere1m_full_size(dda):
 
 # boxes whose padded grids put every compile-time FFT length on the y and
 # the z axis (x extents small and ragged: partial column tiles)
-VARIANT_BOXES = [(13, 14, 32), (5, 24, 16), (5, 40, 48), (3, 64, 40), (3, 32, 128), (3, 128, 64)]
+VARIANT_BOXES = [(13, 14, 32), (5, 24, 16), (5, 40, 48), (3, 64, 40), (3, 32, 128), (3, 128, 64), (3, 80, 96),
+                 (3, 96, 80)]
 
 
 def _box_target(dda, box, seed):
@@ -357,7 +362,7 @@ def test_every_tiling_variant_bitwise(dda, variant):
             y = dda.apply(tgt, dda.Options.for_size_parameter(1.1, precision=prec, kernel_variant=variant), kh, e0,
                           xv)
             assert torch.equal(y, ref), (prec, variant, box, tgt.grid)
-    assert {32, 48, 64, 80, 96, 128, 256} <= seen
+    assert {32, 48, 64, 80, 96, 128, 160, 192, 256} <= seen
 
 
 # ------------------------------------------------------------------ adjoint at full size
