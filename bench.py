@@ -432,6 +432,42 @@ def nearfield_measurement(dda, np, torch, job, d, reps: int = 10, cpu: bool = Tr
     return out
 
 
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+
+
+def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
+    """dda_scattering_averages (Gauss-Legendre 48 x 64 directions, both
+    polarizations) and dda_far_field on 74 directions, on the workload's
+    solution.  The kernel's work is one term per (direction, site, right-hand
+    side): a phase k n.r (5 flops), its sincos, and three complex
+    multiply-adds (24 flops); the rate is quoted as terms/s and as the 29
+    flops/term against the FP64 vector peak (the sincos not counted)."""
+    t, o, kh, e0 = job
+    P, _ = dda.solve(t, o, kh, e0)
+    n_rhs, n_sites = P.shape[0], P.shape[1]
+    n_theta, n_phi = 48, 64
+    theta = np.linspace(0.0, 180.0, 74)
+    nh, th, ph = dda.lab_directions(theta, np.zeros_like(theta))
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+    ms_avg = timed(lambda: dda.scattering_averages(t, o, kh, e0, P, n_theta, n_phi))
+    ms_ff = timed(lambda: dda.far_field(t, o, P, nh, th, ph))
+    terms = float(n_theta * n_phi) * n_sites * n_rhs
+    tflops = 29.0 * terms / (ms_avg * 1e-3) / 1e12
+    return {"averages_ms": ms_avg, "directions": n_theta * n_phi, "far_field_74_dirs_ms": ms_ff,
+            "terms_per_s": terms / (ms_avg * 1e-3), "bound": "alu", "achieved_tflops": tflops,
+            "peak_tflops": FP64_VALU_PEAK_TFLOPS, "frac": tflops / FP64_VALU_PEAK_TFLOPS,
+            "note": "wall time per call, both polarizations, host quadrature weights and result copies included; "
+                    "flops exclude the sincos of each term"}
+
+
 def plain_reference(dda, np, torch, jobs, results, ms_per_step):
     """The plain method on the same workload: every right-hand side solved
     alone by BiCGSTAB with the FP64 matvec at the same tolerance, one after
@@ -647,6 +683,9 @@ def main():
         out["guide_context"] = dict(GUIDE_CONTEXT[args.workload],
                                     hardware="one 2.53 GHz CPU core, whole DDSCAT run (target generation, solve, "
                                              "scattering directions), precision not stated")
+    if len(jobs) == 1 and jobs[0][0].n_sites <= 100_000:
+        log("timing the far field and the averages over scattering directions ...")
+        out["farfield"] = farfield_measurement(dda, np, torch, jobs[0])
     if "nf_ext" in d:
         log("timing the near field on the solution ...")
         out["nearfield"] = nearfield_measurement(dda, np, torch, jobs[0], d, cpu=not args.no_cpu_baseline)

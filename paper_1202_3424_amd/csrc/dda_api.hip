@@ -668,16 +668,36 @@ void run_chunk(Work& w, int chunk) {
         if (ws.graphs.size() >= 32) ws.drop_graphs();
         Workspace::Graph gr{};
         for (long long& n : c->tcap) n = 0;
-        const hipStream_t keep = w.s;
-        w.s = gs;
-        c->tsuppress = true;
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-        launch_chunk(w, chunk);
-        const hipError_t ce = hipStreamEndCapture(gs, &g);
-        c->tsuppress = false;
-        w.s = keep;
-        HIPCHK(ce);
+        {
+            // the chunk is recorded on gs with timing events off; if a launch
+            // throws, the capture is still ended and both settings restored
+            struct Capture {
+                Work& w;
+                hipStream_t gs, keep;
+                hipGraph_t* g;
+                bool ended = false;
+                Capture(Work& w_, hipStream_t gs_, hipGraph_t* g_) : w(w_), gs(gs_), keep(w_.s), g(g_) {
+                    w.s = gs;
+                    w.c->tsuppress = true;
+                }
+                hipError_t end() {
+                    ended = true;
+                    w.c->tsuppress = false;
+                    w.s = keep;
+                    return hipStreamEndCapture(gs, g);
+                }
+                ~Capture() {
+                    if (ended) return;
+                    (void)end();
+                    if (*g) (void)hipGraphDestroy(*g);
+                    *g = nullptr;
+                }
+            } cap(w, gs, &g);
+            launch_chunk(w, chunk);
+            HIPCHK(cap.end());
+        }
         for (int i = 0; i < DDA_TIMING_CATEGORIES; ++i) gr.launches[i] = c->tcap[i];
         const hipError_t ie = hipGraphInstantiateWithFlags(&gr.exec, g, 0);
         (void)hipGraphDestroy(g);
@@ -1517,7 +1537,8 @@ dda_status dda_far_field(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n
         double* cdev = (double*)(buf + pb + db + fb);
         HIPCHK(hipMemcpyAsync(ddev, dirs.data(), db, hipMemcpyHostToDevice, c->stream));
         launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P, Ps, true, c->stream);
-        launch_farfield(t->nsites, (const int*)t->coords.p, Ps, n_rhs, ddev, n_dir, kd, fdev, cdev, c->stream);
+        launch_farfield(t->nsites, (const int*)t->coords.p, Ps, n_rhs, ddev, n_dir, kd, t->lo, t->geo.n, fdev, cdev,
+                        c->stream);
         HIPCHK(hipGetLastError());
         if (f) HIPCHK(hipMemcpyAsync(f, fdev, fb, hipMemcpyDeviceToHost, c->stream));
         if (dcs) HIPCHK(hipMemcpyAsync(dcs, cdev, cb, hipMemcpyDeviceToHost, c->stream));
@@ -1612,8 +1633,8 @@ dda_status dda_scattering_averages(dda_ctx* c, dda_target* t, const dda_opts* o,
                 }
             }
             HIPCHK(hipMemcpyAsync(ddev, dirs.data(), db, hipMemcpyHostToDevice, c->stream));
-            launch_farfield(t->nsites, (const int*)t->coords.p, Ps + (size_t)q * n3, 1, ddev, nd, kd, fdev, cdev,
-                            c->stream);
+            launch_farfield(t->nsites, (const int*)t->coords.p, Ps + (size_t)q * n3, 1, ddev, nd, kd, t->lo,
+                            t->geo.n, fdev, cdev, c->stream);
             HIPCHK(hipGetLastError());
             HIPCHK(hipMemcpyAsync(dcs.data(), cdev, cb, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));

@@ -140,9 +140,10 @@ void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_b2_update(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
 // far-field amplitudes: P sorted [nrhs][nsites][3], dirs [ndir][9] (n, theta,
-// phi), f [nrhs][ndir][2], dcs [nrhs][ndir]
+// phi), f [nrhs][ndir][2], dcs [nrhs][ndir]; every site coordinate lies in the
+// box lo .. lo + n - 1
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
-                     double k, double2* f, double* dcs, hipStream_t s);
+                     double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s);
 // near field on an extended lattice box (first point org, extents dims):
 // P (caller order) into the box-scan site vector x at the target's sites;
 // E_sca = -v and E_inc at every point (either output may be null); the

@@ -400,42 +400,70 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
 // Draine 1988): per direction n and right-hand side, A = k^3 sum_j P_j
 // exp(-i k n . r_j), then f_1 = theta . A, f_2 = phi . A and the differential
 // cross section (|f_1|^2 + |f_2|^2) / k^2.  dirs holds n, theta, phi per
-// direction; one workgroup per (direction, right-hand side), deterministic
-// sums.
+// direction.  On the lattice the phase factor separates by axis,
+// exp(-i k n . r) = w_x(x) w_y(y) w_z(z), so one workgroup per direction
+// tabulates the n_x + n_y + n_z factors of its direction in LDS and every
+// term costs two complex products instead of a sine and cosine; the
+// right-hand sides are taken FR at a time over the same factors.
+// Deterministic sums (fixed per-thread order, then the workgroup reduction).
+constexpr int FR = 2;
+
 __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, const double2* P, long long n3,
-                                                 const double* dirs, double k, double2* f, double* dcs, int ndir) {
-    __shared__ double sh[8 * NT / 64];
-    const int d = blockIdx.x, q = blockIdx.y;
+                                                 int nrhs, const double* dirs, double k, int lox, int loy, int loz,
+                                                 int nx, int ny, int nz, double2* f, double* dcs, int ndir) {
+    extern __shared__ double2 wtab[];     // [nx + ny + nz] phase factors of this direction
+    __shared__ double sh[6 * FR * NT / 64];   // block_sum scratch: one value per wave and sum
+    const int d = blockIdx.x;
     const double* dv = dirs + (long long)d * 9;
-    const double nx = dv[0], ny = dv[1], nz = dv[2];
-    const double2* Pq = P + (long long)q * n3;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int s = threadIdx.x; s < nsites; s += NT) {
-        const double ph = -k * (nx * coords[s * 3 + 0] + ny * coords[s * 3 + 1] + nz * coords[s * 3 + 2]);
+    const int nt = nx + ny + nz;
+    for (int i = threadIdx.x; i < nt; i += NT) {
+        const int a = i < nx ? 0 : (i < nx + ny ? 1 : 2);
+        const int c = a == 0 ? lox + i : (a == 1 ? loy + (i - nx) : loz + (i - nx - ny));
         double sn, cs;
-        sincos(ph, &sn, &cs);
-        const double2 w = {cs, sn};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double2 v = cmul(Pq[(long long)s * 3 + c], w);
-            acc[2 * c] += v.x;
-            acc[2 * c + 1] += v.y;
-        }
+        sincos(-k * dv[a] * c, &sn, &cs);
+        wtab[i] = double2{cs, sn};
     }
-    block_sum<6>(acc, sh);
-    if (threadIdx.x != 0) return;
+    __syncthreads();
+    const double2* wy = wtab + nx;
+    const double2* wz = wtab + nx + ny;
     const double k3 = k * k * k;
-    double2 f1 = {0.0, 0.0}, f2 = {0.0, 0.0};
+    for (int q0 = 0; q0 < nrhs; q0 += FR) {
+        double acc[6 * FR];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double2 A = {k3 * acc[2 * c], k3 * acc[2 * c + 1]};
-        f1 = cadd(f1, double2{dv[3 + c] * A.x, dv[3 + c] * A.y});
-        f2 = cadd(f2, double2{dv[6 + c] * A.x, dv[6 + c] * A.y});
+        for (int i = 0; i < 6 * FR; ++i) acc[i] = 0.0;
+        for (int s = threadIdx.x; s < nsites; s += NT) {
+            const double2 w = cmul(cmul(wtab[coords[s * 3 + 0] - lox], wy[coords[s * 3 + 1] - loy]),
+                                   wz[coords[s * 3 + 2] - loz]);
+#pragma unroll
+            for (int r = 0; r < FR; ++r) {
+                if (q0 + r < nrhs) {
+                    const double2* Pq = P + (long long)(q0 + r) * n3 + (long long)s * 3;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double2 v = cmul(Pq[c], w);
+                        acc[6 * r + 2 * c] += v.x;
+                        acc[6 * r + 2 * c + 1] += v.y;
+                    }
+                }
+            }
+        }
+        block_sum<6 * FR>(acc, sh);
+        if (threadIdx.x == 0) {
+            for (int r = 0; r < FR && q0 + r < nrhs; ++r) {
+                double2 f1 = {0.0, 0.0}, f2 = {0.0, 0.0};
+                for (int c = 0; c < 3; ++c) {
+                    const double2 A = {k3 * acc[6 * r + 2 * c], k3 * acc[6 * r + 2 * c + 1]};
+                    f1 = cadd(f1, double2{dv[3 + c] * A.x, dv[3 + c] * A.y});
+                    f2 = cadd(f2, double2{dv[6 + c] * A.x, dv[6 + c] * A.y});
+                }
+                const long long o = (long long)(q0 + r) * ndir + d;
+                f[o * 2 + 0] = f1;
+                f[o * 2 + 1] = f2;
+                dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
+            }
+        }
+        __syncthreads();
     }
-    const long long o = (long long)q * ndir + d;
-    f[o * 2 + 0] = f1;
-    f[o * 2 + 1] = f2;
-    dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
 }
 
 // ------------------------------------------------------------------ near field
@@ -992,9 +1020,10 @@ void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qmr_final, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
-                     double k, double2* f, double* dcs, hipStream_t s) {
-    hipLaunchKernelGGL(k_farfield, dim3(ndir, nrhs), dim3(NT), 0, s, nsites, coords, P, 3LL * nsites, dirs, k, f, dcs,
-                       ndir);
+                     double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
+    const size_t shm = (size_t)(n[0] + n[1] + n[2]) * sizeof(double2);
+    hipLaunchKernelGGL(k_farfield, dim3(ndir), dim3(NT), shm, s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k,
+                       lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir);
 }
 void launch_nf_place(int nsites, const int* perm, const int* coords, const double2* P, int nrhs, const int org[3],
                      const int dims[3], double2* x, hipStream_t s) {
