@@ -1597,58 +1597,68 @@ dda_status dda_scattering_averages(dda_ctx* c, dda_target* t, const dda_opts* o,
         std::vector<double> mu, wmu;
         gauss_legendre(n_theta, mu, wmu);
         const int nd = n_theta * n_phi;
+        // right-hand sides in groups of at most 4M directions, each group one launch
+        const int qg = std::max(1, std::min(n_rhs, (1 << 22) / nd));
+        const long long ndt = (long long)nd * qg;
         const size_t n3 = 3 * (size_t)t->nsites;
-        const size_t pb = (size_t)n_rhs * n3 * sizeof(double2), db = (size_t)nd * 9 * sizeof(double);
-        const size_t fb = (size_t)nd * 2 * sizeof(double2), cb = (size_t)nd * sizeof(double);
+        const size_t pb = (size_t)n_rhs * n3 * sizeof(double2), db = (size_t)ndt * 9 * sizeof(double);
+        const size_t fb = (size_t)ndt * 2 * sizeof(double2), cb = (size_t)ndt * sizeof(double);
         char* buf = (char*)c->ffbuf.ensure(pb + db + fb + cb + 256);
         double2* Ps = (double2*)buf;
         double* ddev = (double*)(buf + pb);
         double2* fdev = (double2*)(buf + pb + db);
         double* cdev = (double*)(buf + pb + db + fb);
         launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P, Ps, true, c->stream);
-        std::vector<double> dirs((size_t)nd * 9), dcs(nd);
-        for (int q = 0; q < n_rhs; ++q) {
-            // frame (khat, u, v) and directions n = mu khat + sqrt(1-mu^2)(cos p u + sin p v)
-            const double* k = kh.data() + 3 * q;
-            double u[3], v[3];
-            const double ref[3] = {std::fabs(k[0]) < 0.9 ? 1.0 : 0.0, std::fabs(k[0]) < 0.9 ? 0.0 : 1.0, 0.0};
-            u[0] = k[1] * ref[2] - k[2] * ref[1];
-            u[1] = k[2] * ref[0] - k[0] * ref[2];
-            u[2] = k[0] * ref[1] - k[1] * ref[0];
-            const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            for (double& x : u) x /= un;
-            v[0] = k[1] * u[2] - k[2] * u[1];
-            v[1] = k[2] * u[0] - k[0] * u[2];
-            v[2] = k[0] * u[1] - k[1] * u[0];
-            for (int i = 0; i < n_theta; ++i) {
-                const double ct = mu[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
-                for (int j = 0; j < n_phi; ++j) {
-                    const double p = 2.0 * M_PI * j / n_phi, cp = std::cos(p), sp = std::sin(p);
-                    double* D = dirs.data() + ((size_t)i * n_phi + j) * 9;
-                    for (int m = 0; m < 3; ++m) {
-                        D[m] = ct * k[m] + st * (cp * u[m] + sp * v[m]);
-                        D[3 + m] = ct * (cp * u[m] + sp * v[m]) - st * k[m];
-                        D[6 + m] = -sp * u[m] + cp * v[m];
+        std::vector<double> dirs((size_t)ndt * 9), dcs((size_t)ndt);
+        for (int g0 = 0; g0 < n_rhs; g0 += qg) {
+            const int ng = std::min(qg, n_rhs - g0);
+            for (int q = g0; q < g0 + ng; ++q) {
+                // frame (khat, u, v) and directions n = mu khat + sqrt(1-mu^2)(cos p u + sin p v)
+                const double* k = kh.data() + 3 * q;
+                double u[3], v[3];
+                const double ref[3] = {std::fabs(k[0]) < 0.9 ? 1.0 : 0.0, std::fabs(k[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+                u[0] = k[1] * ref[2] - k[2] * ref[1];
+                u[1] = k[2] * ref[0] - k[0] * ref[2];
+                u[2] = k[0] * ref[1] - k[1] * ref[0];
+                const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                for (double& x : u) x /= un;
+                v[0] = k[1] * u[2] - k[2] * u[1];
+                v[1] = k[2] * u[0] - k[0] * u[2];
+                v[2] = k[0] * u[1] - k[1] * u[0];
+                for (int i = 0; i < n_theta; ++i) {
+                    const double ct = mu[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+                    for (int j = 0; j < n_phi; ++j) {
+                        const double p = 2.0 * M_PI * j / n_phi, cp = std::cos(p), sp = std::sin(p);
+                        double* D = dirs.data() + (((size_t)(q - g0) * n_theta + i) * n_phi + j) * 9;
+                        for (int m = 0; m < 3; ++m) {
+                            D[m] = ct * k[m] + st * (cp * u[m] + sp * v[m]);
+                            D[3 + m] = ct * (cp * u[m] + sp * v[m]) - st * k[m];
+                            D[6 + m] = -sp * u[m] + cp * v[m];
+                        }
                     }
                 }
             }
-            HIPCHK(hipMemcpyAsync(ddev, dirs.data(), db, hipMemcpyHostToDevice, c->stream));
-            launch_farfield(t->nsites, (const int*)t->coords.p, Ps + (size_t)q * n3, 1, ddev, nd, kd, t->lo,
-                            t->geo.n, fdev, cdev, c->stream);
+            HIPCHK(hipMemcpyAsync(ddev, dirs.data(), (size_t)ng * nd * 9 * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+            launch_farfield_sets(t->nsites, (const int*)t->coords.p, Ps + (size_t)g0 * n3, ng, ddev, nd, kd, t->lo,
+                                 t->geo.n, fdev, cdev, c->stream);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(dcs.data(), cdev, cb, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(dcs.data(), cdev, (size_t)ng * nd * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int i = 0; i < n_theta; ++i)
-                for (int j = 0; j < n_phi; ++j) {
-                    const double wgt = wmu[i] * (2.0 * M_PI / n_phi) * dcs[(size_t)i * n_phi + j];
-                    s0 += wgt;
-                    s1 += wgt * mu[i];
-                    s2 += wgt * mu[i] * mu[i];
-                }
-            out[3 * q + 0] = s0 / (M_PI * a * a);
-            out[3 * q + 1] = s0 > 0 ? s1 / s0 : 0.0;
-            out[3 * q + 2] = s0 > 0 ? s2 / s0 : 0.0;
+            for (int q = g0; q < g0 + ng; ++q) {
+                const double* dq = dcs.data() + (size_t)(q - g0) * nd;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+                for (int i = 0; i < n_theta; ++i)
+                    for (int j = 0; j < n_phi; ++j) {
+                        const double wgt = wmu[i] * (2.0 * M_PI / n_phi) * dq[(size_t)i * n_phi + j];
+                        s0 += wgt;
+                        s1 += wgt * mu[i];
+                        s2 += wgt * mu[i] * mu[i];
+                    }
+                out[3 * q + 0] = s0 / (M_PI * a * a);
+                out[3 * q + 1] = s0 > 0 ? s1 / s0 : 0.0;
+                out[3 * q + 2] = s0 > 0 ? s2 / s0 : 0.0;
+            }
         }
         return DDA_OK;
     });

@@ -144,6 +144,10 @@ void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
 // box lo .. lo + n - 1
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
                      double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s);
+// the same with a set of per directions for each right-hand side: dirs
+// [nrhs * per][9], f [nrhs * per][2], dcs [nrhs * per]
+void launch_farfield_sets(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int per,
+                          double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s);
 // near field on an extended lattice box (first point org, extents dims):
 // P (caller order) into the box-scan site vector x at the target's sites;
 // E_sca = -v and E_inc at every point (either output may be null); the

@@ -404,13 +404,17 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
 // exp(-i k n . r) = w_x(x) w_y(y) w_z(z), so one workgroup per direction
 // tabulates the n_x + n_y + n_z factors of its direction in LDS and every
 // term costs two complex products instead of a sine and cosine; the
-// right-hand sides are taken FR at a time over the same factors.
-// Deterministic sums (fixed per-thread order, then the workgroup reduction).
+// right-hand sides are taken FR at a time over the same factors.  per > 0:
+// direction d belongs to right-hand side d / per alone (every right-hand
+// side with its own direction set in one launch) and its results go to
+// entry d.  Deterministic sums (fixed per-thread order, then the workgroup
+// reduction).
 constexpr int FR = 2;
 
 __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, const double2* P, long long n3,
                                                  int nrhs, const double* dirs, double k, int lox, int loy, int loz,
-                                                 int nx, int ny, int nz, double2* f, double* dcs, int ndir) {
+                                                 int nx, int ny, int nz, double2* f, double* dcs, int ndir,
+                                                 int per) {
     extern __shared__ double2 wtab[];     // [nx + ny + nz] phase factors of this direction
     __shared__ double sh[6 * FR * NT / 64];   // block_sum scratch: one value per wave and sum
     const int d = blockIdx.x;
@@ -427,7 +431,9 @@ __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, 
     const double2* wy = wtab + nx;
     const double2* wz = wtab + nx + ny;
     const double k3 = k * k * k;
-    for (int q0 = 0; q0 < nrhs; q0 += FR) {
+    const int qa = per > 0 ? d / per : 0;
+    const int qb = per > 0 ? qa + 1 : nrhs;
+    for (int q0 = qa; q0 < qb; q0 += FR) {
         double acc[6 * FR];
 #pragma unroll
         for (int i = 0; i < 6 * FR; ++i) acc[i] = 0.0;
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, 
                                    wz[coords[s * 3 + 2] - loz]);
 #pragma unroll
             for (int r = 0; r < FR; ++r) {
-                if (q0 + r < nrhs) {
+                if (q0 + r < qb) {
                     const double2* Pq = P + (long long)(q0 + r) * n3 + (long long)s * 3;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -449,14 +455,14 @@ __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, 
         }
         block_sum<6 * FR>(acc, sh);
         if (threadIdx.x == 0) {
-            for (int r = 0; r < FR && q0 + r < nrhs; ++r) {
+            for (int r = 0; r < FR && q0 + r < qb; ++r) {
                 double2 f1 = {0.0, 0.0}, f2 = {0.0, 0.0};
                 for (int c = 0; c < 3; ++c) {
                     const double2 A = {k3 * acc[6 * r + 2 * c], k3 * acc[6 * r + 2 * c + 1]};
                     f1 = cadd(f1, double2{dv[3 + c] * A.x, dv[3 + c] * A.y});
                     f2 = cadd(f2, double2{dv[6 + c] * A.x, dv[6 + c] * A.y});
                 }
-                const long long o = (long long)(q0 + r) * ndir + d;
+                const long long o = per > 0 ? (long long)d : (long long)(q0 + r) * ndir + d;
                 f[o * 2 + 0] = f1;
                 f[o * 2 + 1] = f2;
                 dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
@@ -1023,7 +1029,14 @@ void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, 
                      double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
     const size_t shm = (size_t)(n[0] + n[1] + n[2]) * sizeof(double2);
     hipLaunchKernelGGL(k_farfield, dim3(ndir), dim3(NT), shm, s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k,
-                       lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir);
+                       lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
+}
+void launch_farfield_sets(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int per,
+                          double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
+    const size_t shm = (size_t)(n[0] + n[1] + n[2]) * sizeof(double2);
+    const int ndt = per * nrhs;
+    hipLaunchKernelGGL(k_farfield, dim3(ndt), dim3(NT), shm, s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k,
+                       lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndt, per);
 }
 void launch_nf_place(int nsites, const int* perm, const int* coords, const double2* P, int nrhs, const int org[3],
                      const int dims[3], double2* x, hipStream_t s) {
