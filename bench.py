@@ -229,7 +229,7 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
         by_variant[str(v)] = {"kernel_name": fv[v][0], "fetch_bytes_per_launch": fv[v][1],
                               "write_bytes_per_launch": wv[v][1], "bytes_per_launch": tot,
                               "bytes_per_rhs_matvec": tot / n_rhs, "over_algorithmic": tot / n_rhs / alg_full}
-    cmds = profile_commands(workload, prec)
+    cmds = profile_commands(workload, prec, os.path.abspath(tr))
     chosen = ub["autotuned_variants"][slot] if ub.get("autotuned_variants") else None
     rec = {"kernel": dom, "workload": workload, "precision": prec, "rhs_per_launch": n_rhs,
            "variant_unprofiled_run": chosen, "algorithmic_bytes_per_rhs_matvec": alg_full,
@@ -527,6 +527,8 @@ def main():
                     help="print the rocprofv3 runs behind the profiles/ summaries of --workload")
     ap.add_argument("--summarize", metavar="DIR",
                     help="write the profiles/ summaries of --workload from those runs' outputs under DIR")
+    ap.add_argument("--profile-dir", metavar="DIR", default="/root/repo/gpurun_out/tr",
+                    help="with --print-profile-commands: where the runs write their outputs")
     ap.add_argument("--unprofiled", metavar="JSON", help="with --summarize: the unprofiled bench line")
     args = ap.parse_args()
     if args.copy_probe:
@@ -537,7 +539,7 @@ def main():
         if args.summarize:
             summarize_profiles(args.summarize, args.workload, prec, args.unprofiled)
         else:
-            for k, c in profile_commands(args.workload, prec).items():
+            for k, c in profile_commands(args.workload, prec, args.profile_dir).items():
                 print(f"# {k}\n{c}")
         return
     if args.gpus != 1:

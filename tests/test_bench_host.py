@@ -1,0 +1,61 @@
+"""Host logic of bench.py (no GPU): the measured-traffic lookup, the
+profile-command contract and the refusal of more than one GPU."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _record(tmp_path, digest, variant_bytes):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"kernel": "fft_z_green", "source_sha256": digest,
+           "by_variant": {str(v): {"bytes_per_rhs_matvec": b} for v, b in variant_bytes.items()}}
+    (prof / "fft_z_green_ellipsoid51k_fp64_traffic.json").write_text(json.dumps(rec))
+
+
+def test_traffic_is_taken_for_the_run_variant_and_scaled_per_launch(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "abc")
+    _record(tmp_path, "abc", {3: 50e6, 10: 40e6})
+    # variants are (y forward, z, y inverse); the z slot decides
+    assert bench.load_traffic("fft_z_green", "ellipsoid51k", "fp64", [4, 3, 4], 1.5) == 75e6
+    assert bench.load_traffic("fft_z_green", "ellipsoid51k", "fp64", [4, 10, 4], 2.0) == 80e6
+    assert bench.load_traffic("fft_z_green", "ellipsoid51k", "fp64", [4, 7, 4], 2.0) is None
+    assert bench.load_traffic("fft_z_green", "ellipsoid51k", "fp64", None, 2.0) is None
+    assert bench.load_traffic("fft_z_green", "brick48", "fp64", [4, 3, 4], 2.0) is None
+
+
+def test_traffic_is_null_once_the_pass_sources_change(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "new")
+    _record(tmp_path, "old", {3: 50e6})
+    assert bench.load_traffic("fft_z_green", "ellipsoid51k", "fp64", [4, 3, 4], 1.5) is None
+
+
+def test_source_digest_covers_the_pass_kernels():
+    d = bench.kernel_source_digest()
+    assert len(d) == 64 and d == bench.kernel_source_digest()
+
+
+def test_profile_commands_run_committed_files_under_the_profiler():
+    c = bench.profile_commands("sphere1m", "fp32_matvec", "/root/repo/gpurun_out/tr_x")
+    assert set(c) == {"trace", "fetch", "write", "copy_fetch", "copy_write", "unprofiled"}
+    for k in ("trace", "fetch", "write", "copy_fetch", "copy_write"):
+        assert c[k].startswith("cd /tmp && export TMPDIR=/tmp && timeout ")
+        assert "-- python -u /root/repo/bench.py" in c[k] and "/root/repo/gpurun_out/tr_x/" in c[k]
+    assert "--pmc FETCH_SIZE" in c["fetch"] and "--pmc WRITE_SIZE" in c["write"]
+    assert "--kernel-trace --stats" in c["trace"] and "--pmc" not in c["trace"]
+    assert "--workload sphere1m --precision fp32_matvec" in c["unprofiled"]
+    # the default workload and precision add no flags
+    assert "--workload" not in bench.profile_commands("ellipsoid51k", "fp64")["unprofiled"]
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
