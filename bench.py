@@ -141,6 +141,9 @@ PASS_PATTERNS = {
     "fft_x_gather": r"k_gather_x<",
 }
 AUTOTUNE_LAUNCHES = 6   # launches of each candidate while the autotuner times it
+# FFT lengths with compile-time kernels, and their autotuned variants per pass
+CT_LENGTHS = (32, 48, 64, 80, 96, 128, 160, 192, 256)
+CT_VARIANTS = {"fft_y_fwd": 8, "fft_z_green": 24, "fft_y_inv": 8}
 
 
 def profile_commands(workload: str, prec: str, out: str = "/root/repo/gpurun_out/tr") -> dict:
@@ -239,8 +242,6 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
                    "launches of each variant on the real grid (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, "
                    "averaged over those launches, times the copy-probe factors)"}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}_{prec}_traffic.json"), "w") as fh:
-        json.dump(rec, fh, indent=1)
     ks = sorted(rows(os.path.join(tr, "kt", "run_kernel_stats.csv")), key=lambda r: -float(r["TotalDurationNs"]))
     lines = [f"# rocprofv3 kernel-trace summary: {workload}, {prec}",
              f"# command: {cmds['trace']}",
@@ -269,6 +270,39 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
     for v, e in by_variant.items():
         lines.append(f"#     {int(v):2d} {e['kernel_name'][:64]:64s} {e['fetch_bytes_per_launch'] / n_rhs / 1e6:7.2f} + "
                      f"{e['write_bytes_per_launch'] / n_rhs / 1e6:6.2f} MB  x{e['over_algorithmic']:.2f}")
+    # every pass: HBM bytes per production launch (the autotuner's timing
+    # launches left out) against the algorithmic bytes per launch of the
+    # unprofiled run's calibration step, and over that step's launch time
+    grid = ub["config"]["fft_grid"]
+    frows = rows(os.path.join(tr, "f", "run_counter_collection.csv"))
+    wrows = rows(os.path.join(tr, "w", "run_counter_collection.csv"))
+    per_pass = {}
+    for name, cal in ub["matvec"]["passes_calibration_step"].items():
+        pp = re.compile(PASS_PATTERNS[name])
+        L = grid[SLOT_OF_PASS[name] // 2 + 1] if name in SLOT_OF_PASS else None
+        trials = AUTOTUNE_LAUNCHES * (CT_VARIANTS[name] if L in CT_LENGTHS else 1) if L else 0
+
+        def prod(rs, counter, scale):
+            fam = sorted((r for r in rs if r["Counter_Name"] == counter and pp.search(r["Kernel_Name"])),
+                         key=lambda r: int(r["Dispatch_Id"]))[trials:]
+            return statistics.mean(float(r["Counter_Value"]) for r in fam) * 1024 * scale if fam else None
+        fb, wb = prod(frows, "FETCH_SIZE", fscale), prod(wrows, "WRITE_SIZE", wscale)
+        if fb is None or wb is None:
+            continue
+        alg = cal["GBps"] * cal["ms_per_launch"] * 1e6
+        per_pass[name] = {"measured_bytes_per_launch": fb + wb, "algorithmic_bytes_per_launch": alg,
+                          "over_algorithmic": (fb + wb) / alg, "us_per_launch": cal["ms_per_launch"] * 1e3,
+                          "measured_GBps": (fb + wb) / (cal["ms_per_launch"] * 1e-3) / 1e9,
+                          "measured_frac": (fb + wb) / (cal["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    rec["passes"] = per_pass
+    with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}_{prec}_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines += ["#   every pass, production launches (measured HBM bytes from the counters; time per launch from the",
+              "#   unprofiled run's calibration step):",
+              f"#     {'pass':14s} {'us/launch':>9s} {'measured MB':>11s} {'x alg':>6s} {'measured GB/s':>13s} {'frac':>5s}"]
+    for name, e in per_pass.items():
+        lines.append(f"#     {name:14s} {e['us_per_launch']:9.2f} {e['measured_bytes_per_launch'] / 1e6:11.2f} "
+                     f"{e['over_algorithmic']:6.2f} {e['measured_GBps']:13.0f} {e['measured_frac']:5.2f}")
     with open(os.path.join(ROOT, "profiles", f"dda_kernels_{workload}_{prec}_trace.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
