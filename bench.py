@@ -89,8 +89,12 @@ def kernel_source_digest() -> str:
 
 
 def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
-    """Algorithmic HBM bytes of each matvec pass for one right-hand side
-    (one read and one write of exactly the data the pruned pass needs)."""
+    """Algorithmic HBM bytes of each matvec pass: one read and one write of
+    exactly the data the pruned pass needs.  Returns {pass: (per right-hand
+    side, once per launch)}: the grids and site vectors belong to each
+    right-hand side; the tensor octant, the box map and the materials are
+    shared by every right-hand side of a launch (the R of the pruned model's
+    6M/R term)."""
     nx, ny, nz = tgt.box
     Mx, My, Mz = tgt.grid
     Hx, Hy, Hz = Mx // 2 + 1, My // 2 + 1, Mz // 2 + 1
@@ -98,14 +102,16 @@ def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
     site = 3 * n_sites * 16             # one FP64 site vector
     nbox = nx * ny * nz
     return {
-        # write the x-transformed occupied lines; read the box map and on
-        # average 2.5 site vectors, write 1 (p = r + beta(p - omega v) / s = r - alpha v)
-        "scatter_fft_x": Mx * ny * nz * g + 4 * nbox + 3.5 * site,
-        "fft_y_fwd": Mx * ny * nz * g + Mx * My * nz * g,
-        "fft_z_green": 2 * Mx * My * nz * g + Hx * Hy * Hz * 6 * csize,
-        "fft_y_inv": Mx * My * nz * g + Mx * ny * nz * g,
-        # read the x lines, box map, materials, the input and one more site vector, write the output
-        "fft_x_gather": Mx * ny * nz * g + 4 * nbox + 4 * n_sites + 3 * site,
+        # write the x-transformed occupied lines; read on average 2.5 site
+        # vectors and write 1 (p = r + beta(p - omega v) / s = r - alpha v);
+        # the box map once
+        "scatter_fft_x": (Mx * ny * nz * g + 3.5 * site, 4 * nbox),
+        "fft_y_fwd": (Mx * ny * nz * g + Mx * My * nz * g, 0),
+        "fft_z_green": (2 * Mx * My * nz * g, Hx * Hy * Hz * 6 * csize),
+        "fft_y_inv": (Mx * My * nz * g + Mx * ny * nz * g, 0),
+        # read the x lines, the input and one more site vector, write the
+        # output; the box map and materials once
+        "fft_x_gather": (Mx * ny * nz * g + 3 * site, 4 * nbox + 4 * n_sites),
     }
 
 
@@ -207,12 +213,15 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
     n_rhs = ub["config"]["rhs_per_step"]
     pat = re.compile(PASS_PATTERNS[dom])
 
+    L_dom = ub["config"]["fft_grid"][SLOT_OF_PASS[dom] // 2 + 1]
+    n_var = CT_VARIANTS[dom] if L_dom in CT_LENGTHS else 1
+
     def per_variant(path, counter, scale):
         fam = sorted((r for r in rows(path) if r["Counter_Name"] == counter and pat.search(r["Kernel_Name"])),
                      key=lambda r: int(r["Dispatch_Id"]))
         out = {}
         v = 0
-        while (v + 1) * AUTOTUNE_LAUNCHES <= len(fam):
+        while v < n_var and (v + 1) * AUTOTUNE_LAUNCHES <= len(fam):
             grp = fam[v * AUTOTUNE_LAUNCHES:(v + 1) * AUTOTUNE_LAUNCHES]
             names = {short(r["Kernel_Name"]) for r in grp}
             if len(names) != 1:
@@ -223,7 +232,9 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
 
     fv = per_variant(os.path.join(tr, "f", "run_counter_collection.csv"), "FETCH_SIZE", fscale)
     wv = per_variant(os.path.join(tr, "w", "run_counter_collection.csv"), "WRITE_SIZE", wscale)
-    alg_full = ub["matvec"]["passes_calibration_step"][dom]["bytes_per_rhs_matvec"]
+    cal_dom = ub["matvec"]["passes_calibration_step"][dom]
+    # a full launch: every right-hand side of the workload plus the shared bytes once
+    alg_full = cal_dom["bytes_per_rhs_matvec"] * n_rhs + cal_dom.get("bytes_per_launch_shared", 0.0)
     by_variant = {}
     for v in sorted(set(fv) & set(wv)):
         if fv[v][0] != wv[v][0]:
@@ -231,11 +242,11 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
         tot = fv[v][1] + wv[v][1]
         by_variant[str(v)] = {"kernel_name": fv[v][0], "fetch_bytes_per_launch": fv[v][1],
                               "write_bytes_per_launch": wv[v][1], "bytes_per_launch": tot,
-                              "bytes_per_rhs_matvec": tot / n_rhs, "over_algorithmic": tot / n_rhs / alg_full}
+                              "bytes_per_rhs_matvec": tot / n_rhs, "over_algorithmic": tot / alg_full}
     cmds = profile_commands(workload, prec, os.path.abspath(tr))
     chosen = ub["autotuned_variants"][slot] if ub.get("autotuned_variants") else None
     rec = {"kernel": dom, "workload": workload, "precision": prec, "rhs_per_launch": n_rhs,
-           "variant_unprofiled_run": chosen, "algorithmic_bytes_per_rhs_matvec": alg_full,
+           "variant_unprofiled_run": chosen, "algorithmic_bytes_per_full_launch": alg_full,
            "by_variant": by_variant, "fetch_scale": fscale, "write_scale": wscale,
            "source_sha256": kernel_source_digest(), "commands": cmds,
            "note": "bytes of one launch over all right-hand sides of the workload, from the autotuner's timing "
@@ -264,9 +275,10 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
               f"#   unprofiled run ({cmds['unprofiled']}): HIP events {urf['avg_launch_us']:.2f} us/launch over "
               f"{urf['launches']} launches, {urf['achieved']:.0f} GB/s algorithmic, frac {urf['frac']:.3f}; "
               f"ms/step {ub['ms_per_step']:.3f}",
-              f"#   algorithmic bytes per right-hand-side matvec: {alg_full / 1e6:.2f} MB",
+              f"#   algorithmic bytes of a full launch ({n_rhs} right-hand sides, the shared tensor octant once): "
+              f"{alg_full / 1e6:.2f} MB",
               f"#   counter scales from the copy probe: FETCH_SIZE x {fscale:.3f}, WRITE_SIZE x {wscale:.3f}",
-              "#   measured HBM bytes per right-hand-side matvec by variant (fetch + write, x algorithmic):"]
+              "#   measured HBM bytes of a full launch by variant, per right-hand side (fetch + write, x algorithmic):"]
     for v, e in by_variant.items():
         lines.append(f"#     {int(v):2d} {e['kernel_name'][:64]:64s} {e['fetch_bytes_per_launch'] / n_rhs / 1e6:7.2f} + "
                      f"{e['write_bytes_per_launch'] / n_rhs / 1e6:6.2f} MB  x{e['over_algorithmic']:.2f}")
@@ -440,10 +452,10 @@ def nearfield_measurement(dda, np, torch, job, d, reps: int = 10, cpu: bool = Tr
     for name in PASSES:
         pms, nl, _ = tm[name]
         if nl:
-            gbs = bp[name] * n_rhs * nl / reps / (pms / reps * 1e-3) / 1e9
+            gbs = (bp[name][0] * n_rhs + bp[name][1]) * nl / reps / (pms / reps * 1e-3) / 1e9
             passes[name] = {"ms_per_call": pms / reps, "GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
     kern_ms = sum(tm[k][0] for k in PASSES) / reps
-    kern_bytes = sum(bp[k] for k in PASSES) * n_rhs
+    kern_bytes = sum(bp[k][0] * n_rhs + bp[k][1] for k in PASSES)
     out = {"ms_per_call": ms, "ms_per_call_tensor_rebuilt": ms_new, "points": npts,
            "dims": [int(v) for v in dims], "fft_grid": list(Vol.grid),
            "n_rhs": n_rhs, "product_kernels_ms": kern_ms,
@@ -621,8 +633,12 @@ def main():
     csize = 8 if prec == "fp32_matvec" else 16
     bpus = [pass_bytes(j[0], j[0].n_sites, csize) for j in jobs]
 
-    def pass_traffic(name, units):
-        return sum(b[name] * u for b, u in zip(bpus, units))
+    def pass_traffic(name, units, launches):
+        # per-RHS bytes times the RHS-matvecs each job executed, plus the
+        # shared bytes once per launch (several jobs: their launches taken as
+        # equal shares)
+        per_rhs = sum(b[name][0] * u for b, u in zip(bpus, units))
+        return per_rhs + sum(b[name][1] for b in bpus) * launches / len(bpus)
 
     # warmup; the last warmup step times every kernel category to find the
     # dominant matvec pass, which alone is timed during the measured steps
@@ -661,7 +677,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; results {results[0]}")
 
     ms_tot, launches, all_launches = timing[dominant]
-    bytes_tot = pass_traffic(dominant, units)
+    bytes_tot = pass_traffic(dominant, units, all_launches)
     # algorithmic bytes per launch (all launches) over the sampled average launch time
     avg_s = ms_tot * 1e-3 / launches
     gbs = bytes_tot / all_launches / avg_s / 1e9
@@ -678,11 +694,11 @@ def main():
         ms, nl, _ = calib[name]
         if nl == 0 or ms == 0:
             continue
-        g = pass_traffic(name, cal_units) / (ms * 1e-3) / 1e9
-        passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": bpus[0][name],
-                        "GBps": g, "frac": g / HBM_PEAK_GBS}
+        g = pass_traffic(name, cal_units, nl) / (ms * 1e-3) / 1e9
+        passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": bpus[0][name][0],
+                        "bytes_per_launch_shared": bpus[0][name][1], "GBps": g, "frac": g / HBM_PEAK_GBS}
     matvec_ms = sum(calib[k][0] for k in PASSES)
-    matvec_bytes = sum(pass_traffic(k, cal_units) for k in PASSES)
+    matvec_bytes = sum(pass_traffic(k, cal_units, calib[k][1]) for k in PASSES)
     out = {
         "metric": METRIC,
         "value": s_per_orientation,
