@@ -21,7 +21,12 @@
  *   - Q_ext, Q_abs, Q_sca, Q_pha: "What Does It Calculate?";
  *   - P and 1/alpha as stored for post-processing: appendix ".pol Files".
  * The interaction matrix is applied as an FFT convolution on a zero-padded
- * grid ("Choice of FFT Algorithm"), inside BiCGSTAB (the PBCGST option).
+ * grid ("Choice of FFT Algorithm"), inside BiCGSTAB, QMR for complex-symmetric
+ * A or BiCGstab(2) (the PBCGST, QMRCCG and PBCGS2 options).  From P the
+ * library also gives the far-field amplitudes, the Mueller matrix and the
+ * averages over scattering directions, the electric field in and around the
+ * target ("Near-Field Calculations"), and the adjoint gradient of Q_abs and
+ * Q_ext in the per-site permittivity.
  *
  * Conventions
  *   - Lengths are in units of the lattice spacing d internally; E0 has unit
@@ -112,7 +117,8 @@ typedef struct {
     double aeff;         /* effective radius, same unit > 0 */
     double m_medium;     /* real refractive index of the ambient medium > 0 (1 = vacuum) */
     double tol;          /* stop when |E - A P| / |E| < tol; > 0 */
-    int32_t max_iter;    /* BiCGSTAB iteration cap >= 1 (two matvecs per iteration) */
+    int32_t max_iter;    /* iteration cap >= 1 (matvecs per iteration: BiCGSTAB 2, QMR 1,
+                            BiCGstab(2) 4) */
     int32_t polarizability;  /* dda_polarizability */
     int32_t solver;          /* dda_solver */
     int32_t precision;       /* dda_precision */
@@ -128,7 +134,7 @@ typedef struct {
     double normal_eq_residual;       /* |A^H A P - A^H E| / |A^H E| (eq. err_tol) */
     double kd;                       /* k d in the ambient medium */
     double aeff_d;                   /* a_eff / d */
-    int32_t iters;                   /* BiCGSTAB iterations taken */
+    int32_t iters;                   /* iterations of the chosen solver taken */
     int32_t matvecs;                 /* FFT matrix-vector products in the iteration */
     int32_t status;                  /* dda_status of this right-hand side */
     int32_t restarts;                /* breakdown restarts taken (0 or 1) */
@@ -149,7 +155,8 @@ dda_status dda_ctx_destroy(dda_ctx* ctx);
  * The library keeps sorted device copies, the occupancy map of the bounding
  * box and, lazily, the FFT of the interaction tensor per (kd, precision).
  * Errors: DDA_E_INVALID for n_sites < 1, duplicate sites, a box extent above
- * 4096, more than 65535 distinct materials, or non-finite m; DDA_E_NOMEM. */
+ * 4096 or one whose padded FFT extent exceeds 341, more than 65535 distinct
+ * materials, a vacuum site (m = 1) or non-finite m; DDA_E_NOMEM. */
 dda_status dda_target_create(dda_ctx* ctx, int64_t n_sites, const int32_t* ijk,
                              const dda_c64* m_site, dda_target** out);
 dda_status dda_target_destroy(dda_target* t);
