@@ -146,7 +146,7 @@ PASS_PATTERNS = {
     "fft_y_inv": r"k_strided<(double|float), 3, 0, 1,|k_strided_rf<(double|float), 0, 1,",
     "fft_x_gather": r"k_gather_x<",
 }
-AUTOTUNE_LAUNCHES = 6   # launches of each candidate while the autotuner times it
+AUTOTUNE_LAUNCHES = 21   # launches of each candidate while the autotuner times it (1 + 20)
 # FFT lengths with compile-time kernels, and their autotuned variants per pass
 CT_LENGTHS = (32, 48, 64, 80, 96, 128, 160, 192, 256)
 CT_VARIANTS = {"fft_y_fwd": 8, "fft_z_green": 24, "fft_y_inv": 8}
@@ -297,12 +297,20 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
         def prod(rs, counter, scale):
             fam = sorted((r for r in rs if r["Counter_Name"] == counter and pp.search(r["Kernel_Name"])),
                          key=lambda r: int(r["Dispatch_Id"]))[trials:]
-            return statistics.mean(float(r["Counter_Value"]) for r in fam) * 1024 * scale if fam else None
-        fb, wb = prod(frows, "FETCH_SIZE", fscale), prod(wrows, "WRITE_SIZE", wscale)
-        if fb is None or wb is None:
+            if not fam:
+                return None, None
+            # the kernel the counted run launched most (its autotuner's choice)
+            top = statistics.mode(short(r["Kernel_Name"]) for r in fam)
+            return statistics.mean(float(r["Counter_Value"]) for r in fam) * 1024 * scale, top
+        (fb, kf), (wb, kw) = prod(frows, "FETCH_SIZE", fscale), prod(wrows, "WRITE_SIZE", wscale)
+        if fb is None or wb is None or kf != kw:
+            # the two counter runs' autotuners chose different variants of a
+            # pass that ties: their counts do not add up to one kernel's
+            per_pass[name] = {"kernel_counted": f"{kf} / {kw}", "measured_bytes_per_launch": None}
             continue
         alg = cal["GBps"] * cal["ms_per_launch"] * 1e6
-        per_pass[name] = {"measured_bytes_per_launch": fb + wb, "algorithmic_bytes_per_launch": alg,
+        per_pass[name] = {"kernel_counted": kf if kf == kw else f"{kf} / {kw}",
+                          "measured_bytes_per_launch": fb + wb, "algorithmic_bytes_per_launch": alg,
                           "over_algorithmic": (fb + wb) / alg, "us_per_launch": cal["ms_per_launch"] * 1e3,
                           "measured_GBps": (fb + wb) / (cal["ms_per_launch"] * 1e-3) / 1e9,
                           "measured_frac": (fb + wb) / (cal["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -310,11 +318,18 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
     with open(os.path.join(ROOT, "profiles", f"{dom}_{workload}_{prec}_traffic.json"), "w") as fh:
         json.dump(rec, fh, indent=1)
     lines += ["#   every pass, production launches (measured HBM bytes from the counters; time per launch from the",
-              "#   unprofiled run's calibration step):",
-              f"#     {'pass':14s} {'us/launch':>9s} {'measured MB':>11s} {'x alg':>6s} {'measured GB/s':>13s} {'frac':>5s}"]
+              "#   unprofiled run's calibration step, whose autotuned variants are given above; the kernel counted",
+              "#   is the one the counter runs launched, which may be another variant of a pass that ties):",
+              f"#     {'pass':14s} {'us/launch':>9s} {'measured MB':>11s} {'x alg':>6s} {'measured GB/s':>13s} {'frac':>5s}"
+              "  kernel counted"]
     for name, e in per_pass.items():
+        if e["measured_bytes_per_launch"] is None:
+            lines.append(f"#     {name:14s} the FETCH_SIZE and WRITE_SIZE runs launched different variants "
+                         f"({e['kernel_counted']}); see the per-variant table for pass 3")
+            continue
         lines.append(f"#     {name:14s} {e['us_per_launch']:9.2f} {e['measured_bytes_per_launch'] / 1e6:11.2f} "
-                     f"{e['over_algorithmic']:6.2f} {e['measured_GBps']:13.0f} {e['measured_frac']:5.2f}")
+                     f"{e['over_algorithmic']:6.2f} {e['measured_GBps']:13.0f} {e['measured_frac']:5.2f}"
+                     f"  {e['kernel_counted']}")
     with open(os.path.join(ROOT, "profiles", f"dda_kernels_{workload}_{prec}_trace.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))

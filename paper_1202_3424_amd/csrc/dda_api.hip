@@ -425,8 +425,9 @@ struct Work {
     // Pick, once per (grid, box, right-hand sides, precision), a compile-time
     // variant of each strided pass by timing every candidate on the workspace
     // grid (its contents are scratch at this point; all variants compute
-    // bitwise-identical results): the lowest-numbered variant within 3% of
-    // the fastest, so that near-ties resolve the same way from run to run.
+    // bitwise-identical results), one warm-up and twenty timed launches
+    // each: the lowest-numbered variant within 3% of the fastest, so that
+    // near-ties resolve the same way from run to run.
     void autotune(bool enabled, int forced = 0) {
         const Geo& g = t->geo;
         if (forced > 0) {
@@ -456,7 +457,7 @@ struct Work {
                     };
                     run();
                     HIPCHK(hipEventRecord(e0, s));
-                    for (int k = 0; k < 5; ++k) run();
+                    for (int k = 0; k < 20; ++k) run();
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
                     HIPCHK(hipEventElapsedTime(&t_ms[v], e0, e1));

@@ -18,7 +18,7 @@
 // Each kernel has two forms.  For the FFT lengths in CT_LENGTHS the length,
 // the tile shape and the radix plan are compile-time constants (index
 // arithmetic folds to shifts and multiplies); the x passes then run one
-// x-line (three components) per 64-thread workgroup.  Other lengths use the
+// x-line (three components) per workgroup of one or two wavefronts.  Other lengths use the
 // runtime plan with twiddles staged in LDS.
 #pragma once
 
@@ -41,7 +41,10 @@ constexpr int ct_cols(int L) {
     while (p * 2 <= tx && p * 2 <= 16) p *= 2;
     return p;
 }
-constexpr int XTHR = 64;   // threads of a compile-time x-pass workgroup (one wavefront)
+// threads of a compile-time x-pass workgroup: one wavefront up to length
+// 128, two beyond (a line of 3 x 256 values gives one wavefront 12 elements
+// per thread, which serialises its dependent map and site loads)
+constexpr int xthr(int L) { return L > 128 ? 128 : 64; }
 
 template <typename C> __device__ __forceinline__ C to_c(double2 u) {
     C c;
@@ -881,7 +884,7 @@ void scatter_dispatch(int chk, const Geo& g, const SiteArgs& a, typename V2<T>::
     switch (L) {
 #define DDA_CASE(LL)                                                                                            \
     case LL:                                                                                                   \
-        DDA_LAUNCH((k_scatter_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid, \
+        DDA_LAUNCH((k_scatter_x<T, MODE, LL, xthr(LL)>), grd, dim3(xthr(LL)), smem_ct<C>(LL, 3), s, g, a, grid, \
                            tw, 1, chk);                                                                        \
         return;
         DDA_CT_LENGTHS(DDA_CASE)
@@ -902,7 +905,7 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
     switch (L) {
 #define DDA_CASE(LL)                                                                                            \
     case LL:                                                                                                   \
-        DDA_LAUNCH((k_gather_x<T, MODE, LL, XTHR>), grd, dim3(XTHR), smem_ct<C>(LL, 3), s, g, a, grid,  \
+        DDA_LAUNCH((k_gather_x<T, MODE, LL, xthr(LL)>), grd, dim3(xthr(LL)), smem_ct<C>(LL, 3), s, g, a, grid,  \
                            tw, 1, chk);                                                                        \
         return;
         DDA_CT_LENGTHS(DDA_CASE)
