@@ -46,6 +46,9 @@ WORKLOADS = {
     "au_sphere_nf": ("the guide's near-field example: 48^3-box gold pseudosphere (N=59728), m=0.96+1.01i, x=5, "
                      "GKDLDR, BiCGSTAB to 1e-5, FFT grid 96^3; then E on the 96^3 volume grown by half the box on "
                      "every side (FFT grid 192^3), timed separately", "fp64"),
+    "twomat40": ("40^3 brick, every site occupied, two materials (m=1.5+0.01i or 2.0+0.5i, each with probability "
+                 "1/2), x=6, LATTDR, BiCGSTAB to 1e-5, FFT grid 80^3, incidence +x, polarization y; then the adjoint "
+                 "gradient of Q_abs in the per-site permittivity, timed separately", "fp64"),
     "config3": ("the 48x24x16 brick at 64 orientations x 2 polarizations plus 32 integer-site spheres with radii "
                 "U(6,20) (x=4, m=1.33+0.01i) x 2 polarizations, one batched call, BiCGSTAB to 1e-5", "fp64"),
 }
@@ -102,15 +105,17 @@ def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
     site = 3 * n_sites * 16             # one FP64 site vector
     nbox = nx * ny * nz
     return {
-        # write the x-transformed occupied lines; read on average 2.5 site
-        # vectors and write 1 (p = r + beta(p - omega v) / s = r - alpha v);
-        # the box map once
-        "scatter_fft_x": (Mx * ny * nz * g + 3.5 * site, 4 * nbox),
+        # write the x-transformed occupied lines; the two BiCGSTAB scatters
+        # read on average 4 site vectors and write 2 (r, p, v, x, t -> r, p,
+        # x: the previous iteration's x += alpha p + omega s, r = s - omega t,
+        # then p = r + beta(p - omega v); r, v, rhat -> r: s = r - alpha v
+        # with <rhat, s>); the box map once
+        "scatter_fft_x": (Mx * ny * nz * g + 6 * site, 4 * nbox),
         "fft_y_fwd": (Mx * ny * nz * g + Mx * My * nz * g, 0),
         "fft_z_green": (2 * Mx * My * nz * g, Hx * Hy * Hz * 6 * csize),
         "fft_y_inv": (Mx * My * nz * g + Mx * ny * nz * g, 0),
-        # read the x lines, the input and one more site vector, write the
-        # output; the box map and materials once
+        # read the x lines, the input and one more site vector (rhat), write
+        # the output; the box map and materials once
         "fft_x_gather": (Mx * ny * nz * g + 3 * site, 4 * nbox + 4 * n_sites),
     }
 
@@ -493,6 +498,37 @@ def nearfield_measurement(dda, np, torch, job, d, reps: int = 10, cpu: bool = Tr
     return out
 
 
+def adjoint_measurement(dda, np, torch, job, reps: int = 5) -> dict:
+    """dda_grad_eps on the workload's solution: wall time of one gradient of
+    Q_abs in the per-site permittivity (the adjoint right-hand side, one
+    solve with the same product, the gradient kernel), and of the forward
+    solve and gradient together (one value-and-gradient evaluation)."""
+    t, o, kh, e0 = job
+    kh1, e01 = kh[:1], e0[:1]
+    P, res = dda.solve(t, o, kh1, e01)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, r
+
+    ms_grad, (g, adj) = timed(lambda: dda.grad_eps(t, o, kh1, e01, P[0], 1.0, 0.0))
+
+    def value_and_grad():
+        Pv, _ = dda.solve(t, o, kh1, e01)
+        return dda.grad_eps(t, o, kh1, e01, Pv[0], 1.0, 0.0)
+    ms_both, _ = timed(value_and_grad)
+    return {"grad_ms": ms_grad, "value_and_grad_ms": ms_both, "forward_iters": res[0]["iters"],
+            "adjoint_iters": adj["iters"], "adjoint_rel_residual": adj["rel_residual"],
+            "grad_norm": float(torch.linalg.vector_norm(g).item()),
+            "note": "wall time per call; grad_ms: adjoint right-hand side, adjoint solve and gradient kernel on a "
+                    "kept solution; value_and_grad_ms: the forward solve and the gradient"}
+
+
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 
 
@@ -500,9 +536,11 @@ def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
     """dda_scattering_averages (Gauss-Legendre 48 x 64 directions, both
     polarizations) and dda_far_field on 74 directions, on the workload's
     solution.  The kernel's work is one term per (direction, site, right-hand
-    side): a phase k n.r (5 flops), its sincos, and three complex
-    multiply-adds (24 flops); the rate is quoted as terms/s and as the 29
-    flops/term against the FP64 vector peak (the sincos not counted)."""
+    side): three complex multiply-adds (24 flops), plus the site's phase
+    factor w_x w_y w_z (two complex products, 12 flops) shared by the
+    right-hand sides taken together (two at a time); the rate is quoted as
+    terms/s and as flops against the FP64 vector peak (the per-direction
+    sincos of the factor table not counted)."""
     t, o, kh, e0 = job
     P, _ = dda.solve(t, o, kh, e0)
     n_rhs, n_sites = P.shape[0], P.shape[1]
@@ -521,12 +559,14 @@ def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
     ms_avg = timed(lambda: dda.scattering_averages(t, o, kh, e0, P, n_theta, n_phi))
     ms_ff = timed(lambda: dda.far_field(t, o, P, nh, th, ph))
     terms = float(n_theta * n_phi) * n_sites * n_rhs
-    tflops = 29.0 * terms / (ms_avg * 1e-3) / 1e12
+    flops_per_term = 24.0 + 12.0 / min(2, n_rhs)
+    tflops = flops_per_term * terms / (ms_avg * 1e-3) / 1e12
     return {"averages_ms": ms_avg, "directions": n_theta * n_phi, "far_field_74_dirs_ms": ms_ff,
-            "terms_per_s": terms / (ms_avg * 1e-3), "bound": "alu", "achieved_tflops": tflops,
+            "terms_per_s": terms / (ms_avg * 1e-3), "flops_per_term": flops_per_term, "bound": "alu",
+            "achieved_tflops": tflops,
             "peak_tflops": FP64_VALU_PEAK_TFLOPS, "frac": tflops / FP64_VALU_PEAK_TFLOPS,
             "note": "wall time per call, both polarizations, host quadrature weights and result copies included; "
-                    "flops exclude the sincos of each term"}
+                    "flops exclude the sincos of the per-direction factor table"}
 
 
 def plain_reference(dda, np, torch, jobs, results, ms_per_step):
@@ -753,6 +793,9 @@ def main():
     if len(jobs) == 1 and jobs[0][0].n_sites <= 100_000:
         log("timing the far field and the averages over scattering directions ...")
         out["farfield"] = farfield_measurement(dda, np, torch, jobs[0])
+    if args.workload == "twomat40":
+        log("timing the adjoint gradient on the solution ...")
+        out["adjoint"] = adjoint_measurement(dda, np, torch, jobs[0])
     if "nf_ext" in d:
         log("timing the near field on the solution ...")
         out["nearfield"] = nearfield_measurement(dda, np, torch, jobs[0], d, cpu=not args.no_cpu_baseline)

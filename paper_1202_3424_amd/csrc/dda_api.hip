@@ -564,6 +564,21 @@ void fetch_state(dda_ctx* c, Work& w) {
     flush_timing(c);
 }
 
+// x <- the solution of the iterations so far: QMR's smoothed iterate, or
+// BiCGSTAB's x and r with the end of the latest iteration applied
+// (idempotent; nothing for BiCGstab(2)).
+void settle_solution(Work& w) {
+    if (w.b2) return;
+    Timed tm(w.c, T_KRYLOV, w.s);
+    if (w.qmr) {
+        launch_qmr_final(w.a, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_QFINAL, 0, w.s);
+    } else {
+        launch_bicg_flush(w.a, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_FLUSH, 0, w.s);
+    }
+}
+
 // BiCGSTAB iterations until no right-hand side is active (the device keeps
 // every scalar and status; the host polls once per chunk of iterations).
 // After a status copy: restart broken-down right-hand sides (once); true if
@@ -577,6 +592,7 @@ bool any_active_after_restart(Work& w) {
         if (!w.qmr && st.status == ST_BREAKDOWN && st.restarts == 0) restart = true;
     }
     if (restart) {
+        settle_solution(w);   // the restart starts from r = s - omega t
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_restart(w.a, w.site_blocks, w.s);
         launch_finalize(w.a, FIN_RESTART, w.site_blocks, w.s);
@@ -615,12 +631,11 @@ void launch_chunk(Work& w, int chunk) {
         HIPCHK(hipGetLastError());
         return;
     }
+    // BiCGSTAB: the end of each iteration (x and r) is applied by the next
+    // iteration's first scatter, or by settle_solution once it has stopped
     for (int k = 0; k < chunk; ++k) {
         w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
         w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
-        Timed tm(w.c, T_KRYLOV, w.s);
-        launch_update(w.a, w.site_blocks, w.s);
-        launch_finalize(w.a, FIN_UPD, w.site_blocks, w.s);
     }
     HIPCHK(hipGetLastError());
 }
@@ -758,17 +773,9 @@ void start_iteration(Work& w, const dda_opts* o, bool warm) {
 
 // FP64 residual r = b - A x of every converged right-hand side; those that
 // miss the tolerance iterate on from x (FP32-matvec mode).
-// x <- QMR's smoothed iterate (idempotent; nothing for BiCGSTAB).
-void qmr_solution(Work& w) {
-    if (!w.qmr) return;
-    Timed tm(w.c, T_KRYLOV, w.s);
-    launch_qmr_final(w.a, w.site_blocks, w.s);
-    launch_finalize(w.a, FIN_QFINAL, 0, w.s);
-}
-
 void launch_refinement(Work& w) {
+    settle_solution(w);
     if (w.qmr) {
-        qmr_solution(w);
         w.a.in = w.a.x;
         w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
         Timed tm(w.c, T_KRYLOV, w.s);
@@ -801,7 +808,7 @@ void iterate(Work& w, const dda_opts* o, bool warm) {
             iterate_loop(w, o);
         }
     }
-    qmr_solution(w);
+    settle_solution(w);
 }
 
 // true residual, eq. err_tol and the efficiency sums at x
@@ -1014,7 +1021,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
     };
     auto finish = [&](Job& j) {
         Work& w = *j.w;
-        qmr_solution(w);
+        settle_solution(w);
         final_checks(w, (j.o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0);
         {
             Timed tm(c, T_SETUP, w.s);

@@ -53,6 +53,7 @@ struct RhsState {
     double w_new;
     double2 g1;      // BiCGstab(2): minimal-residual coefficients of r_1 and r_2
     double2 g2;
+    double2 rs;      // BiCGSTAB: <rhat, s> of the latest half step
     double red[8];   // end-of-solve reductions (see kernels)
     int status;
     int iters;
@@ -61,7 +62,11 @@ struct RhsState {
     int max_iter;
     int restarts;
     int pad0;        // FP64 residual refinements taken (FP32-matvec mode)
-    int pend;        // QMR: the smoothing step (w_old, w_new) has not been applied yet
+    // QMR: the smoothing step (w_old, w_new) has not been applied yet.
+    // BiCGSTAB: the end of the latest iteration has not been applied to x
+    // and r yet (1: x += alpha p + omega s, r = s - omega t; 2: x += alpha p,
+    // after a half-step convergence)
+    int pend;
 };
 
 template <typename T> struct V2;

@@ -81,7 +81,10 @@ enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4, GA_
 enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
 // what k_finalize makes of the partial sums of the kernel before it
 enum FinKind {
-    FIN_S = 0, FIN_V, FIN_T, FIN_UPD, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE,
+    // BiCGSTAB: |s|^2 and <rhat, s> after the half step; alpha after the
+    // first product; omega, rho, beta and the status after the second; the
+    // pending flag cleared after k_bicg_flush
+    FIN_S = 0, FIN_V, FIN_T, FIN_FLUSH, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE,
     // QMR: after the product (alpha), after the update (smoothing, beta,
     // status), after the cold / warm start, after an FP64 refinement residual
     // and after k_qmr_final (clears the pending smoothing step)
@@ -129,7 +132,8 @@ void launch_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, 
 void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s);
 void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s);
-void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s);
+// BiCGSTAB: apply the pending end of the latest iteration to x and r
+void launch_bicg_flush(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s);
 // QMR: start (cold: r = b, x = 0; warm: r holds b - A x), update, and the
 // pending smoothing step applied to x (x <- the smoothed iterate)

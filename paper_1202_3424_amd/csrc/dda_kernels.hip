@@ -218,34 +218,27 @@ __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
     publish_partial<2>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
-// End of a BiCGSTAB iteration: x += alpha p + omega s, r = s - omega t (or,
-// after a half-step convergence, x += alpha p, r = s); rho = <rhat, r>,
-// beta for the next direction, convergence |r|^2 <= tol^2 |b|^2.
-__global__ __launch_bounds__(NT) void k_update(SiteArgs a) {
-    __shared__ double sh[8 * NT / 64];
+// The end of the latest BiCGSTAB iteration, where still pending (see
+// RhsState::pend): x += alpha p + omega s, r = s - omega t, or x += alpha p
+// after a half-step convergence.  During the iteration the next pass-1
+// scatter applies it; this kernel applies it once the iteration has
+// stopped, or before a restart.  A FIN_FLUSH finalize then clears the flag.
+__global__ __launch_bounds__(NT) void k_bicg_flush(SiteArgs a) {
     const int q = blockIdx.y;
     const RhsState* st = a.st + q;
-    if (st->status != ST_ACTIVE) return;
-    const int sconv = st->sconv;
+    const int pend = st->pend;
+    if (pend == 0) return;
     const double2 alpha = st->alpha, omega = st->omega;
     const long long vb = (long long)q * a.n3;
-    double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
         const double2 s = a.r[vb + i];
         double2 xx = cadd(a.x[vb + i], cmul(alpha, a.p[vb + i]));
-        double2 rr = s;
-        if (!sconv) {
+        if (pend == 1) {
             xx = cadd(xx, cmul(omega, s));
-            rr = csub(s, cmul(omega, a.t[vb + i]));
-            a.r[vb + i] = rr;
+            a.r[vb + i] = csub(s, cmul(omega, a.t[vb + i]));
         }
         a.x[vb + i] = xx;
-        const double2 w = cdotc(a.rhat[vb + i], rr);
-        acc[0] += w.x;
-        acc[1] += w.y;
-        acc[2] += rr.x * rr.x + rr.y * rr.y;
     }
-    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // One restart after a breakdown: rhat = r, p = v = 0, rho = |r|^2.
@@ -593,7 +586,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     const double* part = a.partials + (long long)q * a.maxblk * PSTRIDE;
     bool run;
     switch (kind) {
-        case FIN_S: case FIN_V: case FIN_UPD: run = st->status == ST_ACTIVE; break;
+        case FIN_S: case FIN_V: run = st->status == ST_ACTIVE; break;
         case FIN_T: run = st->status == ST_ACTIVE && !st->sconv; break;
         case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
         case FIN_REFINE: case FIN_QREFINE: run = st->status == ST_CONVERGED; break;
@@ -607,6 +600,10 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (kind == FIN_B_MR) {
         sum_partials<8>(acc, part, nblk, sh);
+    } else if (kind == FIN_T) {
+        double a5[5];
+        sum_partials<5>(a5, part, nblk, sh);
+        for (int i = 0; i < 5; ++i) acc[i] = a5[i];
     } else if (four) {
         double a4[4];
         sum_partials<4>(a4, part, nblk, sh);
@@ -620,13 +617,26 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     }
     if (threadIdx.x != 0) return;
     switch (kind) {
-        case FIN_S:
+        case FIN_S: {
+            // |s|^2 and <rhat, s>; a half-step convergence ends the
+            // iteration with x += alpha p pending
+            const double2 rs = {acc[1], acc[2]};
             st->snorm2 = acc[0];
-            if (!isfinite(acc[0])) st->status = ST_NONFINITE;
-            else st->sconv = (acc[0] <= st->tol2 * st->bnorm2) ? 1 : 0;
+            st->rs = rs;
+            if (!isfinite(acc[0]) || !finite2(rs)) {
+                st->status = ST_NONFINITE;
+            } else if (acc[0] <= st->tol2 * st->bnorm2) {
+                st->sconv = 1;
+                st->iters += 1;
+                st->rnorm2 = acc[0];
+                st->pend = 2;
+                st->status = ST_CONVERGED;
+            }
             break;
+        }
         case FIN_V: {
             const double2 rv = {acc[0], acc[1]};
+            st->pend = 0;   // the scatter before this product applied it
             st->matvecs += 1;
             if (!finite2(rv)) st->status = ST_NONFINITE;
             else if (rv.x == 0.0 && rv.y == 0.0) st->status = ST_BREAKDOWN;
@@ -634,21 +644,27 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             break;
         }
         case FIN_T: {
-            const double2 ts = {acc[0], acc[1]};
+            // omega = <t, s> / |t|^2, and the end of the iteration from the
+            // sums alone (r = s - omega t itself is formed later, by the
+            // next scatter or the flush): rho' = <rhat, r> = <rhat, s> -
+            // omega <rhat, t>, and |r|^2 = |s|^2 - |<t, s>|^2 / |t|^2 since
+            // omega t is the projection of s on t
+            const double2 ts = {acc[0], acc[1]}, rt = {acc[3], acc[4]};
+            const double tt = acc[2];
             st->matvecs += 1;
-            if (!finite2(ts) || !isfinite(acc[2])) st->status = ST_NONFINITE;
-            else if (acc[2] == 0.0) st->omega = double2{0.0, 0.0};
-            else st->omega = double2{ts.x / acc[2], ts.y / acc[2]};
-            break;
-        }
-        case FIN_UPD: {
-            const double2 alpha = st->alpha, omega = st->omega;
-            st->iters += 1;
-            st->rnorm2 = acc[2];
-            const double2 rho_new = {acc[0], acc[1]};
-            if (!isfinite(acc[2]) || !finite2(rho_new)) {
+            if (!finite2(ts) || !isfinite(tt) || !finite2(rt)) {
                 st->status = ST_NONFINITE;
-            } else if (st->sconv || acc[2] <= st->tol2 * st->bnorm2) {
+                break;
+            }
+            const double2 alpha = st->alpha;
+            const double2 omega = tt == 0.0 ? double2{0.0, 0.0} : double2{ts.x / tt, ts.y / tt};
+            const double2 rho_new = csub(st->rs, cmul(omega, rt));
+            const double r2 = tt == 0.0 ? st->snorm2 : fmax(st->snorm2 - (ts.x * ts.x + ts.y * ts.y) / tt, 0.0);
+            st->omega = omega;
+            st->iters += 1;
+            st->rnorm2 = r2;
+            st->pend = 1;
+            if (r2 <= st->tol2 * st->bnorm2) {
                 st->status = ST_CONVERGED;
             } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) || (omega.x == 0.0 && omega.y == 0.0)) {
                 st->status = ST_BREAKDOWN;
@@ -659,6 +675,9 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
             break;
         }
+        case FIN_FLUSH:
+            st->pend = 0;
+            break;
         case FIN_COLD:
             st->bnorm2 = acc[0];
             st->rnorm2 = acc[0];
@@ -669,6 +688,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             st->iters = 0;
             st->matvecs = 0;
             st->sconv = 0;
+            st->pend = 0;
             st->restarts = 0;
             st->status = isfinite(acc[0]) ? (acc[0] > 0.0 ? ST_ACTIVE : ST_CONVERGED) : ST_NONFINITE;
             break;
@@ -682,6 +702,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             st->iters = 0;
             st->matvecs = 1;
             st->sconv = 0;
+            st->pend = 0;
             st->restarts = 0;
             if (!isfinite(acc[0]) || !isfinite(acc[1])) st->status = ST_NONFINITE;
             else st->status = (acc[0] <= st->tol2 * acc[1]) ? ST_CONVERGED : ST_ACTIVE;
@@ -692,6 +713,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             st->omega = double2{1.0, 0.0};
             st->beta = double2{0.0, 0.0};
             st->sconv = 0;
+            st->pend = 0;
             st->restarts += 1;
             st->status = (acc[0] > 0.0 && isfinite(acc[0])) ? ST_ACTIVE : ST_BREAKDOWN;
             break;
@@ -707,6 +729,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                 st->omega = double2{1.0, 0.0};
                 st->beta = double2{0.0, 0.0};
                 st->sconv = 0;
+                st->pend = 0;
                 st->pad0 += 1;
                 st->status = st->iters >= st->max_iter ? ST_MAXITER : ST_ACTIVE;
             }
@@ -1007,8 +1030,8 @@ void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s) {
 void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_init_warm, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
-void launch_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
+void launch_bicg_flush(const SiteArgs& a, int site_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_flush, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
 void launch_restart(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_restart, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);

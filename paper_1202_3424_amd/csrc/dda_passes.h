@@ -119,14 +119,15 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
     }
     double2 beta = {0, 0}, omega = {0, 0}, alpha = {0, 0};
     double w_old = 0.0, w_new = 0.0;
-    if (MODE == SC_P) { beta = st->beta; omega = st->omega; }
+    int pend = 0;
+    if (MODE == SC_P) { beta = st->beta; omega = st->omega; alpha = st->alpha; pend = st->pend; }
     if (MODE == SC_S) alpha = st->alpha;
     if (MODE == SC_Q) { beta = st->beta; w_old = st->w_old; w_new = st->w_new; }
     if (MODE == SC_B0 || MODE == SC_B2) beta = st->beta;
     if (MODE == SC_B1 || MODE == SC_B3) alpha = st->alpha;
     const long long vb = (long long)q * a.n3;
     const int* mrow = a.map + ((long long)z * ny + y0) * nx;
-    double ss = 0.0;
+    double ss[3] = {0.0, 0.0, 0.0};
     // forward transform of a line that is zero beyond nx: with 2 nx <= Mx the
     // first radix pass never reads the upper half, which is then not filled
     bool hin = false;
@@ -151,8 +152,17 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
                 } else if (MODE == SC_CONJ) {
                     u = cconj(a.in[i]);
                 } else if (MODE == SC_P) {
+                    // the previous iteration's end, if pending: x += alpha p
+                    // + omega s, r = s - omega t (s is held in r); then
                     // p = r + beta (p - omega v)
-                    u = cadd(a.r[i], cmul(beta, csub(a.p[i], cmul(omega, a.v[i]))));
+                    double2 rr = a.r[i];
+                    const double2 pp = a.p[i];
+                    if (pend) {
+                        a.x[i] = cadd(cadd(a.x[i], cmul(alpha, pp)), cmul(omega, rr));
+                        rr = csub(rr, cmul(omega, a.t[i]));
+                        a.r[i] = rr;
+                    }
+                    u = cadd(rr, cmul(beta, csub(pp, cmul(omega, a.v[i]))));
                     a.p[i] = u;
                 } else if (MODE == SC_B0) {
                     // BiCGstab(2), first BiCG step: u_0 = r_0 - beta u_0
@@ -184,10 +194,13 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
                     a.rhat[i] = double2{w_old * sm.x + w_new * rr.x, w_old * sm.y + w_new * rr.y};
                     a.t[i] = double2{w_old * ym.x + w_new * xx.x, w_old * ym.y + w_new * xx.y};
                 } else {
-                    // s = r - alpha v, stored over r
+                    // s = r - alpha v, stored over r; |s|^2 and <rhat, s>
                     u = csub(a.r[i], cmul(alpha, a.v[i]));
                     a.r[i] = u;
-                    ss += u.x * u.x + u.y * u.y;
+                    const double2 w = cdotc(a.rhat[i], u);
+                    ss[0] += u.x * u.x + u.y * u.y;
+                    ss[1] += w.x;
+                    ss[2] += w.y;
                 }
                 val = to_c<C>(u);
             }
@@ -211,10 +224,9 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         gq[idx] = lds[(yo * 3 + c) * Lp + e];
     }
     if (MODE == SC_S) {
-        double v[1] = {ss};
         double* sh = (double*)(lds + nlines * Lp);
         const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        publish_partial<1, NTHR>(v, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        publish_partial<3, NTHR>(ss, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
     }
 }
 
@@ -304,10 +316,13 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             acc[1] += w.y;
         } else if (MODE == GA_T) {
             a.t[i] = y;
-            const double2 w = cdotc(y, xin);   // <t, s>
+            const double2 w = cdotc(y, xin);          // <t, s>
+            const double2 wr = cdotc(a.rhat[i], y);   // <rhat, t>
             acc[0] += w.x;
             acc[1] += w.y;
             acc[2] += y.x * y.x + y.y * y.y;
+            acc[3] += wr.x;
+            acc[4] += wr.y;
         } else if (MODE == GA_Q) {
             a.v[i] = y;
             acc[0] += xin.x * y.x - xin.y * y.y;   // p^T v (bilinear)
@@ -344,6 +359,9 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         const int blk = blockIdx.y * gridDim.x + blockIdx.x;
         if constexpr (MODE == GA_B3) {
             publish_partial<8, NTHR>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        } else if constexpr (MODE == GA_T) {
+            double a5[5] = {acc[0], acc[1], acc[2], acc[3], acc[4]};
+            publish_partial<5, NTHR>(a5, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
         } else {
             double a3[3] = {acc[0], acc[1], acc[2]};
             publish_partial<3, NTHR>(a3, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
