@@ -590,10 +590,13 @@ __device__ __forceinline__ void publish_partial(double (&v)[NV], double* partial
 }
 
 // Sum the partials of nblk workgroups in block order; result in thread 0.
+// The loop is unrolled so that several blocks' loads are in flight before
+// the first add (the adds keep their order).
 template <int NV>
 __device__ __forceinline__ void sum_partials(double (&acc)[NV], const double* partials, int nblk, double* sh) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+#pragma unroll 8
     for (int b = threadIdx.x; b < nblk; b += NT) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[i] += partials[(long)b * PSTRIDE + i];
