@@ -509,7 +509,44 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
                 fft_lines<T, -1>(lds, tws, nlines, Lp, pl);
             }
             // y_a = sum_b Ghat_ab x_b at (kx, ky = o, kz)
-            if constexpr (CT) {
+            if constexpr (CT && VAR != 0) {
+                // kz and L - kz share the stored tensor entry; the xz and yz
+                // components change sign between them (odd in z).  One
+                // thread takes both points of a pair from one read: the
+                // pairs (h, L - h) for 0 < h < L / 2, and h = 0 and h = L / 2
+                // alone.
+                constexpr int UNITS = TXC * (LC / 2 + 1);
+#pragma unroll
+                for (int i = 0; i < (UNITS + NT - 1) / NT; ++i) {
+                    const int u = threadIdx.x + i * NT;
+                    const int xo = u % TX;
+                    const int h = u / TX;
+                    if (u < UNITS && xo < nxl) {
+                        C Gl[6];
+                        tensor_at(xo, h, Gl);
+                        C* px = lds + (xo * 3 + 0) * Lp;
+                        C* py = lds + (xo * 3 + 1) * Lp;
+                        C* pz = lds + (xo * 3 + 2) * Lp;
+                        {
+                            const C X = px[h], Y = py[h], Z = pz[h];
+                            px[h] = trow(Gl[0], Gl[1], Gl[2], X, Y, Z);
+                            py[h] = trow(Gl[1], Gl[3], Gl[4], X, Y, Z);
+                            pz[h] = trow(Gl[2], Gl[4], Gl[5], X, Y, Z);
+                        }
+                        if (h > 0 && 2 * h < LC) {
+                            const int m = LC - h;
+                            Gl[2].x = -Gl[2].x;
+                            Gl[2].y = -Gl[2].y;
+                            Gl[4].x = -Gl[4].x;
+                            Gl[4].y = -Gl[4].y;
+                            const C X = px[m], Y = py[m], Z = pz[m];
+                            px[m] = trow(Gl[0], Gl[1], Gl[2], X, Y, Z);
+                            py[m] = trow(Gl[1], Gl[3], Gl[4], X, Y, Z);
+                            pz[m] = trow(Gl[2], Gl[4], Gl[5], X, Y, Z);
+                        }
+                    }
+                }
+            } else if constexpr (CT) {
 #pragma unroll
                 for (int i = 0; i < MAXP; ++i) {
                     const int p = threadIdx.x + i * NT;
