@@ -259,6 +259,21 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         lds = tws + even_up(Mx);
         load_twiddles<T, NTHR>(tws, tw64, g.ax[0]);
     }
+    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    const int tout = nl * nx * 3;
+    // compile-time lengths (one line per workgroup): the site index and
+    // material of each element this thread gathers are loaded before the
+    // transform, so only the operand loads follow it (e < nx <= (L + 1) / 2
+    // since L >= 2 nx - 1)
+    constexpr int PF = CT ? (3 * ((LC + 1) / 2) + NTHR - 1) / NTHR : 1;
+    int ps[PF], pm[PF];
+    if constexpr (CT) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            ps[k] = idx < tout ? mrow[idx / 3] : -1;
+        }
+    }
     const C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
     const int tot = nl * Mx * 3;
     for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
@@ -267,6 +282,10 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         const int e = rest % Mx;
         const int yo = rest / Mx;
         lds[(yo * 3 + c) * Lp + e] = gq[idx];
+    }
+    if constexpr (CT) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) pm[k] = ps[k] >= 0 ? a.mat[ps[k]] : 0;
     }
     __syncthreads();
     if constexpr (CT) {
@@ -278,20 +297,13 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
     }
 
     const long long vb = (long long)q * a.n3;
-    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
     const double2* ai = a.ainv + (long long)q * a.nmat * 3;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const int tout = nl * nx * 3;
-    for (int idx = threadIdx.x; idx < tout; idx += NTHR) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % nx;
-        const int yo = rest / nx;
-        const int s = mrow[yo * nx + e];
-        if (s < 0) continue;
+    // element (line yo, point e, component c) at site s of material mt
+    auto site = [&](int c, int e, int yo, int s, int mt) {
         const long long i = vb + (long long)s * 3 + c;
         const double2 gv = to_d(lds[(yo * 3 + c) * Lp + e]);
-        const double2 d = ai[a.mat[s] * 3 + c];
+        const double2 d = ai[mt * 3 + c];
         double2 xin;
         if (MODE == GA_PLAIN) xin = a.in[i];
         if (MODE == GA_CONJ) xin = cconj(a.in[i]);
@@ -352,6 +364,22 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             const double2 rr = csub(a.b[i], y);
             a.r[i] = rr;
             acc[0] += rr.x * rr.x + rr.y * rr.y;
+        }
+    };
+    if constexpr (CT) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            if (idx < tout && ps[k] >= 0) site(idx % 3, idx / 3, 0, ps[k], pm[k]);
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < tout; idx += NTHR) {
+            const int c = idx % 3;
+            const int rest = idx / 3;
+            const int e = rest % nx;
+            const int yo = rest / nx;
+            const int s = mrow[yo * nx + e];
+            if (s >= 0) site(c, e, yo, s, a.mat[s]);
         }
     }
     if (MODE != GA_PLAIN) {
