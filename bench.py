@@ -91,7 +91,20 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
+# FP64 site vectors (read + written) per scatter and per gather, averaged
+# over the modes one iteration of each solver uses.  BiCGSTAB: the scatter
+# of p reads r, p, v, x, t and writes r, p, x (the previous iteration's
+# x += alpha p + omega s, r = s - omega t, then p = r + beta(p - omega v));
+# the scatter of s = r - alpha v reads r, v, rhat and writes r; each gather
+# reads its input and rhat and writes its output.  QMR: the scatter reads r,
+# p and the smoothed pair (s, y) and x, and writes p, s, y; the gather reads
+# p and writes v.  BiCGstab(2): 3, 6, 6 and 9 vectors in the four scatters,
+# 3 in every gather.  The plain product (near field): its input, and input
+# plus output.
+SITE_VECTORS = {"bicgstab": (6, 3), "qmr": (8, 2), "bicgstab2": (6, 3), "plain": (1, 2)}
+
+
+def pass_bytes(tgt, n_sites: int, csize: int, solver: str = "bicgstab") -> dict:
     """Algorithmic HBM bytes of each matvec pass: one read and one write of
     exactly the data the pruned pass needs.  Returns {pass: (per right-hand
     side, once per launch)}: the grids and site vectors belong to each
@@ -104,19 +117,17 @@ def pass_bytes(tgt, n_sites: int, csize: int) -> dict:
     g = 3 * csize                       # three components per grid point
     site = 3 * n_sites * 16             # one FP64 site vector
     nbox = nx * ny * nz
+    sv_scatter, sv_gather = SITE_VECTORS[solver]
     return {
-        # write the x-transformed occupied lines; the two BiCGSTAB scatters
-        # read on average 4 site vectors and write 2 (r, p, v, x, t -> r, p,
-        # x: the previous iteration's x += alpha p + omega s, r = s - omega t,
-        # then p = r + beta(p - omega v); r, v, rhat -> r: s = r - alpha v
-        # with <rhat, s>); the box map once
-        "scatter_fft_x": (Mx * ny * nz * g + 6 * site, 4 * nbox),
+        # write the x-transformed occupied lines; the solver's site vectors;
+        # the box map once
+        "scatter_fft_x": (Mx * ny * nz * g + sv_scatter * site, 4 * nbox),
         "fft_y_fwd": (Mx * ny * nz * g + Mx * My * nz * g, 0),
         "fft_z_green": (2 * Mx * My * nz * g, Hx * Hy * Hz * 6 * csize),
         "fft_y_inv": (Mx * My * nz * g + Mx * ny * nz * g, 0),
-        # read the x lines, the input and one more site vector (rhat), write
-        # the output; the box map and materials once
-        "fft_x_gather": (Mx * ny * nz * g + 3 * site, 4 * nbox + 4 * n_sites),
+        # read the x lines and the solver's site vectors; the box map and
+        # materials once
+        "fft_x_gather": (Mx * ny * nz * g + sv_gather * site, 4 * nbox + 4 * n_sites),
     }
 
 
@@ -467,7 +478,7 @@ def nearfield_measurement(dda, np, torch, job, d, reps: int = 10, cpu: bool = Tr
     class Vol:   # the grown volume as the product sees it: every point a site
         box = tuple(int(v) for v in dims)
         grid = tuple(padded(int(v)) for v in dims)
-    bp = pass_bytes(Vol, npts, 16)
+    bp = pass_bytes(Vol, npts, 16, "plain")
     passes = {}
     for name in PASSES:
         pms, nl, _ = tm[name]
@@ -686,7 +697,7 @@ def main():
         return out
 
     csize = 8 if prec == "fp32_matvec" else 16
-    bpus = [pass_bytes(j[0], j[0].n_sites, csize) for j in jobs]
+    bpus = [pass_bytes(j[0], j[0].n_sites, csize, args.solver) for j in jobs]
 
     def pass_traffic(name, units, launches):
         # per-RHS bytes times the RHS-matvecs each job executed, plus the
