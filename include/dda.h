@@ -71,7 +71,11 @@ typedef enum { DDA_LATTDR = 0, DDA_GKDLDR = 1 } dda_polarizability;
 
 /* Iterative method ("Choice of Iterative Algorithm"):
  *   DDA_BICGSTAB  PBCGST: BiCGSTAB (van der Vorst 1992), two products per
- *                 iteration; one automatic restart after a breakdown.
+ *                 iteration; stops when the recursive residual satisfies
+ *                 |r| / |E| < tol, checked after the half step (|s|) and
+ *                 after the iteration (|r|^2 = |s|^2 - |<t,s>|^2 / |t|^2, the
+ *                 norm of s - omega t); one automatic restart after a
+ *                 breakdown.
  *   DDA_QMR_SYM   QMRCCG: QMR for complex-symmetric A, read as COCG (van der
  *                 Vorst & Melissen 1990) with quasi-minimal-residual smoothing
  *                 (Zhou & Walker 1994); one product per iteration; stops on
