@@ -485,10 +485,6 @@ struct Work {
             Timed tm(c, T_SCATTER, s);
             launch_scatter_x<T>(sc, chk_sc, g, a, gr, tw, s);
         }
-        if (sc == SC_S) {
-            Timed tm(c, T_KRYLOV, s);
-            launch_finalize(a, FIN_S, pass_blocks, s);
-        }
         {
             Timed tm(c, T_FFTY_FWD, s);
             strided_slot<T>(0, chk_rest, vars[0]);
@@ -635,7 +631,7 @@ void launch_chunk(Work& w, int chunk) {
     // iteration's first scatter, or by settle_solution once it has stopped
     for (int k = 0; k < chunk; ++k) {
         w.matvec(SC_P, GA_V, CHK_ACTIVE, CHK_ACTIVE);
-        w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE_NOT_SCONV);
+        w.matvec(SC_S, GA_T, CHK_ACTIVE, CHK_ACTIVE);
     }
     HIPCHK(hipGetLastError());
 }

@@ -578,14 +578,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 // Doubles of partial sums per workgroup and right-hand side.
 constexpr int PSTRIDE = 8;
 
-// This workgroup's sums go to partials[blk * PSTRIDE + i] (no atomics, no
-// fences: the consumer is a later kernel on the same stream).
-template <int NV, int NTHR = NT>
+// This workgroup's sums go to partials[blk * PSTRIDE + OFF + i] (no atomics,
+// no fences: the consumer is a later kernel on the same stream).  Two
+// kernels with the same grid may fill disjoint slots of one block entry.
+template <int NV, int NTHR = NT, int OFF = 0>
 __device__ __forceinline__ void publish_partial(double (&v)[NV], double* partials, int blk, double* sh) {
+    static_assert(OFF + NV <= PSTRIDE, "partial slots");
     block_sum<NV, NTHR>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) partials[(long)blk * PSTRIDE + i] = v[i];
+        for (int i = 0; i < NV; ++i) partials[(long)blk * PSTRIDE + OFF + i] = v[i];
     }
 }
 

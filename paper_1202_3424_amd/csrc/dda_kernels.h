@@ -78,13 +78,13 @@ struct SiteArgs {
 enum ScatterMode { SC_PLAIN = 0, SC_CONJ = 1, SC_P = 2, SC_S = 3, SC_Q = 4, SC_B0 = 5, SC_B1 = 6, SC_B2 = 7, SC_B3 = 8 };
 enum GatherMode { GA_PLAIN = 0, GA_CONJ = 1, GA_V = 2, GA_T = 3, GA_RES = 4, GA_Q = 5, GA_B1 = 6, GA_B2 = 7, GA_B3 = 8 };
 // which right-hand sides a pass skips
-enum Check { CHK_NONE = 0, CHK_ACTIVE = 1, CHK_ACTIVE_NOT_SCONV = 2 };
+enum Check { CHK_NONE = 0, CHK_ACTIVE = 1 };
 // what k_finalize makes of the partial sums of the kernel before it
 enum FinKind {
-    // BiCGSTAB: |s|^2 and <rhat, s> after the half step; alpha after the
-    // first product; omega, rho, beta and the status after the second; the
-    // pending flag cleared after k_bicg_flush
-    FIN_S = 0, FIN_V, FIN_T, FIN_FLUSH, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE,
+    // BiCGSTAB: alpha after the first product; the half-step check, omega,
+    // rho, beta and the status after the second; the pending flag cleared
+    // after k_bicg_flush
+    FIN_V = 0, FIN_T, FIN_FLUSH, FIN_COLD, FIN_WARM, FIN_RESTART, FIN_QSUM, FIN_RES, FIN_CONJ, FIN_REFINE,
     // QMR: after the product (alpha), after the update (smoothing, beta,
     // status), after the cold / warm start, after an FP64 refinement residual
     // and after k_qmr_final (clears the pending smoothing step)

@@ -586,8 +586,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     const double* part = a.partials + (long long)q * a.maxblk * PSTRIDE;
     bool run;
     switch (kind) {
-        case FIN_S: case FIN_V: run = st->status == ST_ACTIVE; break;
-        case FIN_T: run = st->status == ST_ACTIVE && !st->sconv; break;
+        case FIN_V: case FIN_T: run = st->status == ST_ACTIVE; break;
         case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
         case FIN_REFINE: case FIN_QREFINE: run = st->status == ST_CONVERGED; break;
         case FIN_QV: case FIN_QUPD: case FIN_B_BETA: case FIN_B_MR: case FIN_B_UPD:
@@ -598,12 +597,8 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     if (!run) return;
     const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (kind == FIN_B_MR) {
+    if (kind == FIN_B_MR || kind == FIN_T) {
         sum_partials<8>(acc, part, nblk, sh);
-    } else if (kind == FIN_T) {
-        double a5[5];
-        sum_partials<5>(a5, part, nblk, sh);
-        for (int i = 0; i < 5; ++i) acc[i] = a5[i];
     } else if (four) {
         double a4[4];
         sum_partials<4>(a4, part, nblk, sh);
@@ -617,23 +612,6 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     }
     if (threadIdx.x != 0) return;
     switch (kind) {
-        case FIN_S: {
-            // |s|^2 and <rhat, s>; a half-step convergence ends the
-            // iteration with x += alpha p pending
-            const double2 rs = {acc[1], acc[2]};
-            st->snorm2 = acc[0];
-            st->rs = rs;
-            if (!isfinite(acc[0]) || !finite2(rs)) {
-                st->status = ST_NONFINITE;
-            } else if (acc[0] <= st->tol2 * st->bnorm2) {
-                st->sconv = 1;
-                st->iters += 1;
-                st->rnorm2 = acc[0];
-                st->pend = 2;
-                st->status = ST_CONVERGED;
-            }
-            break;
-        }
         case FIN_V: {
             const double2 rv = {acc[0], acc[1]};
             st->pend = 0;   // the scatter before this product applied it
@@ -644,14 +622,32 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             break;
         }
         case FIN_T: {
-            // omega = <t, s> / |t|^2, and the end of the iteration from the
-            // sums alone (r = s - omega t itself is formed later, by the
-            // next scatter or the flush): rho' = <rhat, r> = <rhat, s> -
-            // omega <rhat, t>, and |r|^2 = |s|^2 - |<t, s>|^2 / |t|^2 since
-            // omega t is the projection of s on t
-            const double2 ts = {acc[0], acc[1]}, rt = {acc[3], acc[4]};
+            // slots 5-7, from the scatter of s: |s|^2 and <rhat, s>.  A
+            // half-step convergence ends the iteration with x += alpha p
+            // pending (the product t = A s is then not used).  Otherwise
+            // omega = <t, s> / |t|^2 from slots 0-4 (the gather of t), and
+            // the end of the iteration from the sums alone (r = s - omega t
+            // itself is formed later, by the next scatter or the flush):
+            // rho' = <rhat, r> = <rhat, s> - omega <rhat, t>, and |r|^2 =
+            // |s|^2 - |<t, s>|^2 / |t|^2 since omega t is the projection of
+            // s on t
+            const double2 ts = {acc[0], acc[1]}, rt = {acc[3], acc[4]}, rs = {acc[6], acc[7]};
             const double tt = acc[2];
             st->matvecs += 1;
+            st->snorm2 = acc[5];
+            st->rs = rs;
+            if (!isfinite(acc[5]) || !finite2(rs)) {
+                st->status = ST_NONFINITE;
+                break;
+            }
+            if (acc[5] <= st->tol2 * st->bnorm2) {
+                st->sconv = 1;
+                st->iters += 1;
+                st->rnorm2 = acc[5];
+                st->pend = 2;
+                st->status = ST_CONVERGED;
+                break;
+            }
             if (!finite2(ts) || !isfinite(tt) || !finite2(rt)) {
                 st->status = ST_NONFINITE;
                 break;

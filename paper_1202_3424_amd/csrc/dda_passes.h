@@ -60,9 +60,7 @@ template <typename C> __device__ __forceinline__ double2 to_d(C u) {
 }
 
 __device__ __forceinline__ bool skip_rhs(const RhsState* st, int chk) {
-    if (chk == CHK_NONE) return false;
-    if (st->status != ST_ACTIVE) return true;
-    return chk == CHK_ACTIVE_NOT_SCONV && st->sconv;
+    return chk != CHK_NONE && st->status != ST_ACTIVE;
 }
 
 // g_a X + g_b Y + g_c Z for one row of the symmetric tensor product, each
@@ -224,9 +222,11 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         gq[idx] = lds[(yo * 3 + c) * Lp + e];
     }
     if (MODE == SC_S) {
+        // slots 5-7 of the block's entry; the gather of t (same grid) fills
+        // slots 0-4 and one finalize reads both
         double* sh = (double*)(lds + nlines * Lp);
         const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-        publish_partial<3, NTHR>(ss, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        publish_partial<3, NTHR, 5>(ss, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
     }
 }
 
