@@ -59,3 +59,22 @@ def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_pass_bytes_count_each_solvers_site_vectors():
+    class Tgt:
+        box = (64, 48, 32)
+        grid = (128, 96, 64)
+    n = 51488
+    site = 3 * n * 16
+    b = {s: bench.pass_bytes(Tgt, n, 16, s) for s in ("bicgstab", "qmr", "bicgstab2", "plain")}
+    lines = 128 * 48 * 32 * 3 * 16            # the x-transformed occupied lines of one RHS
+    for s, (sc, ga) in bench.SITE_VECTORS.items():
+        assert b[s]["scatter_fft_x"][0] == lines + sc * site
+        assert b[s]["fft_x_gather"][0] == lines + ga * site
+        # the strided passes and the shared bytes do not depend on the solver
+        for k in ("fft_y_fwd", "fft_z_green", "fft_y_inv"):
+            assert b[s][k] == b["bicgstab"][k]
+        assert b[s]["scatter_fft_x"][1] == 4 * 64 * 48 * 32
+    # pass 3: forward and inverse grids of every RHS; the tensor octant once per launch
+    assert b["plain"]["fft_z_green"] == (2 * 128 * 96 * 32 * 48, 65 * 49 * 33 * 6 * 16)
