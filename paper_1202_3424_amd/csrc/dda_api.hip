@@ -426,8 +426,10 @@ struct Work {
     // variant of each strided pass by timing every candidate on the workspace
     // grid (its contents are scratch at this point; all variants compute
     // bitwise-identical results), one warm-up and twenty timed launches
-    // each: the lowest-numbered variant within 3% of the fastest, so that
-    // near-ties resolve the same way from run to run.
+    // each.  Among the variants within 3% of the fastest it takes the
+    // lowest-numbered XCD-grouped one of pass 3 if there is one, else the
+    // lowest-numbered: near-ties then resolve the same way from run to run,
+    // and towards the order that reads the tensor from HBM about once.
     void autotune(bool enabled, int forced = 0) {
         const Geo& g = t->geo;
         if (forced > 0) {
@@ -463,8 +465,12 @@ struct Work {
                     HIPCHK(hipEventElapsedTime(&t_ms[v], e0, e1));
                 }
                 const float fastest = *std::min_element(t_ms.begin(), t_ms.end());
-                for (int v = nv - 1; v >= 0; --v)
-                    if (t_ms[v] <= 1.03f * fastest) best[slot] = v;
+                int pick = -1;
+                for (int v = 0; v < nv && pick < 0; ++v)
+                    if (t_ms[v] <= 1.03f * fastest && strided_variant_xcd(L, slot == 1, fp32, v)) pick = v;
+                for (int v = 0; v < nv && pick < 0; ++v)
+                    if (t_ms[v] <= 1.03f * fastest) pick = v;
+                best[slot] = pick < 0 ? 0 : pick;
             }
             HIPCHK(hipGetLastError());
             c->evpool.push_back(e0);
