@@ -166,7 +166,9 @@ def test_worked_example_on_gpu(dda):
 
 def test_solve_full_size_ellipsoid_vs_oracle(dda):
     """The 51,488-site ellipsoid at tol 1e-5 (the benchmark workload):
-    Q within 1e-4 of the oracle's FFT-BiCGSTAB, P close at sampled sites."""
+    Q within 1e-4 of the oracle's FFT-BiCGSTAB, P close at sampled sites;
+    the iteration count within one of the oracle's at the same tolerance,
+    two products per iteration (a half-step convergence included)."""
     d = w.workload("ellipsoid51k")
     tgt = dda.Target(d["ijk"], d["m"])
     opts = dda.Options.for_size_parameter(d["x"], tol=1e-5)
@@ -181,6 +183,8 @@ def test_solve_full_size_ellipsoid_vs_oracle(dda):
         for key in ("qext", "qabs", "qsca"):
             assert abs(r[key] - o[key]) <= 1e-4 * abs(o[key]), (key, r[key], o[key])
         assert np.abs(P[q][sample] - o["P"][sample]).max() <= 1e-3 * np.abs(o["P"]).max()
+        o5 = fftsolve.solve_case(d["ijk"], d["m"], d["x"], d["khat"][q], d["e0"][q], tol=1e-5)
+        assert abs(r["iters"] - o5["iters"]) <= 1 and r["matvecs"] == 2 * r["iters"], (r, o5["iters"])
 
 
 def test_batched_equals_single_bitwise(dda):
