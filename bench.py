@@ -198,8 +198,9 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
     Traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) times the factor
     that makes the same counter read the known size of a plain device copy.
     Every candidate of the dominant pass runs AUTOTUNE_LAUNCHES times on the
-    real grid, in variant order, while the autotuner times it: those
-    dispatches give each variant's bytes per full launch."""
+    real grid, in variant order, while the autotuner times it (pass 3's
+    behind the forward y pass, as in the solve): those dispatches give each
+    variant's bytes per full launch."""
     import csv
     import re
     import statistics
@@ -309,6 +310,11 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
         pp = re.compile(PASS_PATTERNS[name])
         L = grid[SLOT_OF_PASS[name] // 2 + 1] if name in SLOT_OF_PASS else None
         trials = AUTOTUNE_LAUNCHES * (CT_VARIANTS[name] if L in CT_LENGTHS else 1) if L else 0
+        if name == "fft_y_fwd" and grid[2] in CT_LENGTHS:
+            # pass 3's candidates are timed behind the chosen forward y pass:
+            # one warm-up and twenty launches of it alone, then twenty per
+            # candidate
+            trials += AUTOTUNE_LAUNCHES + (AUTOTUNE_LAUNCHES - 1) * CT_VARIANTS["fft_z_green"]
 
         def prod(rs, counter, scale):
             fam = sorted((r for r in rs if r["Counter_Name"] == counter and pp.search(r["Kernel_Name"])),

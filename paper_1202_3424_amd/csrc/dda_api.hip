@@ -426,10 +426,9 @@ struct Work {
     // variant of each strided pass by timing every candidate on the workspace
     // grid (its contents are scratch at this point; all variants compute
     // bitwise-identical results), one warm-up and twenty timed launches
-    // each.  Among the variants within 3% of the fastest it takes the
-    // lowest-numbered XCD-grouped one of pass 3 if there is one, else the
-    // lowest-numbered: near-ties then resolve the same way from run to run,
-    // and towards the order that reads the tensor from HBM about once.
+    // each, pass 3 each time behind the forward y pass.  Among the variants
+    // within 3% of the fastest it takes the lowest-numbered, so that
+    // near-ties resolve the same way from run to run.
     void autotune(bool enabled, int forced = 0) {
         const Geo& g = t->geo;
         if (forced > 0) {
@@ -452,6 +451,24 @@ struct Work {
                 const int L = g.M[slot == 1 ? 2 : 1];
                 const int nv = strided_variants(L, slot == 1);
                 std::vector<float> t_ms(nv, 0.f);
+                // pass 3 is timed behind the chosen forward y pass, which
+                // writes its input in the solve, less the time of that y pass
+                // alone: back-to-back launches of pass 3 alone find its grid
+                // and tensor in the caches, and there the variants that
+                // re-read the tensor look faster than they are in the solve
+                auto run_y = [&]() {
+                    if (fp32) strided_slot<float>(0, CHK_NONE, best[0]);
+                    else strided_slot<double>(0, CHK_NONE, best[0]);
+                };
+                float t_y = 0.f;
+                if (slot == 1) {
+                    run_y();
+                    HIPCHK(hipEventRecord(e0, s));
+                    for (int k = 0; k < 20; ++k) run_y();
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    HIPCHK(hipEventElapsedTime(&t_y, e0, e1));
+                }
                 for (int v = 0; v < nv; ++v) {
                     auto run = [&]() {
                         if (fp32) strided_slot<float>(slot, CHK_NONE, v);
@@ -459,18 +476,18 @@ struct Work {
                     };
                     run();
                     HIPCHK(hipEventRecord(e0, s));
-                    for (int k = 0; k < 20; ++k) run();
+                    for (int k = 0; k < 20; ++k) {
+                        if (slot == 1) run_y();
+                        run();
+                    }
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
                     HIPCHK(hipEventElapsedTime(&t_ms[v], e0, e1));
+                    t_ms[v] -= t_y;
                 }
                 const float fastest = *std::min_element(t_ms.begin(), t_ms.end());
-                int pick = -1;
-                for (int v = 0; v < nv && pick < 0; ++v)
-                    if (t_ms[v] <= 1.03f * fastest && strided_variant_xcd(L, slot == 1, fp32, v)) pick = v;
-                for (int v = 0; v < nv && pick < 0; ++v)
-                    if (t_ms[v] <= 1.03f * fastest) pick = v;
-                best[slot] = pick < 0 ? 0 : pick;
+                for (int v = nv - 1; v >= 0; --v)
+                    if (t_ms[v] <= 1.03f * fastest) best[slot] = v;
             }
             HIPCHK(hipGetLastError());
             c->evpool.push_back(e0);
@@ -731,15 +748,38 @@ void run_chunk(Work& w, int chunk) {
     }
 }
 
-// BiCGSTAB iterations until no right-hand side is active (the host polls
-// once per chunk of iterations).
+// Iterations to enqueue before the next status poll, at most cap.  Once
+// every right-hand side has stopped, the launches of the rest of a chunk
+// only read statuses, but each still costs a launch; so the chunk shrinks to
+// what the slowest active right-hand side is predicted to need: its average
+// reduction of the squared residual per iteration so far, carried on to the
+// tolerance, rounded down, at least one.  Before any iteration (or when the
+// residual has not fallen) the chunk is cap.  Results do not depend on it.
+int next_chunk(const Work& w, int cap) {
+    double need = 0.0;
+    for (int q = 0; q < w.nrhs; ++q) {
+        const RhsState& st = w.ws.host_state[q];
+        if (st.status != ST_ACTIVE) continue;
+        const double res2 = w.qmr ? st.snorm2 : st.rnorm2;   // what the solver's stop test reads
+        const double target = st.tol2 * st.bnorm2;
+        if (st.iters < 1 || !(res2 > 0.0) || !(target > 0.0) || !(st.bnorm2 > res2)) return cap;
+        const double per_iter = std::log(st.bnorm2 / res2) / st.iters;
+        need = std::max(need, std::log(res2 / target) / per_iter);
+    }
+    if (!(need < cap)) return cap;
+    return std::max(1, (int)std::floor(need));
+}
+
+// Iterations until no right-hand side is active (the host polls once per
+// chunk of iterations).
 void iterate_loop(Work& w, const dda_opts* o) {
     dda_ctx* c = w.c;
     int launched = 0;
-    const int chunk = std::min(8, o->max_iter);
+    const int cap = std::min(8, o->max_iter);
     while (true) {
         fetch_state(c, w);
-        if (!any_active_after_restart(w) || launched > o->max_iter + 2 * chunk) break;
+        if (!any_active_after_restart(w) || launched > o->max_iter + 2 * cap) break;
+        const int chunk = next_chunk(w, cap);
         run_chunk(w, chunk);
         launched += chunk;
     }
@@ -1056,10 +1096,11 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
             if (q == hipErrorNotReady) continue;
             HIPCHK(q);
             progress = true;
-            const int chunk = std::min(8, j.o->max_iter);
+            const int cap = std::min(8, j.o->max_iter);
             if (j.phase == Job::ITER || j.phase == Job::REFINE) {
                 const bool active = any_active_after_restart(w);
-                if (active && j.launched <= j.o->max_iter + 2 * chunk) {
+                if (active && j.launched <= j.o->max_iter + 2 * cap) {
+                    const int chunk = next_chunk(w, cap);
                     run_chunk(w, chunk);
                     j.launched += chunk;
                     j.phase = Job::ITER;

@@ -123,11 +123,6 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant = 0);
 inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 24 : 8) : 1; }
-// true if pass-3 variant v runs in the XCD-grouped workgroup order at this
-// length and precision (a register-resident variant whose data do not fit
-// runs the default LDS form instead), so that workgroups sharing tensor
-// values share one XCD's L2
-bool strided_variant_xcd(int L, bool gh, bool fp32, int v);
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);
