@@ -770,18 +770,35 @@ int next_chunk(const Work& w, int cap) {
     return std::max(1, (int)std::floor(need));
 }
 
-// Iterations until no right-hand side is active (the host polls once per
-// chunk of iterations).
+// Iterations until no right-hand side is active.  The statuses are copied
+// to the host one iteration before the end of each chunk: the host reads
+// them and enqueues the next chunk while the GPU runs that last iteration.
+// Only when the slowest right-hand side is predicted to finish within it
+// does the host wait for the end of the chunk and decide on fresh statuses.
 void iterate_loop(Work& w, const dda_opts* o) {
     dda_ctx* c = w.c;
     int launched = 0;
     const int cap = std::min(8, o->max_iter);
-    while (true) {
-        fetch_state(c, w);
-        if (!any_active_after_restart(w) || launched > o->max_iter + 2 * cap) break;
-        const int chunk = next_chunk(w, cap);
-        run_chunk(w, chunk);
+    fetch_state(c, w);
+    if (!any_active_after_restart(w)) return;
+    int chunk = next_chunk(w, cap);
+    while (launched <= o->max_iter + 2 * cap) {
+        if (chunk > 1) run_chunk(w, chunk - 1);
+        post_state(w);
+        run_chunk(w, 1);
         launched += chunk;
+        HIPCHK(hipEventSynchronize(w.ws.ready));
+        flush_timing(c);
+        // statuses as of one iteration before the end of the chunk
+        if (!any_active_after_restart(w)) break;
+        const int need = next_chunk(w, cap + 1);
+        if (need >= 2) {
+            chunk = std::min(cap, need - 1);
+            continue;
+        }
+        fetch_state(c, w);
+        if (!any_active_after_restart(w)) break;
+        chunk = next_chunk(w, cap);
     }
 }
 
