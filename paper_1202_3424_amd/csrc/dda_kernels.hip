@@ -397,71 +397,90 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
 // exp(-i k n . r) = w_x(x) w_y(y) w_z(z), so one workgroup per direction
 // tabulates the n_x + n_y + n_z factors of its direction in LDS and every
 // term costs two complex products instead of a sine and cosine; the
-// right-hand sides are taken FR at a time over the same factors.  per > 0:
-// direction d belongs to right-hand side d / per alone (every right-hand
-// side with its own direction set in one launch) and its results go to
-// entry d.  Deterministic sums (fixed per-thread order, then the workgroup
-// reduction).
+// right-hand sides are taken FR at a time over the same factors, and DW
+// directions at a time over the same loaded sites (each site's P is read
+// once for all DW).  per > 0: direction d belongs to right-hand side d / per
+// alone (every right-hand side with its own direction set in one launch;
+// DW divides per) and its results go to entry d.  Deterministic sums (each
+// direction: fixed per-thread order, then the workgroup reduction; the same
+// for every DW).
 constexpr int FR = 2;
 
+template <int DW>
 __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, const double2* P, long long n3,
                                                  int nrhs, const double* dirs, double k, int lox, int loy, int loz,
                                                  int nx, int ny, int nz, double2* f, double* dcs, int ndir,
                                                  int per) {
-    extern __shared__ double2 wtab[];     // [nx + ny + nz] phase factors of this direction
+    extern __shared__ double2 wtab[];     // [DW][nx + ny + nz] phase factors of the group's directions
     __shared__ double sh[6 * FR * NT / 64];   // block_sum scratch: one value per wave and sum
-    const int d = blockIdx.x;
-    const double* dv = dirs + (long long)d * 9;
+    const int d0 = blockIdx.x * DW;
     const int nt = nx + ny + nz;
-    for (int i = threadIdx.x; i < nt; i += NT) {
-        const int a = i < nx ? 0 : (i < nx + ny ? 1 : 2);
-        const int c = a == 0 ? lox + i : (a == 1 ? loy + (i - nx) : loz + (i - nx - ny));
+    for (int i = threadIdx.x; i < DW * nt; i += NT) {
+        const int j = i / nt, ii = i % nt;
+        const int d = min(d0 + j, ndir - 1);   // past the end: a copy of the last direction, not stored
+        const double* dv = dirs + (long long)d * 9;
+        const int a = ii < nx ? 0 : (ii < nx + ny ? 1 : 2);
+        const int c = a == 0 ? lox + ii : (a == 1 ? loy + (ii - nx) : loz + (ii - nx - ny));
         double sn, cs;
         sincos(-k * dv[a] * c, &sn, &cs);
         wtab[i] = double2{cs, sn};
     }
     __syncthreads();
-    const double2* wy = wtab + nx;
-    const double2* wz = wtab + nx + ny;
     const double k3 = k * k * k;
-    const int qa = per > 0 ? d / per : 0;
+    const int qa = per > 0 ? d0 / per : 0;
     const int qb = per > 0 ? qa + 1 : nrhs;
     for (int q0 = qa; q0 < qb; q0 += FR) {
-        double acc[6 * FR];
+        double acc[DW][6 * FR];
 #pragma unroll
-        for (int i = 0; i < 6 * FR; ++i) acc[i] = 0.0;
+        for (int j = 0; j < DW; ++j)
+#pragma unroll
+            for (int i = 0; i < 6 * FR; ++i) acc[j][i] = 0.0;
         for (int s = threadIdx.x; s < nsites; s += NT) {
-            const double2 w = cmul(cmul(wtab[coords[s * 3 + 0] - lox], wy[coords[s * 3 + 1] - loy]),
-                                   wz[coords[s * 3 + 2] - loz]);
+            const int cx = coords[s * 3 + 0] - lox, cy = nx + coords[s * 3 + 1] - loy;
+            const int cz = nx + ny + coords[s * 3 + 2] - loz;
+            double2 pv[FR][3];
 #pragma unroll
             for (int r = 0; r < FR; ++r) {
-                if (q0 + r < qb) {
-                    const double2* Pq = P + (long long)(q0 + r) * n3 + (long long)s * 3;
+                const double2* Pq = P + (long long)(q0 + r) * n3 + (long long)s * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pv[r][c] = q0 + r < qb ? Pq[c] : double2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int j = 0; j < DW; ++j) {
+                const double2* wt = wtab + j * nt;
+                const double2 w = cmul(cmul(wt[cx], wt[cy]), wt[cz]);
+#pragma unroll
+                for (int r = 0; r < FR; ++r) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const double2 v = cmul(Pq[c], w);
-                        acc[6 * r + 2 * c] += v.x;
-                        acc[6 * r + 2 * c + 1] += v.y;
+                        const double2 v = cmul(pv[r][c], w);
+                        acc[j][6 * r + 2 * c] += v.x;
+                        acc[j][6 * r + 2 * c + 1] += v.y;
                     }
                 }
             }
         }
-        block_sum<6 * FR>(acc, sh);
-        if (threadIdx.x == 0) {
-            for (int r = 0; r < FR && q0 + r < qb; ++r) {
-                double2 f1 = {0.0, 0.0}, f2 = {0.0, 0.0};
-                for (int c = 0; c < 3; ++c) {
-                    const double2 A = {k3 * acc[6 * r + 2 * c], k3 * acc[6 * r + 2 * c + 1]};
-                    f1 = cadd(f1, double2{dv[3 + c] * A.x, dv[3 + c] * A.y});
-                    f2 = cadd(f2, double2{dv[6 + c] * A.x, dv[6 + c] * A.y});
+#pragma unroll
+        for (int j = 0; j < DW; ++j) {
+            block_sum<6 * FR>(acc[j], sh);
+            const int d = d0 + j;
+            if (threadIdx.x == 0 && d < ndir) {
+                const double* dv = dirs + (long long)d * 9;
+                for (int r = 0; r < FR && q0 + r < qb; ++r) {
+                    double2 f1 = {0.0, 0.0}, f2 = {0.0, 0.0};
+                    for (int c = 0; c < 3; ++c) {
+                        const double2 A = {k3 * acc[j][6 * r + 2 * c], k3 * acc[j][6 * r + 2 * c + 1]};
+                        f1 = cadd(f1, double2{dv[3 + c] * A.x, dv[3 + c] * A.y});
+                        f2 = cadd(f2, double2{dv[6 + c] * A.x, dv[6 + c] * A.y});
+                    }
+                    const long long o = per > 0 ? (long long)d : (long long)(q0 + r) * ndir + d;
+                    f[o * 2 + 0] = f1;
+                    f[o * 2 + 1] = f2;
+                    dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
                 }
-                const long long o = per > 0 ? (long long)d : (long long)(q0 + r) * ndir + d;
-                f[o * 2 + 0] = f1;
-                f[o * 2 + 1] = f2;
-                dcs[o] = (f1.x * f1.x + f1.y * f1.y + f2.x * f2.x + f2.y * f2.y) / (k * k);
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -1044,18 +1063,35 @@ void launch_b2_update(const SiteArgs& a, int site_blocks, hipStream_t s) {
 void launch_qmr_final(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qmr_final, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
+// directions per workgroup of the far field: four where the direction sets
+// allow it and the launch still has at least FF_MIN_WG workgroups (each
+// site's P then serves four directions), else one
+constexpr int FF_DW = 4;
+constexpr int FF_MIN_WG = 512;
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
                      double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
-    const size_t shm = (size_t)(n[0] + n[1] + n[2]) * sizeof(double2);
-    hipLaunchKernelGGL(k_farfield, dim3(ndir), dim3(NT), shm, s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k,
-                       lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
+    const size_t nt = (size_t)(n[0] + n[1] + n[2]);
+    if (ndir >= FF_DW * FF_MIN_WG) {
+        hipLaunchKernelGGL(k_farfield<FF_DW>, dim3((ndir + FF_DW - 1) / FF_DW), dim3(NT),
+                           FF_DW * nt * sizeof(double2), s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k, lo[0],
+                           lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
+    } else {
+        hipLaunchKernelGGL(k_farfield<1>, dim3(ndir), dim3(NT), nt * sizeof(double2), s, nsites, coords, P,
+                           3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
+    }
 }
 void launch_farfield_sets(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int per,
                           double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
-    const size_t shm = (size_t)(n[0] + n[1] + n[2]) * sizeof(double2);
+    const size_t nt = (size_t)(n[0] + n[1] + n[2]);
     const int ndt = per * nrhs;
-    hipLaunchKernelGGL(k_farfield, dim3(ndt), dim3(NT), shm, s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k,
-                       lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndt, per);
+    if (per % FF_DW == 0 && ndt >= FF_DW * FF_MIN_WG) {
+        hipLaunchKernelGGL(k_farfield<FF_DW>, dim3(ndt / FF_DW), dim3(NT), FF_DW * nt * sizeof(double2), s, nsites,
+                           coords, P, 3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs,
+                           ndt, per);
+    } else {
+        hipLaunchKernelGGL(k_farfield<1>, dim3(ndt), dim3(NT), nt * sizeof(double2), s, nsites, coords, P,
+                           3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndt, per);
+    }
 }
 void launch_nf_place(int nsites, const int* perm, const int* coords, const double2* P, int nrhs, const int org[3],
                      const int dims[3], double2* x, hipStream_t s) {
