@@ -348,16 +348,66 @@ def test_bicgstab2_residual_consistent_and_minimal():
         assert np.linalg.norm(t["r"]) <= np.linalg.norm(t["r_bicg"]) * (1 + 1e-12)
 
 
+def _err_tol_by_differences(A, P, E):
+    """eq. err_tol without forming A^H: phi(P) = |A P - E|^2 / 2 has the
+    gradient dphi/dRe P + i dphi/dIm P = A^H (A P - E), and at P = 0 that is
+    -A^H E.  Central differences of the quadratic phi are exact up to rounding."""
+    p0 = np.asarray(P, dtype=np.complex128).reshape(-1)
+    e = np.asarray(E, dtype=np.complex128).reshape(-1)
+
+    def grad(p):
+        phi = lambda v: 0.5 * float(np.sum(np.abs(A @ v - e) ** 2))
+        h = 1e-4 * max(np.abs(p).max(), 1.0)
+        g = np.zeros(len(p), dtype=np.complex128)
+        for i in range(len(p)):
+            for unit in (1.0, 1j):
+                d = np.zeros(len(p), dtype=np.complex128)
+                d[i] = unit * h
+                g[i] += unit * (phi(p + d) - phi(p - d)) / (2 * h)
+        return g
+
+    return float(np.linalg.norm(grad(p0)) / np.linalg.norm(grad(np.zeros_like(p0))))
+
+
+def _err_tol_case():
+    """A 20-site ragged target of a lossy material at oblique elliptical
+    incidence (A far from Hermitian), and a P away from the solution."""
+    rng = np.random.default_rng(41)
+    ijk = np.unique(rng.integers(0, 4, size=(26, 3)), axis=0)[:20].astype(np.int32)
+    kh = np.array([0.36, 0.48, 0.8])
+    e0 = np.array([0.8, -0.6, 0.0]) + 0.4j * np.cross(kh, [0.8, -0.6, 0.0])
+    s = dense.solve_case(ijk, np.full(len(ijk), 2.0 + 0.7j), 1.2, kh, e0, with_qsca=False)
+    P = s["P"] + 0.05 * np.abs(s["P"]).max() * w.random_vectors(12, s["P"].shape)
+    return s, P
+
+
 def test_normal_equation_residual_definition():
-    """eq. err_tol: |A^H A P - A^H E| / |A^H E| is zero at the exact solution
-    and equals the explicit expression for a perturbed P."""
+    """eq. err_tol |A^H A P - A^H E| / |A^H E|: zero at the LU solution, and
+    at a P away from it equal to the value found from finite differences of
+    |A P - E|^2 (which never forms A^H)."""
     d = w.workload("sphere389")
     s = dense.solve_case(d["ijk"], d["m"], d["x"], d["khat"][0], d["e0"][0], with_qsca=False)
     true_r, ne_r = dense.residuals(s["A"], s["P"], s["E"])
     assert true_r < 1e-13 and ne_r < 1e-12
-    Pp = s["P"] * (1 + 1e-3)
-    true_r, ne_r = dense.residuals(s["A"], Pp, s["E"])
-    assert 5e-4 < true_r < 2e-3 and ne_r > 0
+    s, P = _err_tol_case()
+    fd = _err_tol_by_differences(s["A"], P, s["E"])
+    true_r, ne_r = dense.residuals(s["A"], P, s["E"])
+    assert abs(ne_r - fd) <= 1e-7 * fd and true_r > 1e-3
+
+
+def test_err_tol_pin_rejects_transpose_for_adjoint(monkeypatch):
+    """Planted in the oracle: A^T in place of A^H (for the complex-symmetric A
+    that is A itself) changes the value beyond the pin's tolerance."""
+    def residuals_t(A, P, E):
+        p = np.asarray(P).reshape(-1)
+        e = np.asarray(E).reshape(-1)
+        r = A @ p - e
+        return (float(np.linalg.norm(r) / np.linalg.norm(e)),
+                float(np.linalg.norm(A.T @ r) / np.linalg.norm(A.T @ e)))
+    monkeypatch.setattr(dense, "residuals", residuals_t)
+    s, P = _err_tol_case()
+    fd = _err_tol_by_differences(s["A"], P, s["E"])
+    assert abs(dense.residuals(s["A"], P, s["E"])[1] - fd) > 1e-3 * fd
 
 
 # ---------------------------------------------------------------- adjoint
