@@ -111,7 +111,7 @@ AxisPlan make_plan(int L) {
 struct Workspace {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    DevBuf grid, vecs, state, partials, inc, ainv, mrel;
+    DevBuf grid, vecs, state, partials, inc, ainv;
     RhsState* host_state = nullptr;
     int host_state_cap = 0;
     hipEvent_t ready = nullptr;   // recorded after the last asynchronous status copy
@@ -137,7 +137,7 @@ struct Workspace {
             if (e) (void)hipEventDestroy(e);
             e = nullptr;
         }
-        for (DevBuf* b : {&grid, &vecs, &state, &partials, &inc, &ainv, &mrel}) b->release();
+        for (DevBuf* b : {&grid, &vecs, &state, &partials, &inc, &ainv}) b->release();
         if (host_state) (void)hipHostFree(host_state);
         host_state = nullptr;
         host_state_cap = 0;
@@ -179,8 +179,8 @@ struct dda_target {
     int nsites = 0;
     int nmat = 0;
     Geo geo{};
-    std::vector<double2> mats;       // distinct refractive indices
-    DevBuf map, mat, coords, perm, tw;
+    std::vector<double2> mats;       // distinct refractive indices (and their device copy mdev)
+    DevBuf map, mat, coords, perm, tw, mdev;
     // cached FFT of the interaction tensor
     double green_kd = -1.0;
     bool have64 = false, have32 = false;
@@ -304,10 +304,8 @@ void check_opts(const dda_opts* o) {
 }
 
 // Normalised incidences packed for the device: khat [n][3], e0 [n][3].
-void pack_incidence(int n, const dda_incidence* inc, std::vector<double>& kh, std::vector<double2>& e0) {
+void pack_incidence(int n, const dda_incidence* inc, double* kh, double2* e0) {
     if (!inc) invalid("incidence array is NULL");
-    kh.resize((size_t)n * 3);
-    e0.resize((size_t)n * 3);
     for (int q = 0; q < n; ++q) {
         const dda_incidence& I = inc[q];
         double kn = 0, en = 0;
@@ -334,6 +332,12 @@ void pack_incidence(int n, const dda_incidence* inc, std::vector<double>& kh, st
         }
     }
 }
+void pack_incidence(int n, const dda_incidence* inc, std::vector<double>& kh, std::vector<double2>& e0) {
+    kh.resize((size_t)n * 3);
+    e0.resize((size_t)n * 3);
+    pack_incidence(n, inc, kh.data(), e0.data());
+}
+
 
 // Everything one batched solve on one target needs on the device.
 struct Work {
@@ -392,6 +396,10 @@ struct Work {
         e0 = (double2*)(ib + (((size_t)nrhs * 3 * sizeof(double) + 15) & ~(size_t)15));
     }
 
+    void upload_incidence(const double* khv, const double2* e0v) {
+        HIPCHK(hipMemcpyAsync(kh, khv, (size_t)nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(e0, e0v, (size_t)nrhs * 3 * sizeof(double2), hipMemcpyHostToDevice, s));
+    }
     void upload_incidence(const std::vector<double>& khv, const std::vector<double2>& e0v) {
         HIPCHK(hipMemcpyAsync(kh, khv.data(), khv.size() * sizeof(double), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(e0, e0v.data(), e0v.size() * sizeof(double2), hipMemcpyHostToDevice, s));
@@ -399,11 +407,7 @@ struct Work {
 
     // 1/alpha for every (right-hand side, material); scheme + 2 = derivative
     void alpha_table(int scheme, double m_medium, double2* out) {
-        std::vector<double2> mrel(t->nmat);
-        for (int i = 0; i < t->nmat; ++i) mrel[i] = double2{t->mats[i].x / m_medium, t->mats[i].y / m_medium};
-        double2* dm = (double2*)ws.mrel.ensure(mrel.size() * sizeof(double2));
-        HIPCHK(hipMemcpyAsync(dm, mrel.data(), mrel.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-        launch_alpha(nrhs, t->nmat, dm, kh, e0, kd, scheme, out, s);
+        launch_alpha(nrhs, t->nmat, (const double2*)t->mdev.p, m_medium, kh, e0, kd, scheme, out, s);
     }
 
     // the three strided passes: 0 = y forward, 1 = z with the tensor product, 2 = y inverse
@@ -1244,9 +1248,10 @@ dda_target* create_target(dda_ctx* c, int64_t n_sites, const int32_t* ijk, const
         up(t->mat, mat.data(), mat.size() * sizeof(int));
         up(t->coords, coords.data(), coords.size() * sizeof(int));
         up(t->tw, tw.data(), tw.size() * sizeof(double2));
+        up(t->mdev, t->mats.data(), t->mats.size() * sizeof(double2));
         for (int a = 0; a < 3; ++a) t->lo[a] = lo[a];
     } catch (...) {
-        for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw}) b->release();
+        for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->mdev}) b->release();
         delete t;
         throw;
     }
@@ -1258,7 +1263,7 @@ void free_target(dda_target* t) {
     if (!t) return;
     free_target(t->nf);
     t->nf = nullptr;
-    for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->gh64, &t->gh32}) b->release();
+    for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->mdev, &t->gh64, &t->gh32}) b->release();
     delete t;
 }
 

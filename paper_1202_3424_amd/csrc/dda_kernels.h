@@ -127,8 +127,11 @@ void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);
 void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* gh32, hipStream_t s);
-void launch_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, const double2* e0, double kd,
-                  int scheme, double2* ainv, hipStream_t s);
+// 1/alpha (scheme + 2: its derivative in eps) per (right-hand side, material)
+// from the target's distinct refractive indices mats [nmat] and the ambient
+// medium's index
+void launch_alpha(int nrhs, int nmat, const double2* mats, double m_medium, const double* khat, const double2* e0,
+                  double kd, int scheme, double2* ainv, hipStream_t s);
 void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s);
 void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s);

@@ -131,14 +131,15 @@ __global__ __launch_bounds__(NT) void k_green_octant(Geo g, const double2* G, do
 //       + (b1 + eps b2 + eps b3 S) (kd)^2 - (2/3) i (kd)^3,
 //       S = sum_mu khat_mu^2 |e_mu|^2, 1/alpha_CM = (4 pi/3)(eps+2)/(eps-1).
 //   GKDLDR (Gutkowicz-Krusin & Draine 2004): S -> khat_mu^2 on axis mu.
-__global__ void k_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, const double2* e0, double kd,
-                        int scheme, double2* out) {
+__global__ void k_alpha(int nrhs, int nmat, const double2* mats, double m_medium, const double* khat,
+                        const double2* e0, double kd, int scheme, double2* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrhs * nmat) return;
     const int q = i / nmat, mt = i % nmat;
     const double b1 = -1.891531, b2 = 0.1648469, b3 = -1.7700004;
     const double pi = 3.14159265358979323846;
-    const double2 m = m_rel[mt];
+    // refractive index relative to the ambient medium
+    const double2 m = {mats[mt].x / m_medium, mats[mt].y / m_medium};
     const double2 eps = cmul(m, m);
     const double* kh = khat + q * 3;
     const double2* e = e0 + q * 3;
@@ -1029,10 +1030,11 @@ void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* 
     hipLaunchKernelGGL(k_green_octant, dim3((unsigned)((nh + NT - 1) / NT)), dim3(NT), 0, s, g, G, gh64, gh32);
 }
 
-void launch_alpha(int nrhs, int nmat, const double2* m_rel, const double* khat, const double2* e0, double kd,
-                  int scheme, double2* ainv, hipStream_t s) {
+void launch_alpha(int nrhs, int nmat, const double2* mats, double m_medium, const double* khat, const double2* e0,
+                  double kd, int scheme, double2* ainv, hipStream_t s) {
     const int n = nrhs * nmat;
-    hipLaunchKernelGGL(k_alpha, dim3((n + 63) / 64), dim3(64), 0, s, nrhs, nmat, m_rel, khat, e0, kd, scheme, ainv);
+    hipLaunchKernelGGL(k_alpha, dim3((n + 63) / 64), dim3(64), 0, s, nrhs, nmat, mats, m_medium, khat, e0, kd, scheme,
+                       ainv);
 }
 
 void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s) {

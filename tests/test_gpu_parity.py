@@ -305,8 +305,12 @@ def test_mixed_precision_matches_fp64_solve(dda):
 
 def test_sphere1m_full_size(dda):
     """The 1,099,136-site sphere on its 256^3 grid: sampled rows of A x in FP64
-    and FP32 against the oracle's direct sums; the FP32-matvec solve against
-    the FP64 solve (1e-4) and Mie theory (the DDA error bound per quantity)."""
+    and FP32 against the oracle's direct sums; the FP64 and FP32-matvec solves
+    against the oracle's FP64 FFT-BiCGSTAB solution (tests/golden/
+    sphere1m_oracle.json, written by make_sphere1m_oracle.py from the oracle
+    alone: Q within 1e-4, P at its 64 stored sites within 1e-3 of max|P|),
+    against each other (1e-4) and against Mie theory (the DDA error bound per
+    quantity)."""
     d = w.workload("sphere1m")
     n = len(d["ijk"])
     tgt = dda.Target(d["ijk"], d["m"])
@@ -322,9 +326,22 @@ def test_sphere1m_full_size(dda):
         assert np.abs(y[rows] - ref).max() <= tol * np.abs(ref).max(), prec
     o64 = dda.Options.for_size_parameter(d["x"], tol=1e-5)
     o32 = dda.Options.for_size_parameter(d["x"], tol=1e-5, precision="fp32_matvec")
-    _, r64 = dda.solve(tgt, o64, d["khat"], d["e0"], want_P=False)
-    _, r32 = dda.solve(tgt, o32, d["khat"], d["e0"], want_P=False)
+    P64, r64 = dda.solve(tgt, o64, d["khat"], d["e0"])
+    P32, r32 = dda.solve(tgt, o32, d["khat"], d["e0"])
     q_mie = mie.efficiencies(1.33 + 0.01j, d["x"])
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sphere1m_oracle.json")))
+    assert g["n_sites"] == n and abs(g["kd"] - k) < 1e-14
+    sample = np.array(g["sample_sites"])
+    for q, ref in enumerate(g["rhs"]):
+        assert ref["converged"] and ref["true_residual"] < 1e-6
+        Pref = np.array(ref["P_sample_re"]) + 1j * np.array(ref["P_sample_im"])
+        for r, P in ((r64[q], P64), (r32[q], P32)):
+            for key in ("qext", "qabs", "qsca"):
+                assert abs(r[key] - ref[key]) <= 1e-4 * abs(ref[key]), (q, key, r[key], ref[key])
+            Ps = P[q].cpu().numpy()[sample]
+            assert np.abs(Ps - Pref).max() <= 1e-3 * np.abs(Pref).max()
     for a, b in zip(r32, r64):
         assert a["status"] == 0 and b["status"] == 0
         assert a["rel_residual"] < 1e-5 and b["rel_residual"] < 1e-5
@@ -1012,3 +1029,102 @@ def test_largest_padded_extent_matches_dense(dda, axis):
     A = _dense_A(ijk, np.full(160, 1.4 + 0.2j), 3.0, kh[0], e0[0], "LATTDR")
     ref = (A @ xv[0].reshape(-1)).reshape(-1, 3)
     assert np.abs(y[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ runtime-planned FFT lengths
+
+def _three_lines(n):
+    """Three perpendicular lines of n[0], n[1], n[2] sites from one corner:
+    a sparse target whose padded grid has the extents of n on every axis."""
+    pts = [[i, 0, 0] for i in range(n[0])] + [[0, j, 0] for j in range(n[1])] + [[0, 0, k] for k in range(n[2])]
+    return np.unique(np.array(pts), axis=0).astype(np.int32)
+
+
+# padded extents 27, 30, 36 | 40, 45, 50 | 54, 60, 72 | 75, 81, 45: the
+# lengths the ragged sphere batch's grids use (radii 6..20), all of them
+# runtime-planned (no compile-time kernel)
+RT_LINES = [(14, 15, 18), (20, 23, 25), (27, 30, 36), (38, 41, 23)]
+
+
+@pytest.mark.parametrize("n", RT_LINES, ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_matvec", 2e-5)])
+def test_matvec_runtime_lengths_match_dense(dda, n, precision, tol):
+    ijk = _three_lines(n)
+    tgt = dda.Target(ijk, np.where(np.arange(len(ijk)) % 2 == 0, 1.33 + 0.01j, 1.6 + 0.2j))
+    assert tgt.grid == tuple(fftsolve.padded_extent(v) for v in n)
+    m = np.where(np.arange(len(ijk)) % 2 == 0, 1.33 + 0.01j, 1.6 + 0.2j)
+    kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
+    e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
+    opts = dda.Options.for_size_parameter(2.5, precision=precision)
+    xv = w.random_vectors(40 + n[0], (2, len(ijk), 3))
+    y = dda.apply(tgt, opts, kh, e0, _cuda(xv)).cpu().numpy()
+    for q in range(2):
+        ref = (_dense_A(ijk, m, 2.5, kh[q], e0[q], "LATTDR") @ xv[q].reshape(-1)).reshape(-1, 3)
+        assert np.abs(y[q] - ref).max() <= tol * np.abs(ref).max(), (n, tgt.grid, q)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_matvec", 2e-5)])
+def test_matvec_sphere_batch_grids_match_oracle_fft(dda, precision, tol):
+    """One sphere of the ragged batch per distinct padded grid (every grid
+    the 32 spheres use), A x at full size against the oracle's FFT operator,
+    element by element."""
+    radii = w.sphere_radii(0)
+    seen = {}
+    for r in radii:
+        ijk = w.sphere_integer(r)
+        g = fftsolve.padded_extent(int(ijk[:, 0].max() - ijk[:, 0].min() + 1))
+        seen.setdefault(g, r)
+    assert len(seen) >= 9
+    kh, e0 = w.along_x_yz()
+    for g, r in sorted(seen.items()):
+        ijk = w.sphere_integer(r)
+        n = len(ijk)
+        tgt = dda.Target(ijk, 1.33 + 0.01j)
+        assert tgt.grid == (g, g, g)
+        opts = dda.Options.for_size_parameter(4.0, precision=precision)
+        xv = w.random_vectors(50 + g, (1, n, 3))
+        y = dda.apply(tgt, opts, kh[1:], e0[1:], _cuda(xv)).cpu().numpy()[0]
+        k = dense.kd_from_size_parameter(4.0, n)
+        ref = fftsolve.FFTOperator(ijk, dense.site_alpha_inverse(np.full(n, 1.33 + 0.01j), k, kh[1], e0[1]),
+                                   k).apply(xv[0])
+        assert np.abs(y - ref).max() <= tol * np.abs(ref).max(), (g, r)
+
+
+# ------------------------------------------------------------------ non-finite inputs
+
+def test_nonfinite_right_hand_side_or_start_is_reported(dda):
+    """A NaN in b (dda_solve_rhs) or in the warm start P0 (dda_solve) ends
+    that right-hand side with DDA_E_NONFINITE; the others are unaffected."""
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8)
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    b = P.clone()
+    b[1, 7, 2] = complex(np.nan, 0.0)
+    x, r = dda.solve_rhs(tgt, opts, d["khat"], d["e0"], b)
+    assert r[0]["status"] == 0 and r[1]["status"] == 6
+    P0 = P.clone()
+    P0[0, 3, 1] = complex(0.0, np.inf)
+    _, r = dda.solve(tgt, opts, d["khat"], d["e0"], P0=P0)
+    assert r[0]["status"] == 6 and r[1]["status"] == 0
+
+
+# ------------------------------------------------------------------ far field, grouped directions
+
+def test_far_field_four_directions_per_workgroup_match_oracle(dda):
+    """2,051 directions: the far-field launch takes four directions per
+    workgroup (partial last group of three) against the oracle's sums."""
+    from oracle import farfield
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-10)
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    nh, th, ph = _random_frames(np.random.default_rng(5), 2051)
+    f, dcs = dda.far_field(tgt, opts, P, nh, th, ph)
+    Pn = P.cpu().numpy()
+    for q in range(2):
+        A = farfield.amplitude_vectors(d["ijk"], Pn[q], res[q]["kd"], nh)
+        ref = np.stack([np.sum(th * A, axis=1), np.sum(ph * A, axis=1)], axis=1)
+        assert np.abs(f[q] - ref).max() <= 1e-12 * np.abs(ref).max()
+        rd = (np.abs(ref[:, 0]) ** 2 + np.abs(ref[:, 1]) ** 2) / res[q]["kd"] ** 2
+        assert np.abs(dcs[q] - rd).max() <= 1e-12 * rd.max()
