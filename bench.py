@@ -40,7 +40,8 @@ WORKLOADS = {
     "au_brick": ("16x32x32 gold brick (N=16384), m=0.9656+1.8628i, x=3.093665, BiCGSTAB to 1e-5, FFT grid 32x64x64",
                  "fp64"),
     "sphere1m": ("sphere of radius 64 in a 128^3 box (N=1099136), m=1.33+0.01i, x=20, LATTDR, BiCGSTAB to 1e-5, "
-                 "FFT grid 256^3", "fp64"),
+                 "FFT grid 256^3, incidence +x, polarizations y and z; FP32 FFT matvec with FP64 Krylov "
+                 "recurrences, inner products and residual refinement unless --precision fp64", "fp32_matvec"),
     "brick48": ("48x24x16 brick (N=18432), m=1.6+0.1i, x=4, 64 random orientations x 2 polarizations = 128 "
                 "right-hand sides in one solve, BiCGSTAB to 1e-5, FFT grid 96x48x32", "fp64"),
     "au_sphere_nf": ("the guide's near-field example: 48^3-box gold pseudosphere (N=59728), m=0.96+1.01i, x=5, "
@@ -74,6 +75,13 @@ def build_jobs(dda, w, name, seed, prec, solver="bicgstab"):
                                           solver=solver, polarizability=d.get("polarizability", "LATTDR"))
     return [(dda.Target(d["ijk"], d["m"]), opts, d["khat"], d["e0"])], len(d["khat"]) / 2.0, d
 
+
+# the largest single-GPU configuration: its working set (two FP32 grids of
+# 403 MB, the 103 MB tensor octant, the FP64 site vectors) exceeds the 256 MB
+# Infinity Cache, so its pass bandwidths are HBM bandwidths
+DEFAULT_WORKLOAD = "sphere1m"
+# measured in the same run as the default line, for context (cache-resident)
+EXTRA_WORKLOAD = "ellipsoid51k"
 
 PASSES = ["scatter_fft_x", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x_gather"]
 
@@ -158,34 +166,34 @@ def load_traffic(kernel: str, workload: str, precision: str, variants, rhs_matve
 PASS_PATTERNS = {
     "scatter_fft_x": r"k_scatter_x<",
     "fft_y_fwd": r"k_strided<(double|float), 3, 0, -1,|k_strided_rf<(double|float), 0, -1,",
-    "fft_z_green": r"k_strided<(double|float), 3, 1, -1,|k_strided_rf<(double|float), 1, -1,|k_zfold<",
+    "fft_z_green": r"k_strided<(double|float), 3, 1, -1,|k_strided_rf<(double|float), 1, -1,|k_zfold<|k_zsq<",
     "fft_y_inv": r"k_strided<(double|float), 3, 0, 1,|k_strided_rf<(double|float), 0, 1,",
     "fft_x_gather": r"k_gather_x<",
 }
 AUTOTUNE_LAUNCHES = 21   # launches of each candidate while the autotuner times it (1 + 20)
 # FFT lengths with compile-time kernels, and their autotuned variants per pass
 CT_LENGTHS = (32, 48, 64, 80, 96, 128, 160, 192, 256)
-CT_VARIANTS = {"fft_y_fwd": 8, "fft_z_green": 24, "fft_y_inv": 8}
+CT_VARIANTS = {"fft_y_fwd": 8, "fft_z_green": 28, "fft_y_inv": 8}
 
 
 def profile_commands(workload: str, prec: str, out: str = "/root/repo/gpurun_out/tr") -> dict:
     """The rocprofv3 runs behind the committed summaries (run from /tmp)."""
-    wl = "" if workload == "ellipsoid51k" else f" --workload {workload}"
+    wl = "" if workload == DEFAULT_WORKLOAD else f" --workload {workload}"
     pr = "" if prec == WORKLOADS[workload][1] else f" --precision {prec}"
     b = f"python -u /root/repo/bench.py{wl}{pr}"
     pre = "cd /tmp && export TMPDIR=/tmp && "
     return {
         "trace": pre + f"timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d {out}/kt -o run "
-                       f"-- {b} --steps 20 --warmup 3 --no-cpu-baseline --no-plain",
+                       f"-- {b} --steps 20 --warmup 3 --no-cpu-baseline --no-plain --no-extra",
         "fetch": pre + f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/f -o run "
-                       f"-- {b} --steps 2 --warmup 1 --no-cpu-baseline --no-plain",
+                       f"-- {b} --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-extra",
         "write": pre + f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/w -o run "
-                       f"-- {b} --steps 2 --warmup 1 --no-cpu-baseline --no-plain",
+                       f"-- {b} --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-extra",
         "copy_fetch": pre + f"timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {out}/cf -o run "
                             f"-- python -u /root/repo/bench.py --copy-probe",
         "copy_write": pre + f"timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {out}/cw -o run "
                             f"-- python -u /root/repo/bench.py --copy-probe",
-        "unprofiled": f"{b} --steps 20 --warmup 3 --no-cpu-baseline --no-plain",
+        "unprofiled": f"{b} --steps 20 --warmup 3 --no-cpu-baseline --no-plain --no-extra",
     }
 
 
@@ -563,7 +571,7 @@ def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
     n_rhs, n_sites = P.shape[0], P.shape[1]
     n_theta, n_phi = 48, 64
     theta = np.linspace(0.0, 180.0, 74)
-    nh, th, ph = dda.lab_directions(theta, np.zeros_like(theta))
+    nh, th, ph = w.lab_directions(theta, np.zeros_like(theta))
 
     def timed(f):
         f()
@@ -628,15 +636,182 @@ def copy_probe(mib: int = 1024, reps: int = 4):
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "copies": reps}), flush=True)
 
 
+def fp64_comparison(dda, np, torch, jobs, results, steps: int = 3) -> dict:
+    """The same workload solved with the FP64 matvec at the same tolerance
+    (one batched solve per step, the FP64 tensor FFT built beforehand): its
+    time per step, and each efficiency's relative difference between the
+    measured step and it, and between each and the FP64 oracle reference
+    (tests/golden/<workload>_oracle.json, written by the oracle alone)."""
+    import dataclasses
+    t, o, kh, e0 = jobs[0]
+    o64 = dataclasses.replace(o, precision="fp64", recompute_green=False)
+    dda.solve(t, o64, kh, e0, want_P=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r64 = dda.solve(t, o64, kh, e0, want_P=False)[1]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    keys = ("qext", "qabs", "qsca")
+    out = {"ms_per_step": ms, "iters": [r["iters"] for r in r64],
+           "rel_diff_vs_fp64_gpu": {k: [abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(results, r64)] for k in keys}}
+    gold = os.path.join(ROOT, "tests", "golden", "sphere1m_oracle.json")
+    if len(results) == 2 and t.n_sites == 1099136 and os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        ref = g["rhs"]
+        out["rel_diff_vs_oracle"] = {k: [abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(results, ref)] for k in keys}
+        out["fp64_gpu_rel_diff_vs_oracle"] = {k: [abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(r64, ref)]
+                                              for k in keys}
+        out["oracle_reference"] = (f"tests/golden/sphere1m_oracle.json: the oracle's FP64 FFT-BiCGSTAB to true "
+                                   f"residual {max(r['true_residual'] for r in ref):.1e}")
+    return out
+
+
+def measure_workload(dda, np, torch, w, wname: str, prec: str, solver: str, seed: int, steps: int, warmup: int):
+    """Warm up, then time ``steps`` whole solves of a workload with the
+    dominant matvec pass event-timed; returns (the bench line's fields, the
+    jobs, the workload dict, the last step's results, ms per step)."""
+    desc = WORKLOADS[wname][0]
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    jobs, orientations, d = build_jobs(dda, w, wname, seed, prec, solver)
+    torch.cuda.synchronize()
+    target_create_ms = (time.perf_counter() - t_create) * 1e3
+    n_rhs = sum(len(j[2]) for j in jobs)
+    log(f"workload {wname}: {len(jobs)} target(s), {n_rhs} right-hand sides, prec={prec}, "
+        f"first target N={jobs[0][0].n_sites} grid={jobs[0][0].grid}")
+
+    def step():
+        if len(jobs) == 1:
+            t, o, kh, e0 = jobs[0]
+            return dda.solve(t, o, kh, e0, want_P=False)[1]
+        rt = [i for i, j in enumerate(jobs) for _ in range(len(j[2]))]
+        kh = np.vstack([j[2] for j in jobs])
+        e0 = np.vstack([j[3] for j in jobs])
+        return dda.solve_batched([j[0] for j in jobs], [j[1] for j in jobs], rt, kh, e0, want_P=False)[1]
+
+    def job_units(results):
+        """RHS-matvec units each job executed (iteration matvecs + 3 checks per RHS)."""
+        out, k = [], 0
+        for j in jobs:
+            n = len(j[2])
+            out.append(sum(r["matvecs"] for r in results[k:k + n]) + 3 * n)
+            k += n
+        return out
+
+    csize = 8 if prec == "fp32_matvec" else 16
+    bpus = [pass_bytes(j[0], j[0].n_sites, csize, solver) for j in jobs]
+
+    def pass_traffic(name, units, launches):
+        # per-RHS bytes times the RHS-matvecs each job executed, plus the
+        # shared bytes once per launch (several jobs: their launches taken as
+        # equal shares)
+        per_rhs = sum(b[name][0] * u for b, u in zip(bpus, units))
+        return per_rhs + sum(b[name][1] for b in bpus) * launches / len(bpus)
+
+    # warmup; the last warmup step times every kernel category to find the
+    # dominant matvec pass, which alone is timed during the measured steps
+    for i in range(max(warmup, 1)):
+        if i == max(warmup, 1) - 1:
+            dda.set_timing(True)
+        res = step()
+        log(f"warmup {i}: iters={[r['iters'] for r in res][:8]} status={set(r['status'] for r in res)}")
+    calib = dda.get_timing()
+    dda.set_timing(False)
+    cal_units = job_units(res)
+    dominant = max(PASSES, key=lambda k: calib[k][0])
+    log(f"dominant matvec kernel: {dominant} ({calib[dominant][0]:.3f} ms in the last warmup step)")
+
+    # events on every TIMING_SAMPLE-th launch of the dominant pass only (a
+    # systematic sample over the timed steps; the others carry no event cost)
+    dda.set_timing([dominant])
+    dda.set_timing_sample(TIMING_SAMPLE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    units = [0] * len(jobs)
+    results = None
+    for i in range(steps):
+        results = step()
+        units = [a + b for a, b in zip(units, job_units(results))]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = dda.get_timing()
+    dda.set_timing(False)
+    dda.set_timing_sample(1)
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    s_per_orientation = ms_per_step / 1e3 / orientations
+    for r in results:
+        if r["status"] != 0:
+            raise SystemExit(f"solve did not converge: {r}")
+    log(f"timed {steps} steps: {ms_per_step:.3f} ms/step; results {results[0]}")
+
+    ms_tot, launches, all_launches = timing[dominant]
+    bytes_tot = pass_traffic(dominant, units, all_launches)
+    # algorithmic bytes per launch (all launches) over the sampled average launch time
+    avg_s = ms_tot * 1e-3 / launches
+    gbs = bytes_tot / all_launches / avg_s / 1e9
+    variants = dda.tuned_variants(jobs[0][0], len(jobs[0][2]), prec) if len(jobs) == 1 else None
+    traffic = (load_traffic(dominant, wname, prec, variants, sum(units) / all_launches)
+               if len(jobs) == 1 else None)
+    roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
+                "algorithmic_bytes_per_launch": bytes_tot / all_launches, "avg_launch_us": avg_s * 1e6,
+                "launches": all_launches, "timed_launches": launches}
+    # every pass, from the calibration step (one warmup step with all categories timed)
+    passes = {}
+    for name in PASSES:
+        ms, nl, _ = calib[name]
+        if nl == 0 or ms == 0:
+            continue
+        g = pass_traffic(name, cal_units, nl) / (ms * 1e-3) / 1e9
+        passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": bpus[0][name][0],
+                        "bytes_per_launch_shared": bpus[0][name][1], "GBps": g, "frac": g / HBM_PEAK_GBS}
+    matvec_ms = sum(calib[k][0] for k in PASSES)
+    matvec_bytes = sum(pass_traffic(k, cal_units, calib[k][1]) for k in PASSES)
+    out = {
+        "metric": METRIC,
+        "value": s_per_orientation,
+        "unit": "s/orientation",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32 matvec / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": f"{wname}: {desc}", "solver": solver, "targets": len(jobs),
+                   "n_sites": [j[0].n_sites for j in jobs][:4], "fft_grid": list(jobs[0][0].grid),
+                   "rhs_per_step": n_rhs, "orientations_per_step": orientations, "precision": prec,
+                   "seed": seed},
+        "roofline": roofline,
+        "autotuned_variants": variants,
+        "target_create_ms": target_create_ms,
+        "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9,
+                   "units_per_step": sum(units) / steps, "passes_calibration_step": passes},
+        "kernel_ms_calibration_step": {k: v[0] for k, v in calib.items()},
+        "solver": {"iters": [r["iters"] for r in results][:8], "matvecs": [r["matvecs"] for r in results][:8],
+                   "qext": [r["qext"] for r in results][:8], "qabs": [r["qabs"] for r in results][:8],
+                   "qsca": [r["qsca"] for r in results][:8], "rel_residual": [r["rel_residual"] for r in results][:8],
+                   "normal_eq_residual": [r["normal_eq_residual"] for r in results][:8],
+                   "refinements": [r["refinements"] for r in results][:8]},
+    }
+    return out, jobs, d, results, ms_per_step
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ellipsoid51k", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32_matvec"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 single-RHS comparison")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the FP64 comparisons (each right-hand side alone; the FP64-matvec solve)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the context measurement of the default line")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "qmr", "bicgstab2"])
     ap.add_argument("--copy-probe", action="store_true",
@@ -673,133 +848,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    desc, prec = WORKLOADS[args.workload]
-    prec = args.precision or prec
-    torch.cuda.synchronize()
-    t_create = time.perf_counter()
-    jobs, orientations, d = build_jobs(dda, w, args.workload, args.seed, prec, args.solver)
-    torch.cuda.synchronize()
-    target_create_ms = (time.perf_counter() - t_create) * 1e3
-    n_rhs = sum(len(j[2]) for j in jobs)
-    log(f"workload {args.workload}: {len(jobs)} target(s), {n_rhs} right-hand sides, prec={prec}, "
-        f"first target N={jobs[0][0].n_sites} grid={jobs[0][0].grid}")
-
-    def step():
-        if len(jobs) == 1:
-            t, o, kh, e0 = jobs[0]
-            return dda.solve(t, o, kh, e0, want_P=False)[1]
-        rt = [i for i, j in enumerate(jobs) for _ in range(len(j[2]))]
-        kh = np.vstack([j[2] for j in jobs])
-        e0 = np.vstack([j[3] for j in jobs])
-        return dda.solve_batched([j[0] for j in jobs], [j[1] for j in jobs], rt, kh, e0, want_P=False)[1]
-
-    def job_units(results):
-        """RHS-matvec units each job executed (iteration matvecs + 3 checks per RHS)."""
-        out, k = [], 0
-        for j in jobs:
-            n = len(j[2])
-            out.append(sum(r["matvecs"] for r in results[k:k + n]) + 3 * n)
-            k += n
-        return out
-
-    csize = 8 if prec == "fp32_matvec" else 16
-    bpus = [pass_bytes(j[0], j[0].n_sites, csize, args.solver) for j in jobs]
-
-    def pass_traffic(name, units, launches):
-        # per-RHS bytes times the RHS-matvecs each job executed, plus the
-        # shared bytes once per launch (several jobs: their launches taken as
-        # equal shares)
-        per_rhs = sum(b[name][0] * u for b, u in zip(bpus, units))
-        return per_rhs + sum(b[name][1] for b in bpus) * launches / len(bpus)
-
-    # warmup; the last warmup step times every kernel category to find the
-    # dominant matvec pass, which alone is timed during the measured steps
-    for i in range(max(args.warmup, 1)):
-        if i == max(args.warmup, 1) - 1:
-            dda.set_timing(True)
-        res = step()
-        log(f"warmup {i}: iters={[r['iters'] for r in res][:8]} status={set(r['status'] for r in res)}")
-    calib = dda.get_timing()
-    dda.set_timing(False)
-    cal_units = job_units(res)
-    dominant = max(PASSES, key=lambda k: calib[k][0])
-    log(f"dominant matvec kernel: {dominant} ({calib[dominant][0]:.3f} ms in the last warmup step)")
-
-    # events on every TIMING_SAMPLE-th launch of the dominant pass only (a
-    # systematic sample over the timed steps; the others carry no event cost)
-    dda.set_timing([dominant])
-    dda.set_timing_sample(TIMING_SAMPLE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    units = [0] * len(jobs)
-    results = None
-    for i in range(args.steps):
-        results = step()
-        units = [a + b for a, b in zip(units, job_units(results))]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timing = dda.get_timing()
-    dda.set_timing(False)
-    dda.set_timing_sample(1)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    s_per_orientation = ms_per_step / 1e3 / orientations
-    for r in results:
-        if r["status"] != 0:
-            raise SystemExit(f"solve did not converge: {r}")
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; results {results[0]}")
-
-    ms_tot, launches, all_launches = timing[dominant]
-    bytes_tot = pass_traffic(dominant, units, all_launches)
-    # algorithmic bytes per launch (all launches) over the sampled average launch time
-    avg_s = ms_tot * 1e-3 / launches
-    gbs = bytes_tot / all_launches / avg_s / 1e9
-    variants = dda.tuned_variants(jobs[0][0], len(jobs[0][2]), prec) if len(jobs) == 1 else None
-    traffic = (load_traffic(dominant, args.workload, prec, variants, sum(units) / all_launches)
-               if len(jobs) == 1 else None)
-    roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
-                "algorithmic_bytes_per_launch": bytes_tot / all_launches, "avg_launch_us": avg_s * 1e6,
-                "launches": all_launches, "timed_launches": launches}
-    # every pass, from the calibration step (one warmup step with all categories timed)
-    passes = {}
-    for name in PASSES:
-        ms, nl, _ = calib[name]
-        if nl == 0 or ms == 0:
-            continue
-        g = pass_traffic(name, cal_units, nl) / (ms * 1e-3) / 1e9
-        passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": bpus[0][name][0],
-                        "bytes_per_launch_shared": bpus[0][name][1], "GBps": g, "frac": g / HBM_PEAK_GBS}
-    matvec_ms = sum(calib[k][0] for k in PASSES)
-    matvec_bytes = sum(pass_traffic(k, cal_units, calib[k][1]) for k in PASSES)
-    out = {
-        "metric": METRIC,
-        "value": s_per_orientation,
-        "unit": "s/orientation",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32 matvec / f64 Krylov",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "solver": args.solver, "targets": len(jobs),
-                   "n_sites": [j[0].n_sites for j in jobs][:4], "fft_grid": list(jobs[0][0].grid),
-                   "rhs_per_step": n_rhs, "orientations_per_step": orientations, "precision": prec,
-                   "seed": args.seed},
-        "roofline": roofline,
-        "autotuned_variants": variants,
-        "target_create_ms": target_create_ms,
-        "matvec": {"GBps_all_passes": matvec_bytes / (matvec_ms * 1e-3) / 1e9,
-                   "units_per_step": sum(units) / args.steps, "passes_calibration_step": passes},
-        "kernel_ms_calibration_step": {k: v[0] for k, v in calib.items()},
-        "solver": {"iters": [r["iters"] for r in results][:8], "matvecs": [r["matvecs"] for r in results][:8],
-                   "qext": [r["qext"] for r in results][:8], "qabs": [r["qabs"] for r in results][:8],
-                   "qsca": [r["qsca"] for r in results][:8], "rel_residual": [r["rel_residual"] for r in results][:8],
-                   "normal_eq_residual": [r["normal_eq_residual"] for r in results][:8],
-                   "refinements": [r["refinements"] for r in results][:8]},
-    }
+    prec = args.precision or WORKLOADS[args.workload][1]
+    out, jobs, d, results, ms_per_step = measure_workload(dda, np, torch, w, args.workload, prec, args.solver,
+                                                          args.seed, args.steps, args.warmup)
+    if prec == "fp32_matvec" and len(jobs) == 1 and not args.no_plain:
+        log("solving the same workload with the FP64 matvec ...")
+        out["fp64_matvec"] = fp64_comparison(dda, np, torch, jobs, results)
+    if args.workload == DEFAULT_WORKLOAD and not args.no_extra:
+        log(f"measuring {EXTRA_WORKLOAD} for context ...")
+        xo, xjobs, _, xres, xms = measure_workload(dda, np, torch, w, EXTRA_WORKLOAD, WORKLOADS[EXTRA_WORKLOAD][1],
+                                                   args.solver, args.seed, args.steps, args.warmup)
+        out["also"] = {EXTRA_WORKLOAD: {k: xo[k] for k in ("value", "unit", "ms_per_step", "roofline", "dtype")}}
+        out["also"][EXTRA_WORKLOAD]["note"] = ("the 51,488-site ellipsoid (FFT grid 128x96x64, FP64): its ~130 MB "
+                                               "working set fits the 256 MB Infinity Cache")
     if not args.no_plain:
         log("timing the plain FP64 single-right-hand-side solves of the same workload ...")
         out["vs_plain_fp64_single_rhs"] = plain_reference(dda, np, torch, jobs, results, ms_per_step)

@@ -290,19 +290,6 @@ def set_timing(categories=True, device: int | None = None) -> None:
     _check(_lib.dda_ctx_set_timing(context(device), mask), "dda_ctx_set_timing")
 
 
-def lab_directions(theta_deg, phi_deg):
-    """Scattering directions for incidence along x (the guide's Lab Frame):
-    n = x cos t + (y cos p + z sin p) sin t and the unit vectors theta_s,
-    phi_s of the scattered polarizations (phi = 0: the x-y scattering plane).
-    Returns three float64 arrays [n_dir, 3]."""
-    t = np.radians(np.asarray(theta_deg, dtype=np.float64).reshape(-1))
-    p = np.radians(np.asarray(phi_deg, dtype=np.float64).reshape(-1))
-    n = np.stack([np.cos(t), np.sin(t) * np.cos(p), np.sin(t) * np.sin(p)], axis=-1)
-    th = np.stack([-np.sin(t), np.cos(t) * np.cos(p), np.cos(t) * np.sin(p)], axis=-1)
-    ph = np.stack([np.zeros_like(t), -np.sin(p), np.cos(p)], axis=-1)
-    return n, th, ph
-
-
 def far_field(target: "Target", opts: Options, P: torch.Tensor, n_hat, theta_hat, phi_hat):
     """Scattering amplitudes f [n_rhs, n_dir, 2] (complex128: theta, phi
     components) and differential cross sections dcs [n_rhs, n_dir] of the

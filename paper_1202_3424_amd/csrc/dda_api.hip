@@ -180,7 +180,7 @@ struct dda_target {
     int nmat = 0;
     Geo geo{};
     std::vector<double2> mats;       // distinct refractive indices (and their device copy mdev)
-    DevBuf map, mat, coords, perm, tw, mdev;
+    DevBuf map, mat, coords, perm, tw, tw32, mdev;
     // cached FFT of the interaction tensor
     double green_kd = -1.0;
     bool have64 = false, have32 = false;
@@ -1248,10 +1248,14 @@ dda_target* create_target(dda_ctx* c, int64_t n_sites, const int32_t* ijk, const
         up(t->mat, mat.data(), mat.size() * sizeof(int));
         up(t->coords, coords.data(), coords.size() * sizeof(int));
         up(t->tw, tw.data(), tw.size() * sizeof(double2));
+        std::vector<float2> tw32(tw.size());
+        for (size_t i = 0; i < tw.size(); ++i) tw32[i] = float2{(float)tw[i].x, (float)tw[i].y};
+        up(t->tw32, tw32.data(), tw32.size() * sizeof(float2));
+        t->geo.tw32 = (const float2*)t->tw32.p;
         up(t->mdev, t->mats.data(), t->mats.size() * sizeof(double2));
         for (int a = 0; a < 3; ++a) t->lo[a] = lo[a];
     } catch (...) {
-        for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->mdev}) b->release();
+        for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->tw32, &t->mdev}) b->release();
         delete t;
         throw;
     }
@@ -1263,7 +1267,8 @@ void free_target(dda_target* t) {
     if (!t) return;
     free_target(t->nf);
     t->nf = nullptr;
-    for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->mdev, &t->gh64, &t->gh32}) b->release();
+    for (DevBuf* b : {&t->map, &t->perm, &t->mat, &t->coords, &t->tw, &t->tw32, &t->mdev, &t->gh64, &t->gh32})
+        b->release();
     delete t;
 }
 

@@ -417,12 +417,15 @@ constexpr bool ct_half_out_ok(int L) { return ct_plan(L, ct_plan(L, -1) - 1) % 2
 // whose frequency agrees modulo P (second group), which is what lets a thread
 // run a whole group on its own registers.
 
+// The twiddle table TW is the host's FP64 W_L^t (double2) or its values
+// rounded to FP32 (float2); either way the factors used equal those of the
+// LDS form, which rounds the FP64 table the same way.
 // First group on NCL lines of one subsequence each (the lines share the
 // twiddles), thread index t: on entry v[a][m] = x_a[t + Q m]; on exit
 // v[a][f] = element t*P + f of line a.  HIN: x[e] = 0 for e >= L/2 (the
 // first pass reads only its lower inputs, as fft_pass_ct does).
-template <typename T, int DIR, int L, bool HIN, int NCL, int S = 0, int NS = 1>
-__device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[NCL][ct_split(L)], const double2* tw) {
+template <typename T, int DIR, int L, bool HIN, int NCL, int S = 0, int NS = 1, typename TW>
+__device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[NCL][ct_split(L)], const TW* tw) {
     using C = typename V2<T>::t;
     constexpr int P = ct_split(L);
     if constexpr (NS < P) {
@@ -438,7 +441,7 @@ __device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[NCL][ct_split(
                 if constexpr (NS > 1) {
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
-                        const double2 t = tw[r * k * TSTEP];
+                        const TW t = tw[r * k * TSTEP];
                         w[r].x = (decltype(w[r].x))t.x;
                         w[r].y = (decltype(w[r].y))(DIR > 0 ? -t.y : t.y);
                     }
@@ -479,8 +482,9 @@ __device__ __forceinline__ void rf_group_a(typename V2<T>::t (&v)[NCL][ct_split(
 // v[a][c*Q + jj] = element jj*P + kappa_c of line a; on exit
 // v[a][c*Q + g] = X_a[kappa_c + P g].  HOUT: only X[e], e < L/2, is wanted
 // (the last pass computes only its lower outputs, as fft_pass_ct does).
-template <typename T, int DIR, int L, bool HOUT, int NCL, int S = ct_split_passes(L), int NS = ct_split(L)>
-__device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[NCL][ct_split(L)], int t, const double2* tw) {
+template <typename T, int DIR, int L, bool HOUT, int NCL, int S = ct_split_passes(L), int NS = ct_split(L),
+          typename TW>
+__device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[NCL][ct_split(L)], int t, const TW* tw) {
     using C = typename V2<T>::t;
     constexpr int P = ct_split(L);
     constexpr int Q = L / P;
@@ -502,7 +506,7 @@ __device__ __forceinline__ void rf_group_b(typename V2<T>::t (&v)[NCL][ct_split(
                     C w[R];
 #pragma unroll
                     for (int r = 1; r < R; ++r) {
-                        const double2 tt = tw[r * ks * TSTEP];
+                        const TW tt = tw[r * ks * TSTEP];
                         w[r].x = (decltype(w[r].x))tt.x;
                         w[r].y = (decltype(w[r].y))(DIR > 0 ? -tt.y : tt.y);
                     }

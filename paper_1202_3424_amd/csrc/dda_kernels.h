@@ -35,12 +35,14 @@ LaunchEvents& launch_events();
 //   H[a]  M[a]/2 + 1: extent of the stored octant of the tensor FFT
 // Grids hold NC complex components interleaved per point, point index
 // (z * My + y) * Mx + x, right-hand side outermost.
+//   tw32  the twiddle tables W_L^t rounded to FP32 (the FP64 tables' offsets)
 struct Geo {
     int n[3];
     int M[3];
     int H[3];
     long long npts;
     AxisPlan ax[3];
+    const float2* tw32;
 };
 
 // Site-indexed FP64 vectors of one batched solve, each [nrhs][n3] with
@@ -122,7 +124,7 @@ template <typename T>
 void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant = 0);
-inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 24 : 8) : 1; }
+inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 28 : 8) : 1; }
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);

@@ -955,6 +955,176 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
     }
 }
 
+// Pass 3 for the square lengths L = P^2 (64 = 8 x 8, 256 = 16 x 16) in
+// register-resident form.  With P = Q the forward transform's second pass
+// group leaves thread t with the frequencies kz = t + P g (g < P), which is
+// the subsequence t + Q m the inverse transform's first group reads: the
+// product goes from the forward to the inverse transform without the
+// exchange k_strided_rf makes (two exchanges per column instead of three,
+// the same passes and twiddles, so bitwise-identical results).  Also: the
+// twiddles come from the table in the grid's precision (no FP64 -> FP32
+// conversion), the z extent is the compile-time L so the z parities and the
+// octant rows of the tensor are compile-time for all but one frequency per
+// thread, and each thread keeps one base address per column.  TX columns per
+// workgroup, Q threads per column (thread t = threadIdx.x / TX); one
+// right-hand side per workgroup; XR exchange rounds; XG: the XCD-grouped
+// order of xcd_tile; WV: occupancy asked of the compiler; PD: how many
+// points ahead the tensor values are loaded (0: where the compiler puts
+// them, which is all sixteen at once).
+template <typename T> __device__ __forceinline__ const typename V2<T>::t* tw_table(const Geo& g, const double2* tw64);
+template <> __device__ __forceinline__ const double2* tw_table<double>(const Geo&, const double2* tw64) { return tw64; }
+template <> __device__ __forceinline__ const float2* tw_table<float>(const Geo& g, const double2*) { return g.tw32; }
+
+constexpr bool zsq_length(int L) { return L == 64 || L == 256; }
+
+template <typename T, int L, int TX, int XR, bool XG, int WV, int PD = 0>
+__global__ __launch_bounds__(TX * (L / ct_split(L))) __attribute__((amdgpu_waves_per_eu(WV)))
+void k_zsq(Geo g, typename V2<T>::t* grid, const double2* tw64, const typename V2<T>::t* ghat, const RhsState* st,
+           int lin, int lout, int chk, int nrhs) {
+    using C = typename V2<T>::t;
+    constexpr int P = ct_split(L);
+    constexpr int Q = L / P;
+    static_assert(P == Q, "square lengths only");
+    constexpr int LS = rf_line_stride<L>();
+    static_assert((3 * TX) % XR == 0, "exchange rounds must split the tile's lines");
+    extern __shared__ __align__(16) unsigned char smem[];
+    C* lds = (C*)smem;
+    const int Mx = g.M[0], My = g.M[1];
+    int q, o, xt;
+    if constexpr (XG) {
+        if (!xcd_tile(Mx, My, TX, nrhs, xt, o, q)) return;
+    } else {
+        q = blockIdx.z;
+        o = blockIdx.y;
+        xt = blockIdx.x;
+    }
+    if (skip_rhs(st + q, chk)) return;
+    const int in = threadIdx.x % TX;
+    const int t = threadIdx.x / TX;
+    const int kx = xt * TX + in;
+    const bool col = kx < Mx;
+    const C* tw = tw_table<T>(g, tw64) + g.ax[2].tw;
+    const long long zs = (long long)My * Mx * 3;   // z stride of the grid
+    // this thread's column at z = t; element m of its subsequence is z = t + Q m
+    C* gc = grid + (long long)q * g.npts * 3 + (long long)o * Mx * 3 + (long long)kx * 3 + (long long)t * zs;
+    C v[3][P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (2 * m < P && col && t + Q * m < lin) {
+                v[a][m] = gc[(long long)m * Q * zs + a];
+            } else {
+                v[a][m].x = 0;
+                v[a][m].y = 0;
+            }
+        }
+    }
+    // residue classes <-> subsequences through LDS, one component of XR per round
+    auto exchange = [&]() {
+#pragma unroll
+        for (int rd = 0; rd < XR; ++rd) {
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int ln = in * 3 + a;
+                if (ln % XR == rd) {
+                    C* row = lds + (ln / XR) * LS + t * (P + 1);
+#pragma unroll
+                    for (int f = 0; f < P; ++f) row[f] = v[a][f];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int ln = in * 3 + a;
+                if (ln % XR == rd) {
+                    const C* row = lds + (ln / XR) * LS + t;
+#pragma unroll
+                    for (int jj = 0; jj < Q; ++jj) v[a][jj] = row[jj * (P + 1)];
+                }
+            }
+        }
+    };
+    rf_group_a<T, -1, L, true, 3>(v, tw);
+    exchange();
+    rf_group_b<T, -1, L, false, 3>(v, t, tw);
+    // y_a = sum_b Ghat_ab x_b at (kx, ky = o, kz = t + P gg); the stored
+    // octant and the parities (diagonal even, ab odd in a and b)
+    if (col) {
+        const int Hx = g.H[0], Hy = g.H[1];
+        const int fx = (kx <= Mx / 2) ? kx : Mx - kx;
+        const int fy = (o <= My / 2) ? o : My - o;
+        const bool fxy = (kx <= Mx / 2) != (o <= My / 2);   // sx sy < 0
+        const bool nx = kx > Mx / 2, ny = o > My / 2;       // sx < 0, sy < 0
+        const long long hz = (long long)Hy * Hx * 6;        // octant z stride
+        const C* gl = ghat + ((long long)fy * Hx + fx) * 6 + (long long)t * hz;        // fz = t + P gg
+        const C* gu = ghat + ((long long)fy * Hx + fx) * 6 + (long long)(L - t) * hz;  // fz = L - t - P gg
+        // kz = t + P gg <= L/2 for gg < P/2, > L/2 for gg > P/2; at gg = P/2
+        // only t = 0 (kz = L/2) is in the lower half
+        auto gptr = [&](int gg) {
+            const bool up = 2 * gg > P || (2 * gg == P && t != 0);
+            return up ? gu - (long long)P * gg * hz : gl + (long long)P * gg * hz;
+        };
+        // PD > 0: the tensor values of point gg + PD are loaded while point gg
+        // is formed, and not earlier (their address is tied to point gg's
+        // result), which bounds the registers the loads hold
+        C Gb[PD > 0 ? PD : 1][6];
+        if constexpr (PD > 0) {
+#pragma unroll
+            for (int d = 0; d < PD; ++d) {
+                const C* Gp = gptr(d);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Gb[d][k] = Gp[k];
+            }
+        }
+#pragma unroll
+        for (int gg = 0; gg < P; ++gg) {
+            const bool up = 2 * gg > P || (2 * gg == P && t != 0);   // sz < 0
+            C G6[6];
+            if constexpr (PD > 0) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) G6[k] = Gb[gg % PD][k];
+            } else {
+                const C* Gp = gptr(gg);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) G6[k] = Gp[k];
+            }
+            const bool f2 = nx != up, f4 = ny != up;   // sx sz < 0, sy sz < 0
+            G6[1].x = fxy ? -G6[1].x : G6[1].x;
+            G6[1].y = fxy ? -G6[1].y : G6[1].y;
+            G6[2].x = f2 ? -G6[2].x : G6[2].x;
+            G6[2].y = f2 ? -G6[2].y : G6[2].y;
+            G6[4].x = f4 ? -G6[4].x : G6[4].x;
+            G6[4].y = f4 ? -G6[4].y : G6[4].y;
+            const C X = v[0][gg], Y = v[1][gg], Z = v[2][gg];
+            v[0][gg] = trow(G6[0], G6[1], G6[2], X, Y, Z);
+            v[1][gg] = trow(G6[1], G6[3], G6[4], X, Y, Z);
+            v[2][gg] = trow(G6[2], G6[4], G6[5], X, Y, Z);
+            if constexpr (PD > 0) {
+                if (gg + PD < P) {
+                    const C* Gp = gptr(gg + PD);
+                    asm volatile("" : "+v"(Gp) : "v"(v[2][gg].x));
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) Gb[gg % PD][k] = Gp[k];
+                }
+            }
+        }
+    }
+    rf_group_a<T, 1, L, false, 3>(v, tw);
+    exchange();
+    rf_group_b<T, 1, L, true, 3>(v, t, tw);
+    if (col) {
+#pragma unroll
+        for (int gg = 0; gg < Q / 2; ++gg) {
+            if (t + P * gg < lout) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) gc[(long long)gg * P * zs + a] = v[a][gg];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename T, int MODE>
@@ -1009,7 +1179,26 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
 // bounded by 48 KB per workgroup.
 constexpr int n_lds_variants(int gh) { return gh ? 12 : 4; }
 constexpr int rf_variants(int gh) { return gh ? 12 : 4; }
-constexpr int n_strided_variants(int gh) { return n_lds_variants(gh) + rf_variants(gh); }
+// pass 3 at the square lengths: k_zsq variants after the register-resident
+// ones (elsewhere they fall back to variant 0)
+constexpr int zsq_variants(int gh) { return gh ? 4 : 0; }
+constexpr int n_strided_variants(int gh) { return n_lds_variants(gh) + rf_variants(gh) + zsq_variants(gh); }
+// k_zsq variant r: (tile width, tensor prefetch distance), all in the
+// XCD-grouped order, three exchange rounds and the occupancy the line data
+// allow: r = 0 (16, 2), 1 (8, 4), 2 (8, 2), 3 (16, none); each exists where
+// its LDS tile fits 64 KB
+constexpr int zsq_tx(int r) { return (r == 1 || r == 2) ? 8 : 16; }
+constexpr int zsq_xr(int) { return 3; }
+constexpr bool zsq_xg(int) { return true; }
+constexpr int zsq_pd(int r) { return r == 1 ? 4 : (r == 3 ? 0 : 2); }
+template <typename T> constexpr bool zsq_feasible(int L, int r) {
+    const int P = ct_split(L);
+    return (size_t)(3 * zsq_tx(r) / zsq_xr(r)) * (((L / P) * (P + 1)) | 1) * 2 * sizeof(T) <= 65536;
+}
+template <typename T> constexpr int zsq_wv(int L, int) {
+    const int d = 3 * ct_split(L) * (int)(2 * sizeof(T) / 4);   // VGPRs of line data
+    return d <= 48 ? 4 : (d <= 96 ? 2 : 1);
+}
 template <typename T> constexpr int ct_budget() { return sizeof(T) == 4 ? 6144 : 3072; }
 template <typename T> constexpr int variant_tx(int L, int gh, int v) {
     const int base = ct_cols(L);
@@ -1067,7 +1256,24 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                        typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
                        const RhsState* st, hipStream_t s) {
     using C = typename V2<T>::t;
-    if constexpr (V >= n_lds_variants(GH)) {
+    if constexpr (V >= n_lds_variants(GH) + rf_variants(GH)) {
+        constexpr int R = V - n_lds_variants(GH) - rf_variants(GH);
+        if constexpr (NC == 3 && GH && zsq_length(LL) && zsq_feasible<T>(LL, R)) {
+            constexpr int TX = zsq_tx(R), XR = zsq_xr(R);
+            constexpr bool XG = zsq_xg(R);
+            constexpr int WV = zsq_wv<T>(LL, R);
+            if (2 * lin <= LL && 2 * lout <= LL) {
+                constexpr int Q = LL / ct_split(LL);
+                dim3 grd((g.M[0] + TX - 1) / TX, n_outer, nrhs);
+                if (XG) grd = dim3(xcd_grid(g.M[0], g.M[1], TX, nrhs));
+                const size_t shm = (size_t)(3 * TX / XR) * rf_line_stride<LL>() * sizeof(C);
+                DDA_LAUNCH((k_zsq<T, LL, TX, XR, XG, WV, zsq_pd(R)>), grd, dim3(TX * Q), shm, s, g, grid, tw, ghat, st,
+                           lin, lout, chk, nrhs);
+                return;
+            }
+        }
+        strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+    } else if constexpr (V >= n_lds_variants(GH)) {
         constexpr int R = V - n_lds_variants(GH);
         constexpr int TX = rf_tx(GH, R), XR = rf_xr(GH, R);
         constexpr bool XG = rf_xg(GH, R);
@@ -1125,7 +1331,7 @@ void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_
         break;
         DDA_V(1) DDA_V(2) DDA_V(3) DDA_V(4) DDA_V(5) DDA_V(6) DDA_V(7) DDA_V(8) DDA_V(9) DDA_V(10) DDA_V(11)
         DDA_V(12) DDA_V(13) DDA_V(14) DDA_V(15) DDA_V(16) DDA_V(17) DDA_V(18) DDA_V(19) DDA_V(20) DDA_V(21)
-        DDA_V(22) DDA_V(23)
+        DDA_V(22) DDA_V(23) DDA_V(24) DDA_V(25) DDA_V(26) DDA_V(27)
 #undef DDA_V
         default:
             break;
@@ -1212,7 +1418,7 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
     }
 }
 
-static_assert(passes::n_strided_variants(1) == 24 && passes::n_strided_variants(0) == 8,
+static_assert(passes::n_strided_variants(1) == 28 && passes::n_strided_variants(0) == 8,
               "strided_variants() in dda_kernels.h counts these variants");
 
 #define DDA_INSTANTIATE_PASSES(T)                                                                                 \

@@ -50,9 +50,13 @@ def test_profile_commands_run_committed_files_under_the_profiler():
         assert "-- python -u /root/repo/bench.py" in c[k] and "/root/repo/gpurun_out/tr_x/" in c[k]
     assert "--pmc FETCH_SIZE" in c["fetch"] and "--pmc WRITE_SIZE" in c["write"]
     assert "--kernel-trace --stats" in c["trace"] and "--pmc" not in c["trace"]
-    assert "--workload sphere1m --precision fp32_matvec" in c["unprofiled"]
-    # the default workload and precision add no flags
-    assert "--workload" not in bench.profile_commands("ellipsoid51k", "fp64")["unprofiled"]
+    # the default workload (sphere1m, FP32 matvec) adds no flags; others do
+    assert "--workload" not in c["unprofiled"] and "--precision" not in c["unprofiled"]
+    assert "--precision fp64" in bench.profile_commands("sphere1m", "fp64")["unprofiled"]
+    assert "--workload ellipsoid51k" in bench.profile_commands("ellipsoid51k", "fp64")["unprofiled"]
+    # profiled runs hold the measured workload's kernels only
+    for k in ("trace", "fetch", "write", "unprofiled"):
+        assert "--no-plain --no-extra" in c[k]
 
 
 def test_more_than_one_gpu_is_refused():

@@ -114,6 +114,21 @@ def incidences_for_orientations(seed: int, count: int) -> tuple[np.ndarray, np.n
     return np.array(kh), np.array(e0)
 
 
+def lab_directions(theta_deg, phi_deg) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Scattering directions for incidence along x (the Lab Frame of "Target
+    Orientation"): for scattering angle theta and scattering-plane angle phi
+    (phi = 0: the x-y plane), the unit vector n of the direction and the unit
+    vectors theta_s, phi_s of the two scattered polarizations, as three
+    float64 arrays [n_dir, 3] (n, theta_s, phi_s a right-handed frame)."""
+    t = np.radians(np.asarray(theta_deg, dtype=np.float64).reshape(-1))
+    p = np.radians(np.asarray(phi_deg, dtype=np.float64).reshape(-1))
+    ct, st, cp, sp = np.cos(t), np.sin(t), np.cos(p), np.sin(p)
+    n = np.stack([ct, st * cp, st * sp], axis=-1)
+    theta_s = np.stack([-st, ct * cp, ct * sp], axis=-1)
+    phi_s = np.stack([np.zeros_like(t), -sp, cp], axis=-1)
+    return n, theta_s, phi_s
+
+
 def along_x_yz() -> tuple[np.ndarray, np.ndarray]:
     """Incidence along +x with the two linear polarizations y and z."""
     kh = np.array([[1.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
