@@ -175,6 +175,31 @@ dda_status dda_target_geometry(const dda_target* t, int32_t box[3], int32_t grid
 dda_status dda_apply(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
                      const dda_incidence* inc, const dda_c64* x, dda_c64* y);
 
+/* dda_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same product (the same kernels: results are bitwise those of dda_apply),
+ * with every work buffer -- the incidences, 1/alpha, the sorted input and
+ * output site vectors and the padded FFT grid -- taken from one fixed
+ * 128 MiB (134217728-byte) device array that the library holds on each GPU it
+ * runs on until the process ends; the call makes no hipMalloc or hipFree.
+ *   Needs, rounded up to 256 bytes per part: n_rhs * (72 + 48 n_materials
+ *   + 96 n_sites + 24 c M) bytes, c = 2 (DDA_FP64) or 1 (DDA_FP32_MATVEC),
+ *   M = the padded grid's point count; E_INVALID above the 128 MiB, or for
+ *   n_rhs outside 1..256.
+ *   The FFT of the interaction tensor at this kd and precision must already
+ *   be built on the target (by a dda_apply or dda_solve call with the same
+ *   wavelength, aeff, m_medium and precision), else E_INVALID; so must not
+ *   DDA_FLAG_RECOMPUTE_GREEN be set.  The strided-pass tiling is the one the
+ *   autotuner chose for this shape, if any, else the default (or
+ *   opts->kernel_variant); no timing events are recorded.
+ * x, y, inc and the errors otherwise as dda_apply.  The work array keeps the
+ * last call's contents and nothing in it needs to start at zero; every call
+ * on one GPU shares it, so calls that overlap on one GPU (several streams or
+ * host threads) race and must be serialised by the caller.  Enqueued on the
+ * context's stream; returns without synchronising. */
+dda_status dda_apply_noalloc(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int32_t n_rhs,
+                             const dda_incidence* inc, const dda_c64* x, dda_c64* y);
+
 /* Solve A P = E for n_rhs incidences on one target (batched in every kernel;
  * the right-hand sides share the interaction-tensor FFT).
  *   P   device [n_rhs][n_sites][3] output (may be NULL: Q only);

@@ -17,7 +17,7 @@ arguments.  ``paper_1202_3424_amd.build.build()`` compiles the library.
 The public names below load libdda.so on first use and raise ImportError if
 it has not been built: there is no fallback implementation.
 """
-_PUBLIC = ("DDAError", "Options", "QEff", "Target", "apply", "context", "far_field", "field_line", "get_timing",
+_PUBLIC = ("DDAError", "Options", "QEff", "Target", "apply", "apply_noalloc", "context", "far_field", "field_line", "get_timing",
            "grad_eps", "last_error", "mueller", "nearfield", "nearfield_volume",
            "scattering_averages", "set_timing", "set_timing_sample", "solve", "solve_batched", "solve_rhs",
            "tuned_variants")

@@ -82,6 +82,8 @@ SIGNATURES = {
     "dda_target_destroy": (ctypes.c_int, [VP]),
     "dda_target_geometry": (ctypes.c_int, [VP, VP, VP]),
     "dda_apply": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP]),
+    "dda_apply_noalloc": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP,
+                                         VP]),
     "dda_solve": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP,
                                  ctypes.POINTER(Result)]),
     "dda_solve_rhs": (ctypes.c_int, [VP, VP, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Incidence), VP, VP,

@@ -176,6 +176,21 @@ def apply(target: Target, opts: Options, khat, e0, x: torch.Tensor) -> torch.Ten
     return y
 
 
+def apply_noalloc(target: Target, opts: Options, khat, e0, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """y = A x into the caller's y (complex128 CUDA [n_rhs, N, 3]) with the
+    library's fixed work memory (dda_apply_noalloc: no device allocation; the
+    target's tensor FFT for these options must already be built)."""
+    inc = _incidences(khat, e0)
+    x = _dev_c128(x, (len(inc), target.n_sites, 3), "x")
+    _dev_c128(y, (len(inc), target.n_sites, 3), "y")
+    if not y.is_contiguous():
+        raise ValueError("y must be contiguous")
+    o = opts.c()
+    _check(_lib.dda_apply_noalloc(target.ctx, target.handle, ctypes.byref(o), len(inc), inc, x.data_ptr(),
+                                  y.data_ptr()), "dda_apply_noalloc")
+    return y
+
+
 def solve(target: Target, opts: Options, khat, e0, P0: torch.Tensor | None = None, want_P: bool = True,
           raise_on_failure: bool = False):
     """Solve A P = E for every incidence; returns (P or None, [result dict])."""

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <array>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -193,6 +194,65 @@ struct dda_target {
 };
 
 namespace {
+
+// Work memory of dda_apply_noalloc: one fixed device array, a copy of it on
+// every GPU the library runs on, held until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: its device address on each
+// GPU comes from hipGetSymbolAddress, taken once per device when a context is
+// created there (scratch_setup) and kept in g_scratch.
+constexpr size_t SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+constexpr int NOALLOC_MAX_RHS = 256;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch[SCRATCH_MAX_DEVICES] = {};
+
+// With the context's device current: look up this device's copy of the
+// work array once.
+void scratch_setup(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        set_err(std::string("hipGetSymbolAddress of the work array failed: ") + hipGetErrorString(e));
+        throw Fail{DDA_E_DEVICE};
+    }
+    g_scratch[device] = p;
+}
+void* scratch_of(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
+
+// Layout of the work memory of dda_apply_noalloc (byte offsets, 256-byte
+// aligned): incidences, 1/alpha, the sorted input and output site vectors
+// and the padded grid of the product's precision.
+struct Carve {
+    size_t kh, e0, ainv, xs, ys, grid, total;
+};
+Carve carve_layout(const dda_target* t, int nrhs, bool fp32) {
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t n3 = 3 * (size_t)t->nsites;
+    Carve L{};
+    size_t off = 0;
+    L.kh = off;
+    off = up(off + (size_t)nrhs * 3 * sizeof(double));
+    L.e0 = off;
+    off = up(off + (size_t)nrhs * 3 * sizeof(double2));
+    L.ainv = off;
+    off = up(off + (size_t)nrhs * t->nmat * 3 * sizeof(double2));
+    L.xs = off;
+    off = up(off + (size_t)nrhs * n3 * sizeof(double2));
+    L.ys = off;
+    off = up(off + (size_t)nrhs * n3 * sizeof(double2));
+    L.grid = off;
+    off = up(off + (size_t)nrhs * (size_t)t->geo.npts * 3 * (fp32 ? sizeof(float2) : sizeof(double2)));
+    L.total = off;
+    return L;
+}
 
 struct Scope {  // make the context's device current for the duration of a call
     int prev = 0;
@@ -394,6 +454,27 @@ struct Work {
         char* ib = (char*)ws.inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
         kh = (double*)ib;
         e0 = (double2*)(ib + (((size_t)nrhs * 3 * sizeof(double) + 15) & ~(size_t)15));
+    }
+
+    // The plain product only, every buffer carved from `base` as laid out by
+    // carve_layout (the fixed work memory of dda_apply_noalloc): nothing is
+    // allocated.  The product reads a.p and writes a.v; the solver vectors,
+    // states and partial sums stay null (a plain product never touches them).
+    Work(dda_ctx* c_, Workspace& ws_, dda_target* t_, int nrhs_, double kd_, bool fp32_, char* base, const Carve& L)
+        : c(c_), ws(ws_), s(ws_.stream), t(t_), nrhs(nrhs_), kd(kd_), fp32(fp32_) {
+        a.nsites = t->nsites;
+        a.n3 = 3LL * t->nsites;
+        a.nrhs = nrhs;
+        a.nmat = t->nmat;
+        a.map = (const int*)t->map.p;
+        a.mat = (const int*)t->mat.p;
+        a.kd = kd;
+        a.p = (double2*)(base + L.xs);
+        a.v = (double2*)(base + L.ys);
+        a.ainv = (const double2*)(base + L.ainv);
+        grid = base + L.grid;
+        kh = (double*)(base + L.kh);
+        e0 = (double2*)(base + L.e0);
     }
 
     void upload_incidence(const double* khv, const double2* e0v) {
@@ -1327,11 +1408,15 @@ dda_status dda_ctx_create(int device, void* hip_stream, dda_ctx** out) {
         int n = 0;
         HIPCHK(hipGetDeviceCount(&n));
         if (device < 0 || device >= n) invalid("no HIP device " + std::to_string(device));
-        auto* c = new dda_ctx();
+        std::unique_ptr<dda_ctx> c(new dda_ctx());
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
         c->main.stream = c->stream;
-        *out = c;
+        {
+            Scope sc(c.get());
+            scratch_setup(device);
+        }
+        *out = c.release();
         return DDA_OK;
     });
 }
@@ -1420,6 +1505,49 @@ dda_status dda_apply(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs
         w.a.out = w.a.v;
         w.matvec(SC_PLAIN, GA_PLAIN, CHK_NONE, CHK_NONE);
         launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, w.a.v, (double2*)y, false, c->stream);
+        HIPCHK(hipGetLastError());
+        return DDA_OK;
+    });
+}
+
+dda_status dda_apply_noalloc(dda_ctx* c, dda_target* t, const dda_opts* o, int32_t n_rhs,
+                             const dda_incidence* inc, const dda_c64* x, dda_c64* y) {
+    return guarded([&]() -> dda_status {
+        if (!c || !t || !x || !y) invalid("NULL argument");
+        if (x == y) invalid("x and y alias");
+        if (n_rhs < 1 || n_rhs > NOALLOC_MAX_RHS) invalid("n_rhs must lie in 1..256");
+        check_opts(o);
+        Scope sc(c);
+        double khv[3 * NOALLOC_MAX_RHS];
+        double2 e0v[3 * NOALLOC_MAX_RHS];
+        pack_incidence(n_rhs, inc, khv, e0v);
+        const double kd = kd_of(o, t->nsites);
+        const bool fp32 = o->precision == DDA_FP32_MATVEC;
+        if ((o->flags & DDA_FLAG_RECOMPUTE_GREEN) || t->green_kd != kd || !(fp32 ? t->have32 : t->have64))
+            invalid("the interaction-tensor FFT of this target at this kd and precision is not built (a dda_apply "
+                    "or dda_solve call with the same options builds it)");
+        char* base = (char*)scratch_of(c->device);
+        if (!base) invalid("no work memory on this device");
+        const Carve L = carve_layout(t, n_rhs, fp32);
+        if (L.total > SCRATCH_BYTES)
+            invalid("the product needs " + std::to_string(L.total) + " bytes of work memory, above the fixed " +
+                    std::to_string(SCRATCH_BYTES));
+        // no timing events (they would be created on first use)
+        struct NoEvents {
+            dda_ctx* c;
+            bool keep;
+            explicit NoEvents(dda_ctx* c_) : c(c_), keep(c_->tsuppress) { c->tsuppress = true; }
+            ~NoEvents() { c->tsuppress = keep; }
+        } ne(c);
+        Work w(c, c->main, t, n_rhs, kd, fp32, base, L);
+        w.autotune(false, o->kernel_variant);   // the tiling tuned for this shape, else the default
+        w.upload_incidence(khv, e0v);
+        w.alpha_table(o->polarizability, o->m_medium, (double2*)w.a.ainv);
+        launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)x, w.a.p, true, w.s);
+        w.a.in = w.a.p;
+        w.a.out = w.a.v;
+        w.matvec(SC_PLAIN, GA_PLAIN, CHK_NONE, CHK_NONE);
+        launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, w.a.v, (double2*)y, false, w.s);
         HIPCHK(hipGetLastError());
         return DDA_OK;
     });
