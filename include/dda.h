@@ -62,7 +62,7 @@ typedef enum {
     DDA_E_NOMEM = 2,          /* device or host allocation failed */
     DDA_E_DEVICE = 3,         /* a HIP call failed */
     DDA_E_NOT_CONVERGED = 4,  /* max_iter reached; best iterate returned */
-    DDA_E_BREAKDOWN = 5,      /* Krylov breakdown (BiCGSTAB: after one restart) */
+    DDA_E_BREAKDOWN = 5,      /* Krylov breakdown (BiCGSTAB, BiCGstab(2): after one restart) */
     DDA_E_NONFINITE = 6       /* NaN or Inf met in the iteration */
 } dda_status;
 
@@ -74,18 +74,25 @@ typedef enum { DDA_LATTDR = 0, DDA_GKDLDR = 1 } dda_polarizability;
  *                 iteration; stops when the recursive residual satisfies
  *                 |r| / |E| < tol, checked after the half step (|s|) and
  *                 after the iteration (|r|^2 = |s|^2 - |<t,s>|^2 / |t|^2, the
- *                 norm of s - omega t); one automatic restart after a
- *                 breakdown.
+ *                 norm of s - omega t).
  *   DDA_QMR_SYM   QMRCCG: QMR for complex-symmetric A, read as COCG (van der
  *                 Vorst & Melissen 1990) with quasi-minimal-residual smoothing
  *                 (Zhou & Walker 1994); one product per iteration; stops on
  *                 the smoothed residual |E - A P| / |E| < tol and returns the
- *                 smoothed iterate; a breakdown (P^T A P = 0 or r^T r = 0) ends
- *                 the solve with DDA_E_BREAKDOWN and that iterate (no restart).
+ *                 smoothed iterate.  A breakdown (p^T A p or r^T r vanishing)
+ *                 ends the solve with DDA_E_BREAKDOWN and that iterate (no
+ *                 restart).
  *   DDA_BICGSTAB2 PBCGS2: BiCGstab(l) with l = 2 (Sleijpen & Fokkema 1993), four
  *                 products per iteration (iters counts these iterations);
- *                 stops on |E - A P| / |E| < tol after an iteration; one
- *                 automatic restart after a breakdown. */
+ *                 stops on |E - A P| / |E| < tol after an iteration.
+ * Breakdown: an inner product that divides (<rhat, A p>, <rhat, r>, <t, s>;
+ * p^T A p, r^T r for QMR) is taken as zero when its modulus is at most 1e-12
+ * times the product of the norms of its two vectors (FP64 rounding level).
+ * BiCGSTAB and BiCGstab(2) then restart once from the current iterate with
+ * the shadow residual conj(r) in place of r (for A = A^T the form <conj(r),
+ * A r> = r^T A r is independent of <r, A r>, so a breakdown in the first
+ * step after a start is not repeated); a second breakdown ends the solve
+ * with DDA_E_BREAKDOWN. */
 typedef enum { DDA_BICGSTAB = 0, DDA_QMR_SYM = 1, DDA_BICGSTAB2 = 2 } dda_solver;
 
 /* Arithmetic of the FFT matrix-vector product.  The Krylov recurrences,

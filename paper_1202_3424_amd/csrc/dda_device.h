@@ -54,6 +54,7 @@ struct RhsState {
     double2 g1;      // BiCGstab(2): minimal-residual coefficients of r_1 and r_2
     double2 g2;
     double2 rs;      // BiCGSTAB: <rhat, s> of the latest half step
+    double rhat2;    // |rhat|^2 (BiCGSTAB, BiCGstab(2)): bounds the inner products with rhat
     double red[8];   // end-of-solve reductions (see kernels)
     int status;
     int iters;

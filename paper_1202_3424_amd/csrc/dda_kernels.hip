@@ -242,22 +242,29 @@ __global__ __launch_bounds__(NT) void k_bicg_flush(SiteArgs a) {
     }
 }
 
-// One restart after a breakdown: rhat = r, p = v = 0, rho = |r|^2.
+// One restart after a breakdown, from the current x and r: p = v = 0 and
+// the shadow residual rhat = conj(r), so that rho = <rhat, r> = r^T r.  A
+// shadow residual rhat = r would repeat a breakdown met in the first step
+// after a start (<r, A r> = 0 again); for A = A^T, <conj(r), A r> = r^T A r
+// is the bilinear form, independent of the Hermitian one.  Sums r^T r and
+// |r|^2 (= |rhat|^2).
 __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
     __shared__ double sh[8 * NT / 64];
     const int q = blockIdx.y;
     const RhsState* st = a.st + q;
     if (st->status != ST_BREAKDOWN || st->restarts > 0) return;
     const long long vb = (long long)q * a.n3;
-    double acc[1] = {0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
         const double2 rr = a.r[vb + i];
-        a.rhat[vb + i] = rr;
+        a.rhat[vb + i] = cconj(rr);
         a.p[vb + i] = double2{0.0, 0.0};
         a.v[vb + i] = double2{0.0, 0.0};
-        acc[0] += rr.x * rr.x + rr.y * rr.y;
+        acc[0] += rr.x * rr.x - rr.y * rr.y;
+        acc[1] += 2.0 * rr.x * rr.y;
+        acc[2] += rr.x * rr.x + rr.y * rr.y;
     }
-    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------------ QMR
@@ -340,6 +347,15 @@ __global__ __launch_bounds__(NT) void k_qmr_final(SiteArgs a) {
     }
 }
 
+// Breakdown tests compare a quantity with the norms that bound it: an inner
+// product <u, v> (or u^T v) is taken as zero when |<u, v>| <= BD_EPS |u| |v|,
+// the size of its FP64 rounding error over millions of terms (a single test
+// on exact zero would almost never fire).  bound2 is |u|^2 |v|^2.
+constexpr double BD_EPS = 1e-12;
+__device__ __forceinline__ bool vanishes(double2 z, double bound2) {
+    return z.x * z.x + z.y * z.y <= BD_EPS * BD_EPS * bound2;
+}
+
 // QMR state from the start sums: r^T r = (acc0, acc1), |r|^2 = acc2, |b|^2 =
 // acc3.  The first smoothing step is (0, 1): y = x, s = r.
 __device__ void qmr_start(RhsState* st, const double* acc) {
@@ -358,7 +374,7 @@ __device__ void qmr_start(RhsState* st, const double* acc) {
     } else if (acc[2] <= st->tol2 * acc[3]) {
         st->status = ST_CONVERGED;
     } else {
-        st->status = (acc[0] == 0.0 && acc[1] == 0.0) ? ST_BREAKDOWN : ST_ACTIVE;
+        st->status = vanishes(double2{acc[0], acc[1]}, acc[2] * acc[2]) ? ST_BREAKDOWN : ST_ACTIVE;
     }
 }
 
@@ -615,7 +631,8 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
         default: run = true; break;
     }
     if (!run) return;
-    const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE;
+    const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE ||
+                      kind == FIN_QV;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (kind == FIN_B_MR || kind == FIN_T) {
         sum_partials<8>(acc, part, nblk, sh);
@@ -633,11 +650,12 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     if (threadIdx.x != 0) return;
     switch (kind) {
         case FIN_V: {
+            // <rhat, v>, and |v|^2 in slot 2
             const double2 rv = {acc[0], acc[1]};
             st->pend = 0;   // the scatter before this product applied it
             st->matvecs += 1;
-            if (!finite2(rv)) st->status = ST_NONFINITE;
-            else if (rv.x == 0.0 && rv.y == 0.0) st->status = ST_BREAKDOWN;
+            if (!finite2(rv) || !isfinite(acc[2])) st->status = ST_NONFINITE;
+            else if (vanishes(rv, st->rhat2 * acc[2])) st->status = ST_BREAKDOWN;
             else st->alpha = cdiv(st->rho, rv);
             break;
         }
@@ -682,7 +700,8 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             st->pend = 1;
             if (r2 <= st->tol2 * st->bnorm2) {
                 st->status = ST_CONVERGED;
-            } else if ((rho_new.x == 0.0 && rho_new.y == 0.0) || (omega.x == 0.0 && omega.y == 0.0)) {
+            } else if (vanishes(rho_new, st->rhat2 * r2) || vanishes(ts, tt * acc[5])) {
+                // <rhat, r'> = 0, or <t, s> = 0 (omega = 0: no stabilising step)
                 st->status = ST_BREAKDOWN;
             } else {
                 st->beta = cmul(cdiv(rho_new, st->rho), cdiv(alpha, omega));
@@ -697,6 +716,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
         case FIN_COLD:
             st->bnorm2 = acc[0];
             st->rnorm2 = acc[0];
+            st->rhat2 = acc[0];
             st->rho = double2{acc[0], 0.0};
             st->alpha = double2{1.0, 0.0};
             st->omega = double2{1.0, 0.0};
@@ -711,6 +731,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
         case FIN_WARM:
             st->bnorm2 = acc[1];
             st->rnorm2 = acc[0];
+            st->rhat2 = acc[0];
             st->rho = double2{acc[0], 0.0};
             st->alpha = double2{1.0, 0.0};
             st->omega = double2{1.0, 0.0};
@@ -724,14 +745,18 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             else st->status = (acc[0] <= st->tol2 * acc[1]) ? ST_CONVERGED : ST_ACTIVE;
             break;
         case FIN_RESTART:
-            st->rho = double2{acc[0], 0.0};
+            // rho = r^T r (rhat = conj(r)), |rhat|^2 = |r|^2
+            st->rho = double2{acc[0], acc[1]};
+            st->rhat2 = acc[2];
+            st->rnorm2 = acc[2];
             st->alpha = double2{1.0, 0.0};
             st->omega = double2{1.0, 0.0};
             st->beta = double2{0.0, 0.0};
             st->sconv = 0;
             st->pend = 0;
             st->restarts += 1;
-            st->status = (acc[0] > 0.0 && isfinite(acc[0])) ? ST_ACTIVE : ST_BREAKDOWN;
+            if (!isfinite(acc[0]) || !isfinite(acc[1]) || !isfinite(acc[2])) st->status = ST_NONFINITE;
+            else st->status = vanishes(st->rho, acc[2] * acc[2]) ? ST_BREAKDOWN : ST_ACTIVE;
             break;
         case FIN_REFINE:
             // r holds the FP64 residual b - A x: keep converged or iterate on from x
@@ -741,6 +766,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                 st->status = ST_NONFINITE;
             } else if (acc[0] > st->tol2 * st->bnorm2) {
                 st->rho = double2{acc[0], 0.0};
+                st->rhat2 = acc[0];
                 st->alpha = double2{1.0, 0.0};
                 st->omega = double2{1.0, 0.0};
                 st->beta = double2{0.0, 0.0};
@@ -751,12 +777,13 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             }
             break;
         case FIN_QV: {
-            // mu = p^T A p; the scatter has applied the pending smoothing step
+            // mu = p^T A p; the scatter has applied the pending smoothing
+            // step; |v|^2 and |p|^2 in slots 2 and 3
             const double2 mu = {acc[0], acc[1]};
             st->matvecs += 1;
             st->pend = 0;
-            if (!finite2(mu)) st->status = ST_NONFINITE;
-            else if (mu.x == 0.0 && mu.y == 0.0) st->status = ST_BREAKDOWN;
+            if (!finite2(mu) || !isfinite(acc[2]) || !isfinite(acc[3])) st->status = ST_NONFINITE;
+            else if (vanishes(mu, acc[2] * acc[3])) st->status = ST_BREAKDOWN;
             else st->alpha = cdiv(st->rho, mu);
             break;
         }
@@ -785,7 +812,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             st->snorm2 = s2;
             if (s2 <= st->tol2 * st->bnorm2) {
                 st->status = ST_CONVERGED;
-            } else if (rho_new.x == 0.0 && rho_new.y == 0.0) {
+            } else if (vanishes(rho_new, nu2 * nu2)) {   // r^T r against |r|^2
                 st->status = ST_BREAKDOWN;
             } else {
                 st->beta = cdiv(rho_new, st->rho);
@@ -799,10 +826,10 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             break;
         case FIN_B_BETA: {
             // rho_1 = <rhat, r_1>: beta = alpha rho_1 / rho_0, rho_0 <- rho_1
-            const double2 rho1 = {acc[0], acc[1]};
+            const double2 rho1 = {acc[0], acc[1]};   // |r_1|^2 in slot 2
             st->matvecs += 1;
-            if (!finite2(rho1)) st->status = ST_NONFINITE;
-            else if (rho1.x == 0.0 && rho1.y == 0.0) st->status = ST_BREAKDOWN;
+            if (!finite2(rho1) || !isfinite(acc[2])) st->status = ST_NONFINITE;
+            else if (vanishes(rho1, st->rhat2 * acc[2])) st->status = ST_BREAKDOWN;
             else {
                 st->beta = cmul(st->alpha, cdiv(rho1, st->rho));
                 st->rho = rho1;
@@ -828,7 +855,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
             }
             const double2 tau = {c12.x / s1, c12.y / s1};
             const double s2 = acc[3] - (c12.x * c12.x + c12.y * c12.y) / s1;
-            if (!(s2 > 0.0)) {
+            if (!(s2 > BD_EPS * BD_EPS * acc[3])) {   // r_2 parallel to r_1 within rounding
                 st->status = ST_BREAKDOWN;
                 break;
             }
@@ -851,7 +878,7 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                 st->status = ST_NONFINITE;
             } else if (acc[2] <= st->tol2 * st->bnorm2) {
                 st->status = ST_CONVERGED;
-            } else if ((rho1.x == 0.0 && rho1.y == 0.0) || (om.x == 0.0 && om.y == 0.0)) {
+            } else if (vanishes(rho1, st->rhat2 * acc[2]) || (om.x == 0.0 && om.y == 0.0)) {
                 st->status = ST_BREAKDOWN;
             } else {
                 const double2 rho0 = cmul(double2{-om.x, -om.y}, st->rho);

@@ -326,6 +326,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             const double2 w = cdotc(a.rhat[i], y);
             acc[0] += w.x;
             acc[1] += w.y;
+            acc[2] += y.x * y.x + y.y * y.y;   // |v|^2: bounds <rhat, v> with |rhat|
         } else if (MODE == GA_T) {
             a.t[i] = y;
             const double2 w = cdotc(y, xin);          // <t, s>
@@ -339,6 +340,8 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             a.v[i] = y;
             acc[0] += xin.x * y.x - xin.y * y.y;   // p^T v (bilinear)
             acc[1] += xin.x * y.y + xin.y * y.x;
+            acc[2] += y.x * y.x + y.y * y.y;       // |v|^2 and |p|^2 bound |p^T v|
+            acc[3] += xin.x * xin.x + xin.y * xin.y;
         } else if (MODE == GA_B1 || MODE == GA_B2) {
             // r_1 = A r_0 or u_2 = A u_1, and <rhat, .>
             if (MODE == GA_B1) a.t[i] = y;
@@ -346,6 +349,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             const double2 w = cdotc(a.rhat[i], y);
             acc[0] += w.x;
             acc[1] += w.y;
+            acc[2] += y.x * y.x + y.y * y.y;
         } else if (MODE == GA_B3) {
             // r_2 = A r_1 and the minimal-residual sums |r_1|^2, <r_1, r_2>,
             // |r_2|^2, <r_1, r_0>, <r_2, r_0>
@@ -390,6 +394,9 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         } else if constexpr (MODE == GA_T) {
             double a5[5] = {acc[0], acc[1], acc[2], acc[3], acc[4]};
             publish_partial<5, NTHR>(a5, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        } else if constexpr (MODE == GA_Q) {
+            double a4[4] = {acc[0], acc[1], acc[2], acc[3]};
+            publish_partial<4, NTHR>(a4, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
         } else {
             double a3[3] = {acc[0], acc[1], acc[2]};
             publish_partial<3, NTHR>(a3, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);

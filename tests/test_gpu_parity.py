@@ -1128,3 +1128,44 @@ def test_far_field_four_directions_per_workgroup_match_oracle(dda):
         assert np.abs(f[q] - ref).max() <= 1e-12 * np.abs(ref).max()
         rd = (np.abs(ref[:, 0]) ** 2 + np.abs(ref[:, 1]) ** 2) / res[q]["kd"] ** 2
         assert np.abs(dcs[q] - rd).max() <= 1e-12 * rd.max()
+
+
+# ------------------------------------------------------------------ breakdown and restart
+
+@pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
+def test_first_step_breakdown_restarts_and_converges(dda, solver):
+    """A right-hand side with b^H A b = 0 (a gain material puts 0 in A's
+    numerical range; the oracle's dense A gives b) breaks BiCGSTAB and
+    BiCGstab(2) down in their first step; the one restart, with the conjugate
+    shadow residual, converges to the LU solution."""
+    import breakdown_rhs as br
+    ijk = w.brick(2, 2, 2)
+    m = np.full(len(ijk), br.GAIN_M)
+    kh, e0 = np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]], dtype=complex)
+    A = _dense_A(ijk, m, 1.0, kh[0], e0[0], "LATTDR")
+    b = br.hermitian_zero(A).reshape(-1, 3)
+    tgt = dda.Target(ijk, m)
+    x, r = dda.solve_rhs(tgt, dda.Options.for_size_parameter(1.0, tol=1e-10, solver=solver), kh, e0,
+                         _cuda(b[None]))
+    assert r[0]["restarts"] == 1 and r[0]["status"] == 0, r[0]
+    ref = np.linalg.solve(A, b.reshape(-1)).reshape(-1, 3)
+    assert np.abs(x.cpu().numpy()[0] - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_qmr_breakdown_is_reported(dda):
+    """b^T A b = 0 (exact up to rounding, from the oracle's dense A) breaks
+    QMR down in its first step: the solve ends with DDA_E_BREAKDOWN and no
+    restart; the same b solves normally with BiCGSTAB (b^H A b != 0)."""
+    import breakdown_rhs as br
+    ijk = w.brick(3, 3, 3)
+    m = np.full(len(ijk), 1.5 + 0.1j)
+    kh, e0 = np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]], dtype=complex)
+    A = _dense_A(ijk, m, 1.0, kh[0], e0[0], "LATTDR")
+    b = br.bilinear_zero(A).reshape(-1, 3)
+    tgt = dda.Target(ijk, m)
+    _, r = dda.solve_rhs(tgt, dda.Options.for_size_parameter(1.0, tol=1e-10, solver="qmr"), kh, e0, _cuda(b[None]))
+    assert r[0]["status"] == 5 and r[0]["restarts"] == 0, r[0]
+    x, r = dda.solve_rhs(tgt, dda.Options.for_size_parameter(1.0, tol=1e-10), kh, e0, _cuda(b[None]))
+    assert r[0]["status"] == 0 and r[0]["restarts"] == 0
+    ref = np.linalg.solve(A, b.reshape(-1)).reshape(-1, 3)
+    assert np.abs(x.cpu().numpy()[0] - ref).max() <= 1e-8 * np.abs(ref).max()

@@ -706,3 +706,29 @@ def test_trilinear_reproduces_linear_fields():
     pts = nearfield.line_points([-1.3, 0.25, 2.0], [4.7, 3.5, -1.1], 23)
     assert np.abs(nearfield.trilinear(lin, pts) - lin(pts)).max() < 1e-12
     assert np.allclose(pts[0], [-1.3, 0.25, 2.0]) and np.allclose(pts[-1], [4.7, 3.5, -1.1])
+
+
+# ---------------------------------------------------------------- breakdown right-hand sides
+
+def test_breakdown_right_hand_sides_zero_their_forms():
+    """The right-hand sides the GPU breakdown tests use: b^H A b vanishes to
+    rounding for the gain target (0 in its numerical range) while b^T A b does
+    not, so a restart with the conjugate shadow residual can proceed; for a
+    passive target b^H A b stays away from 0 (its imaginary part is minus the
+    extinguished power), while b^T A b can be zeroed."""
+    import breakdown_rhs as br
+    cube = w.brick(2, 2, 2)
+    k = dense.kd_from_size_parameter(1.0, len(cube))
+    A = dense.assemble(cube, dense.site_alpha_inverse(np.full(len(cube), br.GAIN_M), k, [1, 0, 0], [0, 1, 0]), k)
+    b = br.hermitian_zero(A)
+    nAb = np.linalg.norm(A @ b)
+    assert abs(np.vdot(b, A @ b)) <= 1e-15 * nAb and abs(b @ A @ b) >= 0.05 * nAb
+    ijk = w.brick(3, 3, 3)
+    k = dense.kd_from_size_parameter(1.0, len(ijk))
+    Ap = dense.assemble(ijk, dense.site_alpha_inverse(np.full(len(ijk), 1.5 + 0.1j), k, [1, 0, 0], [0, 1, 0]), k)
+    bp = br.bilinear_zero(Ap)
+    assert abs(bp @ Ap @ bp) <= 1e-14 * np.linalg.norm(Ap @ bp)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        u = rng.standard_normal(81) + 1j * rng.standard_normal(81)
+        assert np.vdot(u, Ap @ u).imag < 0
