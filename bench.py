@@ -441,18 +441,23 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
 
 
 def padded(n: int) -> int:
-    """The library's padded FFT extent: 2n if 2,3,5-smooth, else the smallest
-    smooth extent >= 2n - 1."""
+    """The library's padded FFT extent: the smallest compile-time FFT length
+    (32 ... 256) >= 2n - 1 when at most 1.4 times the smooth extent, else the
+    smooth extent (2n if 2,3,5-smooth, else the smallest smooth one >= 2n - 1)."""
     def smooth(m):
         for p in (2, 3, 5):
             while m % p == 0:
                 m //= p
         return m == 1
     if smooth(2 * n):
-        return 2 * n
-    m = max(2 * n - 1, 1)
-    while not smooth(m):
-        m += 1
+        m = 2 * n
+    else:
+        m = max(2 * n - 1, 1)
+        while not smooth(m):
+            m += 1
+    for L in (32, 48, 64, 80, 96, 128, 160, 192, 256):
+        if L >= 2 * n - 1:
+            return L if 5 * L <= 7 * m else m
     return m
 
 

@@ -122,6 +122,9 @@ typedef struct {
                                         host's launch rate is the limit; single-target calls always
                                         launch directly; with kernel timing on, one chunk in the
                                         timing sample period runs as direct launches) */
+#define DDA_FLAG_SEPARATE_TARGETS 16u /* dda_solve_batched: give this target launches of its own
+                                         instead of sharing them with the other targets on the
+                                         same padded grid (results are identical) */
 
 typedef struct {
     double wavelength;   /* vacuum wavelength (any physical unit) > 0 */
@@ -235,7 +238,16 @@ dda_status dda_solve_rhs(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int3
  *   targets[n_targets], opts[n_targets];
  *   rhs_target[n_rhs] gives the target index of each right-hand side,
  *   inc[n_rhs], P[n_rhs] (per right-hand side device pointer of
- *   [n_sites(target)][3], or NULL), res[n_rhs]. */
+ *   [n_sites(target)][3], or NULL), res[n_rhs].
+ * Targets whose padded grids are equal, with compile-time FFT lengths on every
+ * axis (32, 48, 64, 80, 96, 128, 160, 192, 256), and whose options agree in
+ * solver, precision, flags and kernel_variant share every launch: one kernel
+ * per step covers all their right-hand sides, each reading its own target's
+ * box, sites, materials, kd and tensor.  Other targets run as their own
+ * batches on up to four streams.  Every right-hand side's result is bitwise
+ * the one dda_solve gives for its target and its right-hand sides alone.
+ * A target may appear under several indices only with one kd (equal
+ * wavelength and aeff); E_INVALID otherwise. */
 dda_status dda_solve_batched(dda_ctx* ctx, int32_t n_targets, dda_target* const* targets,
                              const dda_opts* opts, int32_t n_rhs, const int32_t* rhs_target,
                              const dda_incidence* inc, dda_c64* const* P, dda_result* res);

@@ -29,6 +29,7 @@ DDA_FLAG_RECOMPUTE_GREEN = 1
 DDA_FLAG_NO_FINAL_CHECKS = 2
 DDA_FLAG_NO_AUTOTUNE = 4
 DDA_FLAG_NO_GRAPH = 8
+DDA_FLAG_SEPARATE_TARGETS = 16
 
 
 class C64(ctypes.Structure):

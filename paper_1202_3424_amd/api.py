@@ -76,6 +76,7 @@ class Options:
     final_checks: bool = True
     autotune: bool = True
     graphs: bool = True
+    share_launches: bool = True
     kernel_variant: int = 0
 
     @classmethod
@@ -93,6 +94,8 @@ class Options:
             flags |= _abi.DDA_FLAG_NO_AUTOTUNE
         if not self.graphs:
             flags |= _abi.DDA_FLAG_NO_GRAPH
+        if not self.share_launches:
+            flags |= _abi.DDA_FLAG_SEPARATE_TARGETS
         return _abi.Opts(self.wavelength, self.aeff, self.m_medium, self.tol, int(self.max_iter),
                          _POLZ[self.polarizability], _SOLVER[self.solver], _PREC[self.precision], flags,
                          int(self.kernel_variant))

@@ -73,13 +73,24 @@ bool smooth235(int m) {
     return m == 1;
 }
 
-// 2n when 2,3,5-smooth, else the smallest smooth extent >= 2n - 1: every
-// separation -(n-1)..(n-1) then has its own slot, so the circulant product
-// equals the Toeplitz one exactly.
-int padded_extent(int n) {
+// Any padded extent M >= 2n - 1 gives every separation -(n-1)..(n-1) its own
+// slot, so the circulant product equals the Toeplitz one exactly.  The
+// smooth extent: 2n when 2,3,5-smooth, else the smallest smooth one >=
+// 2n - 1.  The padded extent: the smallest FFT length with compile-time
+// kernels >= 2n - 1 when that is at most 1.4 times the smooth extent (those
+// kernels are several times faster than the runtime-planned ones, and
+// targets of similar size then share a grid, which lets a batched solve run
+// them in the same launches), else the smooth extent.
+int smooth_extent(int n) {
     if (smooth235(2 * n)) return 2 * n;
     int m = std::max(2 * n - 1, 1);
     while (!smooth235(m)) ++m;
+    return m;
+}
+int padded_extent(int n) {
+    const int m = smooth_extent(n);
+    for (int L : {32, 48, 64, 80, 96, 128, 160, 192, 256})
+        if (L >= 2 * n - 1) return 5 * L <= 7 * m ? L : m;
     return m;
 }
 
@@ -400,6 +411,15 @@ void pack_incidence(int n, const dda_incidence* inc, std::vector<double>& kh, st
 
 
 // Everything one batched solve on one target needs on the device.
+// The right-hand sides [first, first + count) of one target in a ragged
+// batch, with that target's options and kd.
+struct Seg {
+    dda_target* t;
+    const dda_opts* o;
+    int first, count;
+    double kd;
+};
+
 struct Work {
     dda_ctx* c;
     Workspace& ws;
@@ -418,6 +438,9 @@ struct Work {
     void* grid = nullptr;
     double* kh = nullptr;
     double2* e0 = nullptr;
+    // ragged batch (several targets on one padded grid): each target's
+    // right-hand sides; empty for one target
+    std::vector<Seg> segs;
 
     Work(dda_ctx* c_, Workspace& ws_, dda_target* t_, int nrhs_, double kd_, bool fp32_)
         : c(c_), ws(ws_), s(ws_.stream), t(t_), nrhs(nrhs_), kd(kd_), fp32(fp32_) {
@@ -477,6 +500,41 @@ struct Work {
         e0 = (double2*)(base + L.e0);
     }
 
+    // Make this a ragged batch: t is the batch target (its geometry's rg is
+    // the device table rg), the site kernels launch the largest per-target
+    // workgroup count sblk, and every reduction reads its own target's
+    // block count from the table.
+    void set_ragged(const std::vector<Seg>& sg, const RhsGeo* rg, int sblk) {
+        segs = sg;
+        a.rg = rg;
+        site_blocks = sblk;
+        a.maxblk = std::max(pass_blocks, site_blocks);
+        a.partials = (double*)ws.partials.ensure((size_t)nrhs * a.maxblk * PSTRIDE * sizeof(double));
+    }
+    // block counts k_finalize sums over: this launch's, or each right-hand
+    // side's own in a ragged batch
+    int fin_site() const { return a.rg ? NBLK_SITE : site_blocks; }
+    int fin_pass() const { return a.rg ? NBLK_PASS : pass_blocks; }
+    // the targets and their right-hand sides
+    std::vector<Seg> parts() const {
+        if (!segs.empty()) return segs;
+        return {Seg{t, nullptr, 0, nrhs, kd}};
+    }
+    // tensor FFT handed to pass 3 (a ragged batch's kernels take each right-
+    // hand side's own from the table)
+    const void* ghat(bool f32) const {
+        const dda_target* src = segs.empty() ? t : segs[0].t;
+        return f32 ? src->gh32.p : src->gh64.p;
+    }
+    // per-right-hand-side tolerance and iteration limit, every status active
+    void set_states(const dda_opts* o) {
+        if (segs.empty()) {
+            launch_set_state(a.st, nrhs, o->tol, o->max_iter, s);
+            return;
+        }
+        for (const Seg& sg : segs) launch_set_state(a.st + sg.first, sg.count, sg.o->tol, sg.o->max_iter, s);
+    }
+
     void upload_incidence(const double* khv, const double2* e0v) {
         HIPCHK(hipMemcpyAsync(kh, khv, (size_t)nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(e0, e0v, (size_t)nrhs * 3 * sizeof(double2), hipMemcpyHostToDevice, s));
@@ -487,8 +545,18 @@ struct Work {
     }
 
     // 1/alpha for every (right-hand side, material); scheme + 2 = derivative
+    // (a ragged batch: each target's own materials, options and kd, rows of
+    // the largest material count)
     void alpha_table(int scheme, double m_medium, double2* out) {
-        launch_alpha(nrhs, t->nmat, (const double2*)t->mdev.p, m_medium, kh, e0, kd, scheme, out, s);
+        if (segs.empty()) {
+            launch_alpha(nrhs, t->nmat, (const double2*)t->mdev.p, m_medium, kh, e0, kd, scheme, out, s);
+            return;
+        }
+        const int shift = scheme >= 2 ? 2 : 0;
+        for (const Seg& sg : segs)
+            launch_alpha(sg.count, sg.t->nmat, (const double2*)sg.t->mdev.p, sg.o->m_medium, kh + 3 * sg.first,
+                         e0 + 3 * sg.first, sg.kd, sg.o->polarizability + shift,
+                         out + (size_t)sg.first * t->nmat * 3, s, t->nmat);
     }
 
     // the three strided passes: 0 = y forward, 1 = z with the tensor product, 2 = y inverse
@@ -497,7 +565,7 @@ struct Work {
         using C = typename V2<T>::t;
         const Geo& g = t->geo;
         C* gr = (C*)grid;
-        const C* gh = (const C*)(sizeof(T) == 4 ? t->gh32.p : t->gh64.p);
+        const C* gh = (const C*)ghat(sizeof(T) == 4);
         const double2* tw = (const double2*)t->tw.p;
         if (slot == 0)
             launch_strided<T>(1, -1, chk, g, nrhs, 3, g.n[2], g.n[1], g.M[1], gr, tw, nullptr, a.st, s, variant);
@@ -523,7 +591,8 @@ struct Work {
             }
             return;
         }
-        auto key = std::make_tuple(g.M[0], g.M[1], g.M[2], g.n[0], g.n[1], g.n[2], nrhs, fp32 ? 1 : 0);
+        auto key = std::make_tuple(g.M[0], g.M[1], g.M[2], g.n[0], g.n[1], g.n[2], nrhs,
+                                   (fp32 ? 1 : 0) | (a.rg ? 2 : 0));
         auto it = c->tuned.find(key);
         if (it != c->tuned.end()) {
             for (int i = 0; i < 3; ++i) var[i] = it->second[i];
@@ -555,6 +624,10 @@ struct Work {
                     HIPCHK(hipEventElapsedTime(&t_y, e0, e1));
                 }
                 for (int v = 0; v < nv; ++v) {
+                    if (a.rg && !ragged_variant(slot == 1, v)) {
+                        t_ms[v] = std::numeric_limits<float>::infinity();
+                        continue;
+                    }
                     auto run = [&]() {
                         if (fp32) strided_slot<float>(slot, CHK_NONE, v);
                         else strided_slot<double>(slot, CHK_NONE, v);
@@ -587,7 +660,6 @@ struct Work {
         using C = typename V2<T>::t;
         const Geo& g = t->geo;
         C* gr = (C*)grid;
-        const C* gh = (const C*)(sizeof(T) == 4 ? t->gh32.p : t->gh64.p);
         const double2* tw = (const double2*)t->tw.p;
         {
             Timed tm(c, T_SCATTER, s);
@@ -612,7 +684,7 @@ struct Work {
         if (ga != GA_PLAIN) {
             static const int kind_of[] = {-1, FIN_CONJ, FIN_V, FIN_T, FIN_RES, FIN_QV, FIN_B_BETA, FIN_V, FIN_B_MR};
             Timed tm(c, T_KRYLOV, s);
-            launch_finalize(a, kind_of[ga], pass_blocks, s);
+            launch_finalize(a, kind_of[ga], fin_pass(), s);
         }
     }
     // fp64: force an FP64 product in the FP32-matvec mode (refinement, checks)
@@ -699,7 +771,7 @@ bool any_active_after_restart(Work& w) {
         settle_solution(w);   // the restart starts from r = s - omega t
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_restart(w.a, w.site_blocks, w.s);
-        launch_finalize(w.a, FIN_RESTART, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_RESTART, w.fin_site(), w.s);
         active = true;
     }
     return active;
@@ -718,7 +790,7 @@ void launch_chunk(Work& w, int chunk) {
             w.matvec(SC_B3, GA_B3, CHK_ACTIVE, CHK_ACTIVE);   // r_2 = A r_1, g1, g2
             Timed tm(w.c, T_KRYLOV, w.s);
             launch_b2_update(w.a, w.site_blocks, w.s);
-            launch_finalize(w.a, FIN_B_UPD, w.site_blocks, w.s);
+            launch_finalize(w.a, FIN_B_UPD, w.fin_site(), w.s);
         }
         HIPCHK(hipGetLastError());
         return;
@@ -730,7 +802,7 @@ void launch_chunk(Work& w, int chunk) {
             w.matvec(SC_Q, GA_Q, CHK_ACTIVE, CHK_ACTIVE);
             Timed tm(w.c, T_KRYLOV, w.s);
             launch_qmr_update(w.a, w.site_blocks, w.s);
-            launch_finalize(w.a, FIN_QUPD, w.site_blocks, w.s);
+            launch_finalize(w.a, FIN_QUPD, w.fin_site(), w.s);
         }
         HIPCHK(hipGetLastError());
         return;
@@ -889,7 +961,7 @@ void iterate_loop(Work& w, const dda_opts* o) {
 
 // Start of BiCGSTAB: state, then r and rhat from b (cold) or b - A x (warm).
 void start_iteration(Work& w, const dda_opts* o, bool warm) {
-    launch_set_state(w.a.st, w.nrhs, o->tol, o->max_iter, w.s);
+    w.set_states(o);
     if (w.qmr) {
         if (warm) {
             w.a.in = w.a.x;
@@ -897,7 +969,7 @@ void start_iteration(Work& w, const dda_opts* o, bool warm) {
         }
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_qmr_init(w.a, !warm, w.site_blocks, w.s);
-        launch_finalize(w.a, warm ? FIN_QWARM : FIN_QCOLD, w.site_blocks, w.s);
+        launch_finalize(w.a, warm ? FIN_QWARM : FIN_QCOLD, w.fin_site(), w.s);
         HIPCHK(hipGetLastError());
         return;
     }
@@ -906,11 +978,11 @@ void start_iteration(Work& w, const dda_opts* o, bool warm) {
         w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);  // r = b - A x0
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_init_warm(w.a, w.site_blocks, w.s);
-        launch_finalize(w.a, FIN_WARM, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_WARM, w.fin_site(), w.s);
     } else {
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_init_cold(w.a, w.site_blocks, w.s);
-        launch_finalize(w.a, FIN_COLD, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_COLD, w.fin_site(), w.s);
     }
     HIPCHK(hipGetLastError());
 }
@@ -924,14 +996,14 @@ void launch_refinement(Work& w) {
         w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_qmr_init(w.a, false, w.site_blocks, w.s);
-        launch_finalize(w.a, FIN_QREFINE, w.site_blocks, w.s);
+        launch_finalize(w.a, FIN_QREFINE, w.fin_site(), w.s);
         return;
     }
     w.a.in = w.a.x;
     w.matvec(SC_PLAIN, GA_RES, CHK_NONE, CHK_NONE, true);
     Timed tm(w.c, T_KRYLOV, w.s);
     launch_init_warm(w.a, w.site_blocks, w.s);
-    launch_finalize(w.a, FIN_REFINE, w.site_blocks, w.s);
+    launch_finalize(w.a, FIN_REFINE, w.fin_site(), w.s);
 }
 
 // BiCGSTAB on every right-hand side of w (b, ainv prepared); warm start when
@@ -974,7 +1046,7 @@ void final_checks(Work& w, bool normal_eq) {
     {
         Timed tm(w.c, T_KRYLOV, w.s);
         launch_qsum(a, w.site_blocks, w.s);
-        launch_finalize(a, FIN_QSUM, w.site_blocks, w.s);
+        launch_finalize(a, FIN_QSUM, w.fin_site(), w.s);
     }
     HIPCHK(hipGetLastError());
 }
@@ -990,10 +1062,11 @@ dda_status to_status(int s) {
 }
 
 dda_status fill_results(const Work& w, bool normal_eq, dda_result* res) {
-    const double a = aeff_over_d(w.t->nsites);
-    const double cq = 4.0 * M_PI * w.kd / (M_PI * a * a);
     dda_status worst = DDA_OK;
-    for (int q = 0; q < w.nrhs; ++q) {
+    for (const Seg& sg : w.parts()) {
+    const double a = aeff_over_d(sg.t->nsites);
+    const double cq = 4.0 * M_PI * sg.kd / (M_PI * a * a);
+    for (int q = sg.first; q < sg.first + sg.count; ++q) {
         const RhsState& s = w.ws.host_state[q];
         dda_result r{};
         r.qext = cq * s.red[3];
@@ -1002,7 +1075,7 @@ dda_status fill_results(const Work& w, bool normal_eq, dda_result* res) {
         r.qsca = r.qext - r.qabs;
         r.rel_residual = std::sqrt(s.red[0] / s.bnorm2);
         r.normal_eq_residual = normal_eq ? std::sqrt(s.red[1] / s.red[2]) : -1.0;
-        r.kd = w.kd;
+        r.kd = sg.kd;
         r.aeff_d = a;
         r.iters = s.iters;
         r.matvecs = s.matvecs;
@@ -1011,6 +1084,7 @@ dda_status fill_results(const Work& w, bool normal_eq, dda_result* res) {
         r.status = to_status(s.status);
         if (r.status != DDA_OK && (worst == DDA_OK || r.status > worst)) worst = (dda_status)r.status;
         if (res) res[q] = r;
+    }
     }
     return worst;
 }
@@ -1108,11 +1182,140 @@ struct Job {
     std::vector<dda_c64*> P;
     double kd = 0;
     bool fp32 = false;
+    int max_iter = 0;                     // the largest of its targets' limits
     std::unique_ptr<Work> w;
     Phase phase = PENDING;
     int launched = 0;
     int refines = 0;
+    // several targets on one padded grid (else null, segs empty)
+    std::unique_ptr<struct Batch> batch;
+    std::vector<Seg> segs;
+    int batch_site_blocks = 0;
 };
+
+// Targets of one dda_solve_batched call that share their padded grid, run as
+// one job: each step is one launch per kernel over every right-hand side of
+// every member, each reading its own target through the RhsGeo table.  The
+// batch target holds the members' occupancy maps, materials and coordinates
+// back to back, the twiddles of the shared grid, and as its box the largest
+// member extent on each axis (the launch shape).
+struct Batch {
+    dda_target t;
+    DevBuf rg;
+    std::vector<RhsGeo> host_rg;
+    ~Batch() {
+        for (DevBuf* b : {&t.map, &t.mat, &t.coords, &t.tw, &t.tw32, &rg}) b->release();
+    }
+};
+
+// Merge the jobs `mem` (equal padded grids, tensors built) into one job.
+Job make_batch(dda_ctx* c, const std::vector<Job*>& mem) {
+    Job m;
+    m.batch.reset(new Batch());
+    Batch& b = *m.batch;
+    dda_target& bt = b.t;
+    bt.ctx = c;
+    const dda_target* t0 = mem[0]->t;
+    Geo g = t0->geo;
+    size_t map_tot = 0, site_tot = 0;
+    for (const Job* j : mem) {
+        for (int a = 0; a < 3; ++a) g.n[a] = std::max(g.n[a], j->t->geo.n[a]);
+        map_tot += j->t->map.bytes / sizeof(int);
+        site_tot += (size_t)j->t->nsites;
+        bt.nsites = std::max(bt.nsites, j->t->nsites);
+        bt.nmat = std::max(bt.nmat, j->t->nmat);
+    }
+    hipStream_t s = c->stream;
+    bt.map.ensure(map_tot * sizeof(int));
+    bt.mat.ensure(site_tot * sizeof(int));
+    bt.coords.ensure(site_tot * 3 * sizeof(int));
+    bt.tw.ensure(t0->tw.bytes);
+    bt.tw32.ensure(t0->tw32.bytes);
+    HIPCHK(hipMemcpyAsync(bt.tw.p, t0->tw.p, t0->tw.bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(bt.tw32.p, t0->tw32.p, t0->tw32.bytes, hipMemcpyDeviceToDevice, s));
+    m.t = &bt;
+    m.o = mem[0]->o;
+    m.kd = mem[0]->kd;
+    m.fp32 = mem[0]->fp32;
+    size_t map_off = 0, site_off = 0;
+    for (Job* j : mem) {
+        const dda_target* jt = j->t;
+        const size_t nmap = jt->map.bytes / sizeof(int), ns = (size_t)jt->nsites;
+        HIPCHK(hipMemcpyAsync((int*)bt.map.p + map_off, jt->map.p, nmap * sizeof(int), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync((int*)bt.mat.p + site_off, jt->mat.p, ns * sizeof(int), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync((int*)bt.coords.p + 3 * site_off, jt->coords.p, 3 * ns * sizeof(int),
+                              hipMemcpyDeviceToDevice, s));
+        const int count = (int)j->idx.size();
+        m.segs.push_back(Seg{j->t, j->o, (int)m.idx.size(), count, j->kd});
+        RhsGeo r{};
+        for (int a = 0; a < 3; ++a) r.n[a] = jt->geo.n[a];
+        r.nsites = jt->nsites;
+        r.map_off = (long long)map_off;
+        r.site_off = (int)site_off;
+        r.pass_blocks = x_pass_blocks(jt->geo, count, j->fp32);
+        r.site_blocks = site_blocks_for(3LL * jt->nsites, count);
+        r.kd = j->kd;
+        r.ghat[0] = jt->gh64.p;
+        r.ghat[1] = jt->gh32.p;
+        for (int k = 0; k < count; ++k) b.host_rg.push_back(r);
+        m.batch_site_blocks = std::max(m.batch_site_blocks, r.site_blocks);
+        m.idx.insert(m.idx.end(), j->idx.begin(), j->idx.end());
+        m.kh.insert(m.kh.end(), j->kh.begin(), j->kh.end());
+        m.e0.insert(m.e0.end(), j->e0.begin(), j->e0.end());
+        m.P.insert(m.P.end(), j->P.begin(), j->P.end());
+        m.max_iter = std::max(m.max_iter, j->o->max_iter);
+        map_off += nmap;
+        site_off += ns;
+    }
+    b.rg.ensure(b.host_rg.size() * sizeof(RhsGeo));
+    HIPCHK(hipMemcpyAsync(b.rg.p, b.host_rg.data(), b.host_rg.size() * sizeof(RhsGeo), hipMemcpyHostToDevice, s));
+    g.tw32 = (const float2*)bt.tw32.p;
+    g.rg = (const RhsGeo*)b.rg.p;
+    bt.geo = g;
+    return m;
+}
+
+// The solver configuration that must agree for targets to share launches.
+std::tuple<int, int, int, int, int, unsigned, int> batch_key(const Job& j) {
+    const Geo& g = j.t->geo;
+    return std::make_tuple(g.M[0], g.M[1], g.M[2], (int)j.o->solver, (int)j.o->precision, j.o->flags,
+                           j.o->kernel_variant);
+}
+
+// Replace every set of at least two jobs with equal batch_key, whose padded
+// grid has a compile-time FFT length on every axis, by one merged job (in the
+// position of its first member).
+void merge_jobs(dda_ctx* c, std::vector<Job>& jobs) {
+    std::map<std::tuple<int, int, int, int, int, unsigned, int>, std::vector<size_t>> groups;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const Geo& g = jobs[i].t->geo;
+        if ((jobs[i].o->flags & DDA_FLAG_SEPARATE_TARGETS) || !ct_length(g.M[0]) || !ct_length(g.M[1]) ||
+            !ct_length(g.M[2]))
+            continue;
+        groups[batch_key(jobs[i])].push_back(i);
+    }
+    std::vector<Job> out;
+    std::vector<bool> taken(jobs.size(), false);
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        if (taken[i]) continue;
+        const Geo& g = jobs[i].t->geo;
+        auto it = groups.end();
+        if (!(jobs[i].o->flags & DDA_FLAG_SEPARATE_TARGETS) && ct_length(g.M[0]) && ct_length(g.M[1]) &&
+            ct_length(g.M[2]))
+            it = groups.find(batch_key(jobs[i]));
+        if (it == groups.end() || it->second.size() < 2) {
+            out.push_back(std::move(jobs[i]));
+            continue;
+        }
+        std::vector<Job*> mem;
+        for (size_t k : it->second) {
+            mem.push_back(&jobs[k]);
+            taken[k] = true;
+        }
+        out.push_back(make_batch(c, mem));
+    }
+    jobs = std::move(out);
+}
 
 // Every job's targets iterate concurrently, one workspace and stream per
 // job in flight (at most 4; the hardware runs that many queues at once).
@@ -1120,12 +1323,25 @@ struct Job {
 // each chunk of iterations a job posts an asynchronous status copy and the
 // host moves on to the next job whose copy has landed.
 dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
+    // one tensor per target: a target listed twice must have one kd
+    std::map<const dda_target*, double> kd_of_target;
     for (Job& j : jobs) {
         check_opts(j.o);
         j.kd = kd_of(j.o, j.t->nsites);
         j.fp32 = j.o->precision == DDA_FP32_MATVEC;
-        ensure_green(c, j.t, j.kd, j.fp32, (j.o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+        j.max_iter = j.o->max_iter;
+        auto ins = kd_of_target.emplace(j.t, j.kd);
+        if (!ins.second && ins.first->second != j.kd)
+            invalid("a target listed twice with different wavelength or aeff (one tensor per target)");
     }
+    // tensors: FP64 for every job, FP32 too where any job of that target asks
+    std::map<const dda_target*, bool> want32;
+    for (Job& j : jobs) want32[j.t] = want32[j.t] || j.fp32;
+    for (Job& j : jobs) {
+        const bool f32 = want32[j.t];
+        ensure_green(c, j.t, j.kd, f32, (j.o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
+    }
+    merge_jobs(c, jobs);
     const int nslot = (int)std::min<size_t>(4, jobs.size());
     while ((int)c->extra.size() < nslot - 1) {
         auto* ws = new Workspace();
@@ -1148,6 +1364,7 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
         const int nrhs = (int)j.idx.size();
         j.w.reset(new Work(c, ws, j.t, nrhs, j.kd, j.fp32));
         Work& w = *j.w;
+        if (j.batch) w.set_ragged(j.segs, j.t->geo.rg, j.batch_site_blocks);
         w.qmr = j.o->solver == DDA_QMR_SYM;
         w.b2 = j.o->solver == DDA_BICGSTAB2;
         w.graphs = (j.o->flags & DDA_FLAG_NO_GRAPH) == 0;
@@ -1169,10 +1386,11 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
         final_checks(w, (j.o->flags & DDA_FLAG_NO_FINAL_CHECKS) == 0);
         {
             Timed tm(c, T_SETUP, w.s);
-            for (size_t q = 0; q < j.idx.size(); ++q)
-                if (j.P[q])
-                    launch_permute(1, j.t->nsites, 3, (const int*)j.t->perm.p, w.a.x + (size_t)q * w.a.n3,
-                                   (double2*)j.P[q], false, w.s);
+            for (const Seg& sg : w.parts())
+                for (int q = sg.first; q < sg.first + sg.count; ++q)
+                    if (j.P[q])
+                        launch_permute(1, sg.t->nsites, 3, (const int*)sg.t->perm.p, w.a.x + (size_t)q * w.a.n3,
+                                       (double2*)j.P[q], false, w.s);
         }
         HIPCHK(hipGetLastError());
         post_state(w);
@@ -1198,10 +1416,10 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
             if (q == hipErrorNotReady) continue;
             HIPCHK(q);
             progress = true;
-            const int cap = std::min(8, j.o->max_iter);
+            const int cap = std::min(8, j.max_iter);
             if (j.phase == Job::ITER || j.phase == Job::REFINE) {
                 const bool active = any_active_after_restart(w);
-                if (active && j.launched <= j.o->max_iter + 2 * cap) {
+                if (active && j.launched <= j.max_iter + 2 * cap) {
                     const int chunk = next_chunk(w, cap);
                     run_chunk(w, chunk);
                     j.launched += chunk;

@@ -68,6 +68,9 @@ struct RhsState {
     // and r yet (1: x += alpha p + omega s, r = s - omega t; 2: x += alpha p,
     // after a half-step convergence)
     int pend;
+    // FP32-matvec mode: an FP64 residual of the current x has confirmed its
+    // convergence (later refinement checks leave it alone)
+    int checked;
 };
 
 template <typename T> struct V2;

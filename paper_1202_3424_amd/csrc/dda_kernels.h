@@ -29,13 +29,34 @@ LaunchEvents& launch_events();
         }                                                                                               \
     } while (0)
 
+// One right-hand side of a launch over several targets that share the
+// padded grid (a ragged batch): its target's bounding box and site count, kd,
+// where that target's occupancy map, materials, coordinates and permutation
+// start in the batch's concatenated arrays, its tensor octants (FP64 and FP32),
+// and the workgroup counts its own single-target solve uses for
+// the x passes and for the site kernels (a right-hand side reduces over
+// exactly those blocks, so its results equal that solve's bitwise).
+struct RhsGeo {
+    int n[3];
+    int nsites;
+    long long map_off;
+    int site_off;
+    int pass_blocks;
+    int site_blocks;
+    int pad;
+    double kd;
+    const void* ghat[2];   // tensor FFT: FP64 (double2), FP32 (float2)
+};
+
 // Geometry of one target's FFT grid.
-//   n[a]  occupied bounding-box extent on axis a (x = first ijk index)
-//   M[a]  padded FFT extent (>= 2n-1, 2,3,5-smooth)
+//   n[a]  occupied bounding-box extent on axis a (x = first ijk index); in a
+//         ragged batch the largest over its targets
+//   M[a]  padded FFT extent (>= 2n-1)
 //   H[a]  M[a]/2 + 1: extent of the stored octant of the tensor FFT
 // Grids hold NC complex components interleaved per point, point index
 // (z * My + y) * Mx + x, right-hand side outermost.
 //   tw32  the twiddle tables W_L^t rounded to FP32 (the FP64 tables' offsets)
+//   rg    per right-hand side geometry of a ragged batch, or null (one target)
 struct Geo {
     int n[3];
     int M[3];
@@ -43,6 +64,7 @@ struct Geo {
     long long npts;
     AxisPlan ax[3];
     const float2* tw32;
+    const RhsGeo* rg;
 };
 
 // Site-indexed FP64 vectors of one batched solve, each [nrhs][n3] with
@@ -71,7 +93,21 @@ struct SiteArgs {
     int maxblk;
     int slot;              // RhsState::red slot written by the conjugated product
     double kd;
+    // ragged batch (else null): per right-hand side geometry; n3 and nmat
+    // are then the strides (largest target) of the site vectors and of 1/alpha
+    const RhsGeo* rg;
 };
+
+// Sites of right-hand side q, its kd, and where its target's sites start in
+// the map / material / coordinate arrays.
+__device__ __forceinline__ long long rhs_n3(const SiteArgs& a, int q) { return a.rg ? 3LL * a.rg[q].nsites : a.n3; }
+__device__ __forceinline__ double rhs_kd(const SiteArgs& a, int q) { return a.rg ? a.rg[q].kd : a.kd; }
+__device__ __forceinline__ int rhs_site_off(const SiteArgs& a, int q) { return a.rg ? a.rg[q].site_off : 0; }
+// workgroups of the site kernels for right-hand side q (a ragged batch
+// launches the largest count; the extra workgroups of smaller targets exit)
+__device__ __forceinline__ int rhs_site_blocks(const SiteArgs& a, int q) {
+    return a.rg ? a.rg[q].site_blocks : (int)gridDim.x;
+}
 
 // SC_Q / GA_Q: the QMR iteration (p = r + beta p with the pending smoothing
 // step; v = A p with p^T v).  SC_B0..SC_B3 / GA_B1..GA_B3: the four products
@@ -125,6 +161,12 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant = 0);
 inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 28 : 8) : 1; }
+// the variants a ragged batch runs: every y-pass variant, and the pass-3
+// variants that take one right-hand side per workgroup (each right-hand side
+// reads its own tensor and extent); the others run as variant 3 there
+constexpr bool ragged_variant(int gh, int v) {
+    return !gh || !(v == 0 || v == 1 || v == 2 || v == 7 || v == 8 || v == 9);
+}
 void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);
@@ -133,7 +175,7 @@ void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* 
 // from the target's distinct refractive indices mats [nmat] and the ambient
 // medium's index
 void launch_alpha(int nrhs, int nmat, const double2* mats, double m_medium, const double* khat, const double2* e0,
-                  double kd, int scheme, double2* ainv, hipStream_t s);
+                  double kd, int scheme, double2* ainv, hipStream_t s, int ostride = 0);
 void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s);
 void launch_init_cold(const SiteArgs& a, int site_blocks, hipStream_t s);
 void launch_init_warm(const SiteArgs& a, int site_blocks, hipStream_t s);
@@ -167,6 +209,9 @@ void launch_nf_out(int nrhs, const int org[3], const int dims[3], const double* 
                    const double2* v, double2* einc, double2* esca, hipStream_t s);
 void launch_field_line(int nrhs, const int org[3], const int dims[3], const double2* E, const double a[3],
                        const double b[3], int n, double2* out, hipStream_t s);
+// nblk: the producer's workgroups per right-hand side; in a ragged batch
+// NBLK_PASS / NBLK_SITE take each right-hand side's own count from a.rg
+constexpr int NBLK_PASS = -1, NBLK_SITE = -2;
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(NT) void k_green_octant(Geo g, const double2* G, do
 //       S = sum_mu khat_mu^2 |e_mu|^2, 1/alpha_CM = (4 pi/3)(eps+2)/(eps-1).
 //   GKDLDR (Gutkowicz-Krusin & Draine 2004): S -> khat_mu^2 on axis mu.
 __global__ void k_alpha(int nrhs, int nmat, const double2* mats, double m_medium, const double* khat,
-                        const double2* e0, double kd, int scheme, double2* out) {
+                        const double2* e0, double kd, int scheme, double2* out, int ostride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrhs * nmat) return;
     const int q = i / nmat, mt = i % nmat;
@@ -162,7 +162,7 @@ __global__ void k_alpha(int nrhs, int nmat, const double2* mats, double m_medium
             const double2 d = cdiv(double2{-4.0 * pi, 0.0}, cmul(em1, em1));
             v = cadd(d, double2{(b2 + b3 * Smu) * k2, 0.0});
         }
-        out[(long long)i * 3 + mu] = v;
+        out[((long long)q * ostride + mt) * 3 + mu] = v;
     }
 }
 
@@ -171,8 +171,11 @@ __global__ __launch_bounds__(NT) void k_einc(SiteArgs a, const int* coords, cons
     const int q = blockIdx.y;
     const double* kh = khat + q * 3;
     const double2* e = e0 + q * 3;
-    for (int s = blockIdx.x * NT + threadIdx.x; s < a.nsites; s += gridDim.x * NT) {
-        const double ph = a.kd * (kh[0] * coords[s * 3 + 0] + kh[1] * coords[s * 3 + 1] + kh[2] * coords[s * 3 + 2]);
+    const int ns = a.rg ? a.rg[q].nsites : a.nsites;
+    const double kdq = rhs_kd(a, q);
+    coords += 3LL * rhs_site_off(a, q);
+    for (int s = blockIdx.x * NT + threadIdx.x; s < ns; s += gridDim.x * NT) {
+        const double ph = kdq * (kh[0] * coords[s * 3 + 0] + kh[1] * coords[s * 3 + 1] + kh[2] * coords[s * 3 + 2]);
         double sn, cs;
         sincos(ph, &sn, &cs);
         const double2 w = {cs, sn};
@@ -189,7 +192,10 @@ __global__ __launch_bounds__(NT) void k_init_cold(SiteArgs a) {
     const int q = blockIdx.y;
     const long long vb = (long long)q * a.n3;
     double acc[1] = {0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         const double2 bb = a.b[vb + i];
         a.r[vb + i] = bb;
         a.rhat[vb + i] = bb;
@@ -207,7 +213,10 @@ __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
     const int q = blockIdx.y;
     const long long vb = (long long)q * a.n3;
     double acc[2] = {0.0, 0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         const double2 rr = a.r[vb + i];
         const double2 bb = a.b[vb + i];
         a.rhat[vb + i] = rr;
@@ -231,7 +240,8 @@ __global__ __launch_bounds__(NT) void k_bicg_flush(SiteArgs a) {
     if (pend == 0) return;
     const double2 alpha = st->alpha, omega = st->omega;
     const long long vb = (long long)q * a.n3;
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)gridDim.x * NT) {
         const double2 s = a.r[vb + i];
         double2 xx = cadd(a.x[vb + i], cmul(alpha, a.p[vb + i]));
         if (pend == 1) {
@@ -255,7 +265,10 @@ __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
     if (st->status != ST_BREAKDOWN || st->restarts > 0) return;
     const long long vb = (long long)q * a.n3;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         const double2 rr = a.r[vb + i];
         a.rhat[vb + i] = cconj(rr);
         a.p[vb + i] = double2{0.0, 0.0};
@@ -283,7 +296,10 @@ __global__ __launch_bounds__(NT) void k_qmr_init(SiteArgs a, int cold) {
     const int q = blockIdx.y;
     const long long vb = (long long)q * a.n3;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         const double2 bb = a.b[vb + i];
         double2 rr;
         if (cold) {
@@ -314,7 +330,10 @@ __global__ __launch_bounds__(NT) void k_qmr_update(SiteArgs a) {
     const double2 alpha = st->alpha;
     const long long vb = (long long)q * a.n3;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         a.x[vb + i] = cadd(a.x[vb + i], cmul(alpha, a.p[vb + i]));
         const double2 rr = csub(a.r[vb + i], cmul(alpha, a.v[vb + i]));
         a.r[vb + i] = rr;
@@ -336,7 +355,8 @@ __global__ __launch_bounds__(NT) void k_qmr_final(SiteArgs a) {
     const bool pend = st->pend != 0;
     const double wo = st->w_old, wn = st->w_new;
     const long long vb = (long long)q * a.n3;
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)gridDim.x * NT) {
         double2 y = a.t[vb + i];
         if (pend) {
             const double2 xx = a.x[vb + i];
@@ -391,7 +411,10 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
     const double2 g1 = st->g1, g2 = st->g2;
     const long long vb = (long long)q * a.n3;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         const double2 r0 = a.r[vb + i], r1 = a.t[vb + i];
         a.x[vb + i] = cadd(a.x[vb + i], cadd(cmul(g1, r0), cmul(g2, r1)));
         const double2 rn = csub(r0, cadd(cmul(g1, r1), cmul(g2, a.r2[vb + i])));
@@ -597,14 +620,19 @@ __global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
     const int q = blockIdx.y;
     const long long vb = (long long)q * a.n3;
     const double2* ai = a.ainv + (long long)q * a.nmat * 3;
-    const double rr = (2.0 / 3.0) * a.kd * a.kd * a.kd;
+    const double kdq = rhs_kd(a, q);
+    const double rr = (2.0 / 3.0) * kdq * kdq * kdq;
+    const int* mat = a.mat + rhs_site_off(a, q);
     double acc[3] = {0.0, 0.0, 0.0};
-    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < a.n3; i += (long long)gridDim.x * NT) {
+    const int sb = rhs_site_blocks(a, q);
+    if ((int)blockIdx.x >= sb) return;
+    const long long n3q = rhs_n3(a, q);
+    for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3q; i += (long long)sb * NT) {
         const double2 P = a.x[vb + i];
         const double2 E = a.b[vb + i];
         const double2 w = cdotc(E, P);
         const int s = (int)(i / 3), c = (int)(i % 3);
-        const double2 d = ai[a.mat[s] * 3 + c];
+        const double2 d = ai[mat[s] * 3 + c];
         acc[0] += w.y;
         acc[1] += (-d.y - rr) * (P.x * P.x + P.y * P.y);
         acc[2] += w.x;
@@ -624,13 +652,15 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     switch (kind) {
         case FIN_V: case FIN_T: run = st->status == ST_ACTIVE; break;
         case FIN_RESTART: run = st->status == ST_BREAKDOWN && st->restarts == 0; break;
-        case FIN_REFINE: case FIN_QREFINE: run = st->status == ST_CONVERGED; break;
+        case FIN_REFINE: case FIN_QREFINE: run = st->status == ST_CONVERGED && !st->checked; break;
         case FIN_QV: case FIN_QUPD: case FIN_B_BETA: case FIN_B_MR: case FIN_B_UPD:
             run = st->status == ST_ACTIVE;
             break;
         default: run = true; break;
     }
     if (!run) return;
+    if (nblk == NBLK_PASS) nblk = a.rg[q].pass_blocks;
+    else if (nblk == NBLK_SITE) nblk = a.rg[q].site_blocks;
     const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE ||
                       kind == FIN_QV;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -774,6 +804,8 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                 st->pend = 0;
                 st->pad0 += 1;
                 st->status = st->iters >= st->max_iter ? ST_MAXITER : ST_ACTIVE;
+            } else {
+                st->checked = 1;
             }
             break;
         case FIN_QV: {
@@ -905,6 +937,8 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                 qmr_start(st, acc);
                 st->pad0 += 1;
                 if (st->status == ST_ACTIVE && st->iters >= st->max_iter) st->status = ST_MAXITER;
+            } else {
+                st->checked = 1;
             }
             break;
         case FIN_QSUM:
@@ -1058,10 +1092,10 @@ void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* 
 }
 
 void launch_alpha(int nrhs, int nmat, const double2* mats, double m_medium, const double* khat, const double2* e0,
-                  double kd, int scheme, double2* ainv, hipStream_t s) {
+                  double kd, int scheme, double2* ainv, hipStream_t s, int ostride) {
     const int n = nrhs * nmat;
     hipLaunchKernelGGL(k_alpha, dim3((n + 63) / 64), dim3(64), 0, s, nrhs, nmat, mats, m_medium, khat, e0, kd, scheme,
-                       ainv);
+                       ainv, ostride > 0 ? ostride : nmat);
 }
 
 void launch_einc(const SiteArgs& a, const int* coords, const double* khat, const double2* e0, hipStream_t s) {

@@ -22,6 +22,7 @@
 // runtime plan with twiddles staged in LDS.
 #pragma once
 
+#include <stdexcept>
 #include <type_traits>
 
 #include "dda_kernels.h"
@@ -97,12 +98,23 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
     const int q = blockIdx.z;
     const RhsState* st = a.st + q;
     if (skip_rhs(st, chk)) return;
-    const int nx = g.n[0], ny = g.n[1];
+    int nx = g.n[0], ny = g.n[1];
+    const int* map = a.map;
     const int Mx = CT ? LC : g.M[0];
     const int My = g.M[1];
     const int XL = CT ? 1 : XLrt;
     const int z = blockIdx.y;
     const int y0 = blockIdx.x * XL;
+    // the workgroups of one right-hand side along y, and its partial-sum index
+    int bx = gridDim.x;
+    if (a.rg) {   // ragged batch: this right-hand side's target
+        const RhsGeo& r = a.rg[q];
+        if (z >= r.n[2] || y0 >= r.n[1]) return;
+        nx = r.n[0];
+        ny = r.n[1];
+        map += r.map_off;
+        bx = (ny + XL - 1) / XL;
+    }
     const int nl = CT ? 1 : min(XL, ny - y0);
     const int nlines = 3 * nl;
     const int Lp = pad_len(Mx);
@@ -124,7 +136,7 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
     if (MODE == SC_B0 || MODE == SC_B2) beta = st->beta;
     if (MODE == SC_B1 || MODE == SC_B3) alpha = st->alpha;
     const long long vb = (long long)q * a.n3;
-    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    const int* mrow = map + ((long long)z * ny + y0) * nx;
     double ss[3] = {0.0, 0.0, 0.0};
     // forward transform of a line that is zero beyond nx: with 2 nx <= Mx the
     // first radix pass never reads the upper half, which is then not filled
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         // slots 5-7 of the block's entry; the gather of t (same grid) fills
         // slots 0-4 and one finalize reads both
         double* sh = (double*)(lds + nlines * Lp);
-        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        const int blk = blockIdx.y * bx + blockIdx.x;
         publish_partial<3, NTHR, 5>(ss, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
     }
 }
@@ -241,12 +253,24 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
     const int q = blockIdx.z;
     const RhsState* st = a.st + q;
     if (skip_rhs(st, chk)) return;
-    const int nx = g.n[0], ny = g.n[1];
+    int nx = g.n[0], ny = g.n[1];
+    const int* map = a.map;
+    const int* mat = a.mat;
     const int Mx = CT ? LC : g.M[0];
     const int My = g.M[1];
     const int XL = CT ? 1 : XLrt;
     const int z = blockIdx.y;
     const int y0 = blockIdx.x * XL;
+    int bx = gridDim.x;
+    if (a.rg) {   // ragged batch: this right-hand side's target
+        const RhsGeo& r = a.rg[q];
+        if (z >= r.n[2] || y0 >= r.n[1]) return;
+        nx = r.n[0];
+        ny = r.n[1];
+        map += r.map_off;
+        mat += r.site_off;
+        bx = (ny + XL - 1) / XL;
+    }
     const int nl = CT ? 1 : min(XL, ny - y0);
     const int nlines = 3 * nl;
     const int Lp = pad_len(Mx);
@@ -259,7 +283,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         lds = tws + even_up(Mx);
         load_twiddles<T, NTHR>(tws, tw64, g.ax[0]);
     }
-    const int* mrow = a.map + ((long long)z * ny + y0) * nx;
+    const int* mrow = map + ((long long)z * ny + y0) * nx;
     const int tout = nl * nx * 3;
     // compile-time lengths (one line per workgroup): the site index and
     // material of each element this thread gathers are loaded before the
@@ -285,7 +309,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
     }
     if constexpr (CT) {
 #pragma unroll
-        for (int k = 0; k < PF; ++k) pm[k] = ps[k] >= 0 ? a.mat[ps[k]] : 0;
+        for (int k = 0; k < PF; ++k) pm[k] = ps[k] >= 0 ? mat[ps[k]] : 0;
     }
     __syncthreads();
     if constexpr (CT) {
@@ -383,12 +407,12 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             const int e = rest % nx;
             const int yo = rest / nx;
             const int s = mrow[yo * nx + e];
-            if (s >= 0) site(c, e, yo, s, a.mat[s]);
+            if (s >= 0) site(c, e, yo, s, mat[s]);
         }
     }
     if (MODE != GA_PLAIN) {
         double* sh = (double*)(lds + nlines * Lp);
-        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        const int blk = blockIdx.y * bx + blockIdx.x;
         if constexpr (MODE == GA_B3) {
             publish_partial<8, NTHR>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
         } else if constexpr (MODE == GA_T) {
@@ -405,6 +429,26 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
 }
 
 // ------------------------------------------------------------------ passes 2-4
+
+// Right-hand side q of a strided pass in a ragged batch (g.rg): the y passes
+// (axis 1) cover the planes z < n_z of its target (false beyond) and read its
+// y < n_y (forward) or write them (inverse); pass 3 (axis 2) reads and writes
+// z < n_z with its target's tensor.  Unchanged for a single target.
+template <typename C>
+__device__ __forceinline__ bool ragged_lines(const Geo& g, int q, int axis, int dir, int o, int& lin, int& lout,
+                                             const C*& gh) {
+    if (!g.rg) return true;
+    const RhsGeo& r = g.rg[q];
+    if (axis == 1) {
+        if (o >= r.n[2]) return false;
+        if (dir < 0) lin = r.n[1];
+        else lout = r.n[1];
+    } else {
+        lin = lout = r.n[2];
+        gh = (const C*)r.ghat[sizeof(C) == sizeof(float2) ? 1 : 0];
+    }
+    return true;
+}
 
 // XCD-grouped workgroup order of pass 3: the grid is one-dimensional and
 // ordered so that the workgroups sharing tensor values -- the column tiles x
@@ -514,6 +558,9 @@ __global__ __launch_bounds__(NT) void k_strided(Geo g, typename V2<T>::t* grid, 
     const int q1 = RHS_LOOP ? nrhs : qx + 1;
     // forward transforms with 2 lin <= L never read the upper half of a line;
     // inverse transforms with 2 lout <= L never write it
+    if constexpr (!RHS_LOOP) {
+        if (!ragged_lines(g, qx, axis, DIR, o, lin, lout, ghat)) return;
+    }
     bool hin = false, hout = false;
     if constexpr (CT) {
         hin = (GH || DIR < 0) && ct_half_in_ok(LC) && 2 * lin <= L;
@@ -816,6 +863,7 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
         xt = blockIdx.x;
     }
     if (skip_rhs(st + q, chk)) return;
+    if (!ragged_lines(g, q, axis, DIR, o, lin, lout, ghat)) return;
     const int in = threadIdx.x % NIN;
     const int t = threadIdx.x / NIN;
     const int x0 = xt * TX;
@@ -1006,6 +1054,7 @@ void k_zsq(Geo g, typename V2<T>::t* grid, const double2* tw64, const typename V
         xt = blockIdx.x;
     }
     if (skip_rhs(st + q, chk)) return;
+    if (!ragged_lines(g, q, 2, -1, o, lin, lout, ghat)) return;
     const int in = threadIdx.x % TX;
     const int t = threadIdx.x / TX;
     const int kx = xt * TX + in;
@@ -1258,6 +1307,27 @@ template <typename T> constexpr bool rf_feasible(int L, int gh, int r) {
     return P > 0 && vgpr <= 192 && thr <= 512 && lds <= 65536;
 }
 
+constexpr int RAGGED_FALLBACK = 3;
+
+template <typename T, int NC, int GH, int DIR, int LL, int V>
+void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
+                       typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
+                       const RhsState* st, hipStream_t s);
+
+// the default variant, or for a ragged batch's pass 3 the default among the
+// one-right-hand-side-per-workgroup variants
+template <typename T, int NC, int GH, int DIR, int LL>
+void strided_ct_fallback(int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
+                         typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
+                         const RhsState* st, hipStream_t s) {
+    static_assert(ragged_variant(1, RAGGED_FALLBACK) && RAGGED_FALLBACK < n_lds_variants(1), "fallback");
+    if (GH && g.rg)
+        strided_ct_launch<T, NC, GH, DIR, LL, RAGGED_FALLBACK>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw,
+                                                              ghat, st, s);
+    else
+        strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+}
+
 template <typename T, int NC, int GH, int DIR, int LL, int V>
 void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
                        typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
@@ -1279,7 +1349,7 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                 return;
             }
         }
-        strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+        strided_ct_fallback<T, NC, GH, DIR, LL>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
     } else if constexpr (V >= n_lds_variants(GH)) {
         constexpr int R = V - n_lds_variants(GH);
         constexpr int TX = rf_tx(GH, R), XR = rf_xr(GH, R);
@@ -1303,7 +1373,7 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                 return;
             }
         }
-        strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+        strided_ct_fallback<T, NC, GH, DIR, LL>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
     } else {
         constexpr int TX = variant_tx<T>(LL, GH, V);
         constexpr int VR = variant_var(GH, V);
@@ -1328,6 +1398,7 @@ template <typename T, int NC, int GH, int DIR, int LL>
 void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_outer, int lin, int lout,
                         typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat,
                         const RhsState* st, hipStream_t s) {
+    if (g.rg && !ragged_variant(GH, v)) v = -1;
     switch (v) {
 #define DDA_V(VV)                                                                                             \
     case VV:                                                                                                 \
@@ -1343,7 +1414,7 @@ void strided_ct_variant(int v, int axis, int chk, const Geo& g, int nrhs, int n_
         default:
             break;
     }
-    strided_ct_launch<T, NC, GH, DIR, LL, 0>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
+    strided_ct_fallback<T, NC, GH, DIR, LL>(axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
 }
 
 template <typename T, int NC, int GH, int DIR>
@@ -1365,6 +1436,7 @@ void strided_dispatch(int variant, int axis, int chk, const Geo& g, int nrhs, in
                 break;
         }
     }
+    if (g.rg) throw std::invalid_argument("a ragged batch needs compile-time FFT lengths");
     const int TX = strided_cols_per_tile(L, NC, sizeof(T) == 4);
     dim3 grd((g.M[0] + TX - 1) / TX, n_outer, GH ? 1 : nrhs);
     DDA_LAUNCH((k_strided<T, NC, GH, DIR, 0>), grd, dim3(NT), smem_rt<C>(L, NC * TX), s, g, grid, tw, ghat,

@@ -9,6 +9,7 @@ Tolerances:
   residual bound times a modest condition number), Q within 1e-4 relative of
   the oracle (the target this build works to).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -500,6 +501,70 @@ def test_solve_batched_matches_separate_solves(dda):
             assert res[g]["status"] == 0
             assert abs(res[g]["qext"] / q_mie["qext"] - 1) < 0.05
             assert abs(res[g]["qsca"] / q_mie["qsca"] - 1) < 0.05
+
+
+def _shared_grid_targets(dda):
+    """Four targets on the 32^3 padded grid with different boxes, site
+    counts, material counts and sizes: spheres of radius 5.5, 6.2 and 7.9 and
+    a two-material 12 x 11 x 14 brick."""
+    ts = [dda.Target(w.sphere_integer(r), m) for r, m in ((5.5, 1.33 + 0.01j), (6.2, 1.5 + 0.1j),
+                                                          (7.9, 1.7 + 0.05j))]
+    b = w.brick(12, 11, 14)
+    mb = np.where(np.arange(len(b)) % 3 == 0, 1.4 + 0.02j, 2.0 + 0.3j)
+    ts.append(dda.Target(b, mb))
+    for t in ts:
+        assert tuple(t.grid) == (32, 32, 32)
+    return ts
+
+
+@pytest.mark.parametrize("solver,precision", [("bicgstab", "fp64"), ("bicgstab", "fp32_matvec"),
+                                              ("qmr", "fp64"), ("qmr", "fp32_matvec"),
+                                              ("bicgstab2", "fp64"), ("bicgstab2", "fp32_matvec")])
+def test_shared_launch_batch_matches_separate_solves(dda, solver, precision):
+    """Targets on one padded grid share every launch of dda_solve_batched
+    (each right-hand side reads its own box, sites, materials, kd and tensor
+    through the per-right-hand-side table).  Every right-hand side's P and
+    result equal, bitwise, those of solving its target alone, for each solver
+    and precision, with per-target tolerance, size parameter and
+    polarizability; with share_launches off too."""
+    ts = _shared_grid_targets(dda)
+    xs = (2.0, 3.1, 2.6, 1.7)
+    tols = (1e-5, 1e-6, 3e-5, 1e-5)
+    polz = ("LATTDR", "GKDLDR", "LATTDR", "LATTDR")
+    opts = [dda.Options.for_size_parameter(x, tol=tol, polarizability=pz, solver=solver, precision=precision)
+            for x, tol, pz in zip(xs, tols, polz)]
+    kh_all, e0_all = w.incidences_for_orientations(11, 3)
+    counts = (2, 3, 1, 2)
+    rt, kh, e0 = [], [], []
+    for i, c in enumerate(counts):
+        rt += [i] * c
+        kh.append(kh_all[:c])
+        e0.append(e0_all[:c])
+    # interleave the right-hand sides of different targets
+    order = [0, 2, 5, 1, 3, 6, 4, 7]
+    rt = np.array(rt)[order]
+    kh = np.vstack(kh)[order]
+    e0 = np.vstack(e0)[order]
+    Ps, res = dda.solve_batched(ts, opts, rt, kh, e0)
+    noshare = [dataclasses.replace(o, share_launches=False) for o in opts]
+    Pn, rn = dda.solve_batched(ts, noshare, rt, kh, e0)
+    for i, t in enumerate(ts):
+        qs = [q for q in range(len(rt)) if rt[q] == i]
+        P1, r1 = dda.solve(t, opts[i], kh[qs], e0[qs])
+        for k, q in enumerate(qs):
+            assert res[q]["status"] == 0, (i, res[q])
+            assert torch.equal(Ps[q], P1[k]) and res[q] == r1[k], (i, q)
+            assert torch.equal(Pn[q], P1[k]) and rn[q] == r1[k], (i, q)
+
+
+def test_shared_launch_batch_rejects_one_target_at_two_kd(dda):
+    """A target listed twice must have one kd (it holds one tensor)."""
+    t = _shared_grid_targets(dda)[0]
+    o1 = dda.Options.for_size_parameter(2.0)
+    o2 = dda.Options.for_size_parameter(2.5)
+    kh, e0 = w.along_x_yz()
+    with pytest.raises(RuntimeError, match="listed twice"):
+        dda.solve_batched([t, t], [o1, o2], [0, 1], kh, e0)
 
 
 def test_config3_batch_full(dda):
@@ -1040,18 +1105,27 @@ def _three_lines(n):
     return np.unique(np.array(pts), axis=0).astype(np.int32)
 
 
-# padded extents 27, 30, 36 | 40, 45, 50 | 54, 60, 72 | 75, 81, 45: the
-# lengths the ragged sphere batch's grids use (radii 6..20), all of them
-# runtime-planned (no compile-time kernel)
-RT_LINES = [(14, 15, 18), (20, 23, 25), (27, 30, 36), (38, 41, 23)]
+def _library_extent(n):
+    """The library's padded extent (include/dda.h): the smallest compile-time
+    FFT length >= 2n - 1 when at most 1.4 times the 2,3,5-smooth extent, else
+    the smooth extent."""
+    m = fftsolve.padded_extent(n)
+    for L in (32, 48, 64, 80, 96, 128, 160, 192, 256):
+        if L >= 2 * n - 1:
+            return L if 5 * L <= 7 * m else m
+    return m
 
 
+# box extents whose sites fill a fraction of their compile-time grids (the
+# sphere batch's boxes, 13..41 sites, pad to 32..96), and extents that keep
+# runtime-planned lengths (10, 18, 20 below 32; 270, 288, 300 above 256)
+RT_LINES = [(14, 15, 18), (20, 23, 25), (27, 30, 36), (38, 41, 23), (9, 10, 5), (131, 140, 150)]
 @pytest.mark.parametrize("n", RT_LINES, ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_matvec", 2e-5)])
 def test_matvec_runtime_lengths_match_dense(dda, n, precision, tol):
     ijk = _three_lines(n)
     tgt = dda.Target(ijk, np.where(np.arange(len(ijk)) % 2 == 0, 1.33 + 0.01j, 1.6 + 0.2j))
-    assert tgt.grid == tuple(fftsolve.padded_extent(v) for v in n)
+    assert tgt.grid == tuple(_library_extent(v) for v in n)
     m = np.where(np.arange(len(ijk)) % 2 == 0, 1.33 + 0.01j, 1.6 + 0.2j)
     kh = np.array([[1, 0, 0], [0.36, 0.48, 0.8]])
     e0 = np.array([[0, 1, 0], np.array([0.8, -0.6, 0]) + 1j * np.cross([0.36, 0.48, 0.8], [0.8, -0.6, 0])])
@@ -1066,15 +1140,15 @@ def test_matvec_runtime_lengths_match_dense(dda, n, precision, tol):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_matvec", 2e-5)])
 def test_matvec_sphere_batch_grids_match_oracle_fft(dda, precision, tol):
     """One sphere of the ragged batch per distinct padded grid (every grid
-    the 32 spheres use), A x at full size against the oracle's FFT operator,
-    element by element."""
+    the 32 spheres use), A x at full size against the oracle's FFT operator
+    (on its own padded grid), element by element."""
     radii = w.sphere_radii(0)
     seen = {}
     for r in radii:
         ijk = w.sphere_integer(r)
-        g = fftsolve.padded_extent(int(ijk[:, 0].max() - ijk[:, 0].min() + 1))
+        g = _library_extent(int(ijk[:, 0].max() - ijk[:, 0].min() + 1))
         seen.setdefault(g, r)
-    assert len(seen) >= 9
+    assert sorted(seen) == [32, 48, 64, 80]
     kh, e0 = w.along_x_yz()
     for g, r in sorted(seen.items()):
         ijk = w.sphere_integer(r)
