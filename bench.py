@@ -172,7 +172,7 @@ PASS_PATTERNS = {
 }
 AUTOTUNE_LAUNCHES = 21   # launches of each candidate while the autotuner times it (1 + 20)
 # FFT lengths with compile-time kernels, and their autotuned variants per pass
-CT_LENGTHS = (32, 48, 64, 80, 96, 128, 160, 192, 256)
+CT_LENGTHS = (32, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512)
 CT_VARIANTS = {"fft_y_fwd": 8, "fft_z_green": 28, "fft_y_inv": 8}
 
 
@@ -442,7 +442,7 @@ def cpu_baseline(d: dict, workload: str, gpu_iters: int) -> dict:
 
 def padded(n: int) -> int:
     """The library's padded FFT extent: the smallest compile-time FFT length
-    (32 ... 256) >= 2n - 1 when at most 1.4 times the smooth extent, else the
+    (32 ... 512) >= 2n - 1 when at most 1.4 times the smooth extent, else the
     smooth extent (2n if 2,3,5-smooth, else the smallest smooth one >= 2n - 1)."""
     def smooth(m):
         for p in (2, 3, 5):
@@ -455,7 +455,7 @@ def padded(n: int) -> int:
         m = max(2 * n - 1, 1)
         while not smooth(m):
             m += 1
-    for L in (32, 48, 64, 80, 96, 128, 160, 192, 256):
+    for L in (32, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512):
         if L >= 2 * n - 1:
             return L if 5 * L <= 7 * m else m
     return m

@@ -169,14 +169,18 @@ dda_status dda_ctx_destroy(dda_ctx* ctx);
  * The library keeps sorted device copies, the occupancy map of the bounding
  * box and, lazily, the FFT of the interaction tensor per (kd, precision).
  * Errors: DDA_E_INVALID for n_sites < 1, duplicate sites, a box extent above
- * 4096 or one whose padded FFT extent exceeds 341, more than 65535 distinct
+ * 256 on an axis (a padded FFT extent above 512), more than 65535 distinct
  * materials, a vacuum site (m = 1) or non-finite m; DDA_E_NOMEM. */
 dda_status dda_target_create(dda_ctx* ctx, int64_t n_sites, const int32_t* ijk,
                              const dda_c64* m_site, dda_target** out);
 dda_status dda_target_destroy(dda_target* t);
 
 /* Geometry of a target: box[3] = bounding-box extents n, grid[3] = padded
- * FFT extents M (2n when 2,3,5-smooth, else the smallest such >= 2n-1). */
+ * FFT extents M >= 2n - 1 (every separation -(n-1)..n-1 its own slot, so the
+ * circulant product is exactly the Toeplitz one).  With m the smooth extent
+ * (2n when 2,3,5-smooth, else the smallest 2,3,5-smooth value >= 2n - 1), M is
+ * the smallest of the compile-time lengths 32, 48, 64, 80, 96, 128, 160, 192,
+ * 256, 384, 512 that is >= 2n - 1, when 5 M <= 7 m; else m. */
 dda_status dda_target_geometry(const dda_target* t, int32_t box[3], int32_t grid[3]);
 
 /* y = A x for n_rhs right-hand sides (A depends on the incidence through
@@ -267,7 +271,7 @@ dda_status dda_grad_eps(dda_ctx* ctx, dda_target* t, const dda_opts* opts, const
  * round(r_i * n_a) lattice points on each side, ext = (r1, r2, r3, r4, r5, r6)
  * for -x, +x, -y, +y, -z, +z and n_a the box's extent in sites on axis a;
  * 0 <= r_i <= 16, and each grown extent must allow a padded FFT extent of at
- * most 341 (E_INVALID otherwise).  dda_nearfield_volume writes the lattice
+ * most 512, i.e. at most 256 points (E_INVALID otherwise).  dda_nearfield_volume writes the lattice
  * coordinates of the volume's first point (origin) and its extents (dims). */
 dda_status dda_nearfield_volume(const dda_target* t, const double ext[6], int32_t origin[3], int32_t dims[3]);
 

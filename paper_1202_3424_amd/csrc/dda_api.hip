@@ -89,10 +89,14 @@ int smooth_extent(int n) {
 }
 int padded_extent(int n) {
     const int m = smooth_extent(n);
-    for (int L : {32, 48, 64, 80, 96, 128, 160, 192, 256})
+    for (int L : {32, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512})
         if (L >= 2 * n - 1) return 5 * L <= 7 * m ? L : m;
     return m;
 }
+// Largest padded extent on an axis: the FP64 LDS tile holds three
+// components of a line up to 682 points, and the compile-time kernels stop
+// at 512.  Every box extent up to 256 pads to at most 512.
+constexpr int MAX_PADDED = 512;
 
 // Radix sequence: powers of two as 8s and 4s (a single 2 only for L = 2^1 or
 // 2^(3j+1) with j = 0), then 3s, then 5s.
@@ -579,7 +583,8 @@ struct Work {
     // variant of each strided pass by timing every candidate on the workspace
     // grid (its contents are scratch at this point; all variants compute
     // bitwise-identical results), one warm-up and twenty timed launches
-    // each, pass 3 each time behind the forward y pass.  Among the variants
+    // each (fewer on large grids), pass 3 each time behind the forward y
+    // pass.  Among the variants
     // within 3% of the fastest it takes the lowest-numbered, so that
     // near-ties resolve the same way from run to run.
     void autotune(bool enabled, int forced = 0) {
@@ -614,11 +619,28 @@ struct Work {
                     if (fp32) strided_slot<float>(0, CHK_NONE, best[0]);
                     else strided_slot<double>(0, CHK_NONE, best[0]);
                 };
+                // twenty launches per candidate, fewer (at least three, about
+                // 40 ms) where one launch of the default variant is long
+                int reps = 20;
+                {
+                    auto run0 = [&]() {
+                        if (fp32) strided_slot<float>(slot, CHK_NONE, 0);
+                        else strided_slot<double>(slot, CHK_NONE, 0);
+                    };
+                    run0();
+                    HIPCHK(hipEventRecord(e0, s));
+                    run0();
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float t1 = 0.f;
+                    HIPCHK(hipEventElapsedTime(&t1, e0, e1));
+                    if (t1 > 2.f) reps = std::max(3, std::min(20, (int)(40.f / t1)));
+                }
                 float t_y = 0.f;
                 if (slot == 1) {
                     run_y();
                     HIPCHK(hipEventRecord(e0, s));
-                    for (int k = 0; k < 20; ++k) run_y();
+                    for (int k = 0; k < reps; ++k) run_y();
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
                     HIPCHK(hipEventElapsedTime(&t_y, e0, e1));
@@ -634,7 +656,7 @@ struct Work {
                     };
                     run();
                     HIPCHK(hipEventRecord(e0, s));
-                    for (int k = 0; k < 20; ++k) {
+                    for (int k = 0; k < reps; ++k) {
                         if (slot == 1) run_y();
                         run();
                     }
@@ -705,9 +727,9 @@ void ensure_green(dda_ctx* c, dda_target* t, double kd, bool fp32, bool force) {
     const double2* tw = (const double2*)t->tw.p;
     Timed tm(c, T_GREEN, c->stream);
     launch_green_sample(g, kd, G, c->stream);
-    launch_xgrid6(g, G, tw, c->stream);
-    launch_strided<double>(1, -1, CHK_NONE, g, 1, 6, g.M[2], g.M[1], g.M[1], G, tw, nullptr, nullptr, c->stream);
-    launch_strided<double>(2, -1, CHK_NONE, g, 1, 6, g.M[1], g.M[2], g.M[2], G, tw, nullptr, nullptr, c->stream);
+    launch_xgrid3(g, G, tw, c->stream);
+    launch_strided<double>(1, -1, CHK_NONE, g, 2, 3, g.M[2], g.M[1], g.M[1], G, tw, nullptr, nullptr, c->stream);
+    launch_strided<double>(2, -1, CHK_NONE, g, 2, 3, g.M[1], g.M[2], g.M[2], G, tw, nullptr, nullptr, c->stream);
     const size_t nh = (size_t)g.H[0] * g.H[1] * g.H[2] * 6;
     if (fresh) t->have64 = t->have32 = false;
     double2* g64 = (double2*)t->gh64.ensure(nh * sizeof(double2));
@@ -1481,8 +1503,9 @@ dda_target* create_target(dda_ctx* c, int64_t n_sites, const int32_t* ijk, const
         g.H[a] = g.M[a] / 2 + 1;
     }
     for (int a = 0; a < 3; ++a)
-        if (6 * g.M[a] > Tile<double>::EMAX)
-            invalid("padded FFT extent " + std::to_string(g.M[a]) + " above the supported 341");
+        if (g.M[a] > MAX_PADDED || 3 * g.M[a] > Tile<double>::EMAX)
+            invalid("box extent " + std::to_string(g.n[a]) + " needs a padded FFT extent " +
+                    std::to_string(g.M[a]) + " above the supported 512");
     g.npts = (long long)g.M[0] * g.M[1] * g.M[2];
     const long long boxv = (long long)g.n[0] * g.n[1] * g.n[2];
     if (boxv > ((long long)1 << 31) - 1) invalid("bounding box too large");
@@ -1583,9 +1606,9 @@ void nf_extension(const dda_target* t, const double* r, int e[6], int org[3], in
     for (int a = 0; a < 3; ++a) {
         org[a] = t->lo[a] - e[2 * a];
         dims[a] = t->geo.n[a] + e[2 * a] + e[2 * a + 1];
-        if (padded_extent(dims[a]) > Tile<double>::EMAX / 6)
+        if (padded_extent(dims[a]) > MAX_PADDED)
             invalid("near-field volume of " + std::to_string(dims[a]) + " points on axis " + std::to_string(a) +
-                    " needs a padded FFT extent above the supported 341");
+                    " needs a padded FFT extent above the supported 512");
     }
 }
 

@@ -289,6 +289,8 @@ constexpr int ct_plan(int L, int s) {
         case 160: r[0] = 8; r[1] = 5; r[2] = 4; n = 3; break;
         case 192: r[0] = 8; r[1] = 3; r[2] = 8; n = 3; break;
         case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; n = 4; break;
+        case 384: r[0] = 4; r[1] = 3; r[2] = 4; r[3] = 8; n = 4; break;
+        case 512: r[0] = 8; r[1] = 4; r[2] = 4; r[3] = 4; n = 4; break;
         default: break;
     }
     return s < 0 ? n : r[s];
@@ -304,6 +306,8 @@ constexpr int ct_split(int L) {
         case 160: return 40;
         case 192: return 24;
         case 256: return 16;
+        case 384: return 48;
+        case 512: return 32;
         default: return 0;
     }
 }
@@ -321,7 +325,8 @@ constexpr bool ct_plan_ok(int L) {
     return p == L && pa == ct_split(L) && ct_split(L) % (L / ct_split(L)) == 0;
 }
 static_assert(ct_plan_ok(32) && ct_plan_ok(48) && ct_plan_ok(64) && ct_plan_ok(80) && ct_plan_ok(96) &&
-                  ct_plan_ok(128) && ct_plan_ok(160) && ct_plan_ok(192) && ct_plan_ok(256),
+                  ct_plan_ok(128) && ct_plan_ok(160) && ct_plan_ok(192) && ct_plan_ok(256) && ct_plan_ok(384) &&
+                  ct_plan_ok(512),
               "radix plans must factor L with the split P >= Q, Q | P");
 
 // One radix-R pass over NL lines of compile-time length L (same in-place

@@ -134,7 +134,8 @@ enum FinKind {
 
 // FFT lengths with compile-time kernels (dda_passes.h)
 inline bool ct_length(int L) {
-    return L == 32 || L == 48 || L == 64 || L == 80 || L == 96 || L == 128 || L == 160 || L == 192 || L == 256;
+    return L == 32 || L == 48 || L == 64 || L == 80 || L == 96 || L == 128 || L == 160 || L == 192 || L == 256 ||
+           L == 384 || L == 512;
 }
 
 // tile sizes chosen by the host: x-lines (along y) per workgroup of the x
@@ -167,7 +168,10 @@ inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 28 : 8
 constexpr bool ragged_variant(int gh, int v) {
     return !gh || !(v == 0 || v == 1 || v == 2 || v == 7 || v == 8 || v == 9);
 }
-void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
+// The interaction tensor on the padded grid is held as two three-component
+// slabs [2][npts][3]: (xx, xy, xz) and (yy, yz, zz), so that its transforms
+// run as the three-component passes with two right-hand sides.
+void launch_xgrid3(const Geo& g, double2* grid, const double2* tw, hipStream_t s);
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s);
 void launch_green_octant(const Geo& g, const double2* G, double2* gh64, float2* gh32, hipStream_t s);

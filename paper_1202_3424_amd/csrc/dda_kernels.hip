@@ -2,6 +2,7 @@
 // (dda_passes.h): the interaction-tensor sampling and its FFT, 1/alpha,
 // E_inc, the BiCGSTAB updates and their reductions, the efficiency sums, the
 // adjoint right-hand side and gradient, and small utilities.
+#include <stdexcept>
 #include "dda_kernels.h"
 
 namespace dda {
@@ -28,36 +29,36 @@ template <typename C> __host__ inline size_t fft_smem(int L, int nlines) {
     return ((size_t)((L + 1) & ~1) + (size_t)nlines * pad_len(L)) * sizeof(C) + 8 * (NT / 64) * sizeof(double) + 64;
 }
 
-// Forward FFT along x of every line of a six-component FP64 grid (the
-// interaction tensor).
-__global__ __launch_bounds__(NT) void k_xgrid6(Geo g, double2* grid, const double2* tw64, int XL) {
+// Forward FFT along x of every line of a two-slab three-component FP64 grid
+// (the interaction tensor; slab = grid z).
+__global__ __launch_bounds__(NT) void k_xgrid3(Geo g, double2* grid, const double2* tw64, int XL) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int Mx = g.M[0], My = g.M[1];
     const int z = blockIdx.y;
     const int y0 = blockIdx.x * XL;
     const int nl = min(XL, My - y0);
-    const int nlines = 6 * nl;
+    const int nlines = 3 * nl;
     const int Lp = pad_len(Mx);
     double2* tws = (double2*)smem;
     double2* lds = tws + ((Mx + 1) & ~1);
     load_twiddles<double>(tws, tw64, g.ax[0]);
-    double2* gq = grid + ((long long)z * My + y0) * Mx * 6;
-    const int tot = nl * Mx * 6;
+    double2* gq = grid + (long long)blockIdx.z * g.npts * 3 + ((long long)z * My + y0) * Mx * 3;
+    const int tot = nl * Mx * 3;
     for (int idx = threadIdx.x; idx < tot; idx += NT) {
-        const int c = idx % 6;
-        const int rest = idx / 6;
+        const int c = idx % 3;
+        const int rest = idx / 3;
         const int e = rest % Mx;
         const int yo = rest / Mx;
-        lds[(yo * 6 + c) * Lp + e] = gq[idx];
+        lds[(yo * 3 + c) * Lp + e] = gq[idx];
     }
     __syncthreads();
     fft_lines<double, -1>(lds, tws, nlines, Lp, g.ax[0]);
     for (int idx = threadIdx.x; idx < tot; idx += NT) {
-        const int c = idx % 6;
-        const int rest = idx / 6;
+        const int c = idx % 3;
+        const int rest = idx / 3;
         const int e = rest % Mx;
         const int yo = rest / Mx;
-        gq[idx] = lds[(yo * 6 + c) * Lp + e];
+        gq[idx] = lds[(yo * 3 + c) * Lp + e];
     }
 }
 
@@ -82,10 +83,12 @@ __global__ __launch_bounds__(NT) void k_green_sample(Geo g, double kd, double2* 
     const int my = (int)((i / Mx) % My);
     const int mz = (int)(i / ((long long)Mx * My));
     int dx, dy, dz;
-    double2* out = G + i * 6;
+    // component c in slab c / 3, position c % 3
+    double2* out0 = G + i * 3;
+    double2* out1 = G + (g.npts + i) * 3;
     const bool ok = sep(mx, g.n[0], Mx, dx) && sep(my, g.n[1], My, dy) && sep(mz, g.n[2], Mz, dz);
     if (!ok || (dx == 0 && dy == 0 && dz == 0)) {
-        for (int c = 0; c < 6; ++c) out[c] = double2{0.0, 0.0};
+        for (int c = 0; c < 3; ++c) out0[c] = out1[c] = double2{0.0, 0.0};
         return;
     }
     const double X = dx, Y = dy, Z = dz;
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(NT) void k_green_sample(Geo g, double kd, double2* 
     for (int c = 0; c < 6; ++c) {
         double2 v = cscale(cnn, R[ab[c][0]] * R[ab[c][1]]);
         if (ab[c][0] == ab[c][1]) v = cadd(v, ciso);
-        out[c] = v;
+        (c < 3 ? out0 : out1)[c % 3] = v;
     }
 }
 
@@ -116,10 +119,10 @@ __global__ __launch_bounds__(NT) void k_green_octant(Geo g, const double2* G, do
     const int hx = (int)(i % g.H[0]);
     const int hy = (int)((i / g.H[0]) % g.H[1]);
     const int hz = (int)(i / ((long long)g.H[0] * g.H[1]));
-    const long long src = (((long long)hz * g.M[1] + hy) * g.M[0] + hx) * 6;
+    const long long src = (((long long)hz * g.M[1] + hy) * g.M[0] + hx) * 3;
     const double sc = 1.0 / (double)g.npts;
     for (int c = 0; c < 6; ++c) {
-        const double2 v = cscale(G[src + c], sc);
+        const double2 v = cscale(G[(c < 3 ? 0 : g.npts * 3) + src + c % 3], sc);
         if (gh64) gh64[i * 6 + c] = v;
         if (gh32) gh32[i * 6 + c] = float2{(float)v.x, (float)v.y};
     }
@@ -1075,11 +1078,11 @@ int strided_cols_per_tile(int L, int nc, bool fp32) {
     return p;
 }
 
-void launch_xgrid6(const Geo& g, double2* grid, const double2* tw, hipStream_t s) {
-    int XL = Tile<double>::EMAX / (6 * g.M[0]);
-    if (XL < 1) XL = 1;
-    dim3 grd((g.M[1] + XL - 1) / XL, g.M[2], 1);
-    hipLaunchKernelGGL(k_xgrid6, grd, dim3(NT), fft_smem<double2>(g.M[0], 6 * XL), s, g, grid, tw, XL);
+void launch_xgrid3(const Geo& g, double2* grid, const double2* tw, hipStream_t s) {
+    int XL = Tile<double>::EMAX / (3 * g.M[0]);
+    if (XL < 1) throw std::invalid_argument("x extent above the LDS line tile");
+    dim3 grd((g.M[1] + XL - 1) / XL, g.M[2], 2);
+    hipLaunchKernelGGL(k_xgrid3, grd, dim3(NT), fft_smem<double2>(g.M[0], 3 * XL), s, g, grid, tw, XL);
 }
 
 void launch_green_sample(const Geo& g, double kd, double2* G, hipStream_t s) {

@@ -31,7 +31,7 @@ namespace dda {
 namespace passes {
 
 // lengths with compile-time kernels
-#define DDA_CT_LENGTHS(X) X(32) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256)
+#define DDA_CT_LENGTHS(X) X(32) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(384) X(512)
 
 // x columns per workgroup of a compile-time strided pass: a tile of about
 // 1536 complex values (three components per column)
@@ -1486,9 +1486,8 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant) {
     using namespace passes;
-    if (nc == 6) {
-        strided_dispatch<T, 6, 0, -1>(0, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
-    } else if (ghat) {
+    if (nc != 3) throw std::invalid_argument("strided passes take three-component lines");
+    if (ghat) {
         strided_dispatch<T, 3, 1, -1>(variant, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);
     } else if (dir < 0) {
         strided_dispatch<T, 3, 0, -1>(variant, axis, chk, g, nrhs, n_outer, lin, lout, grid, tw, ghat, st, s);

@@ -1066,34 +1066,100 @@ def test_nearfield_gold_sphere_printed_track_on_gpu(dda):
 
 def test_degenerate_inputs_are_rejected(dda):
     """An empty target, a vacuum site, no right-hand sides, and a box whose
-    padded FFT extent would exceed the supported 341 are errors, not launches."""
+    padded FFT extent would exceed the supported 512 are errors, not launches."""
     with pytest.raises(dda.DDAError):
         dda.Target(np.zeros((0, 3), dtype=np.int32), 1.5)
     with pytest.raises(dda.DDAError):
         dda.Target(np.array([[0, 0, 0], [1, 0, 0]]), np.array([1.5, 1.0]))
-    with pytest.raises(dda.DDAError):        # 171 sites on x: padded extent 342
-        dda.Target(np.array([[i, 0, 0] for i in range(171)]), 1.5)
+    for axis in range(3):                    # 257 sites: padded extent 540
+        ijk = np.zeros((257, 3), dtype=np.int32)
+        ijk[:, axis] = np.arange(257)
+        with pytest.raises(dda.DDAError, match="above the supported 512"):
+            dda.Target(ijk, 1.5)
     tgt = dda.Target(w.sphere_integer(2.0), 1.5 + 0.1j)
     with pytest.raises(dda.DDAError):
         dda.solve(tgt, dda.Options.for_size_parameter(1.0), np.zeros((0, 3)), np.zeros((0, 3), complex))
 
 
+@pytest.mark.parametrize("n,grid", [(135, 270), (160, 384), (256, 512)])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_largest_padded_extent_matches_dense(dda, axis):
-    """A line of 160 sites has the padded extent 320, the largest 2,3,5-smooth
-    one within the supported 341 (a runtime-planned transform); on each axis
-    the product equals the dense one (1e-12 of max|y|)."""
-    ijk = np.zeros((160, 3), dtype=np.int32)
-    ijk[:, axis] = np.arange(160) - 40
+def test_largest_padded_extents_match_dense(dda, axis, n, grid):
+    """A line of n sites on one axis: 135 sites pad to 270 (the largest
+    runtime-planned extent the padding rule produces), 160 to 384 and 256 to
+    512 (the largest compile-time lengths; every extent up to 256 pads to at
+    most 512).  On each axis, in FP64 and in FP32, the product equals the
+    dense one (1e-12 and 2e-5 of max|y|)."""
+    ijk = np.zeros((n, 3), dtype=np.int32)
+    ijk[:, axis] = np.arange(n) - 40
     tgt = dda.Target(ijk, 1.4 + 0.2j)
-    assert tgt.grid[axis] == 320
+    assert tgt.grid[axis] == grid == _library_extent(n)
     kh, e0 = [[0.0, 0.6, 0.8]], [[1.0, 0.0, 0.0]]
-    opts = dda.Options.for_size_parameter(3.0)
-    xv = w.random_vectors(13, (1, 160, 3))
-    y = dda.apply(tgt, opts, kh, e0, _cuda(xv)).cpu().numpy()
-    A = _dense_A(ijk, np.full(160, 1.4 + 0.2j), 3.0, kh[0], e0[0], "LATTDR")
+    xv = w.random_vectors(13, (1, n, 3))
+    A = _dense_A(ijk, np.full(n, 1.4 + 0.2j), 3.0, kh[0], e0[0], "LATTDR")
     ref = (A @ xv[0].reshape(-1)).reshape(-1, 3)
-    assert np.abs(y[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+    for prec, tol in (("fp64", 1e-12), ("fp32_matvec", 2e-5)):
+        opts = dda.Options.for_size_parameter(3.0, precision=prec)
+        y = dda.apply(tgt, opts, kh, e0, _cuda(xv)).cpu().numpy()
+        assert np.abs(y[0] - ref).max() <= tol * np.abs(ref).max(), prec
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_matvec"])
+def test_pass3_variants_at_384_and_512_are_bitwise_equal(dda, precision):
+    """Lines of 160 and 256 sites along z (padded 384 and 512 on z): every
+    tiling variant of the pass-3 kernel (and of the y passes, on lines along y)
+    gives bitwise the default's product."""
+    for n in (160, 256):
+        for axis in (1, 2):
+            ijk = np.zeros((n, 3), dtype=np.int32)
+            ijk[:, axis] = np.arange(n)
+            ijk[: n // 2, 0] = 1            # two columns, so x tiles hold more than one
+            tgt = dda.Target(ijk, 1.5 + 0.1j)
+            kh, e0 = w.along_x_yz()
+            xv = _cuda(w.random_vectors(21 + n, (2, n, 3)))
+            base = dda.apply(tgt, dda.Options.for_size_parameter(2.0, precision=precision, autotune=False), kh,
+                             e0, xv)
+            for v in range(2, 29):
+                o = dda.Options.for_size_parameter(2.0, precision=precision, kernel_variant=v)
+                y = dda.apply(tgt, o, kh, e0, xv)
+                assert torch.equal(y, base), (n, axis, v)
+
+
+def test_box200_sphere_on_the_512_grid(dda):
+    """A sphere of radius 100 (4,187,857 sites, box 201^3, FFT grid 512^3):
+    sampled rows of A x in FP64 and FP32 against the oracle's direct sums
+    (1e-12, 2e-5 of max|y|); the FP32-matvec solve at x = 8 converges, its
+    sampled rows of A P equal E_inc to 1e-3 of max|E| by the oracle's sums,
+    and its efficiencies lie within the DDA error of Mie theory."""
+    ijk = w.sphere_integer(100.0)
+    n = len(ijk)
+    m = 1.33 + 0.01j
+    x = 8.0
+    tgt = dda.Target(ijk, m)
+    assert tgt.grid == (512, 512, 512)
+    k = dense.kd_from_size_parameter(x, n)
+    kh, e0 = w.along_x_yz()
+    ainv = dense.site_alpha_inverse(np.full(n, m), k, kh[0], e0[0])
+    xv = w.random_vectors(9, (1, n, 3))
+    rows = np.random.default_rng(2).choice(n, 4, replace=False)
+    ref = dense.apply_rows(ijk, ainv, k, xv[0], rows)
+    for prec, tol in (("fp64", 1e-12), ("fp32_matvec", 2e-5)):
+        o = dda.Options.for_size_parameter(x, precision=prec)
+        y = dda.apply(tgt, o, kh[:1], e0[:1], _cuda(xv)).cpu().numpy()[0]
+        assert np.abs(y[rows] - ref).max() <= tol * np.abs(ref).max(), prec
+    del xv, y
+    o32 = dda.Options.for_size_parameter(x, tol=1e-5, precision="fp32_matvec")
+    P, res = dda.solve(tgt, o32, kh, e0)
+    q_mie = mie.efficiencies(m, x)
+    for q, r in enumerate(res):
+        assert r["status"] == 0 and r["rel_residual"] < 1e-5, r
+        ainv_q = dense.site_alpha_inverse(np.full(n, m), k, kh[q], e0[q])
+        Pq = P[q].cpu().numpy()
+        E = dense.incident_field(ijk[rows], k, kh[q], e0[q])
+        AP = dense.apply_rows(ijk, ainv_q, k, Pq, rows)
+        assert np.abs(AP - E).max() <= 1e-3 * np.abs(E).max(), q
+        assert abs(r["qext"] / q_mie["qext"] - 1) < 0.05
+        assert abs(r["qsca"] / q_mie["qsca"] - 1) < 0.05
+        assert abs(r["qabs"] / q_mie["qabs"] - 1) < 0.10
 
 
 # ------------------------------------------------------------------ runtime-planned FFT lengths
@@ -1110,7 +1176,7 @@ def _library_extent(n):
     FFT length >= 2n - 1 when at most 1.4 times the 2,3,5-smooth extent, else
     the smooth extent."""
     m = fftsolve.padded_extent(n)
-    for L in (32, 48, 64, 80, 96, 128, 160, 192, 256):
+    for L in (32, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512):
         if L >= 2 * n - 1:
             return L if 5 * L <= 7 * m else m
     return m
