@@ -173,7 +173,7 @@ PASS_PATTERNS = {
 AUTOTUNE_LAUNCHES = 21   # launches of each candidate while the autotuner times it (1 + 20)
 # FFT lengths with compile-time kernels, and their autotuned variants per pass
 CT_LENGTHS = (32, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512)
-CT_VARIANTS = {"fft_y_fwd": 8, "fft_z_green": 28, "fft_y_inv": 8}
+CT_VARIANTS = {"fft_y_fwd": 12, "fft_z_green": 28, "fft_y_inv": 12}
 
 
 def profile_commands(workload: str, prec: str, out: str = "/root/repo/gpurun_out/tr") -> dict:

@@ -1364,6 +1364,15 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
         ensure_green(c, j.t, j.kd, f32, (j.o->flags & DDA_FLAG_RECOMPUTE_GREEN) != 0);
     }
     merge_jobs(c, jobs);
+    // every job's pass tilings are tuned here, on the context stream alone,
+    // before any job iterates (candidates timed while other streams run
+    // would be skewed); start() then finds them in the context's table
+    for (Job& j : jobs) {
+        if ((j.o->flags & DDA_FLAG_NO_AUTOTUNE) || j.o->kernel_variant > 0) continue;
+        Work w(c, c->main, j.t, (int)j.idx.size(), j.kd, j.fp32);
+        if (j.batch) w.set_ragged(j.segs, j.t->geo.rg, j.batch_site_blocks);
+        w.autotune(true);
+    }
     const int nslot = (int)std::min<size_t>(4, jobs.size());
     while ((int)c->extra.size() < nslot - 1) {
         auto* ws = new Workspace();

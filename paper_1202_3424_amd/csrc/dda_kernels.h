@@ -161,7 +161,7 @@ template <typename T>
 void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, int n_outer, int lin, int lout,
                     typename V2<T>::t* grid, const double2* tw, const typename V2<T>::t* ghat, const RhsState* st,
                     hipStream_t s, int variant = 0);
-inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 28 : 8) : 1; }
+inline int strided_variants(int L, bool gh) { return ct_length(L) ? (gh ? 28 : 12) : 1; }
 // the variants a ragged batch runs: every y-pass variant, and the pass-3
 // variants that take one right-hand side per workgroup (each right-hand side
 // reads its own tensor and extent); the others run as variant 3 there

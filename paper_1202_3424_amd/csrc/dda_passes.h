@@ -140,82 +140,176 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
     double ss[3] = {0.0, 0.0, 0.0};
     // forward transform of a line that is zero beyond nx: with 2 nx <= Mx the
     // first radix pass never reads the upper half, which is then not filled
+    // (always so at the compile-time lengths, which are even and >= 2 nx - 1)
     bool hin = false;
     if constexpr (CT) hin = ct_half_in_ok(LC) && 2 * nx <= Mx;
     const int ext = hin ? Mx / 2 : Mx;
     const int tin = nl * ext * 3;
-    for (int idx = threadIdx.x; idx < tin; idx += NTHR) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % ext;
-        const int yo = rest / ext;
-        C val;
-        val.x = 0;
-        val.y = 0;
-        if (e < nx) {
-            const int s = mrow[yo * nx + e];
-            if (s >= 0) {
-                const long long i = vb + (long long)s * 3 + c;
-                double2 u;
-                if (MODE == SC_PLAIN) {
-                    u = a.in[i];
-                } else if (MODE == SC_CONJ) {
-                    u = cconj(a.in[i]);
-                } else if (MODE == SC_P) {
-                    // the previous iteration's end, if pending: x += alpha p
-                    // + omega s, r = s - omega t (s is held in r); then
-                    // p = r + beta (p - omega v)
-                    double2 rr = a.r[i];
-                    const double2 pp = a.p[i];
-                    if (pend) {
-                        a.x[i] = cadd(cadd(a.x[i], cmul(alpha, pp)), cmul(omega, rr));
-                        rr = csub(rr, cmul(omega, a.t[i]));
-                        a.r[i] = rr;
-                    }
-                    u = cadd(rr, cmul(beta, csub(pp, cmul(omega, a.v[i]))));
-                    a.p[i] = u;
-                } else if (MODE == SC_B0) {
-                    // BiCGstab(2), first BiCG step: u_0 = r_0 - beta u_0
-                    u = csub(a.r[i], cmul(beta, a.p[i]));
-                    a.p[i] = u;
-                } else if (MODE == SC_B1) {
-                    // r_0 -= alpha u_1, x += alpha u_0; product of r_0
-                    u = csub(a.r[i], cmul(alpha, a.v[i]));
-                    a.r[i] = u;
-                    a.x[i] = cadd(a.x[i], cmul(alpha, a.p[i]));
-                } else if (MODE == SC_B2) {
-                    // second BiCG step: u_0 = r_0 - beta u_0, u_1 = r_1 - beta u_1; product of u_1
-                    a.p[i] = csub(a.r[i], cmul(beta, a.p[i]));
-                    u = csub(a.t[i], cmul(beta, a.v[i]));
-                    a.v[i] = u;
-                } else if (MODE == SC_B3) {
-                    // r_0 -= alpha u_1, r_1 -= alpha u_2, x += alpha u_0; product of r_1
-                    a.r[i] = csub(a.r[i], cmul(alpha, a.v[i]));
-                    u = csub(a.t[i], cmul(alpha, a.u2[i]));
-                    a.t[i] = u;
-                    a.x[i] = cadd(a.x[i], cmul(alpha, a.p[i]));
-                } else if (MODE == SC_Q) {
-                    // QMR: p = r + beta p, and the pending smoothing step
-                    // (y, s) <- w_old (y, s) + w_new (x, r)
-                    const double2 rr = a.r[i];
-                    u = cadd(rr, cmul(beta, a.p[i]));
-                    a.p[i] = u;
-                    const double2 sm = a.rhat[i], ym = a.t[i], xx = a.x[i];
-                    a.rhat[i] = double2{w_old * sm.x + w_new * rr.x, w_old * sm.y + w_new * rr.y};
-                    a.t[i] = double2{w_old * ym.x + w_new * xx.x, w_old * ym.y + w_new * xx.y};
-                } else {
-                    // s = r - alpha v, stored over r; |s|^2 and <rhat, s>
-                    u = csub(a.r[i], cmul(alpha, a.v[i]));
-                    a.r[i] = u;
-                    const double2 w = cdotc(a.rhat[i], u);
-                    ss[0] += u.x * u.x + u.y * u.y;
-                    ss[1] += w.x;
-                    ss[2] += w.y;
+    // the site-vector values this mode reads at element i (all of them are
+    // loaded before any update is stored, so that the loads of every element
+    // a thread fills are in flight together)
+    struct Ops {
+        double2 o[6];
+    };
+    auto load_ops = [&](long long i) {
+        Ops v;
+        if (MODE == SC_PLAIN || MODE == SC_CONJ) {
+            v.o[0] = a.in[i];
+        } else if (MODE == SC_P) {
+            v.o[0] = a.r[i]; v.o[1] = a.p[i]; v.o[2] = a.v[i]; v.o[3] = a.x[i]; v.o[4] = a.t[i];
+        } else if (MODE == SC_B0) {
+            v.o[0] = a.r[i]; v.o[1] = a.p[i];
+        } else if (MODE == SC_B1) {
+            v.o[0] = a.r[i]; v.o[1] = a.v[i]; v.o[2] = a.x[i]; v.o[3] = a.p[i];
+        } else if (MODE == SC_B2) {
+            v.o[0] = a.r[i]; v.o[1] = a.p[i]; v.o[2] = a.t[i]; v.o[3] = a.v[i];
+        } else if (MODE == SC_B3) {
+            v.o[0] = a.r[i]; v.o[1] = a.v[i]; v.o[2] = a.t[i]; v.o[3] = a.u2[i]; v.o[4] = a.x[i]; v.o[5] = a.p[i];
+        } else if (MODE == SC_Q) {
+            v.o[0] = a.r[i]; v.o[1] = a.p[i]; v.o[2] = a.rhat[i]; v.o[3] = a.t[i]; v.o[4] = a.x[i];
+        } else {   // SC_S
+            v.o[0] = a.r[i]; v.o[1] = a.v[i]; v.o[2] = a.rhat[i];
+        }
+        return v;
+    };
+    // the product's input at element i after this mode's vector update from
+    // the loaded values v, the update stored back (and summed) only where
+    // `live` (a site of this line; elsewhere the value is unused)
+    auto update = [&](long long i, const Ops& v, bool live) -> double2 {
+        double2 u;
+        if (MODE == SC_PLAIN) {
+            u = v.o[0];
+        } else if (MODE == SC_CONJ) {
+            u = cconj(v.o[0]);
+        } else if (MODE == SC_P) {
+            // the previous iteration's end, if pending: x += alpha p + omega
+            // s, r = s - omega t (s is held in r); then p = r + beta (p -
+            // omega v)
+            double2 rr = v.o[0];
+            const double2 pp = v.o[1];
+            if (pend) {
+                const double2 xx = cadd(cadd(v.o[3], cmul(alpha, pp)), cmul(omega, rr));
+                rr = csub(rr, cmul(omega, v.o[4]));
+                if (live) {
+                    a.x[i] = xx;
+                    a.r[i] = rr;
                 }
-                val = to_c<C>(u);
+            }
+            u = cadd(rr, cmul(beta, csub(pp, cmul(omega, v.o[2]))));
+            if (live) a.p[i] = u;
+        } else if (MODE == SC_B0) {
+            // BiCGstab(2), first BiCG step: u_0 = r_0 - beta u_0
+            u = csub(v.o[0], cmul(beta, v.o[1]));
+            if (live) a.p[i] = u;
+        } else if (MODE == SC_B1) {
+            // r_0 -= alpha u_1, x += alpha u_0; product of r_0
+            u = csub(v.o[0], cmul(alpha, v.o[1]));
+            if (live) {
+                a.r[i] = u;
+                a.x[i] = cadd(v.o[2], cmul(alpha, v.o[3]));
+            }
+        } else if (MODE == SC_B2) {
+            // second BiCG step: u_0 = r_0 - beta u_0, u_1 = r_1 - beta u_1; product of u_1
+            u = csub(v.o[2], cmul(beta, v.o[3]));
+            if (live) {
+                a.p[i] = csub(v.o[0], cmul(beta, v.o[1]));
+                a.v[i] = u;
+            }
+        } else if (MODE == SC_B3) {
+            // r_0 -= alpha u_1, r_1 -= alpha u_2, x += alpha u_0; product of r_1
+            u = csub(v.o[2], cmul(alpha, v.o[3]));
+            if (live) {
+                a.r[i] = csub(v.o[0], cmul(alpha, v.o[1]));
+                a.t[i] = u;
+                a.x[i] = cadd(v.o[4], cmul(alpha, v.o[5]));
+            }
+        } else if (MODE == SC_Q) {
+            // QMR: p = r + beta p, and the pending smoothing step
+            // (y, s) <- w_old (y, s) + w_new (x, r)
+            const double2 rr = v.o[0];
+            u = cadd(rr, cmul(beta, v.o[1]));
+            if (live) {
+                const double2 sm = v.o[2], ym = v.o[3], xx = v.o[4];
+                a.p[i] = u;
+                a.rhat[i] = double2{w_old * sm.x + w_new * rr.x, w_old * sm.y + w_new * rr.y};
+                a.t[i] = double2{w_old * ym.x + w_new * xx.x, w_old * ym.y + w_new * xx.y};
+            }
+        } else {
+            // s = r - alpha v, stored over r; |s|^2 and <rhat, s>
+            u = csub(v.o[0], cmul(alpha, v.o[1]));
+            if (live) {
+                const double2 w = cdotc(v.o[2], u);
+                a.r[i] = u;
+                ss[0] += u.x * u.x + u.y * u.y;
+                ss[1] += w.x;
+                ss[2] += w.y;
             }
         }
-        lds[(yo * 3 + c) * Lp + e] = val;
+        return u;
+    };
+    if constexpr (CT) {
+        // one line: the site indices of every element this thread fills are
+        // loaded first, then every operand (clamped to site 0 where there is
+        // no site), so that the loads of all elements are in flight together
+        constexpr int EXT = ct_half_in_ok(LC) ? LC / 2 : LC;
+        constexpr int NPT = (3 * EXT + NTHR - 1) / NTHR;
+        int sk[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            const int e = idx / 3;
+            sk[k] = (idx < tin && e < nx) ? mrow[e] : -1;
+        }
+        Ops ok[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            ok[k] = load_ops(vb + (long long)(sk[k] >= 0 ? sk[k] : 0) * 3 + idx % 3);
+        }
+        double2 uk[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            const bool live = sk[k] >= 0;
+            uk[k] = update(vb + (long long)(live ? sk[k] : 0) * 3 + idx % 3, ok[k], live);
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            if (idx < tin) {
+                C val;
+                val.x = 0;
+                val.y = 0;
+                if (sk[k] >= 0) val = to_c<C>(uk[k]);
+                lds[(idx % 3) * Lp + idx / 3] = val;
+            }
+        }
+        // (a full-length input, never the case at these even lengths: zeros
+        // beyond the half)
+        for (int idx = 3 * EXT + threadIdx.x; idx < tin; idx += NTHR) {
+            C val;
+            val.x = 0;
+            val.y = 0;
+            lds[(idx % 3) * Lp + idx / 3] = val;
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < tin; idx += NTHR) {
+            const int c = idx % 3;
+            const int rest = idx / 3;
+            const int e = rest % ext;
+            const int yo = rest / ext;
+            C val;
+            val.x = 0;
+            val.y = 0;
+            if (e < nx) {
+                const int s = mrow[yo * nx + e];
+                if (s >= 0) {
+                    const long long i = vb + (long long)s * 3 + c;
+                    val = to_c<C>(update(i, load_ops(i), true));
+                }
+            }
+            lds[(yo * 3 + c) * Lp + e] = val;
+        }
     }
     __syncthreads();
     if constexpr (CT) {
@@ -225,13 +319,22 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         fft_lines<T, -1, NTHR>(lds, tws, nlines, Lp, g.ax[0]);
     }
     C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
-    const int tot = nl * Mx * 3;
-    for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % Mx;
-        const int yo = rest / Mx;
-        gq[idx] = lds[(yo * 3 + c) * Lp + e];
+    if constexpr (CT) {
+        constexpr int NPT = (3 * LC + NTHR - 1) / NTHR;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            if ((3 * LC) % NTHR == 0 || idx < 3 * LC) gq[idx] = lds[(idx % 3) * Lp + idx / 3];
+        }
+    } else {
+        const int tot = nl * Mx * 3;
+        for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
+            const int c = idx % 3;
+            const int rest = idx / 3;
+            const int e = rest % Mx;
+            const int yo = rest / Mx;
+            gq[idx] = lds[(yo * 3 + c) * Lp + e];
+        }
     }
     if (MODE == SC_S) {
         // slots 5-7 of the block's entry; the gather of t (same grid) fills
@@ -299,17 +402,56 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         }
     }
     const C* gq = grid + ((long long)q * g.npts + ((long long)z * My + y0) * Mx) * 3;
-    const int tot = nl * Mx * 3;
-    for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
-        const int c = idx % 3;
-        const int rest = idx / 3;
-        const int e = rest % Mx;
-        const int yo = rest / Mx;
-        lds[(yo * 3 + c) * Lp + e] = gq[idx];
-    }
     if constexpr (CT) {
+        // the line's 3 LC values: every load in flight before the LDS stores
+        // (unrolled: the loads need not wait for one another)
+        constexpr int NPT = (3 * LC + NTHR - 1) / NTHR;
 #pragma unroll
-        for (int k = 0; k < PF; ++k) pm[k] = ps[k] >= 0 ? mat[ps[k]] : 0;
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            if ((3 * LC) % NTHR == 0 || idx < 3 * LC) lds[(idx % 3) * Lp + idx / 3] = gq[idx];
+        }
+    } else {
+        const int tot = nl * Mx * 3;
+        for (int idx = threadIdx.x; idx < tot; idx += NTHR) {
+            const int c = idx % 3;
+            const int rest = idx / 3;
+            const int e = rest % Mx;
+            const int yo = rest / Mx;
+            lds[(yo * 3 + c) * Lp + e] = gq[idx];
+        }
+    }
+    // the site operands of the gathered elements (what each mode reads
+    // besides the product), loaded before the transform so that their
+    // latency overlaps it
+    const long long vb = (long long)q * a.n3;
+    auto operand = [&](long long i) -> double2 {
+        if (MODE == GA_PLAIN || MODE == GA_CONJ) return a.in[i];
+        if (MODE == GA_V || MODE == GA_Q) return a.p[i];
+        if (MODE == GA_T || MODE == GA_B1) return a.r[i];
+        if (MODE == GA_RES) return a.x[i];
+        if (MODE == GA_B2) return a.v[i];
+        return a.t[i];   // GA_B3
+    };
+    constexpr bool HAS_AUX = MODE == GA_V || MODE == GA_T || MODE == GA_B1 || MODE == GA_B2 || MODE == GA_B3 ||
+                             MODE == GA_RES;
+    auto auxiliary = [&](long long i) -> double2 {
+        if (MODE == GA_RES) return a.b[i];
+        if (MODE == GA_B3) return a.r[i];
+        return a.rhat[i];
+    };
+    double2 px[PF], pa[PF];
+    if constexpr (CT) {
+        // (clamped to site 0 where there is no site: the value is unused)
+#pragma unroll
+        for (int k = 0; k < PF; ++k) pm[k] = mat[ps[k] >= 0 ? ps[k] : 0];
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int idx = threadIdx.x + k * NTHR;
+            const long long i = vb + (long long)(ps[k] >= 0 ? ps[k] : 0) * 3 + idx % 3;
+            px[k] = operand(i);
+            pa[k] = HAS_AUX ? auxiliary(i) : double2{0.0, 0.0};
+        }
     }
     __syncthreads();
     if constexpr (CT) {
@@ -320,24 +462,15 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         fft_lines<T, 1, NTHR>(lds, tws, nlines, Lp, g.ax[0]);
     }
 
-    const long long vb = (long long)q * a.n3;
     const double2* ai = a.ainv + (long long)q * a.nmat * 3;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    // element (line yo, point e, component c) at site s of material mt
-    auto site = [&](int c, int e, int yo, int s, int mt) {
+    // element (line yo, point e, component c) at site s of material mt, with
+    // its operand xo and auxiliary vector value xa (as loaded)
+    auto site = [&](int c, int e, int yo, int s, int mt, double2 xo, double2 xa) {
         const long long i = vb + (long long)s * 3 + c;
         const double2 gv = to_d(lds[(yo * 3 + c) * Lp + e]);
         const double2 d = ai[mt * 3 + c];
-        double2 xin;
-        if (MODE == GA_PLAIN) xin = a.in[i];
-        if (MODE == GA_CONJ) xin = cconj(a.in[i]);
-        if (MODE == GA_V) xin = a.p[i];
-        if (MODE == GA_T) xin = a.r[i];
-        if (MODE == GA_RES) xin = a.x[i];
-        if (MODE == GA_Q) xin = a.p[i];
-        if (MODE == GA_B1) xin = a.r[i];
-        if (MODE == GA_B2) xin = a.v[i];
-        if (MODE == GA_B3) xin = a.t[i];
+        const double2 xin = MODE == GA_CONJ ? cconj(xo) : xo;
         const double2 y = cadd(gv, cmul(d, xin));
         if (MODE == GA_PLAIN) {
             a.out[i] = y;
@@ -347,14 +480,14 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             acc[0] += yc.x * yc.x + yc.y * yc.y;
         } else if (MODE == GA_V) {
             a.v[i] = y;
-            const double2 w = cdotc(a.rhat[i], y);
+            const double2 w = cdotc(xa, y);
             acc[0] += w.x;
             acc[1] += w.y;
             acc[2] += y.x * y.x + y.y * y.y;   // |v|^2: bounds <rhat, v> with |rhat|
         } else if (MODE == GA_T) {
             a.t[i] = y;
-            const double2 w = cdotc(y, xin);          // <t, s>
-            const double2 wr = cdotc(a.rhat[i], y);   // <rhat, t>
+            const double2 w = cdotc(y, xin);    // <t, s>
+            const double2 wr = cdotc(xa, y);    // <rhat, t>
             acc[0] += w.x;
             acc[1] += w.y;
             acc[2] += y.x * y.x + y.y * y.y;
@@ -370,7 +503,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             // r_1 = A r_0 or u_2 = A u_1, and <rhat, .>
             if (MODE == GA_B1) a.t[i] = y;
             else a.u2[i] = y;
-            const double2 w = cdotc(a.rhat[i], y);
+            const double2 w = cdotc(xa, y);
             acc[0] += w.x;
             acc[1] += w.y;
             acc[2] += y.x * y.x + y.y * y.y;
@@ -378,7 +511,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             // r_2 = A r_1 and the minimal-residual sums |r_1|^2, <r_1, r_2>,
             // |r_2|^2, <r_1, r_0>, <r_2, r_0>
             a.r2[i] = y;
-            const double2 r0 = a.r[i];
+            const double2 r0 = xa;
             const double2 w12 = cdotc(xin, y), w10 = cdotc(xin, r0), w20 = cdotc(y, r0);
             acc[0] += xin.x * xin.x + xin.y * xin.y;
             acc[1] += w12.x;
@@ -389,7 +522,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             acc[6] += w20.x;
             acc[7] += w20.y;
         } else {
-            const double2 rr = csub(a.b[i], y);
+            const double2 rr = csub(xa, y);
             a.r[i] = rr;
             acc[0] += rr.x * rr.x + rr.y * rr.y;
         }
@@ -398,7 +531,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int idx = threadIdx.x + k * NTHR;
-            if (idx < tout && ps[k] >= 0) site(idx % 3, idx / 3, 0, ps[k], pm[k]);
+            if (idx < tout && ps[k] >= 0) site(idx % 3, idx / 3, 0, ps[k], pm[k], px[k], pa[k]);
         }
     } else {
         for (int idx = threadIdx.x; idx < tout; idx += NTHR) {
@@ -407,7 +540,10 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
             const int e = rest % nx;
             const int yo = rest / nx;
             const int s = mrow[yo * nx + e];
-            if (s >= 0) site(c, e, yo, s, mat[s]);
+            if (s >= 0) {
+                const long long i = vb + (long long)s * 3 + c;
+                site(c, e, yo, s, mat[s], operand(i), HAS_AUX ? auxiliary(i) : double2{0.0, 0.0});
+            }
         }
     }
     if (MODE != GA_PLAIN) {
@@ -473,6 +609,25 @@ __device__ __forceinline__ bool xcd_tile(int Mx, int My, int TX, int nrhs, int& 
     xt = (mir & 1) ? ntx - 1 - xi : xi;
     o = (mir & 2) ? (My - yi) % My : yi;
     return !(((mir & 1) && xt == xi) || ((mir & 2) && o == yi));
+}
+// XCD-contiguous order of a y pass (one-dimensional launch): XCD j takes
+// the tiles [j C, (j + 1) C) of the (right-hand side, plane, x tile)
+// row-major order, C the tiles over eight, in that order, so neighbouring x
+// tiles -- which share the cache lines at their edges -- run together on one
+// XCD and meet in its L2.  False for the padding workgroups.
+__device__ __forceinline__ bool xcd_rows(int ntx, int n_outer, int nrhs, int& xt, int& o, int& q) {
+    const long long total = (long long)ntx * n_outer * nrhs;
+    const long long chunk = (total + N_XCD - 1) / N_XCD;
+    const long long t = (long long)(blockIdx.x % N_XCD) * chunk + blockIdx.x / N_XCD;
+    if (t >= total) return false;
+    xt = (int)(t % ntx);
+    o = (int)((t / ntx) % n_outer);
+    q = (int)(t / ((long long)ntx * n_outer));
+    return true;
+}
+inline unsigned xcd_rows_grid(int ntx, int n_outer, int nrhs) {
+    const long long total = (long long)ntx * n_outer * nrhs;
+    return (unsigned)(((total + N_XCD - 1) / N_XCD) * N_XCD);
 }
 inline unsigned xcd_grid(int Mx, int My, int TX, int nrhs) {
     const long long groups = (long long)(((Mx + TX - 1) / TX + 1) / 2) * (My / 2 + 1);
@@ -824,7 +979,8 @@ template <typename T, int L, int TX, int XR> constexpr size_t rf_smem() {
     return (size_t)(3 * TX / XR) * rf_line_stride<L>() * sizeof(typename V2<T>::t);
 }
 
-// XG (pass 3 only): the XCD-grouped workgroup order of xcd_tile.
+// XG: the XCD-grouped workgroup order of xcd_tile (pass 3) or of xcd_rows
+// (y passes; n_outer planes).
 // Occupancy asked of the compiler for passes 2 and 4 (one line per thread):
 // four waves per SIMD (128 VGPRs) when the line data take at most 32 VGPRs,
 // three (168) up to 64, two (256) for the four-pass length 256 -- none of
@@ -840,7 +996,8 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
                                                                        const double2* tw64,
                                                                        const typename V2<T>::t* ghat,
                                                                        const RhsState* st, int axis, int lin,
-                                                                       int lout, int chk, int nrhs) {
+                                                                       int lout, int chk, int nrhs,
+                                                                       int n_outer) {
     using C = typename V2<T>::t;
     constexpr int P = ct_split(L);
     constexpr int Q = L / P;
@@ -855,8 +1012,10 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
     C* lds = (C*)smem;
     const int Mx = g.M[0], My = g.M[1];
     int q, o, xt;
-    if constexpr (XG) {
+    if constexpr (XG && GH) {
         if (!xcd_tile(Mx, My, TX, nrhs, xt, o, q)) return;
+    } else if constexpr (XG) {
+        if (!xcd_rows((Mx + TX - 1) / TX, n_outer, nrhs, xt, o, q)) return;
     } else {
         q = blockIdx.z;
         o = blockIdx.y;
@@ -1234,7 +1393,7 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
 // longer contiguous runs per plane (what large grids need); LDS tiles are
 // bounded by 48 KB per workgroup.
 constexpr int n_lds_variants(int gh) { return gh ? 12 : 4; }
-constexpr int rf_variants(int gh) { return gh ? 12 : 4; }
+constexpr int rf_variants(int gh) { return gh ? 12 : 8; }
 // pass 3 at the square lengths: k_zsq variants after the register-resident
 // ones (elsewhere they fall back to variant 0)
 constexpr int zsq_variants(int gh) { return gh ? 4 : 0; }
@@ -1286,13 +1445,16 @@ constexpr int variant_var(int gh, int v) {
     return v == 0 ? 0 : (v <= 2 ? 1 : 2);
 }
 constexpr bool variant_xg(int gh, int v) { return gh && v >= 10; }
-// register-resident variant r (0 .. rf_variants-1): tile width and rounds;
-// for pass 3 also the XCD-grouped workgroup order (r >= 4) and an occupancy
-// of three waves per SIMD asked of the compiler (r >= 8, where the line data
-// take at most 96 VGPRs; a few spilled registers are the price)
-constexpr int rf_tx(int gh, int r) { return gh ? (r % 2 == 0 ? 16 : 8) : (r == 1 ? 16 : (r == 3 ? 4 : 8)); }
-constexpr int rf_xr(int gh, int r) { return gh ? (r % 4 < 2 ? 3 : 1) : (r == 2 ? 3 : 1); }
-constexpr bool rf_xg(int gh, int r) { return gh && r >= 4; }
+// register-resident variant r (0 .. rf_variants-1): tile width and rounds,
+// and the XCD-grouped workgroup order for r >= 4 (y passes: r - 4's tiling);
+// for pass 3 also an occupancy of three waves per SIMD asked of the compiler
+// (r >= 8, where the line data take at most 96 VGPRs; a few spilled
+// registers are the price)
+constexpr int rf_tx(int gh, int r) {
+    return gh ? (r % 2 == 0 ? 16 : 8) : (r % 4 == 1 ? 16 : (r % 4 == 3 ? 4 : 8));
+}
+constexpr int rf_xr(int gh, int r) { return gh ? (r % 4 < 2 ? 3 : 1) : (r % 4 == 2 ? 3 : 1); }
+constexpr bool rf_xg(int, int r) { return r >= 4; }
 template <typename T> constexpr int rf_wv(int L, int gh, int r) {
     return (gh && r >= 8 && 3 * ct_split(L) * (int)(2 * sizeof(T) / 4) <= 96) ? 3 : 1;
 }
@@ -1365,11 +1527,11 @@ void strided_ct_launch(int axis, int chk, const Geo& g, int nrhs, int n_outer, i
                 constexpr bool HI = GH || DIR < 0, HO = GH || DIR > 0;
                 const int ntx = (g.M[0] + TX - 1) / TX;
                 dim3 grd(ntx, n_outer, nrhs);
-                if (XG) grd = dim3(xcd_grid(g.M[0], g.M[1], TX, nrhs));
+                if (XG) grd = dim3(GH ? xcd_grid(g.M[0], g.M[1], TX, nrhs) : xcd_rows_grid(ntx, n_outer, nrhs));
                 const dim3 blk(rf_threads(LL, TX, rf_nct(GH)));
                 const size_t shm = rf_smem<T, LL, TX, XR>();
                 DDA_LAUNCH((k_strided_rf<T, GH, DIR, LL, TX, XR, HI, HO, XG, WV>), grd, blk, shm, s, g, grid, tw,
-                           ghat, st, axis, lin, lout, chk, nrhs);
+                           ghat, st, axis, lin, lout, chk, nrhs, n_outer);
                 return;
             }
         }
@@ -1496,7 +1658,7 @@ void launch_strided(int axis, int dir, int chk, const Geo& g, int nrhs, int nc, 
     }
 }
 
-static_assert(passes::n_strided_variants(1) == 28 && passes::n_strided_variants(0) == 8,
+static_assert(passes::n_strided_variants(1) == 28 && passes::n_strided_variants(0) == 12,
               "strided_variants() in dda_kernels.h counts these variants");
 
 #define DDA_INSTANTIATE_PASSES(T)                                                                                 \
