@@ -571,6 +571,7 @@ def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
     right-hand sides taken together (two at a time); the rate is quoted as
     terms/s and as flops against the FP64 vector peak (the per-direction
     sincos of the factor table not counted)."""
+    import workloads as w
     t, o, kh, e0 = job
     P, _ = dda.solve(t, o, kh, e0)
     n_rhs, n_sites = P.shape[0], P.shape[1]
@@ -673,6 +674,23 @@ def fp64_comparison(dda, np, torch, jobs, results, steps: int = 3) -> dict:
     return out
 
 
+def launch_groups(jobs) -> list:
+    """The jobs (lists of indices) that share launches in one batched solve:
+    the library merges targets whose padded grids are equal compile-time
+    lengths on every axis and whose solver, precision, flags and variant
+    agree (include/dda.h, dda_solve_batched)."""
+    out, index = [], {}
+    for i, (t, o, _, _) in enumerate(jobs):
+        key = (tuple(t.grid), o.solver, o.precision, o.c().flags, o.kernel_variant)
+        if all(L in CT_LENGTHS for L in t.grid) and o.share_launches and len(jobs) > 1:
+            if key in index:
+                out[index[key]].append(i)
+                continue
+            index[key] = len(out)
+        out.append([i])
+    return out
+
+
 def measure_workload(dda, np, torch, w, wname: str, prec: str, solver: str, seed: int, steps: int, warmup: int):
     """Warm up, then time ``steps`` whole solves of a workload with the
     dominant matvec pass event-timed; returns (the bench line's fields, the
@@ -707,13 +725,21 @@ def measure_workload(dda, np, torch, w, wname: str, prec: str, solver: str, seed
 
     csize = 8 if prec == "fp32_matvec" else 16
     bpus = [pass_bytes(j[0], j[0].n_sites, csize, solver) for j in jobs]
+    groups = launch_groups(jobs)
 
-    def pass_traffic(name, units, launches):
-        # per-RHS bytes times the RHS-matvecs each job executed, plus the
-        # shared bytes once per launch (several jobs: their launches taken as
-        # equal shares)
+    def pass_traffic(name, units, launches, results):
+        # per-RHS bytes times the RHS-matvecs each job executed, plus each
+        # launch's shared bytes: every target of the launch's group once.
+        # Several groups: the launches split between them in proportion to
+        # the products each group ran (its slowest right-hand side's)
         per_rhs = sum(b[name][0] * u for b, u in zip(bpus, units))
-        return per_rhs + sum(b[name][1] for b in bpus) * launches / len(bpus)
+        if len(groups) == 1:
+            return per_rhs + sum(bpus[i][name][1] for i in groups[0]) * launches
+        first = [sum(len(j[2]) for j in jobs[:i]) for i in range(len(jobs))]
+        runs = [max(r["matvecs"] for i in g for r in results[first[i]:first[i] + len(jobs[i][2])]) + 3
+                for g in groups]
+        return per_rhs + sum(sum(bpus[i][name][1] for i in g) * launches * n / sum(runs)
+                             for g, n in zip(groups, runs))
 
     # warmup; the last warmup step times every kernel category to find the
     # dominant matvec pass, which alone is timed during the measured steps
@@ -752,7 +778,7 @@ def measure_workload(dda, np, torch, w, wname: str, prec: str, solver: str, seed
     log(f"timed {steps} steps: {ms_per_step:.3f} ms/step; results {results[0]}")
 
     ms_tot, launches, all_launches = timing[dominant]
-    bytes_tot = pass_traffic(dominant, units, all_launches)
+    bytes_tot = pass_traffic(dominant, units, all_launches, results)
     # algorithmic bytes per launch (all launches) over the sampled average launch time
     avg_s = ms_tot * 1e-3 / launches
     gbs = bytes_tot / all_launches / avg_s / 1e9
@@ -769,11 +795,11 @@ def measure_workload(dda, np, torch, w, wname: str, prec: str, solver: str, seed
         ms, nl, _ = calib[name]
         if nl == 0 or ms == 0:
             continue
-        g = pass_traffic(name, cal_units, nl) / (ms * 1e-3) / 1e9
+        g = pass_traffic(name, cal_units, nl, res) / (ms * 1e-3) / 1e9
         passes[name] = {"ms_per_launch": ms / nl, "launches": nl, "bytes_per_rhs_matvec": bpus[0][name][0],
                         "bytes_per_launch_shared": bpus[0][name][1], "GBps": g, "frac": g / HBM_PEAK_GBS}
     matvec_ms = sum(calib[k][0] for k in PASSES)
-    matvec_bytes = sum(pass_traffic(k, cal_units, calib[k][1]) for k in PASSES)
+    matvec_bytes = sum(pass_traffic(k, cal_units, calib[k][1], res) for k in PASSES)
     out = {
         "metric": METRIC,
         "value": s_per_orientation,
@@ -788,6 +814,8 @@ def measure_workload(dda, np, torch, w, wname: str, prec: str, solver: str, seed
         "dtype": "f64" if prec == "fp64" else "f32 matvec / f64 Krylov",
         "data": "synthetic",
         "config": {"workload": f"{wname}: {desc}", "solver": solver, "targets": len(jobs),
+                   "launch_groups": [[list(jobs[g[0]][0].grid), len(g), sum(len(jobs[i][2]) for i in g)]
+                                     for g in groups] if len(jobs) > 1 else None,
                    "n_sites": [j[0].n_sites for j in jobs][:4], "fft_grid": list(jobs[0][0].grid),
                    "rhs_per_step": n_rhs, "orientations_per_step": orientations, "precision": prec,
                    "seed": seed},

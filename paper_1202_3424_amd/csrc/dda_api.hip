@@ -619,17 +619,20 @@ struct Work {
                     if (fp32) strided_slot<float>(0, CHK_NONE, best[0]);
                     else strided_slot<double>(0, CHK_NONE, best[0]);
                 };
-                // twenty launches per candidate, fewer (at least three, about
-                // 40 ms) where one launch of the default variant is long
+                auto run_v = [&](int v) {
+                    if (fp32) strided_slot<float>(slot, CHK_NONE, v);
+                    else strided_slot<double>(slot, CHK_NONE, v);
+                };
+                auto candidate = [&](int v) { return !a.rg || ragged_variant(slot == 1, v); };
+                int first = 0;
+                while (!candidate(first)) ++first;
+                // the first candidate's warm-up launch, timed: twenty timed
+                // launches per candidate, fewer (at least three, about 40 ms
+                // of launches) where one launch is long
                 int reps = 20;
                 {
-                    auto run0 = [&]() {
-                        if (fp32) strided_slot<float>(slot, CHK_NONE, 0);
-                        else strided_slot<double>(slot, CHK_NONE, 0);
-                    };
-                    run0();
                     HIPCHK(hipEventRecord(e0, s));
-                    run0();
+                    run_v(first);
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
                     float t1 = 0.f;
@@ -646,19 +649,15 @@ struct Work {
                     HIPCHK(hipEventElapsedTime(&t_y, e0, e1));
                 }
                 for (int v = 0; v < nv; ++v) {
-                    if (a.rg && !ragged_variant(slot == 1, v)) {
+                    if (!candidate(v)) {
                         t_ms[v] = std::numeric_limits<float>::infinity();
                         continue;
                     }
-                    auto run = [&]() {
-                        if (fp32) strided_slot<float>(slot, CHK_NONE, v);
-                        else strided_slot<double>(slot, CHK_NONE, v);
-                    };
-                    run();
+                    if (v != first) run_v(v);   // warm-up
                     HIPCHK(hipEventRecord(e0, s));
                     for (int k = 0; k < reps; ++k) {
                         if (slot == 1) run_y();
-                        run();
+                        run_v(v);
                     }
                     HIPCHK(hipEventRecord(e1, s));
                     HIPCHK(hipEventSynchronize(e1));
