@@ -347,7 +347,10 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
 
 // ------------------------------------------------------------------ pass 5
 
-template <typename T, int MODE, int LC, int NTHR>
+// PRE (compile-time lengths): each element's site operands are loaded
+// before the inverse transform, so their latency overlaps it, at the price
+// of the registers that hold them (fewer waves per SIMD); else after it.
+template <typename T, int MODE, int LC, int NTHR, bool PRE = false>
 __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const typename V2<T>::t* grid,
                                                   const double2* tw64, int XLrt, int chk) {
     using C = typename V2<T>::t;
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         return a.rhat[i];
     };
     double2 px[PF], pa[PF];
-    if constexpr (CT) {
+    if constexpr (CT && PRE) {
         // (clamped to site 0 where there is no site: the value is unused)
 #pragma unroll
         for (int k = 0; k < PF; ++k) pm[k] = mat[ps[k] >= 0 ? ps[k] : 0];
@@ -531,7 +534,15 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int idx = threadIdx.x + k * NTHR;
-            if (idx < tout && ps[k] >= 0) site(idx % 3, idx / 3, 0, ps[k], pm[k], px[k], pa[k]);
+            if (idx < tout && ps[k] >= 0) {
+                if constexpr (PRE) {
+                    site(idx % 3, idx / 3, 0, ps[k], pm[k], px[k], pa[k]);
+                } else {
+                    const long long i = vb + (long long)ps[k] * 3 + idx % 3;
+                    site(idx % 3, idx / 3, 0, ps[k], pm[k], operand(i),
+                         HAS_AUX ? auxiliary(i) : double2{0.0, 0.0});
+                }
+            }
         }
     } else {
         for (int idx = threadIdx.x; idx < tout; idx += NTHR) {
@@ -1370,11 +1381,20 @@ void gather_dispatch(int chk, const Geo& g, const SiteArgs& a, const typename V2
     const int L = g.M[0];
     const int XL = x_lines_per_tile(g, a.nrhs, sizeof(T) == 4);
     dim3 grd((g.n[1] + XL - 1) / XL, g.n[2], a.nrhs);
+    // operands before the transform pay in launches of few right-hand sides
+    // (latency-bound workgroups); with many, the launch is bandwidth-bound
+    // and the registers they take cost more occupancy than they save
+    // (measured: 2-RHS solves gain, the 128-RHS brick loses 10%)
+    const bool pre = a.nrhs <= 16;
     switch (L) {
 #define DDA_CASE(LL)                                                                                            \
     case LL:                                                                                                   \
-        DDA_LAUNCH((k_gather_x<T, MODE, LL, xthr(LL)>), grd, dim3(xthr(LL)), smem_ct<C>(LL, 3), s, g, a, grid,  \
-                           tw, 1, chk);                                                                        \
+        if (pre)                                                                                               \
+            DDA_LAUNCH((k_gather_x<T, MODE, LL, xthr(LL), true>), grd, dim3(xthr(LL)), smem_ct<C>(LL, 3), s, g, \
+                       a, grid, tw, 1, chk);                                                                   \
+        else                                                                                                   \
+            DDA_LAUNCH((k_gather_x<T, MODE, LL, xthr(LL), false>), grd, dim3(xthr(LL)), smem_ct<C>(LL, 3), s,   \
+                       g, a, grid, tw, 1, chk);                                                                \
         return;
         DDA_CT_LENGTHS(DDA_CASE)
 #undef DDA_CASE

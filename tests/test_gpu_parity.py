@@ -387,6 +387,23 @@ def test_every_tiling_variant_bitwise(dda, variant):
     assert {32, 48, 64, 80, 96, 128, 160, 192, 256} <= seen
 
 
+def test_gather_forms_agree_bitwise(dda):
+    """The gather loads its site operands before the inverse x transform in
+    launches of at most 16 right-hand sides and after it in larger ones: a
+    20-RHS product equals, bitwise, the same right-hand sides as two 10-RHS
+    products, in FP64 and FP32, at a compile-time and a runtime length."""
+    kh, e0 = w.incidences_for_orientations(41, 10)
+    for bi, box in enumerate([(13, 14, 32), (9, 27, 11)]):
+        tgt = _box_target(dda, box, 140 + bi)
+        xv = _cuda(w.random_vectors(50 + bi, (20, tgt.n_sites, 3)))
+        for prec in ("fp64", "fp32_matvec"):
+            o = dda.Options.for_size_parameter(1.3, precision=prec)
+            y = dda.apply(tgt, o, kh, e0, xv)
+            y0 = dda.apply(tgt, o, kh[:10], e0[:10], xv[:10].contiguous())
+            y1 = dda.apply(tgt, o, kh[10:], e0[10:], xv[10:].contiguous())
+            assert torch.equal(y[:10], y0) and torch.equal(y[10:], y1), (prec, box, tgt.grid)
+
+
 # ------------------------------------------------------------------ adjoint at full size
 
 def _dq_difference(P, dP, E, w_sites, w_site_new, j, cq, wq):
