@@ -82,3 +82,24 @@ def test_pass_bytes_count_each_solvers_site_vectors():
         assert b[s]["scatter_fft_x"][1] == 4 * 64 * 48 * 32
     # pass 3: forward and inverse grids of every RHS; the tensor octant once per launch
     assert b["plain"]["fft_z_green"] == (2 * 128 * 96 * 32 * 48, 65 * 49 * 33 * 6 * 16)
+
+
+def test_launch_groups_follow_the_library_merge_rule():
+    """Targets share launches when their padded grids are equal compile-time
+    lengths on every axis and their options agree (include/dda.h); others,
+    and a single target, are groups of their own."""
+    from types import SimpleNamespace as NS
+
+    def opt(solver="bicgstab", precision="fp64", flags=0, variant=0, share=True):
+        return NS(solver=solver, precision=precision, kernel_variant=variant, share_launches=share,
+                  c=lambda: NS(flags=flags))
+
+    def job(grid, o):
+        return (NS(grid=grid), o, None, None)
+
+    jobs = [job((96, 48, 32), opt()), job((64, 64, 64), opt()), job((80, 80, 80), opt()),
+            job((64, 64, 64), opt()), job((64, 64, 64), opt(precision="fp32_matvec")),
+            job((64, 64, 64), opt(share=False)), job((50, 50, 50), opt()), job((50, 50, 50), opt()),
+            job((80, 80, 80), opt(flags=2)), job((80, 80, 80), opt())]
+    assert bench.launch_groups(jobs) == [[0], [1, 3], [2, 9], [4], [5], [6], [7], [8]]
+    assert bench.launch_groups(jobs[1:2]) == [[0]]
