@@ -248,8 +248,12 @@ dda_status dda_solve_rhs(dda_ctx* ctx, dda_target* t, const dda_opts* opts, int3
  * solver, precision, flags and kernel_variant share every launch: one kernel
  * per step covers all their right-hand sides, each reading its own target's
  * box, sites, materials, kd and tensor.  Other targets run as their own
- * batches on up to four streams.  Every right-hand side's result is bitwise
- * the one dda_solve gives for its target and its right-hand sides alone.
+ * batches on up to four streams: the first calls of a batch shape (the jobs'
+ * grids, right-hand sides, solver and precision) try 4, 2 and 1 jobs in
+ * flight, and later calls of that shape use the fastest (not with
+ * DDA_FLAG_NO_AUTOTUNE: 4).  Every right-hand side's result is bitwise the
+ * one dda_solve gives for its target and its right-hand sides alone, whatever
+ * the schedule.
  * A target may appear under several indices only with one kd (equal
  * wavelength and aeff); E_INVALID otherwise. */
 dda_status dda_solve_batched(dda_ctx* ctx, int32_t n_targets, dda_target* const* targets,

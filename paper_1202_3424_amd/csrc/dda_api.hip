@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstring>
 #include <array>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <memory>
@@ -188,6 +189,10 @@ struct dda_ctx {
     long long tlaunch[DDA_TIMING_CATEGORIES] = {};
     // autotuned strided-pass variants per (grid, box, right-hand sides, precision)
     std::map<std::tuple<int, int, int, int, int, int, int, int>, std::array<int, 3>> tuned;
+    // batched calls: seconds taken with 4, 2 and 1 jobs in flight (< 0: not
+    // tried yet), per batch shape (the jobs' grids and right-hand sides)
+    std::map<std::string, std::array<double, 3>> sched;
+    long long captures = 0;   // iteration chunks captured into graphs so far
 };
 
 struct dda_target {
@@ -882,6 +887,7 @@ void run_chunk(Work& w, int chunk) {
         Workspace::Graph gr{};
         for (long long& n : c->tcap) n = 0;
         hipGraph_t g = nullptr;
+        ++c->captures;
         HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
         {
             // the chunk is recorded on gs with timing events off; if a launch
@@ -1366,13 +1372,45 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
     // every job's pass tilings are tuned here, on the context stream alone,
     // before any job iterates (candidates timed while other streams run
     // would be skewed); start() then finds them in the context's table
+    const auto t_start = std::chrono::steady_clock::now();
+    const size_t n_tuned = c->tuned.size();
     for (Job& j : jobs) {
         if ((j.o->flags & DDA_FLAG_NO_AUTOTUNE) || j.o->kernel_variant > 0) continue;
         Work w(c, c->main, j.t, (int)j.idx.size(), j.kd, j.fp32);
         if (j.batch) w.set_ragged(j.segs, j.t->geo.rg, j.batch_site_blocks);
         w.autotune(true);
     }
-    const int nslot = (int)std::min<size_t>(4, jobs.size());
+    // Jobs in flight (each on its own stream): the first calls of a batch
+    // shape try 4, 2 and 1 in turn, timing each whole call (not a call that
+    // tuned tilings or captured iteration graphs: that work would count), and
+    // later calls take the fastest.  Results do not depend on it; with
+    // autotuning off, 4.
+    static const int kSlots[3] = {4, 2, 1};
+    bool explore = jobs.size() > 1 && (jobs[0].o->flags & DDA_FLAG_NO_AUTOTUNE) == 0;
+    std::string skey;
+    for (const Job& j : jobs) {
+        key_bytes(skey, j.t->geo.M);
+        key_bytes(skey, (int)j.idx.size());
+        key_bytes(skey, j.o->solver);
+        key_bytes(skey, j.o->precision);
+    }
+    int pick = 0;
+    if (explore) {
+        auto ins = c->sched.emplace(skey, std::array<double, 3>{-1.0, -1.0, -1.0});
+        const std::array<double, 3>& sec = ins.first->second;
+        pick = -1;
+        for (int i = 0; i < 3 && pick < 0; ++i)
+            if (sec[i] < 0.0) pick = i;
+        if (pick < 0) {
+            pick = 0;
+            for (int i = 1; i < 3; ++i)
+                if (sec[i] < sec[pick]) pick = i;
+            explore = false;
+        }
+    }
+    const bool tuned_here = c->tuned.size() != n_tuned;
+    const long long captures0 = c->captures;
+    const int nslot = (int)std::min<size_t>(kSlots[pick], jobs.size());
     while ((int)c->extra.size() < nslot - 1) {
         auto* ws = new Workspace();
         c->extra.push_back(ws);
@@ -1486,6 +1524,8 @@ dda_status solve_many(dda_ctx* c, std::vector<Job>& jobs, dda_result* res) {
     }
     for (int i = 1; i < nslot; ++i) HIPCHK(hipStreamSynchronize(slots[i]->stream));
     flush_timing(c);
+    if (explore && !tuned_here && c->captures == captures0)
+        c->sched[skey][pick] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return worst;
 }
 
