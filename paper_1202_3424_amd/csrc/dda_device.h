@@ -591,16 +591,18 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 // Doubles of partial sums per workgroup and right-hand side.
 constexpr int PSTRIDE = 8;
 
-// This workgroup's sums go to partials[blk * PSTRIDE + OFF + i] (no atomics,
-// no fences: the consumer is a later kernel on the same stream).  Two
-// kernels with the same grid may fill disjoint slots of one block entry.
+// This workgroup's sums go to partials[(OFF + i) * stride + blk], stride the
+// workgroups reserved per right-hand side: slot-major, so a finalize's loads
+// of one slot over consecutive workgroups are contiguous (no atomics, no
+// fences: the consumer is a later kernel on the same stream).  Two kernels
+// with the same grid may fill disjoint slots of one workgroup.
 template <int NV, int NTHR = NT, int OFF = 0>
-__device__ __forceinline__ void publish_partial(double (&v)[NV], double* partials, int blk, double* sh) {
+__device__ __forceinline__ void publish_partial(double (&v)[NV], double* partials, int blk, int stride, double* sh) {
     static_assert(OFF + NV <= PSTRIDE, "partial slots");
     block_sum<NV, NTHR>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) partials[(long)blk * PSTRIDE + OFF + i] = v[i];
+        for (int i = 0; i < NV; ++i) partials[(long)(OFF + i) * stride + blk] = v[i];
     }
 }
 
@@ -608,13 +610,14 @@ __device__ __forceinline__ void publish_partial(double (&v)[NV], double* partial
 // The loop is unrolled so that several blocks' loads are in flight before
 // the first add (the adds keep their order).
 template <int NV>
-__device__ __forceinline__ void sum_partials(double (&acc)[NV], const double* partials, int nblk, double* sh) {
+__device__ __forceinline__ void sum_partials(double (&acc)[NV], const double* partials, int nblk, int stride,
+                                             double* sh) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
 #pragma unroll 8
     for (int b = threadIdx.x; b < nblk; b += NT) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += partials[(long)b * PSTRIDE + i];
+        for (int i = 0; i < NV; ++i) acc[i] += partials[(long)i * stride + b];
     }
     block_sum<NV>(acc, sh);
 }

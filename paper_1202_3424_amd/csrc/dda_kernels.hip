@@ -207,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_init_cold(SiteArgs a) {
         a.v[vb + i] = double2{0.0, 0.0};
         acc[0] += bb.x * bb.x + bb.y * bb.y;
     }
-    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<1>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // Warm start: x already holds P0 and r = b - A P0.  rhat = r, p = v = 0.
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_init_warm(SiteArgs a) {
         acc[0] += rr.x * rr.x + rr.y * rr.y;
         acc[1] += bb.x * bb.x + bb.y * bb.y;
     }
-    publish_partial<2>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<2>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // The end of the latest BiCGSTAB iteration, where still pending (see
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(NT) void k_restart(SiteArgs a) {
         acc[1] += 2.0 * rr.x * rr.y;
         acc[2] += rr.x * rr.x + rr.y * rr.y;
     }
-    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // ------------------------------------------------------------------ QMR
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_qmr_init(SiteArgs a, int cold) {
         acc[2] += rr.x * rr.x + rr.y * rr.y;
         acc[3] += bb.x * bb.x + bb.y * bb.y;
     }
-    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // x += alpha p, r -= alpha v; sums r^T r, |r|^2 and Re <s, r> (for the
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_qmr_update(SiteArgs a) {
         acc[2] += rr.x * rr.x + rr.y * rr.y;
         acc[3] += sm.x * rr.x + sm.y * rr.y;
     }
-    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<4>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // x and y <- the smoothed iterate: w_old y + w_new x if a step is pending,
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
         acc[1] += w.y;
         acc[2] += rn.x * rn.x + rn.y * rn.y;
     }
-    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // ------------------------------------------------------------------ far field
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
         acc[1] += (-d.y - rr) * (P.x * P.x + P.y * P.y);
         acc[2] += w.x;
     }
-    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, sh);
+    publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
 // Turn the partial sums of a producer kernel into the right-hand side's
@@ -668,14 +668,14 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
                       kind == FIN_QV;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (kind == FIN_B_MR || kind == FIN_T) {
-        sum_partials<8>(acc, part, nblk, sh);
+        sum_partials<8>(acc, part, nblk, a.maxblk, sh);
     } else if (four) {
         double a4[4];
-        sum_partials<4>(a4, part, nblk, sh);
+        sum_partials<4>(a4, part, nblk, a.maxblk, sh);
         for (int i = 0; i < 4; ++i) acc[i] = a4[i];
     } else {
         double a3[3];
-        sum_partials<3>(a3, part, nblk, sh);
+        sum_partials<3>(a3, part, nblk, a.maxblk, sh);
         acc[0] = a3[0];
         acc[1] = a3[1];
         acc[2] = a3[2];

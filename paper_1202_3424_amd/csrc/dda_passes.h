@@ -341,7 +341,7 @@ __global__ __launch_bounds__(NTHR) void k_scatter_x(Geo g, SiteArgs a, typename 
         // slots 0-4 and one finalize reads both
         double* sh = (double*)(lds + nlines * Lp);
         const int blk = blockIdx.y * bx + blockIdx.x;
-        publish_partial<3, NTHR, 5>(ss, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+        publish_partial<3, NTHR, 5>(ss, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, a.maxblk, sh);
     }
 }
 
@@ -561,16 +561,16 @@ __global__ __launch_bounds__(NTHR) void k_gather_x(Geo g, SiteArgs a, const type
         double* sh = (double*)(lds + nlines * Lp);
         const int blk = blockIdx.y * bx + blockIdx.x;
         if constexpr (MODE == GA_B3) {
-            publish_partial<8, NTHR>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+            publish_partial<8, NTHR>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, a.maxblk, sh);
         } else if constexpr (MODE == GA_T) {
             double a5[5] = {acc[0], acc[1], acc[2], acc[3], acc[4]};
-            publish_partial<5, NTHR>(a5, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+            publish_partial<5, NTHR>(a5, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, a.maxblk, sh);
         } else if constexpr (MODE == GA_Q) {
             double a4[4] = {acc[0], acc[1], acc[2], acc[3]};
-            publish_partial<4, NTHR>(a4, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+            publish_partial<4, NTHR>(a4, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, a.maxblk, sh);
         } else {
             double a3[3] = {acc[0], acc[1], acc[2]};
-            publish_partial<3, NTHR>(a3, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, sh);
+            publish_partial<3, NTHR>(a3, a.partials + (long long)q * a.maxblk * PSTRIDE, blk, a.maxblk, sh);
         }
     }
 }
