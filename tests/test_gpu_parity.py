@@ -574,6 +574,23 @@ def test_shared_launch_batch_matches_separate_solves(dda, solver, precision):
             assert torch.equal(Pn[q], P1[k]) and rn[q] == r1[k], (i, q)
 
 
+def test_batch_schedule_leaves_results_unchanged(dda):
+    """Repeated calls of one batch shape run with 4, 2 and 1 jobs in flight
+    while the schedule is tried, then with the fastest: every call gives the
+    same P and results, bitwise."""
+    ts = _shared_grid_targets(dda)[:2] + [dda.Target(w.sphere_integer(12.2), 1.4 + 0.02j),
+                                          dda.Target(w.brick(20, 9, 7), 1.6 + 0.1j)]
+    opts = [dda.Options.for_size_parameter(x, tol=1e-5) for x in (2.0, 2.4, 3.0, 1.5)]
+    kh, e0 = w.along_x_yz()
+    rt = [0, 0, 1, 1, 2, 2, 3, 3]
+    kh8, e08 = np.vstack([kh] * 4), np.vstack([e0] * 4)
+    P0, r0 = dda.solve_batched(ts, opts, rt, kh8, e08)
+    for _ in range(5):
+        P1, r1 = dda.solve_batched(ts, opts, rt, kh8, e08)
+        assert r1 == r0
+        assert all(torch.equal(a, b) for a, b in zip(P0, P1))
+
+
 def test_shared_launch_batch_rejects_one_target_at_two_kd(dda):
     """A target listed twice must have one kd (it holds one tensor)."""
     t = _shared_grid_targets(dda)[0]
