@@ -1313,27 +1313,24 @@ std::tuple<int, int, int, int, int, unsigned, int> batch_key(const Job& j) {
 // grid has a compile-time FFT length on every axis, by one merged job (in the
 // position of its first member).
 void merge_jobs(dda_ctx* c, std::vector<Job>& jobs) {
+    auto mergeable = [](const Job& j) {
+        const Geo& g = j.t->geo;
+        return !(j.o->flags & DDA_FLAG_SEPARATE_TARGETS) && ct_length(g.M[0]) && ct_length(g.M[1]) &&
+               ct_length(g.M[2]);
+    };
     std::map<std::tuple<int, int, int, int, int, unsigned, int>, std::vector<size_t>> groups;
-    for (size_t i = 0; i < jobs.size(); ++i) {
-        const Geo& g = jobs[i].t->geo;
-        if ((jobs[i].o->flags & DDA_FLAG_SEPARATE_TARGETS) || !ct_length(g.M[0]) || !ct_length(g.M[1]) ||
-            !ct_length(g.M[2]))
-            continue;
-        groups[batch_key(jobs[i])].push_back(i);
-    }
+    for (size_t i = 0; i < jobs.size(); ++i)
+        if (mergeable(jobs[i])) groups[batch_key(jobs[i])].push_back(i);
     std::vector<Job> out;
     std::vector<bool> taken(jobs.size(), false);
     for (size_t i = 0; i < jobs.size(); ++i) {
         if (taken[i]) continue;
-        const Geo& g = jobs[i].t->geo;
-        auto it = groups.end();
-        if (!(jobs[i].o->flags & DDA_FLAG_SEPARATE_TARGETS) && ct_length(g.M[0]) && ct_length(g.M[1]) &&
-            ct_length(g.M[2]))
-            it = groups.find(batch_key(jobs[i]));
+        const auto it = mergeable(jobs[i]) ? groups.find(batch_key(jobs[i])) : groups.end();
         if (it == groups.end() || it->second.size() < 2) {
             out.push_back(std::move(jobs[i]));
             continue;
         }
+        // i is the group's first member, so none of its members has been moved
         std::vector<Job*> mem;
         for (size_t k : it->second) {
             mem.push_back(&jobs[k]);
