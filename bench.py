@@ -567,10 +567,12 @@ def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
     polarizations) and dda_far_field on 74 directions, on the workload's
     solution.  The kernel's work is one term per (direction, site, right-hand
     side): three complex multiply-adds (24 flops), plus the site's phase
-    factor w_x w_y w_z (two complex products, 12 flops) shared by the
-    right-hand sides taken together (two at a time); the rate is quoted as
-    terms/s and as flops against the FP64 vector peak (the per-direction
-    sincos of the factor table not counted)."""
+    factor w_x w_y w_z (two complex products, 12 flops).  The averages use a
+    direction set about each right-hand side's own incidence direction, so
+    every direction serves one right-hand side and the factor is formed for
+    each term: 36 flops per term.  The rate is quoted as terms/s and as
+    flops against the FP64 vector peak (the per-direction sincos of the
+    factor table not counted)."""
     import workloads as w
     t, o, kh, e0 = job
     P, _ = dda.solve(t, o, kh, e0)
@@ -590,7 +592,7 @@ def farfield_measurement(dda, np, torch, job, reps: int = 5) -> dict:
     ms_avg = timed(lambda: dda.scattering_averages(t, o, kh, e0, P, n_theta, n_phi))
     ms_ff = timed(lambda: dda.far_field(t, o, P, nh, th, ph))
     terms = float(n_theta * n_phi) * n_sites * n_rhs
-    flops_per_term = 24.0 + 12.0 / min(2, n_rhs)
+    flops_per_term = 24.0 + 12.0
     tflops = flops_per_term * terms / (ms_avg * 1e-3) / 1e12
     return {"averages_ms": ms_avg, "directions": n_theta * n_phi, "far_field_74_dirs_ms": ms_ff,
             "terms_per_s": terms / (ms_avg * 1e-3), "flops_per_term": flops_per_term, "bound": "alu",

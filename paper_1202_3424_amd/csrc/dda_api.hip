@@ -2095,43 +2095,23 @@ dda_status dda_scattering_averages(dda_ctx* c, dda_target* t, const dda_opts* o,
         const size_t n3 = 3 * (size_t)t->nsites;
         const size_t pb = (size_t)n_rhs * n3 * sizeof(double2), db = (size_t)ndt * 9 * sizeof(double);
         const size_t fb = (size_t)ndt * 2 * sizeof(double2), cb = (size_t)ndt * sizeof(double);
-        char* buf = (char*)c->ffbuf.ensure(pb + db + fb + cb + 256);
+        const size_t kb = (size_t)n_rhs * 3 * sizeof(double), mb = (size_t)n_theta * sizeof(double);
+        char* buf = (char*)c->ffbuf.ensure(pb + db + fb + cb + kb + mb + 256);
         double2* Ps = (double2*)buf;
         double* ddev = (double*)(buf + pb);
         double2* fdev = (double2*)(buf + pb + db);
         double* cdev = (double*)(buf + pb + db + fb);
+        double* kdev = (double*)(buf + pb + db + fb + cb);
+        double* mdev = (double*)(buf + pb + db + fb + cb + kb);
         launch_permute(n_rhs, t->nsites, 3, (const int*)t->perm.p, (const double2*)P, Ps, true, c->stream);
-        std::vector<double> dirs((size_t)ndt * 9), dcs((size_t)ndt);
+        HIPCHK(hipMemcpyAsync(kdev, kh.data(), kb, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(mdev, mu.data(), mb, hipMemcpyHostToDevice, c->stream));
+        std::vector<double> dcs((size_t)ndt);
         for (int g0 = 0; g0 < n_rhs; g0 += qg) {
             const int ng = std::min(qg, n_rhs - g0);
-            for (int q = g0; q < g0 + ng; ++q) {
-                // frame (khat, u, v) and directions n = mu khat + sqrt(1-mu^2)(cos p u + sin p v)
-                const double* k = kh.data() + 3 * q;
-                double u[3], v[3];
-                const double ref[3] = {std::fabs(k[0]) < 0.9 ? 1.0 : 0.0, std::fabs(k[0]) < 0.9 ? 0.0 : 1.0, 0.0};
-                u[0] = k[1] * ref[2] - k[2] * ref[1];
-                u[1] = k[2] * ref[0] - k[0] * ref[2];
-                u[2] = k[0] * ref[1] - k[1] * ref[0];
-                const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                for (double& x : u) x /= un;
-                v[0] = k[1] * u[2] - k[2] * u[1];
-                v[1] = k[2] * u[0] - k[0] * u[2];
-                v[2] = k[0] * u[1] - k[1] * u[0];
-                for (int i = 0; i < n_theta; ++i) {
-                    const double ct = mu[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
-                    for (int j = 0; j < n_phi; ++j) {
-                        const double p = 2.0 * M_PI * j / n_phi, cp = std::cos(p), sp = std::sin(p);
-                        double* D = dirs.data() + (((size_t)(q - g0) * n_theta + i) * n_phi + j) * 9;
-                        for (int m = 0; m < 3; ++m) {
-                            D[m] = ct * k[m] + st * (cp * u[m] + sp * v[m]);
-                            D[3 + m] = ct * (cp * u[m] + sp * v[m]) - st * k[m];
-                            D[6 + m] = -sp * u[m] + cp * v[m];
-                        }
-                    }
-                }
-            }
-            HIPCHK(hipMemcpyAsync(ddev, dirs.data(), (size_t)ng * nd * 9 * sizeof(double), hipMemcpyHostToDevice,
-                                  c->stream));
+            // the directions about each right-hand side's incidence direction,
+            // formed on the device
+            launch_avg_dirs(ng, kdev + 3 * (size_t)g0, mdev, n_theta, n_phi, ddev, c->stream);
             launch_farfield_sets(t->nsites, (const int*)t->coords.p, Ps + (size_t)g0 * n3, ng, ddev, nd, kd, t->lo,
                                  t->geo.n, fdev, cdev, c->stream);
             HIPCHK(hipGetLastError());

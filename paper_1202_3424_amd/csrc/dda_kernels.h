@@ -199,6 +199,11 @@ void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s);
 // box lo .. lo + n - 1
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
                      double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s);
+// the direction sets of the angular averages for ng right-hand sides
+// (incidence directions kh [ng][3], Gauss-Legendre nodes mu [n_theta]):
+// dirs [ng][n_theta][n_phi][9]
+void launch_avg_dirs(int ng, const double* kh, const double* mu, int n_theta, int n_phi, double* dirs,
+                     hipStream_t s);
 // the same with a set of per directions for each right-hand side: dirs
 // [nrhs * per][9], f [nrhs * per][2], dcs [nrhs * per]
 void launch_farfield_sets(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int per,

@@ -444,12 +444,11 @@ __global__ __launch_bounds__(NT) void k_b2_update(SiteArgs a) {
 // directions at a time over the same loaded sites (each site's P is read
 // once for all DW).  per > 0: direction d belongs to right-hand side d / per
 // alone (every right-hand side with its own direction set in one launch;
-// DW divides per) and its results go to entry d.  Deterministic sums (each
-// direction: fixed per-thread order, then the workgroup reduction; the same
-// for every DW).
-constexpr int FR = 2;
-
-template <int DW>
+// DW divides per) and its results go to entry d; there FR is 1.  Each term
+// is accumulated as four fused multiply-adds in a fixed order.
+// Deterministic sums (each direction: fixed per-thread order, then the
+// workgroup reduction; the same for every DW and FR).
+template <int DW, int FR>
 __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, const double2* P, long long n3,
                                                  int nrhs, const double* dirs, double k, int lox, int loy, int loz,
                                                  int nx, int ny, int nz, double2* f, double* dcs, int ndir,
@@ -470,35 +469,51 @@ __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, 
     }
     __syncthreads();
     const double k3 = k * k * k;
-    const int qa = per > 0 ? d0 / per : 0;
-    const int qb = per > 0 ? qa + 1 : nrhs;
+    // per = 0: the right-hand sides FR at a time along the grid's y
+    const int qa = per > 0 ? d0 / per : (int)blockIdx.y * FR;
+    const int qb = per > 0 ? qa + 1 : min(nrhs, qa + FR);
     for (int q0 = qa; q0 < qb; q0 += FR) {
         double acc[DW][6 * FR];
 #pragma unroll
         for (int j = 0; j < DW; ++j)
 #pragma unroll
             for (int i = 0; i < 6 * FR; ++i) acc[j][i] = 0.0;
-        for (int s = threadIdx.x; s < nsites; s += NT) {
-            const int cx = coords[s * 3 + 0] - lox, cy = nx + coords[s * 3 + 1] - loy;
-            const int cz = nx + ny + coords[s * 3 + 2] - loz;
-            double2 pv[FR][3];
+        // a thread's sites s, s + NT, s + 2 NT, ... in that order, two per
+        // iteration with both sites' loads issued first
+        for (int s0 = threadIdx.x; s0 < nsites; s0 += 2 * NT) {
+            int cc[2][3];
+            double2 pv[2][FR][3];
 #pragma unroll
-            for (int r = 0; r < FR; ++r) {
-                const double2* Pq = P + (long long)(q0 + r) * n3 + (long long)s * 3;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) pv[r][c] = q0 + r < qb ? Pq[c] : double2{0.0, 0.0};
-            }
-#pragma unroll
-            for (int j = 0; j < DW; ++j) {
-                const double2* wt = wtab + j * nt;
-                const double2 w = cmul(cmul(wt[cx], wt[cy]), wt[cz]);
+            for (int h = 0; h < 2; ++h) {
+                const int s = min(s0 + h * NT, nsites - 1);   // past the end: loaded, not added
+                cc[h][0] = coords[s * 3 + 0] - lox;
+                cc[h][1] = nx + coords[s * 3 + 1] - loy;
+                cc[h][2] = nx + ny + coords[s * 3 + 2] - loz;
 #pragma unroll
                 for (int r = 0; r < FR; ++r) {
+                    const double2* Pq = P + (long long)(q0 + r) * n3 + (long long)s * 3;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double2 v = cmul(pv[r][c], w);
-                        acc[j][6 * r + 2 * c] += v.x;
-                        acc[j][6 * r + 2 * c + 1] += v.y;
+                    for (int c = 0; c < 3; ++c) pv[h][r][c] = q0 + r < qb ? Pq[c] : double2{0.0, 0.0};
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && s0 + NT >= nsites) break;
+#pragma unroll
+                for (int j = 0; j < DW; ++j) {
+                    const double2* wt = wtab + j * nt;
+                    const double2 w = cmul(cmul(wt[cc[h][0]], wt[cc[h][1]]), wt[cc[h][2]]);
+#pragma unroll
+                    for (int r = 0; r < FR; ++r) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double& ar = acc[j][6 * r + 2 * c];
+                            double& ai = acc[j][6 * r + 2 * c + 1];
+                            ar = fma(pv[h][r][c].x, w.x, ar);
+                            ar = fma(-pv[h][r][c].y, w.y, ar);
+                            ai = fma(pv[h][r][c].x, w.y, ai);
+                            ai = fma(pv[h][r][c].y, w.x, ai);
+                        }
                     }
                 }
             }
@@ -524,6 +539,40 @@ __global__ __launch_bounds__(NT) void k_farfield(int nsites, const int* coords, 
             }
             __syncthreads();
         }
+    }
+}
+
+// Direction sets of the angular averages ("Averaging over Scattering
+// Directions"): for right-hand side q with incidence direction k, the frame
+// (k, u, v), u the unit vector along k x e (e the x axis, or y where k is
+// near x) and v = k x u, and the directions n = mu_i k + sqrt(1 - mu_i^2)
+// (cos p_j u + sin p_j v), p_j = 2 pi j / n_phi, with their theta and phi
+// unit vectors: dirs [ng][n_theta][n_phi][9] (n, theta, phi).
+__global__ __launch_bounds__(NT) void k_avg_dirs(int ng, const double* kh, const double* mu, int n_theta, int n_phi,
+                                                 double* dirs) {
+    const long long nd = (long long)n_theta * n_phi;
+    const long long idx = (long long)blockIdx.x * NT + threadIdx.x;
+    if (idx >= (long long)ng * nd) return;
+    const int q = (int)(idx / nd);
+    const int i = (int)((idx % nd) / n_phi);
+    const int j = (int)(idx % n_phi);
+    const double* k = kh + 3 * q;
+    const bool nx = fabs(k[0]) < 0.9;
+    const double e[3] = {nx ? 1.0 : 0.0, nx ? 0.0 : 1.0, 0.0};
+    double u[3] = {k[1] * e[2] - k[2] * e[1], k[2] * e[0] - k[0] * e[2], k[0] * e[1] - k[1] * e[0]};
+    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    for (double& x : u) x /= un;
+    const double v[3] = {k[1] * u[2] - k[2] * u[1], k[2] * u[0] - k[0] * u[2], k[0] * u[1] - k[1] * u[0]};
+    const double ct = mu[i], st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    const double p = 2.0 * M_PI * j / n_phi;
+    double sp, cp;
+    sincos(p, &sp, &cp);
+    double* D = dirs + idx * 9;
+    for (int m = 0; m < 3; ++m) {
+        const double t = cp * u[m] + sp * v[m];
+        D[m] = ct * k[m] + st * t;
+        D[3 + m] = ct * t - st * k[m];
+        D[6 + m] = -sp * u[m] + cp * v[m];
     }
 }
 
@@ -1137,25 +1186,32 @@ constexpr int FF_MIN_WG = 512;
 void launch_farfield(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int ndir,
                      double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
     const size_t nt = (size_t)(n[0] + n[1] + n[2]);
-    if (ndir >= FF_DW * FF_MIN_WG) {
-        hipLaunchKernelGGL(k_farfield<FF_DW>, dim3((ndir + FF_DW - 1) / FF_DW), dim3(NT),
+    const int npair = (nrhs + 1) / 2;   // grid y: the right-hand sides two at a time
+    if ((long long)((ndir + FF_DW - 1) / FF_DW) * npair >= FF_MIN_WG) {
+        hipLaunchKernelGGL((k_farfield<FF_DW, 2>), dim3((ndir + FF_DW - 1) / FF_DW, npair), dim3(NT),
                            FF_DW * nt * sizeof(double2), s, nsites, coords, P, 3LL * nsites, nrhs, dirs, k, lo[0],
                            lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
     } else {
-        hipLaunchKernelGGL(k_farfield<1>, dim3(ndir), dim3(NT), nt * sizeof(double2), s, nsites, coords, P,
-                           3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
+        hipLaunchKernelGGL((k_farfield<1, 2>), dim3(ndir, npair), dim3(NT), nt * sizeof(double2), s, nsites, coords,
+                           P, 3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndir, 0);
     }
+}
+void launch_avg_dirs(int ng, const double* kh, const double* mu, int n_theta, int n_phi, double* dirs,
+                     hipStream_t s) {
+    const long long tot = (long long)ng * n_theta * n_phi;
+    hipLaunchKernelGGL(k_avg_dirs, dim3((unsigned)((tot + NT - 1) / NT)), dim3(NT), 0, s, ng, kh, mu, n_theta, n_phi,
+                       dirs);
 }
 void launch_farfield_sets(int nsites, const int* coords, const double2* P, int nrhs, const double* dirs, int per,
                           double k, const int lo[3], const int n[3], double2* f, double* dcs, hipStream_t s) {
     const size_t nt = (size_t)(n[0] + n[1] + n[2]);
     const int ndt = per * nrhs;
     if (per % FF_DW == 0 && ndt >= FF_DW * FF_MIN_WG) {
-        hipLaunchKernelGGL(k_farfield<FF_DW>, dim3(ndt / FF_DW), dim3(NT), FF_DW * nt * sizeof(double2), s, nsites,
+        hipLaunchKernelGGL((k_farfield<FF_DW, 1>), dim3(ndt / FF_DW), dim3(NT), FF_DW * nt * sizeof(double2), s, nsites,
                            coords, P, 3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs,
                            ndt, per);
     } else {
-        hipLaunchKernelGGL(k_farfield<1>, dim3(ndt), dim3(NT), nt * sizeof(double2), s, nsites, coords, P,
+        hipLaunchKernelGGL((k_farfield<1, 1>), dim3(ndt), dim3(NT), nt * sizeof(double2), s, nsites, coords, P,
                            3LL * nsites, nrhs, dirs, k, lo[0], lo[1], lo[2], n[0], n[1], n[2], f, dcs, ndt, per);
     }
 }
