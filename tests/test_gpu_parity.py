@@ -1304,6 +1304,29 @@ def test_far_field_four_directions_per_workgroup_match_oracle(dda):
         assert np.abs(dcs[q] - rd).max() <= 1e-12 * rd.max()
 
 
+def test_far_field_rhs_pairs_along_the_grid_match_oracle(dda):
+    """Seven right-hand sides (three pairs, and one with an empty partner)
+    over 522 directions: the launch takes the pairs along its grid's y and,
+    at 131 x 4 workgroups, four directions per workgroup with a partial last
+    group of two.  Every amplitude and cross section of a random P against
+    the oracle's direct sum (1e-12)."""
+    from oracle import dense as odense, farfield
+    d = w.workload("sphere389")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"])
+    n = len(d["ijk"])
+    Pn = w.random_vectors(77, (7, n, 3))
+    nh, th, ph = _random_frames(np.random.default_rng(8), 522)
+    f, dcs = dda.far_field(tgt, opts, _cuda(Pn), nh, th, ph)
+    kd = odense.kd_from_size_parameter(d["x"], n)
+    for q in range(7):
+        A = farfield.amplitude_vectors(d["ijk"], Pn[q], kd, nh)
+        ref = np.stack([np.sum(th * A, axis=1), np.sum(ph * A, axis=1)], axis=1)
+        assert np.abs(f[q] - ref).max() <= 1e-12 * np.abs(ref).max(), q
+        rd = (np.abs(ref[:, 0]) ** 2 + np.abs(ref[:, 1]) ** 2) / kd ** 2
+        assert np.abs(dcs[q] - rd).max() <= 1e-12 * rd.max(), q
+
+
 # ------------------------------------------------------------------ breakdown and restart
 
 @pytest.mark.parametrize("solver", ["bicgstab", "bicgstab2"])
