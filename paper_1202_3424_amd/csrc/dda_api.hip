@@ -128,7 +128,7 @@ AxisPlan make_plan(int L) {
 struct Workspace {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    DevBuf grid, vecs, state, partials, inc, ainv;
+    DevBuf grid, vecs, state, partials, chains, inc, ainv;
     RhsState* host_state = nullptr;
     int host_state_cap = 0;
     hipEvent_t ready = nullptr;   // recorded after the last asynchronous status copy
@@ -154,7 +154,7 @@ struct Workspace {
             if (e) (void)hipEventDestroy(e);
             e = nullptr;
         }
-        for (DevBuf* b : {&grid, &vecs, &state, &partials, &inc, &ainv}) b->release();
+        for (DevBuf* b : {&grid, &vecs, &state, &partials, &chains, &inc, &ainv}) b->release();
         if (host_state) (void)hipHostFree(host_state);
         host_state = nullptr;
         host_state_cap = 0;
@@ -482,6 +482,7 @@ struct Work {
         site_blocks = site_blocks_for(n3, nrhs);
         a.maxblk = std::max(pass_blocks, site_blocks);
         a.partials = (double*)ws.partials.ensure((size_t)nrhs * a.maxblk * PSTRIDE * sizeof(double));
+        a.chains = (double*)ws.chains.ensure((size_t)nrhs * PSTRIDE * NT * sizeof(double));
         a.ainv = (const double2*)ws.ainv.ensure((size_t)nrhs * t->nmat * 3 * sizeof(double2));
         char* ib = (char*)ws.inc.ensure((size_t)nrhs * (3 * sizeof(double) + 3 * sizeof(double2)) + 64);
         kh = (double*)ib;

@@ -89,7 +89,8 @@ struct SiteArgs {
     const double2* in;     // input of the plain / conjugated product
     double2* out;          // output of the plain / conjugated product
     RhsState* st;          // [nrhs]
-    double* partials;      // [nrhs][maxblk][4] per-workgroup sums of the last reducing kernel
+    double* partials;      // [nrhs][PSTRIDE][maxblk] per-workgroup sums of the last reducing kernel
+    double* chains;        // [nrhs][PSTRIDE][NT] k_finalize's per-thread sums of them, or null
     int maxblk;
     int slot;              // RhsState::red slot written by the conjugated product
     double kd;
@@ -131,6 +132,14 @@ enum FinKind {
     // coefficients after the fourth, status and beta after the update
     FIN_B_BETA, FIN_B_MR, FIN_B_UPD
 };
+
+// partial-sum slots k_finalize reads for a kind
+__host__ __device__ constexpr int fin_slots(int kind) {
+    return (kind == FIN_B_MR || kind == FIN_T) ? 8
+           : (kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE || kind == FIN_QV)
+               ? 4
+               : 3;
+}
 
 // FFT lengths with compile-time kernels (dda_passes.h)
 inline bool ct_length(int L) {
@@ -221,6 +230,12 @@ void launch_field_line(int nrhs, const int org[3], const int dims[3], const doub
 // nblk: the producer's workgroups per right-hand side; in a ragged batch
 // NBLK_PASS / NBLK_SITE take each right-hand side's own count from a.rg
 constexpr int NBLK_PASS = -1, NBLK_SITE = -2;
+// Where a right-hand side has at least FIN_CHAIN_MIN workgroups of partial
+// sums (and a.chains is set), k_chain_sums first forms each k_finalize
+// thread's sum of them, one workgroup per slot and right-hand side, with the
+// same additions in the same order; k_finalize then only forms the
+// workgroup's tree, so the results are bitwise those of one workgroup.
+constexpr int FIN_CHAIN_MIN = 2048;
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s);
 // width complex values per site; to_sorted: dst[sorted] = src[caller], else dst[caller] = src[sorted]
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,

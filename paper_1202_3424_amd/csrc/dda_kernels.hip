@@ -692,10 +692,39 @@ __global__ __launch_bounds__(NT) void k_qsum(SiteArgs a) {
     publish_partial<3>(acc, a.partials + (long long)q * a.maxblk * PSTRIDE, blockIdx.x, a.maxblk, sh);
 }
 
+// Each k_finalize thread's sum of the partials of slot i = blockIdx.x,
+// right-hand side q = blockIdx.y: thread t adds workgroups t, t + NT, ...
+// in that order, as sum_partials does.
+__global__ __launch_bounds__(NT) void k_chain_sums(SiteArgs a, int nblk) {
+    const int i = blockIdx.x, q = blockIdx.y;
+    if (nblk == NBLK_PASS) nblk = a.rg[q].pass_blocks;
+    else if (nblk == NBLK_SITE) nblk = a.rg[q].site_blocks;
+    const double* part = a.partials + ((long long)q * PSTRIDE + i) * a.maxblk;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int b = threadIdx.x; b < nblk; b += NT) acc += part[b];
+    a.chains[((long long)q * PSTRIDE + i) * NT + threadIdx.x] = acc;
+}
+
+// The workgroup sums of k_finalize: from the partials, or from the chains
+// k_chain_sums formed of them (the same values, so the same tree).
+template <int NV>
+__device__ __forceinline__ void fin_sums(double (&acc)[NV], const SiteArgs& a, int q, const double* part, int nblk,
+                                         bool chained, double* sh) {
+    if (chained) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = a.chains[((long long)q * PSTRIDE + i) * NT + threadIdx.x];
+        block_sum<NV>(acc, sh);
+    } else {
+        sum_partials<NV>(acc, part, nblk, a.maxblk, sh);
+    }
+}
+
 // Turn the partial sums of a producer kernel into the right-hand side's
 // scalars and status.  One workgroup per right-hand side; it applies the
 // same skip rule as the producer so a skipped right-hand side is untouched.
-__global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk) {
+// chained: k_chain_sums ran before it.
+__global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk, int chained) {
     __shared__ double sh[8 * NT / 64];
     const int q = blockIdx.x;
     RhsState* st = a.st + q;
@@ -713,18 +742,17 @@ __global__ __launch_bounds__(NT) void k_finalize(SiteArgs a, int kind, int nblk)
     if (!run) return;
     if (nblk == NBLK_PASS) nblk = a.rg[q].pass_blocks;
     else if (nblk == NBLK_SITE) nblk = a.rg[q].site_blocks;
-    const bool four = kind == FIN_QUPD || kind == FIN_QCOLD || kind == FIN_QWARM || kind == FIN_QREFINE ||
-                      kind == FIN_QV;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (kind == FIN_B_MR || kind == FIN_T) {
-        sum_partials<8>(acc, part, nblk, a.maxblk, sh);
-    } else if (four) {
+    const int ns = fin_slots(kind);
+    if (ns == 8) {
+        fin_sums<8>(acc, a, q, part, nblk, chained, sh);
+    } else if (ns == 4) {
         double a4[4];
-        sum_partials<4>(a4, part, nblk, a.maxblk, sh);
+        fin_sums<4>(a4, a, q, part, nblk, chained, sh);
         for (int i = 0; i < 4; ++i) acc[i] = a4[i];
     } else {
         double a3[3];
-        sum_partials<3>(a3, part, nblk, a.maxblk, sh);
+        fin_sums<3>(a3, a, q, part, nblk, chained, sh);
         acc[0] = a3[0];
         acc[1] = a3[1];
         acc[2] = a3[2];
@@ -1236,7 +1264,13 @@ void launch_qsum(const SiteArgs& a, int site_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_qsum, dim3(site_blocks, a.nrhs), dim3(NT), 0, s, a);
 }
 void launch_finalize(const SiteArgs& a, int kind, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(a.nrhs), dim3(NT), 0, s, a, kind, nblk);
+    // the largest count a right-hand side can have: its own, or in a ragged
+    // batch the launch's (a.maxblk)
+    const int most = nblk >= 0 ? nblk : a.maxblk;
+    const int chained = a.chains && nblk != 0 && most >= FIN_CHAIN_MIN;
+    if (chained)
+        hipLaunchKernelGGL(k_chain_sums, dim3(fin_slots(kind), a.nrhs), dim3(NT), 0, s, a, nblk);
+    hipLaunchKernelGGL(k_finalize, dim3(a.nrhs), dim3(NT), 0, s, a, kind, nblk, chained);
 }
 
 void launch_permute(int nrhs, int nsites, int width, const int* perm, const double2* src, double2* dst,
