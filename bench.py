@@ -644,6 +644,25 @@ def copy_probe(mib: int = 1024, reps: int = 4):
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "copies": reps}), flush=True)
 
 
+def copy_rate(torch, mib: int = 1024, reps: int = 8) -> float:
+    """GB/s (read plus write) of torch's device-to-device copy of mib MiB:
+    what a plain streaming kernel reaches on this device, beside the 8 TB/s
+    peak, for the HBM-bound passes."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    del a, b
+    return 2.0 * n * 4 * reps / (ms * 1e-3) / 1e9
+
+
 def fp64_comparison(dda, np, torch, jobs, results, steps: int = 3) -> dict:
     """The same workload solved with the FP64 matvec at the same tolerance
     (one batched solve per step, the FP64 tensor FFT built beforehand): its
@@ -886,6 +905,11 @@ def main():
     prec = args.precision or WORKLOADS[args.workload][1]
     out, jobs, d, results, ms_per_step = measure_workload(dda, np, torch, w, args.workload, prec, args.solver,
                                                           args.seed, args.steps, args.warmup)
+    cr = copy_rate(torch)
+    out["roofline"]["plain_copy_GBps"] = cr
+    out["roofline"]["frac_of_plain_copy"] = out["roofline"]["achieved"] / cr
+    for p in out["matvec"]["passes_calibration_step"].values():
+        p["frac_of_plain_copy"] = p["GBps"] / cr
     if prec == "fp32_matvec" and len(jobs) == 1 and not args.no_plain:
         log("solving the same workload with the FP64 matvec ...")
         out["fp64_matvec"] = fp64_comparison(dda, np, torch, jobs, results)
