@@ -1134,32 +1134,22 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
                 }
             }
         }
-        // back to subsequences: X[kappa + P g] -> thread t holds X[t + Q m]
+        // back to subsequences: thread t holds X[kappa_c + P g] = X[t + Q m]
+        // with m = c + (P / Q) g, every element of its subsequence, so the
+        // inverse transform's input is a renumbering of its own registers
+        C w[NCT][P];
 #pragma unroll
-        for (int rd = 0; rd < XR; ++rd) {
-            __syncthreads();
+        for (int a = 0; a < NCT; ++a) {
 #pragma unroll
-            for (int a = 0; a < NCT; ++a) {
-                const int ln = line_of(a);
-                if (round_of(ln) == rd) {
-                    C* row = lds + slot_of(ln) * LS;
+            for (int c = 0; c < P / Q; ++c) {
 #pragma unroll
-                    for (int c = 0; c < P / Q; ++c) {
-#pragma unroll
-                        for (int gg = 0; gg < Q; ++gg) row[t + Q * c + P * gg] = v[a][c * Q + gg];
-                    }
-                }
+                for (int gg = 0; gg < Q; ++gg) w[a][c + (P / Q) * gg] = v[a][c * Q + gg];
             }
-            __syncthreads();
+        }
 #pragma unroll
-            for (int a = 0; a < NCT; ++a) {
-                const int ln = line_of(a);
-                if (round_of(ln) == rd) {
-                    const C* row = lds + slot_of(ln) * LS;
+        for (int a = 0; a < NCT; ++a) {
 #pragma unroll
-                    for (int m = 0; m < P; ++m) v[a][m] = row[t + Q * m];
-                }
-            }
+            for (int m = 0; m < P; ++m) v[a][m] = w[a][m];
         }
         transform(std::integral_constant<int, 1>{}, std::integral_constant<bool, false>{},
                   std::integral_constant<bool, HOUT>{});
@@ -1182,15 +1172,15 @@ __attribute__((amdgpu_waves_per_eu(GH ? WV : rf_waves<T>(L)))) void k_strided_rf
 
 // Pass 3 for the square lengths L = P^2 (64 = 8 x 8, 256 = 16 x 16) in
 // register-resident form.  With P = Q the forward transform's second pass
-// group leaves thread t with the frequencies kz = t + P g (g < P), which is
-// the subsequence t + Q m the inverse transform's first group reads: the
-// product goes from the forward to the inverse transform without the
-// exchange k_strided_rf makes (two exchanges per column instead of three,
-// the same passes and twiddles, so bitwise-identical results).  Also: the
-// twiddles come from the table in the grid's precision (no FP64 -> FP32
-// conversion), the z extent is the compile-time L so the z parities and the
-// octant rows of the tensor are compile-time for all but one frequency per
-// thread, and each thread keeps one base address per column.  TX columns per
+// group leaves thread t with the frequencies kz = t + P g (g < P), in the
+// very order in which the inverse transform's first group reads its
+// subsequence t + Q m (k_strided_rf renumbers its registers there).  The
+// same passes and twiddles as every other form, so bitwise-identical
+// results.  Beyond k_strided_rf: the twiddles come from the table in the
+// grid's precision (no FP64 -> FP32 conversion), the z extent is the
+// compile-time L so the z parities and the octant rows of the tensor are
+// compile-time for all but one frequency per thread, and each thread keeps
+// one base address per column.  TX columns per
 // workgroup, Q threads per column (thread t = threadIdx.x / TX); one
 // right-hand side per workgroup; XR exchange rounds; XG: the XCD-grouped
 // order of xcd_tile; WV: occupancy asked of the compiler; PD: how many
