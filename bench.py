@@ -335,8 +335,23 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
         (fb, kf), (wb, kw) = prod(frows, "FETCH_SIZE", fscale), prod(wrows, "WRITE_SIZE", wscale)
         if fb is None or wb is None or kf != kw:
             # the two counter runs' autotuners chose different variants of a
-            # pass that ties: their counts do not add up to one kernel's
-            per_pass[name] = {"kernel_counted": f"{kf} / {kw}", "measured_bytes_per_launch": None}
+            # pass that ties: their production counts do not add up to one
+            # kernel's.  Both runs make the autotuner's timing launches of
+            # every variant (full launches, every right-hand side), which
+            # give each of the two kernels' traffic instead.
+            def tuned(rs, counter, scale, k):
+                fam = sorted((r for r in rs if r["Counter_Name"] == counter and pp.search(r["Kernel_Name"])),
+                             key=lambda r: int(r["Dispatch_Id"]))[:trials]
+                v = [float(r["Counter_Value"]) for r in fam if short(r["Kernel_Name"]) == k]
+                return statistics.mean(v) * 1024 * scale if v else None
+            alg_full = cal["bytes_per_rhs_matvec"] * n_rhs + cal.get("bytes_per_launch_shared", 0.0)
+            alts = {}
+            for k in sorted({kf, kw} - {None}):
+                f_, w_ = tuned(frows, "FETCH_SIZE", fscale, k), tuned(wrows, "WRITE_SIZE", wscale, k)
+                if f_ is not None and w_ is not None:
+                    alts[k] = {"bytes_per_full_launch": f_ + w_, "over_algorithmic": (f_ + w_) / alg_full}
+            per_pass[name] = {"kernel_counted": f"{kf} / {kw}", "measured_bytes_per_launch": None,
+                              "us_per_launch": cal["ms_per_launch"] * 1e3, "autotune_full_launches": alts}
             continue
         alg = cal["GBps"] * cal["ms_per_launch"] * 1e6
         per_pass[name] = {"kernel_counted": kf if kf == kw else f"{kf} / {kw}",
@@ -355,7 +370,9 @@ def summarize_profiles(tr: str, workload: str, prec: str, unprofiled: str) -> No
     for name, e in per_pass.items():
         if e["measured_bytes_per_launch"] is None:
             lines.append(f"#     {name:14s} the FETCH_SIZE and WRITE_SIZE runs launched different variants "
-                         f"({e['kernel_counted']}); see the per-variant table for pass 3")
+                         f"({e['kernel_counted']}); their autotuning launches (full launches):")
+            for k, a in e.get("autotune_full_launches", {}).items():
+                lines.append(f"#       {k[:70]:70s} {a['bytes_per_full_launch'] / 1e6:9.2f} MB  x{a['over_algorithmic']:.2f}")
             continue
         lines.append(f"#     {name:14s} {e['us_per_launch']:9.2f} {e['measured_bytes_per_launch'] / 1e6:11.2f} "
                      f"{e['over_algorithmic']:6.2f} {e['measured_GBps']:13.0f} {e['measured_frac']:5.2f}"
