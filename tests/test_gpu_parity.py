@@ -574,6 +574,30 @@ def test_shared_launch_batch_matches_separate_solves(dda, solver, precision):
             assert torch.equal(Pn[q], P1[k]) and rn[q] == r1[k], (i, q)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_matvec"])
+def test_shared_launch_batch_with_chained_finalize(dda, precision):
+    """Spheres of radius 30 and 28 (113,081 and 91,965 sites) on one 128^3
+    grid: their x passes have 3,721 and 3,249 workgroups per right-hand side,
+    so the finalizes of the products run from per-thread sums formed one
+    workgroup per slot, in the shared-launch batch with each right-hand
+    side's own count from the batch table.  Every P and result equals,
+    bitwise, that of solving its target alone."""
+    ts = [dda.Target(w.sphere_integer(30.0), 1.33 + 0.01j), dda.Target(w.sphere_integer(28.0), 1.5 + 0.05j)]
+    for t in ts:
+        assert tuple(t.grid) == (128, 128, 128)
+    opts = [dda.Options.for_size_parameter(x, precision=precision) for x in (3.0, 2.6)]
+    kh, e0 = w.along_x_yz()
+    rt = np.array([0, 1, 0, 1])
+    khb, e0b = np.vstack([kh[:1], kh[:1], kh[1:], kh[1:]]), np.vstack([e0[:1], e0[:1], e0[1:], e0[1:]])
+    Ps, res = dda.solve_batched(ts, opts, rt, khb, e0b)
+    for i, t in enumerate(ts):
+        qs = [q for q in range(len(rt)) if rt[q] == i]
+        P1, r1 = dda.solve(t, opts[i], khb[qs], e0b[qs])
+        for k, q in enumerate(qs):
+            assert res[q]["status"] == 0, (i, res[q])
+            assert torch.equal(Ps[q], P1[k]) and res[q] == r1[k], (i, q)
+
+
 def test_batch_schedule_leaves_results_unchanged(dda):
     """Repeated calls of one batch shape run with 4, 2 and 1 jobs in flight
     while the schedule is tried, then with the fastest: every call gives the
