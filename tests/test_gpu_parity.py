@@ -1309,6 +1309,25 @@ def test_nonfinite_right_hand_side_or_start_is_reported(dda):
 
 # ------------------------------------------------------------------ far field, grouped directions
 
+def test_scattering_averages_odd_direction_sets_match_oracle(dda):
+    """Direction sets of 5 x 3 = 15 per right-hand side, not a multiple of
+    the four directions a workgroup takes: the averages run one direction
+    per workgroup, and agree with the oracle's quadrature of the same rule on
+    the same P (1e-10)."""
+    from oracle import dense as odense, farfield
+    d = w.workload("au_brick")
+    tgt = dda.Target(d["ijk"], d["m"])
+    opts = dda.Options.for_size_parameter(d["x"], tol=1e-8, polarizability="GKDLDR")
+    P, res = dda.solve(tgt, opts, d["khat"], d["e0"])
+    av = dda.scattering_averages(tgt, opts, d["khat"], d["e0"], P, 5, 3)
+    a = odense.aeff_over_d(len(d["ijk"]))
+    Pn = P.cpu().numpy()
+    for q in range(2):
+        qs, gg, c2 = farfield.angular_averages(d["ijk"], Pn[q], res[q]["kd"], d["khat"][q], a, 5, 3)
+        assert abs(av[q]["qsca"] - qs) <= 1e-10 * qs
+        assert abs(av[q]["g"] - gg) <= 1e-10 and abs(av[q]["cos2"] - c2) <= 1e-10
+
+
 def test_far_field_four_directions_per_workgroup_match_oracle(dda):
     """2,051 directions: the far-field launch takes four directions per
     workgroup (partial last group of three) against the oracle's sums."""
