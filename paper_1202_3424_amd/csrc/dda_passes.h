@@ -975,9 +975,9 @@ __global__ __launch_bounds__(NT) void k_zfold(Geo g, typename V2<T>::t* grid, co
 // runs the first pass group in registers, the tile is exchanged once through
 // LDS, and the thread then runs the remaining passes on its residue classes
 // and stores X[kappa + P g] directly.  With GH the three components of a
-// column stay in one thread, so the tensor product is applied in registers;
-// a second exchange brings the product back to subsequences for the inverse
-// transform.  The passes are those of fft_lines_ct (bitwise-identical
+// column stay in one thread, so the tensor product is applied in registers,
+// and the thread's frequencies are already its subsequence for the inverse
+// transform (a renumbering of its registers, no exchange).  The passes are those of fft_lines_ct (bitwise-identical
 // results to k_strided); only the data movement differs.  One right-hand
 // side per workgroup (grid z).  XR: the exchange runs in XR rounds over the
 // tile's lines (LDS of 3 TX / XR lines).  HIN / HOUT: the half-line pruning
